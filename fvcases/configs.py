@@ -1,0 +1,286 @@
+"""The synthetic workloads: seeded FV Laplacian systems in LDU form.
+
+The paper evaluates on a Dirichlet heat equation in a cube (laplacianFoam) and
+the pressure equation of a lid-driven cavity (icoFoam) (Section 5, test cases;
+Table pcgs2 for the steady 7-point Laplacian).  Those OpenFOAM case files are
+not used; these generators stand in for them with the same structure: a
+7-point hexahedral stencil, LDU addressing, Dirichlet or Neumann boundaries.
+
+Named workloads (full size; every builder also takes a smaller shape):
+
+* ``laplace32``   32^3 uniform, unit face coefficients, Dirichlet 0 on z-min,
+                  b ~ U[-1,1].
+* ``varcoef192``  192^3, face conductivities lognormal(0,1), Dirichlet 0 on
+                  x-min and x-max, cells randomly permuted then RCM-renumbered,
+                  b ~ U[-1,1].
+* ``cavity256``   256x256x64 with cell heights graded by 1.02 per cell toward
+                  the lid (y-max), Neumann walls, cell 0 pinned by elimination,
+                  b = -div(U) of a random cell velocity, zero mean.
+* ``batch256``    256 independent cubes, edge uniform in {16..64}, as
+                  varcoef but natural order, plus x_target ~ U[-1,1].
+"""
+from __future__ import annotations
+
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import mesh as M
+from . import rng as R
+
+CACHE_VERSION = 1
+
+
+@dataclasses.dataclass
+class Case:
+    name: str
+    shape: tuple
+    n: int
+    owner: np.ndarray      # int32[F]
+    neighbour: np.ndarray  # int32[F]
+    diag: np.ndarray       # float64[n]
+    upper: np.ndarray      # float64[F]
+    lower: np.ndarray      # float64[F]
+    b: np.ndarray          # float64[n]
+    tol: float = 1e-8
+    seed: int = 0
+    meta: dict = dataclasses.field(default_factory=dict)
+    x_target: Optional[np.ndarray] = None
+
+    @property
+    def F(self) -> int:
+        return int(self.owner.shape[0])
+
+    @property
+    def nnz(self) -> int:
+        return self.n + 2 * self.F
+
+    def hashes(self) -> dict:
+        return {
+            "addressing": R.sha256(self.owner, self.neighbour),
+            "coefficients": R.sha256(self.diag, self.upper, self.lower),
+            "rhs": R.sha256(self.b),
+        }
+
+
+def _finish(name, shape, n, owner, nb, diag, upper, lower, b, tol, seed, meta, x_target=None):
+    return Case(
+        name=name, shape=tuple(shape), n=int(n),
+        owner=np.ascontiguousarray(owner, dtype=np.int32),
+        neighbour=np.ascontiguousarray(nb, dtype=np.int32),
+        diag=np.ascontiguousarray(diag, dtype=np.float64),
+        upper=np.ascontiguousarray(upper, dtype=np.float64),
+        lower=np.ascontiguousarray(lower, dtype=np.float64),
+        b=np.ascontiguousarray(b, dtype=np.float64),
+        tol=tol, seed=seed, meta=meta,
+        x_target=None if x_target is None else np.ascontiguousarray(x_target, dtype=np.float64),
+    )
+
+
+def laplace(shape=(32, 32, 32), seed=1, dirichlet=("zmin",), tol=1e-8, rhs="uniform", name="laplace"):
+    """Uniform mesh, unit face coefficients (upper = lower = -1); each
+    Dirichlet side adds 2 to the diagonal of its cells (value 0 at the face).
+    rhs: 'uniform' (U[-1,1], stream rhs) or 'ones'."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    owner, nb, _ = M.structured_faces(nx, ny, nz)
+    bcells = np.concatenate([M.boundary_cells(shape, s) for s in dirichlet]) if dirichlet else np.zeros(0, np.int64)
+    diag, upper, lower = M.assemble_ldu(n, owner, nb, np.ones(owner.shape), bcells, np.full(bcells.shape, 2.0))
+    if rhs == "uniform":
+        b = R.uniform(R.stream(seed, "rhs"), n)
+    elif rhs == "ones":
+        b = np.ones(n)
+    else:
+        raise ValueError(rhs)
+    meta = {"dirichlet": list(dirichlet), "coef": "unit", "ordering": "natural"}
+    return _finish(name, shape, n, owner, nb, diag, upper, lower, b, tol, seed, meta)
+
+
+def varcoef(shape=(192, 192, 192), seed=2, permute=True, tol=1e-8, name="varcoef"):
+    """Lognormal(0,1) conductivities on internal faces and on the Dirichlet
+    faces of x-min then x-max (drawn in that order from stream coef);
+    Dirichlet 0 on x-min/x-max; b ~ U[-1,1] in natural order; then cells
+    randomly permuted (stream perm) and renumbered by RCM."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    owner, nb, _ = M.structured_faces(nx, ny, nz)
+    gcoef = R.stream(seed, "coef")
+    k_int = R.lognormal(gcoef, owner.shape[0])
+    bl = M.boundary_cells(shape, "xmin")
+    bh = M.boundary_cells(shape, "xmax")
+    k_b = R.lognormal(gcoef, bl.shape[0] + bh.shape[0])
+    bcells = np.concatenate([bl, bh])
+    diag, upper, lower = M.assemble_ldu(n, owner, nb, k_int, bcells, 2.0 * k_b)
+    b = R.uniform(R.stream(seed, "rhs"), n)
+    meta = {"dirichlet": ["xmin", "xmax"], "coef": "lognormal(0,1)", "ordering": "natural"}
+    if permute:
+        p1 = R.stream(seed, "perm").permutation(n).astype(np.int64)
+        p2 = M.rcm_order(n, p1[owner], p1[nb])
+        new_index = p2[p1]
+        owner, nb, upper, lower, _ = M.renumber(n, owner, nb, upper, lower, new_index)
+        d2 = np.empty_like(diag)
+        d2[new_index] = diag
+        b2 = np.empty_like(b)
+        b2[new_index] = b
+        diag, b = d2, b2
+        meta["ordering"] = "random permutation, then reverse Cuthill-McKee"
+        meta["bandwidth"] = M.bandwidth(owner, nb)
+    return _finish(name, shape, n, owner, nb, diag, upper, lower, b, tol, seed, meta)
+
+
+def graded_spacing(m, length, ratio):
+    """m cell widths on [0, length], each ``ratio`` times smaller than the
+    previous one (ratio > 1 grades toward the high end)."""
+    w = ratio ** (-np.arange(m, dtype=np.float64))
+    return w * (length / w.sum())
+
+
+def cavity(shape=(256, 256, 64), seed=3, ratio=1.02, tol=1e-9, name="cavity"):
+    """Pressure-equation stand-in for the lid-driven cavity: box
+    [0,1]x[0,1]x[0, nz/nx] with nx uniform cells in x and z and ny cells in y
+    graded by ``ratio`` per cell toward the lid (y-max).  w_f = |S_f|/|d_f|,
+    Neumann on every wall.  Cell 0 (the x-min/y-min/z-min corner, far from
+    the lid) is pinned to 0 by elimination: the couplings of its faces are set
+    to zero in both triangles (the diagonals keep them) and b[0] = 0, so A
+    stays symmetric positive definite and x[0] = 0.
+    b = -div(U): U ~ U[-1,1]^3 per cell (stream vel), face flux
+    0.5*(U_owner + U_neighbour).S_f on internal faces and 0 on walls;
+    b -= mean(b); then b[0] = 0."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    owner, nb, direction = M.structured_faces(nx, ny, nz)
+    h = 1.0 / nx
+    dx = np.full(nx, h)
+    dz = np.full(nz, h)
+    dy = graded_spacing(ny, 1.0, ratio)
+    w = M.geometric_weights(shape, direction, owner, dx, dy, dz)
+    diag, upper, lower = M.assemble_ldu(n, owner, nb, w)
+    pinned = (owner == 0) | (nb == 0)
+    upper[pinned] = 0.0
+    lower[pinned] = 0.0
+    U = R.uniform(R.stream(seed, "vel"), 3 * n).reshape(n, 3)
+    i, j, k = M.cell_ijk(shape, owner)
+    area = np.where(direction == 0, dy[j] * dz[k], np.where(direction == 1, dx[i] * dz[k], dx[i] * dy[j]))
+    d_idx = direction.astype(np.int64)
+    phi = 0.5 * (U[owner, d_idx] + U[nb, d_idx]) * area
+    div = np.zeros(n)
+    np.add.at(div, owner, phi)
+    np.add.at(div, nb, -phi)
+    b = -div
+    b -= b.mean()
+    b[0] = 0.0
+    meta = {"boundary": "Neumann walls, cell 0 pinned", "grading": ratio, "dy_first": float(dy[0]),
+            "dy_last": float(dy[-1]), "ordering": "natural", "pinned_faces": int(pinned.sum())}
+    return _finish(name, shape, n, owner, nb, diag, upper, lower, b, tol, seed, meta)
+
+
+@dataclasses.dataclass
+class Batch:
+    """Concatenated independent systems; addressing is local to each system."""
+    name: str
+    cases: list
+    cell_off: np.ndarray   # int32[nsys+1]
+    face_off: np.ndarray   # int32[nsys+1]
+    owner: np.ndarray
+    neighbour: np.ndarray
+    diag: np.ndarray
+    upper: np.ndarray
+    lower: np.ndarray
+    b: np.ndarray
+    x_target: np.ndarray
+    tol: float = 1e-8
+    seed: int = 0
+
+    @property
+    def nsys(self) -> int:
+        return len(self.cases)
+
+
+def batch(nsys=256, edge_lo=16, edge_hi=64, seed=5, tol=1e-8, name="batch"):
+    """nsys cubes with edge e_s uniform in {edge_lo..edge_hi} (stream sizes);
+    per system: lognormal conductivities (stream coef, consumed system after
+    system), Dirichlet 0 on x-min/x-max, natural order, b ~ U[-1,1] (stream
+    rhs) and x_target ~ U[-1,1] (stream target)."""
+    edges = R.stream(seed, "sizes").integers(edge_lo, edge_hi + 1, size=nsys)
+    gcoef = R.stream(seed, "coef")
+    grhs = R.stream(seed, "rhs")
+    gtgt = R.stream(seed, "target")
+    cases = []
+    for s, e in enumerate(edges):
+        e = int(e)
+        shape = (e, e, e)
+        n = e ** 3
+        owner, nb, _ = M.structured_faces(e, e, e)
+        k_int = R.lognormal(gcoef, owner.shape[0])
+        bl = M.boundary_cells(shape, "xmin")
+        bh = M.boundary_cells(shape, "xmax")
+        k_b = R.lognormal(gcoef, bl.shape[0] + bh.shape[0])
+        diag, upper, lower = M.assemble_ldu(n, owner, nb, k_int, np.concatenate([bl, bh]), 2.0 * k_b)
+        b = R.uniform(grhs, n)
+        xt = R.uniform(gtgt, n)
+        cases.append(_finish(f"{name}[{s}]", shape, n, owner, nb, diag, upper, lower, b, tol, seed,
+                             {"edge": e, "ordering": "natural"}, x_target=xt))
+    cell_off = np.zeros(nsys + 1, dtype=np.int64)
+    face_off = np.zeros(nsys + 1, dtype=np.int64)
+    cell_off[1:] = np.cumsum([c.n for c in cases])
+    face_off[1:] = np.cumsum([c.F for c in cases])
+    if cell_off[-1] >= 2 ** 31 or face_off[-1] >= 2 ** 31:
+        raise ValueError("batch too large for int32 offsets")
+    cat = lambda attr: np.concatenate([getattr(c, attr) for c in cases])
+    return Batch(name=name, cases=cases, cell_off=cell_off.astype(np.int32), face_off=face_off.astype(np.int32),
+                 owner=cat("owner"), neighbour=cat("neighbour"), diag=cat("diag"), upper=cat("upper"),
+                 lower=cat("lower"), b=cat("b"), x_target=cat("x_target"), tol=tol, seed=seed)
+
+
+# ---------------------------------------------------------------------------
+# Named full-size workloads, with an on-disk cache for the large ones.
+
+def _cache_dir():
+    return os.environ.get("FVCASES_CACHE", "/tmp/fvcases_cache")
+
+
+_FIELDS = ("owner", "neighbour", "diag", "upper", "lower", "b")
+
+
+def _cached(key, builder):
+    d = os.path.join(_cache_dir(), f"v{CACHE_VERSION}_{key}")
+    meta_path = os.path.join(d, "meta.json")
+    import json
+    if os.path.exists(meta_path):
+        try:
+            with open(meta_path) as f:
+                info = json.load(f)
+            arrs = {k: np.load(os.path.join(d, k + ".npy"), allow_pickle=False) for k in _FIELDS}
+            return Case(name=info["name"], shape=tuple(info["shape"]), n=info["n"], tol=info["tol"],
+                        seed=info["seed"], meta=info["meta"], **arrs)
+        except Exception:
+            pass
+    case = builder()
+    try:
+        os.makedirs(d, exist_ok=True)
+        for k in _FIELDS:
+            np.save(os.path.join(d, k + ".npy"), getattr(case, k), allow_pickle=False)
+        with open(meta_path + ".tmp", "w") as f:
+            json.dump({"name": case.name, "shape": list(case.shape), "n": case.n, "tol": case.tol,
+                       "seed": case.seed, "meta": case.meta}, f)
+        os.replace(meta_path + ".tmp", meta_path)
+    except OSError:
+        pass
+    return case
+
+
+def make(name: str, cache: bool = True):
+    """Full-size named workload."""
+    if name == "laplace32":
+        return laplace((32, 32, 32), seed=1, name=name)
+    if name == "varcoef192":
+        b = lambda: varcoef((192, 192, 192), seed=2, name=name)
+        return _cached("varcoef192_s2", b) if cache else b()
+    if name == "cavity256":
+        b = lambda: cavity((256, 256, 64), seed=3, name=name)
+        return _cached("cavity256_s3", b) if cache else b()
+    if name == "batch256":
+        return batch(256, 16, 64, seed=5, name=name)
+    raise KeyError(name)

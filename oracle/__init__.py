@@ -1,0 +1,185 @@
+"""ctypes shim over the plain-C CPU oracle -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It is built from ``oracle/oracle.c`` with gcc
+(``-O2 -ffp-contract=off``, no fast-math) and shares nothing with the HIP
+library.  Every function takes NumPy arrays (the seeded inputs) and returns
+NumPy results.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+OK, NOT_CONVERGED, BREAKDOWN = 0, 1, -3
+PRECOND = {"none": 0, "jacobi": 1}
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (plain C99, gcc)."""
+    src = os.path.join(HERE, "oracle.c")
+    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(src):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
+                ("r0_norm", ctypes.c_double), ("b_norm", ctypes.c_double)]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        i32 = ctypes.c_int32
+        d = ctypes.c_double
+        L.or_spmv.argtypes = [i32, i32, P, P, P, P, P, P, P]
+        L.or_spmv.restype = None
+        L.or_dot.argtypes = [i32, P, P]
+        L.or_dot.restype = d
+        L.or_cg.argtypes = [i32, i32, P, P, P, P, P, P, P, d, i32, i32, P, P, P, P]
+        L.or_cg.restype = i32
+        L.or_pipecg.argtypes = [i32, i32, P, P, P, P, P, P, P, d, i32, i32, i32, P, P]
+        L.or_pipecg.restype = i32
+        L.or_refine.argtypes = [i32, i32, P, P, P, P, P, P, P, d, d, i32, i32, P]
+        L.or_refine.restype = i32
+        L.or_adjoint_grads.argtypes = [i32, i32, P, P, P, P, P, P, P]
+        L.or_adjoint_grads.restype = None
+        _lib = L
+    return _lib
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _Sys:
+    """Arrays of one LDU system, converted once."""
+
+    def __init__(self, n, owner, nb, diag, upper, lower=None):
+        self.n = int(n)
+        self.owner = _i32(owner)
+        self.nb = _i32(nb)
+        self.F = int(self.owner.shape[0])
+        self.diag = _f64(diag)
+        self.upper = _f64(upper)
+        self.lower = self.upper if lower is None else _f64(lower)
+
+    def args(self):
+        return (self.n, self.F, _p(self.owner), _p(self.nb), _p(self.diag), _p(self.upper), _p(self.lower))
+
+
+def system(case):
+    return _Sys(case.n, case.owner, case.neighbour, case.diag, case.upper, case.lower)
+
+
+def _as_sys(A):
+    return A if isinstance(A, _Sys) else system(A)
+
+
+def spmv(A, v):
+    A = _as_sys(A)
+    v = _f64(v)
+    y = np.empty(A.n)
+    lib().or_spmv(*A.args(), _p(v), _p(y))
+    return y
+
+
+def dot(a, b):
+    a = _f64(a)
+    b = _f64(b)
+    return lib().or_dot(a.shape[0], _p(a), _p(b))
+
+
+def cg(A, b, x0=None, tol=1e-8, maxit=10000, precond="jacobi", history=False):
+    """Standard PCG.  Returns (x, stats dict[, history dict])."""
+    A = _as_sys(A)
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    st = Stats()
+    m = max(int(maxit), 0) + 1
+    ah = np.zeros(m) if history else None
+    bh = np.zeros(m) if history else None
+    rh = np.zeros(m) if history else None
+    lib().or_cg(*A.args(), _p(b), _p(x), float(tol), int(maxit), PRECOND[precond], ctypes.byref(st),
+                _p(ah), _p(bh), _p(rh))
+    s = st.asdict()
+    if history:
+        k = s["iters"]
+        return x, s, {"alpha": ah[:k], "beta": bh[:k], "res": rh[: k + 1]}
+    return x, s
+
+
+def pipecg(A, b, x0=None, tol=1e-8, maxit=10000, precond="jacobi", folded=True, history=False):
+    """Pipelined PCG (literal or Jacobi-folded).  Returns (x, stats[, res])."""
+    A = _as_sys(A)
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    st = Stats()
+    rh = np.zeros(max(int(maxit), 0) + 1) if history else None
+    lib().or_pipecg(*A.args(), _p(b), _p(x), float(tol), int(maxit), PRECOND[precond], int(bool(folded)),
+                    ctypes.byref(st), _p(rh))
+    s = st.asdict()
+    if history:
+        return x, s, rh[: s["iters"] + 1]
+    return x, s
+
+
+def refine(A, b, x0=None, outer_tol=1e-10, inner_tol=1e-5, max_outer=50, max_inner=20000):
+    A = _as_sys(A)
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    st = Stats()
+    lib().or_refine(*A.args(), _p(b), _p(x), float(outer_tol), float(inner_tol), int(max_outer), int(max_inner),
+                    ctypes.byref(st))
+    return x, st.asdict()
+
+
+def adjoint_grads(A, x, lam):
+    A = _as_sys(A)
+    x = _f64(x)
+    lam = _f64(lam)
+    gd = np.empty(A.n)
+    gu = np.empty(A.F)
+    gl = np.empty(A.F)
+    lib().or_adjoint_grads(A.n, A.F, _p(A.owner), _p(A.nb), _p(x), _p(lam), _p(gd), _p(gu), _p(gl))
+    return gd, gu, gl
+
+
+def dense(A):
+    """Dense matrix of an LDU system (for tiny cases)."""
+    A = _as_sys(A)
+    M = np.diag(A.diag.copy())
+    M[A.owner, A.nb] += A.upper
+    M[A.nb, A.owner] += A.lower
+    return M

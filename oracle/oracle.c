@@ -1,0 +1,388 @@
+/*
+ * CPU oracle for the finite-volume Laplacian CG solve -- TEST INFRASTRUCTURE.
+ *
+ * Written from the paper (AlOnazi, Keyes, Lastovetsky, Rychkov, arXiv
+ * 1505.07630) and from the mathematics of the methods it names:
+ *   - Section 2: A x = b with A square, symmetric positive (semi)definite;
+ *     a CG iteration is a sparse matrix-vector product, an optional
+ *     preconditioner, three global inner products and vector updates.
+ *   - Section 4.1: the pipelined CG of Ghysels and Vanroose, one global
+ *     reduction per iteration, overlapped with the matrix-vector product.
+ *   - Section 5 / Table ai_cg: the kernels are memory bound; nothing here is
+ *     blocked, fused or reordered beyond the definitions.
+ *
+ * Plain FP64, single thread, built with -O2 -ffp-contract=off.  Used only by
+ * tests, the smoke check and the benchmark's CPU-baseline leg.
+ */
+#include "oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- LDU matrix-vector product (Section 4.2: nnz = n + 2F; Section 5:
+ * OpenFOAM lduMatrix).  The plain definition: diagonal term, then each face
+ * adds its upper coefficient to the owner row and its lower coefficient to
+ * the neighbour row. */
+void or_spmv(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+             const double* diag, const double* upper, const double* lower,
+             const double* v, double* y)
+{
+    for (int32_t c = 0; c < n; ++c) y[c] = diag[c] * v[c];
+    for (int32_t f = 0; f < nf; ++f) {
+        y[owner[f]] += upper[f] * v[nb[f]];
+        y[nb[f]] += lower[f] * v[owner[f]];
+    }
+}
+
+double or_dot(int32_t n, const double* a, const double* b)
+{
+    double s = 0.0;
+    for (int32_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+static double* alloc_vec(int32_t n)
+{
+    return (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+}
+
+/* r = b - A x */
+static void residual(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                     const double* diag, const double* upper, const double* lower,
+                     const double* b, const double* x, double* r)
+{
+    or_spmv(n, nf, owner, nb, diag, upper, lower, x, r);
+    for (int32_t c = 0; c < n; ++c) r[c] = b[c] - r[c];
+}
+
+/* z = M^-1 r for M = I or M = diag(A) (the "optional preconditioning" of
+ * Section 2, taken as Jacobi). */
+static void precond_apply(int32_t n, int32_t precond, const double* diag, const double* r, double* z)
+{
+    if (precond == OR_PRECOND_JACOBI)
+        for (int32_t c = 0; c < n; ++c) z[c] = r[c] / diag[c];
+    else
+        for (int32_t c = 0; c < n; ++c) z[c] = r[c];
+}
+
+static int diag_positive(int32_t n, const double* diag)
+{
+    for (int32_t c = 0; c < n; ++c)
+        if (!(diag[c] > 0.0) || !isfinite(diag[c])) return 0;
+    return 1;
+}
+
+static void finish_stats(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                         const double* diag, const double* upper, const double* lower,
+                         const double* b, const double* x, double bnorm, double rnorm,
+                         or_stats* st)
+{
+    if (!st) return;
+    double* r = alloc_vec(n);
+    residual(n, nf, owner, nb, diag, upper, lower, b, x, r);
+    double tr = sqrt(or_dot(n, r, r));
+    free(r);
+    st->b_norm = bnorm;
+    st->rel_res = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+    st->true_rel_res = bnorm > 0.0 ? tr / bnorm : 0.0;
+}
+
+/* ---- Standard preconditioned CG (Section 2).  The three inner products of
+ * each iteration are delta = (p, A p), gamma = (r, z) and rho = (r, r); the
+ * stopping test is ||r||_2 <= tol * ||b||_2 on the recursively updated,
+ * unpreconditioned residual. */
+int32_t or_cg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+              const double* diag, const double* upper, const double* lower,
+              const double* b, double* x, double tol, int32_t maxit, int32_t precond,
+              or_stats* st, double* alpha_hist, double* beta_hist, double* res_hist)
+{
+    if (st) memset(st, 0, sizeof(*st));
+    double bnorm = sqrt(or_dot(n, b, b));
+    if (bnorm == 0.0) {
+        for (int32_t c = 0; c < n; ++c) x[c] = 0.0;
+        if (st) { st->status = OR_OK; st->b_norm = 0.0; }
+        if (res_hist) res_hist[0] = 0.0;
+        return OR_OK;
+    }
+    if (precond == OR_PRECOND_JACOBI && !diag_positive(n, diag)) {
+        if (st) { st->status = OR_BREAKDOWN; st->b_norm = bnorm; }
+        return OR_BREAKDOWN;
+    }
+    double* r = alloc_vec(n);
+    double* z = alloc_vec(n);
+    double* p = alloc_vec(n);
+    double* q = alloc_vec(n);
+
+    residual(n, nf, owner, nb, diag, upper, lower, b, x, r);
+    precond_apply(n, precond, diag, r, z);
+    memcpy(p, z, sizeof(double) * (size_t)n);
+    double gamma = or_dot(n, r, z);
+    double rnorm = sqrt(or_dot(n, r, r));
+    if (st) st->r0_norm = rnorm;
+    if (res_hist) res_hist[0] = rnorm;
+
+    int32_t status = OR_NOT_CONVERGED;
+    int32_t k = 0;
+    if (rnorm <= tol * bnorm) {
+        status = OR_OK;
+    } else {
+        for (k = 1; k <= maxit; ++k) {
+            or_spmv(n, nf, owner, nb, diag, upper, lower, p, q);
+            double delta = or_dot(n, p, q);
+            if (!(delta > 0.0) || !isfinite(delta) || !isfinite(gamma)) {
+                status = OR_BREAKDOWN;
+                k -= 1;
+                break;
+            }
+            double alpha = gamma / delta;
+            for (int32_t c = 0; c < n; ++c) x[c] += alpha * p[c];
+            for (int32_t c = 0; c < n; ++c) r[c] -= alpha * q[c];
+            precond_apply(n, precond, diag, r, z);
+            double gamma_new = or_dot(n, r, z);
+            double rho = or_dot(n, r, r);
+            rnorm = sqrt(rho);
+            if (alpha_hist) alpha_hist[k - 1] = alpha;
+            if (res_hist) res_hist[k] = rnorm;
+            if (rnorm <= tol * bnorm) {
+                status = OR_OK;
+                break;
+            }
+            double beta = gamma_new / gamma;
+            if (beta_hist) beta_hist[k - 1] = beta;
+            gamma = gamma_new;
+            for (int32_t c = 0; c < n; ++c) p[c] = z[c] + beta * p[c];
+        }
+        if (k > maxit) k = maxit;
+    }
+    if (st) { st->iters = k; st->status = status; }
+    finish_stats(n, nf, owner, nb, diag, upper, lower, b, x, bnorm, rnorm, st);
+    free(r); free(z); free(p); free(q);
+    return status;
+}
+
+/* ---- Pipelined preconditioned CG (Ghysels and Vanroose; Section 4.1).
+ * Per iteration i: one reduction of gamma = (r,u), delta = (w,u) and
+ * rho = (r,r); then m = M^-1 w and n = A m (the product the reduction would
+ * overlap); the scalars come from the recurrences
+ *   beta_i = gamma_i / gamma_{i-1},
+ *   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})
+ * (beta_0 = 0, alpha_0 = gamma_0 / delta_0), and the vectors from
+ *   z = n + beta z, q = m + beta q, s = w + beta s, p = u + beta p,
+ *   x += alpha p, r -= alpha s, u -= alpha q, w -= alpha z.
+ * In the folded Jacobi form u = r/d, q = s/d and m = w/d are evaluated
+ * instead of carried.  iters counts updates of x, as in or_cg. */
+int32_t or_pipecg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                  const double* diag, const double* upper, const double* lower,
+                  const double* b, double* x, double tol, int32_t maxit, int32_t precond,
+                  int32_t folded, or_stats* st, double* res_hist)
+{
+    if (st) memset(st, 0, sizeof(*st));
+    if (folded && precond != OR_PRECOND_JACOBI) folded = 0;
+    double bnorm = sqrt(or_dot(n, b, b));
+    if (bnorm == 0.0) {
+        for (int32_t c = 0; c < n; ++c) x[c] = 0.0;
+        if (st) st->status = OR_OK;
+        if (res_hist) res_hist[0] = 0.0;
+        return OR_OK;
+    }
+    if (precond == OR_PRECOND_JACOBI && !diag_positive(n, diag)) {
+        if (st) { st->status = OR_BREAKDOWN; st->b_norm = bnorm; }
+        return OR_BREAKDOWN;
+    }
+    double *r = alloc_vec(n), *u = alloc_vec(n), *w = alloc_vec(n), *m = alloc_vec(n);
+    double *nv = alloc_vec(n), *z = alloc_vec(n), *q = alloc_vec(n), *s = alloc_vec(n);
+    double *p = alloc_vec(n);
+
+    residual(n, nf, owner, nb, diag, upper, lower, b, x, r);
+    precond_apply(n, precond, diag, r, u);
+    or_spmv(n, nf, owner, nb, diag, upper, lower, u, w);
+
+    double gamma_prev = 0.0, alpha_prev = 0.0, rnorm = 0.0;
+    int32_t status = OR_NOT_CONVERGED;
+    int32_t i;
+    for (i = 0;; ++i) {
+        if (folded)
+            for (int32_t c = 0; c < n; ++c) u[c] = r[c] / diag[c];
+        double gamma = or_dot(n, r, u);
+        double delta = or_dot(n, w, u);
+        double rho = or_dot(n, r, r);
+        rnorm = sqrt(rho);
+        if (i == 0 && st) st->r0_norm = rnorm;
+        if (res_hist) res_hist[i] = rnorm;
+        if (rnorm <= tol * bnorm) { status = OR_OK; break; }
+        if (i == maxit) { status = OR_NOT_CONVERGED; break; }
+
+        precond_apply(n, precond, diag, w, m);
+        or_spmv(n, nf, owner, nb, diag, upper, lower, m, nv);
+
+        double alpha, beta, den;
+        if (i == 0) {
+            beta = 0.0;
+            den = delta;
+        } else {
+            beta = gamma / gamma_prev;
+            den = delta - beta * gamma / alpha_prev;
+        }
+        alpha = gamma / den;
+        if (!(den > 0.0) || !isfinite(den) || !isfinite(alpha) || !isfinite(beta)) {
+            status = OR_BREAKDOWN;
+            break;
+        }
+        for (int32_t c = 0; c < n; ++c) {
+            z[c] = nv[c] + beta * z[c];
+            s[c] = w[c] + beta * s[c];
+            p[c] = u[c] + beta * p[c];
+            if (!folded) q[c] = m[c] + beta * q[c];
+        }
+        for (int32_t c = 0; c < n; ++c) {
+            x[c] += alpha * p[c];
+            r[c] -= alpha * s[c];
+            if (!folded) u[c] -= alpha * q[c];
+            w[c] -= alpha * z[c];
+        }
+        gamma_prev = gamma;
+        alpha_prev = alpha;
+    }
+    if (st) { st->iters = i; st->status = status; }
+    finish_stats(n, nf, owner, nb, diag, upper, lower, b, x, bnorm, rnorm, st);
+    free(r); free(u); free(w); free(m); free(nv); free(z); free(q); free(s); free(p);
+    return status;
+}
+
+/* ---- FP32 pieces for the refinement driver: the same LDU product and the
+ * folded pipelined Jacobi-CG in single precision, inner products accumulated
+ * in double. */
+static void spmv32(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                   const float* diag, const float* upper, const float* lower,
+                   const float* v, float* y)
+{
+    for (int32_t c = 0; c < n; ++c) y[c] = diag[c] * v[c];
+    for (int32_t f = 0; f < nf; ++f) {
+        y[owner[f]] += upper[f] * v[nb[f]];
+        y[nb[f]] += lower[f] * v[owner[f]];
+    }
+}
+
+static int32_t pipecg32_folded(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                               const float* diag, const float* upper, const float* lower,
+                               const float* b, float* x, double tol, int32_t maxit, int32_t* iters)
+{
+    float *r = calloc((size_t)n, 4), *u = calloc((size_t)n, 4), *w = calloc((size_t)n, 4);
+    float *m = calloc((size_t)n, 4), *nv = calloc((size_t)n, 4), *z = calloc((size_t)n, 4);
+    float *s = calloc((size_t)n, 4), *p = calloc((size_t)n, 4);
+    double bb = 0.0;
+    for (int32_t c = 0; c < n; ++c) bb += (double)b[c] * (double)b[c];
+    double bnorm = sqrt(bb);
+    spmv32(n, nf, owner, nb, diag, upper, lower, x, r);
+    for (int32_t c = 0; c < n; ++c) r[c] = b[c] - r[c];
+    for (int32_t c = 0; c < n; ++c) u[c] = r[c] / diag[c];
+    spmv32(n, nf, owner, nb, diag, upper, lower, u, w);
+    double gamma_prev = 0.0, alpha_prev = 0.0;
+    int32_t status = OR_NOT_CONVERGED, i;
+    for (i = 0;; ++i) {
+        double gamma = 0.0, delta = 0.0, rho = 0.0;
+        for (int32_t c = 0; c < n; ++c) {
+            u[c] = r[c] / diag[c];
+            gamma += (double)r[c] * (double)u[c];
+            delta += (double)w[c] * (double)u[c];
+            rho += (double)r[c] * (double)r[c];
+        }
+        if (sqrt(rho) <= tol * bnorm) { status = OR_OK; break; }
+        if (i == maxit) break;
+        for (int32_t c = 0; c < n; ++c) m[c] = w[c] / diag[c];
+        spmv32(n, nf, owner, nb, diag, upper, lower, m, nv);
+        double beta, den;
+        if (i == 0) { beta = 0.0; den = delta; }
+        else { beta = gamma / gamma_prev; den = delta - beta * gamma / alpha_prev; }
+        double alpha = gamma / den;
+        if (!(den > 0.0) || !isfinite(alpha) || !isfinite(beta)) { status = OR_BREAKDOWN; break; }
+        float a32 = (float)alpha, b32 = (float)beta;
+        for (int32_t c = 0; c < n; ++c) {
+            z[c] = nv[c] + b32 * z[c];
+            s[c] = w[c] + b32 * s[c];
+            p[c] = u[c] + b32 * p[c];
+            x[c] += a32 * p[c];
+            r[c] -= a32 * s[c];
+            w[c] -= a32 * z[c];
+        }
+        gamma_prev = gamma;
+        alpha_prev = alpha;
+    }
+    *iters = i;
+    free(r); free(u); free(w); free(m); free(nv); free(z); free(s); free(p);
+    return status;
+}
+
+/* ---- Mixed-precision iterative refinement (an extension beside the
+ * paper's FP64 solver).  Outer loop in FP64 with the FP64 matrix:
+ *   r = b - A x; stop when ||r|| <= outer_tol ||b||;
+ *   solve A32 c = fp32(r / ||r||) to inner_tol from c = 0;
+ *   x += ||r|| * c. */
+int32_t or_refine(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                  const double* diag, const double* upper, const double* lower,
+                  const double* b, double* x, double outer_tol, double inner_tol,
+                  int32_t max_outer, int32_t max_inner, or_stats* st)
+{
+    if (st) memset(st, 0, sizeof(*st));
+    double bnorm = sqrt(or_dot(n, b, b));
+    if (bnorm == 0.0) {
+        for (int32_t c = 0; c < n; ++c) x[c] = 0.0;
+        return OR_OK;
+    }
+    if (!diag_positive(n, diag)) {
+        if (st) st->status = OR_BREAKDOWN;
+        return OR_BREAKDOWN;
+    }
+    float* d32 = malloc(sizeof(float) * (size_t)n);
+    float* u32 = malloc(sizeof(float) * (size_t)(nf > 0 ? nf : 1));
+    float* l32 = malloc(sizeof(float) * (size_t)(nf > 0 ? nf : 1));
+    float* rhs = malloc(sizeof(float) * (size_t)n);
+    float* cor = malloc(sizeof(float) * (size_t)n);
+    double* r = alloc_vec(n);
+    for (int32_t c = 0; c < n; ++c) d32[c] = (float)diag[c];
+    for (int32_t f = 0; f < nf; ++f) { u32[f] = (float)upper[f]; l32[f] = (float)lower[f]; }
+
+    int32_t status = OR_NOT_CONVERGED, j, total_inner = 0;
+    double rnorm = 0.0;
+    for (j = 0;; ++j) {
+        residual(n, nf, owner, nb, diag, upper, lower, b, x, r);
+        rnorm = sqrt(or_dot(n, r, r));
+        if (j == 0 && st) st->r0_norm = rnorm;
+        if (rnorm <= outer_tol * bnorm) { status = OR_OK; break; }
+        if (j == max_outer) break;
+        for (int32_t c = 0; c < n; ++c) { rhs[c] = (float)(r[c] / rnorm); cor[c] = 0.0f; }
+        int32_t it = 0;
+        int32_t s = pipecg32_folded(n, nf, owner, nb, d32, u32, l32, rhs, cor, inner_tol, max_inner, &it);
+        total_inner += it;
+        if (s == OR_BREAKDOWN && it == 0) { status = OR_BREAKDOWN; break; }
+        for (int32_t c = 0; c < n; ++c) x[c] += rnorm * (double)cor[c];
+    }
+    if (st) {
+        st->outer_iters = j;
+        st->iters = total_inner;
+        st->status = status;
+        st->b_norm = bnorm;
+        st->rel_res = rnorm / bnorm;
+        st->true_rel_res = rnorm / bnorm;
+    }
+    free(d32); free(u32); free(l32); free(rhs); free(cor); free(r);
+    return status;
+}
+
+/* ---- Adjoint gradients on the sparsity pattern.  For L(x) with A x = b and
+ * lambda = A^-T dL/dx: dL/db = lambda and dL/dA_ij = -lambda_i x_j, so the
+ * diagonal gets -lambda_c x_c, upper[f] (row owner, column neighbour) gets
+ * -lambda_owner x_neighbour and lower[f] gets -lambda_neighbour x_owner. */
+void or_adjoint_grads(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                      const double* x, const double* lam,
+                      double* g_diag, double* g_upper, double* g_lower)
+{
+    if (g_diag)
+        for (int32_t c = 0; c < n; ++c) g_diag[c] = -lam[c] * x[c];
+    for (int32_t f = 0; f < nf; ++f) {
+        if (g_upper) g_upper[f] = -lam[owner[f]] * x[nb[f]];
+        if (g_lower) g_lower[f] = -lam[nb[f]] * x[owner[f]];
+    }
+}

@@ -1,0 +1,81 @@
+/*
+ * CPU oracle for the finite-volume Laplacian CG solve -- TEST INFRASTRUCTURE.
+ *
+ * Plain, slow, single-threaded FP64 C written from the paper's description of
+ * the method, used only by the tests, the benchmark's CPU-baseline leg and the
+ * smoke check to judge the HIP path.  It shares no code, header, table or
+ * helper with the HIP library and must never be called by the product path.
+ *
+ * Matrix convention: OpenFOAM lduMatrix (diag[n], upper[F], lower[F],
+ * owner[F] < neighbour[F]); row owner[f] holds upper[f] in column
+ * neighbour[f], row neighbour[f] holds lower[f] in column owner[f]
+ * (nnz = n + 2F, Section 4.2).
+ */
+#ifndef FV_ORACLE_H
+#define FV_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_OK = 0, OR_NOT_CONVERGED = 1, OR_BREAKDOWN = -3 };
+enum { OR_PRECOND_NONE = 0, OR_PRECOND_JACOBI = 1 };
+
+typedef struct or_stats {
+    int32_t iters;
+    int32_t outer_iters;
+    int32_t status;
+    int32_t reserved;
+    double rel_res;       /* recursive residual norm / ||b|| at exit */
+    double true_rel_res;  /* ||b - A x|| / ||b|| recomputed at exit */
+    double r0_norm;
+    double b_norm;
+} or_stats;
+
+/* y = A v by the LDU definition: diagonal term, then a scatter over faces. */
+void or_spmv(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+             const double* diag, const double* upper, const double* lower,
+             const double* v, double* y);
+
+/* Plain sequential sum of a[i]*b[i]. */
+double or_dot(int32_t n, const double* a, const double* b);
+
+/* Preconditioned CG, standard form (three inner products per iteration,
+ * Section 2).  x holds x0 on entry.  Optional histories (length >= maxit+1,
+ * may be NULL): alpha[k], beta[k] of iteration k and the recursive residual
+ * norm after k updates (res_hist[0] = ||r0||). */
+int32_t or_cg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+              const double* diag, const double* upper, const double* lower,
+              const double* b, double* x, double tol, int32_t maxit, int32_t precond,
+              or_stats* st, double* alpha_hist, double* beta_hist, double* res_hist);
+
+/* Pipelined preconditioned CG of Ghysels and Vanroose, the variant the paper
+ * implements (Section 4.1): one fused reduction per iteration.
+ * folded = 0: literal recurrences for u, q (and m = M^-1 w).
+ * folded = 1 (Jacobi only): u = r/d, q = s/d, m = w/d evaluated directly. */
+int32_t or_pipecg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                  const double* diag, const double* upper, const double* lower,
+                  const double* b, double* x, double tol, int32_t maxit, int32_t precond,
+                  int32_t folded, or_stats* st, double* res_hist);
+
+/* Mixed-precision iterative refinement: FP64 outer residual with the FP64
+ * matrix, FP32 inner folded pipelined Jacobi-CG on the FP32-rounded matrix
+ * with FP64 inner-product accumulation, FP64 correction. */
+int32_t or_refine(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                  const double* diag, const double* upper, const double* lower,
+                  const double* b, double* x, double outer_tol, double inner_tol,
+                  int32_t max_outer, int32_t max_inner, or_stats* st);
+
+/* Gradients of a scalar loss L(x) with A x = b on the LDU pattern, given x
+ * and lambda = A^-T dL/dx:  dL/ddiag = -lambda*x, dL/dupper[f] =
+ * -lambda[owner]*x[nb], dL/dlower[f] = -lambda[nb]*x[owner]. */
+void or_adjoint_grads(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                      const double* x, const double* lam,
+                      double* g_diag, double* g_upper, double* g_lower);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
