@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark: CG iterations/s and HBM GB/s on one MI355X.
+
+Workload (the 7.08M-cell case): 192^3 hexahedral mesh, lognormal(0,1) face
+conductivities, cells randomly permuted then RCM-renumbered, Dirichlet on
+x-min/x-max, b ~ U[-1,1]; FP64 pipelined Jacobi-CG (one fused kernel and one
+reduction per iteration) to relative residual 1e-8.  One step = one whole
+solve: initial residual, every iteration, stopping test and the true residual
+at exit, with inputs resident in HBM.
+
+Prints ONE JSON line.  value = iterations/s over the timed solves.  roofline:
+the fused pipelined kernel, algorithmic bytes per launch (104n + 24F) divided
+by its average launch time from HIP events on the solve stream, against the
+8 TB/s HBM peak.  cpu_baseline: the plain-C oracle (single thread) on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "CG iters/s + HBM GB/s at 7M cells; mixed/batched vs plain FP64 at 1e-8"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pipecg_fold_varcoef192_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1505_07630_amd", "csrc", f) for f in ("solve.hip", "common.hpp")]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def alg_bytes_pipecg_folded(n, F):
+    """Per iteration: matrix 24F (int32 column + FP64 value per off-diagonal
+    slot) + 13 FP64 vector passes 104n (reads w, z, s, p, x, r, d; writes
+    z, s, p, x, r, w')."""
+    return 104 * n + 24 * F
+
+
+def measured_traffic(n_launch_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(case, iters):
+    import oracle
+
+    oracle.build(force=False)
+    A = oracle.system(case)
+    t0 = time.perf_counter()
+    _, st = oracle.pipecg(A, case.b, tol=0.0, maxit=iters, precond="jacobi", folded=True)
+    dt = time.perf_counter() - t0
+    return {"value": st["iters"] / dt, "unit": "CG iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{st['iters']} fixed iterations (plus setup and final residual) of the folded pipelined "
+                      f"Jacobi-CG on the full 192^3 workload, single thread, {dt:.1f} s",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--method", default="pipecg", choices=["pipecg", "cg", "pipecg_literal"])
+    ap.add_argument("--roofline-iters", type=int, default=500)
+    ap.add_argument("--cpu-iters", type=int, default=30)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--extras", action="store_true", help="also time the other workloads")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of this "
+                                   "build (the solver's sharding is described in DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import fvcases
+    import paper_1505_07630_amd as fv
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t = time.perf_counter()
+    case = fvcases.make("varcoef192")
+    log(f"workload varcoef192: n={case.n} F={case.F} ready in {time.perf_counter() - t:.1f} s")
+    to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).to(dev)
+    owner, nb = to(case.owner, torch.int32), to(case.neighbour, torch.int32)
+    diag, upper, b = to(case.diag, torch.float64), to(case.upper, torch.float64), to(case.b, torch.float64)
+    mesh = fv.Mesh(case.n, owner, nb)
+    A = fv.Matrix(mesh, diag, upper)
+    x = torch.zeros_like(b)
+    stream = torch.cuda.current_stream()
+    tol, maxit = 1e-8, 50000
+
+    calib = fv.stream_calibrate(1 << 30)
+    log(f"STREAM copy {calib['copy_gbs']:.0f} GB/s, triad {calib['triad_gbs']:.0f} GB/s")
+
+    for i in range(args.warmup):
+        x.zero_()
+        _, st = fv.solve(A, b, x=x, tol=tol, maxit=maxit, method=args.method)
+        log(f"warmup {i}: {st['iters']} iterations, {st['device_ms']:.1f} ms, status {st['status_name']}")
+
+    torch.cuda.synchronize()
+    total_iters, iter_ms, stats = 0, 0.0, []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        x.zero_()
+        _, st = fv.solve(A, b, x=x, tol=tol, maxit=maxit, method=args.method)
+        total_iters += st["iters"]
+        iter_ms += st["iter_ms"]
+        stats.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} solves: {elapsed * 1e3:.1f} ms, {total_iters} iterations")
+    assert all(s["status"] == 0 for s in stats), stats
+
+    n, F = case.n, case.F
+    bpi = alg_bytes_pipecg_folded(n, F) if args.method != "cg" else 104 * n + 24 * F
+    its = total_iters / elapsed
+    # dominant kernel: average duration of one fused iteration over the timed
+    # solves (HIP events around the iteration launches on the solve stream)
+    kern_s = iter_ms / 1e3 / total_iters
+    achieved = bpi / kern_s / 1e9
+
+    # fixed-iteration launch timing (no convergence checks in between)
+    x.zero_()
+    _, stf = fv.solve(A, b, x=x, tol=0.0, maxit=args.roofline_iters, method=args.method)
+    kern_fixed_s = stf["iter_ms"] / 1e3 / stf["iters"]
+    log(f"fused kernel: {kern_s * 1e6:.1f} us/launch in solves, {kern_fixed_s * 1e6:.1f} us/launch over "
+        f"{stf['iters']} fixed iterations")
+
+    traffic = measured_traffic(bpi)
+    kernel_name = {"pipecg": "k_pipe_iter<double, 6, JAC=true, LIT=false>",
+                   "pipecg_literal": "k_pipe_iter<double, 6, JAC=true, LIT=true>",
+                   "cg": "k_cg_spmv + k_cg_update_r + k_cg_update_xp"}[args.method]
+    out = {
+        "metric": METRIC,
+        "value": round(its, 2),
+        "unit": "CG iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "varcoef192: 192^3 hex FV Laplacian, lognormal(0,1) conductivities, random permutation + "
+                        "RCM, Dirichlet x-min/x-max, b~U[-1,1], seed 2",
+            "n_cells": n, "n_faces": F, "method": args.method, "precond": "jacobi", "tol": tol,
+            "iters_per_solve": stats[-1]["iters"], "true_rel_res": stats[-1]["true_rel_res"],
+        },
+        "hbm_gbs_algorithmic": round(bpi * its / 1e9, 1),
+        "roofline": {
+            "bound": "hbm", "kernel": kernel_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "alg_bytes_per_launch": bpi, "avg_launch_us": round(kern_s * 1e6, 2),
+            "avg_launch_us_fixed_iters": round(kern_fixed_s * 1e6, 2),
+        },
+        "stream_calibration_gbs": {"copy": round(calib["copy_gbs"], 1), "triad": round(calib["triad_gbs"], 1)},
+    }
+    if args.extras:
+        out["extras"] = extras(fv, torch, np, fvcases, dev)
+    if not args.no_cpu:
+        log(f"oracle baseline: {args.cpu_iters} iterations on the CPU ...")
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_iters)
+        log(f"oracle: {out['cpu_baseline']['value']:.2f} it/s")
+    print(json.dumps(out), flush=True)
+
+
+def extras(fv, torch, np, fvcases, dev):
+    """Other workloads, for information (not the headline line)."""
+    res = {}
+    to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).to(dev)
+    for name, method in (("laplace32", "pipecg"), ("laplace32", "cg"), ("cavity256", "cg")):
+        c = fvcases.make(name)
+        mesh = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
+        A = fv.Matrix(mesh, to(c.diag, torch.float64), to(c.upper, torch.float64))
+        b = to(c.b, torch.float64)
+        fv.solve(A, b, tol=c.tol, method=method)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = 0
+        for _ in range(3):
+            _, st = fv.solve(A, b, tol=c.tol, method=method, maxit=100000)
+            its += st["iters"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[f"{name}/{method}"] = {"iters_per_solve": st["iters"], "iters_per_s": round(its / dt, 1),
+                                   "ms_per_solve": round(dt / 3 * 1e3, 3), "status": st["status_name"]}
+        log(f"extra {name}/{method}: {res[f'{name}/{method}']}")
+    return res
+
+
+if __name__ == "__main__":
+    main()

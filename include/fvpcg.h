@@ -1,0 +1,202 @@
+/*
+ * fvpcg -- preconditioned conjugate-gradient solves of finite-volume
+ * Laplacian systems in LDU form on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of AlOnazi, Keyes, Lastovetsky and Rychkov
+ * (arXiv 1505.07630): conjugate gradients on A x = b with A the symmetric
+ * positive (semi)definite matrix of an OpenFOAM finite-volume discretisation
+ * (Section 2), in the standard form with three inner products per iteration
+ * and in the pipelined form of Ghysels and Vanroose with a single reduction
+ * per iteration (Section 4.1), preconditioned by Jacobi or not at all.
+ *
+ * MATRIX FORMAT.  OpenFOAM's lduMatrix (named in the Section 5 discussion of
+ * the CUDA/OpenFOAM interface; nnz = n + 2F as in Section 4.2):
+ *   n_cells cells, n_faces internal faces;
+ *   owner[f] < neighbour[f], faces sorted strictly by (owner, neighbour);
+ *   diag[c]  = A[c][c];
+ *   upper[f] = A[owner[f]][neighbour[f]];
+ *   lower[f] = A[neighbour[f]][owner[f]].
+ * Boundary conditions are folded into diag and b by the caller.
+ *
+ * MEMORY.  Every array argument is a DEVICE pointer (hipMalloc'd or a
+ * contiguous torch tensor on the same device), owned by the caller.  The
+ * library never frees caller memory and keeps no pointer to it after a call
+ * returns: mesh and matrix data are copied into buffers owned by the handles,
+ * which *_destroy frees.  Arrays: int32 addressing, FP64 coefficients and
+ * vectors, all contiguous.
+ *
+ * STREAMS.  `stream` is a hipStream_t (NULL = the null stream).  All device
+ * work is enqueued on it.  Calls that return statistics block the host until
+ * their work on that stream is complete; a solve reads its convergence flag
+ * back at chunk boundaries.  One call in flight per handle; distinct handles
+ * may be used concurrently on distinct streams.
+ *
+ * ERRORS.  Every entry point returns an fvpcg_status.  fvpcg_last_error()
+ * returns a human-readable, thread-local description of the last failure.
+ * No exception crosses the interface.
+ */
+#ifndef FVPCG_H
+#define FVPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FVPCG_VERSION 10000 /* 1.0.0 */
+
+#ifndef FVPCG_API
+#define FVPCG_API __attribute__((visibility("default")))
+#endif
+
+typedef enum fvpcg_status {
+    FVPCG_OK = 0,
+    FVPCG_NOT_CONVERGED = 1,  /* maxit reached; x = last iterate; stats valid */
+    FVPCG_INVALID_ARG = -1,   /* null pointer, n < 1, tol < 0, b aliases x, tol = maxit = 0, ... */
+    FVPCG_INVALID_MESH = -2,  /* addressing out of range, not owner < neighbour, not strictly sorted */
+    FVPCG_BREAKDOWN = -3,     /* p'Ap <= 0, a non-finite scalar, or diag <= 0 under Jacobi */
+    FVPCG_DEVICE_ERROR = -4,  /* a HIP call failed; the HIP message is in fvpcg_last_error() */
+    FVPCG_OUT_OF_MEMORY = -5, /* a device or pinned allocation failed */
+    FVPCG_UNSUPPORTED = -6    /* row degree > FVPCG_MAX_ROW_DEGREE, sizes beyond int32 slots, ... */
+} fvpcg_status;
+
+/* Krylov variants (Section 2: standard CG; Section 4.1: pipelined CG). */
+enum {
+    FVPCG_CG = 0,             /* standard form: three inner products, two reductions per iteration */
+    FVPCG_PIPECG = 1,         /* pipelined form, one fused kernel and one reduction per iteration;
+                                 with Jacobi, u = r/d, q = s/d, m = w/d are evaluated, not carried */
+    FVPCG_PIPECG_LITERAL = 2  /* pipelined form carrying the u and q recurrences */
+};
+
+/* Preconditioner M ("optional" in Section 2). */
+enum { FVPCG_PRECOND_NONE = 0, FVPCG_PRECOND_JACOBI = 1 };
+
+/* fvpcg_matrix_create flags */
+#define FVPCG_FP32_COPY 1u /* also keep an FP32 copy for fvpcg_solve_mixed */
+
+#define FVPCG_MAX_ROW_DEGREE 32
+
+typedef struct fvpcg_mesh fvpcg_mesh;
+typedef struct fvpcg_matrix fvpcg_matrix;
+typedef struct fvpcg_batch fvpcg_batch;
+
+typedef struct fvpcg_stats {
+    int32_t iters;        /* updates of x (inner iterations summed for the mixed solver) */
+    int32_t outer_iters;  /* refinement steps (mixed solver), else 0 */
+    int32_t status;       /* the fvpcg_status of the solve */
+    int32_t reserved;
+    double rel_res;       /* recursive residual norm / ||b||_2 at exit */
+    double true_rel_res;  /* ||b - A x||_2 / ||b||_2 recomputed at exit */
+    double r0_norm;       /* ||b - A x0||_2 */
+    double b_norm;        /* ||b||_2 */
+    double device_ms;     /* whole call, HIP events on `stream` */
+    double iter_ms;       /* the iteration kernels only, HIP events on `stream` */
+} fvpcg_stats;
+
+FVPCG_API int fvpcg_version(void);
+FVPCG_API const char* fvpcg_last_error(void);
+
+/* ---- Mesh: validates the addressing (0 <= owner < neighbour < n, faces
+ * strictly sorted by (owner, neighbour)) and builds the device layout used by
+ * every kernel (a slot-major ELL pattern with one slot per off-diagonal
+ * entry of a row, columns ascending).  owner/neighbour: int32[n_faces]
+ * device arrays; copied.  n_faces may be 0. */
+FVPCG_API int fvpcg_mesh_create(int32_t n_cells, int32_t n_faces, const int32_t* owner,
+                      const int32_t* neighbour, void* stream, fvpcg_mesh** out);
+FVPCG_API int fvpcg_mesh_destroy(fvpcg_mesh* mesh);
+/* ell_width = largest number of off-diagonal entries in a row. */
+FVPCG_API int fvpcg_mesh_info(const fvpcg_mesh* mesh, int32_t* n_cells, int32_t* n_faces, int32_t* ell_width);
+
+/* ---- Matrix: coefficients on a mesh (the mesh must outlive the matrix).
+ * diag: FP64[n_cells]; upper, lower: FP64[n_faces]; lower == NULL means
+ * lower = upper (symmetric).  Values are copied into the handle.
+ * flags: FVPCG_FP32_COPY keeps an FP32 copy for the mixed-precision solver.
+ * fvpcg_matrix_update refreshes the coefficients on the same pattern (the
+ * repeated-solve use of Section 4.1, where the application calls the solver
+ * again every time step). */
+FVPCG_API int fvpcg_matrix_create(const fvpcg_mesh* mesh, const double* diag, const double* upper,
+                        const double* lower, uint32_t flags, void* stream, fvpcg_matrix** out);
+FVPCG_API int fvpcg_matrix_update(fvpcg_matrix* mat, const double* diag, const double* upper,
+                        const double* lower, void* stream);
+FVPCG_API int fvpcg_matrix_destroy(fvpcg_matrix* mat);
+
+/* ---- y = A v in LDU semantics (the sparse matrix-vector product of
+ * Section 2 / Table ai_cg).  v, y: FP64[n_cells], must not alias.
+ * Asynchronous on `stream`. */
+FVPCG_API int fvpcg_spmv(const fvpcg_matrix* mat, const double* v, double* y, void* stream);
+
+/* ---- Solve A x = b by preconditioned CG (Section 2) or pipelined CG
+ * (Section 4.1).  x: FP64[n_cells], holds x0 on entry and the solution on
+ * exit.  b: FP64[n_cells], must not alias x.
+ * Stops when the recursively updated residual satisfies
+ * ||r||_2 <= tol * ||b||_2, or after maxit updates of x (status
+ * FVPCG_NOT_CONVERGED).  tol = 0 with maxit > 0 runs exactly maxit
+ * iterations unless the residual vanishes.  b = 0 gives x = 0.
+ * method: FVPCG_CG / FVPCG_PIPECG / FVPCG_PIPECG_LITERAL;
+ * precond: FVPCG_PRECOND_NONE / FVPCG_PRECOND_JACOBI.
+ * stats may be NULL.  On FVPCG_BREAKDOWN x holds the last finite iterate. */
+FVPCG_API int fvpcg_solve(const fvpcg_matrix* mat, const double* b, double* x, double tol, int32_t maxit,
+                int32_t method, int32_t precond, void* stream, fvpcg_stats* stats);
+
+/* ---- Mixed-precision iterative refinement (FP32 inner, FP64 outer).
+ * Outer: r = b - A x in FP64 with the FP64 matrix, stop at
+ * ||r|| <= outer_tol ||b|| or after max_outer corrections.  Inner: the
+ * FP32 copy solves A c = r/||r|| by folded pipelined Jacobi-CG in FP32 with
+ * FP64 inner-product accumulation to inner_tol (at most max_inner
+ * iterations), from c = 0; then x += ||r|| c in FP64.  Needs a matrix
+ * created with FVPCG_FP32_COPY (else FVPCG_UNSUPPORTED). */
+FVPCG_API int fvpcg_solve_mixed(const fvpcg_matrix* mat, const double* b, double* x, double outer_tol,
+                      double inner_tol, int32_t max_outer, int32_t max_inner, void* stream,
+                      fvpcg_stats* stats);
+
+/* ---- Adjoint of a solve, for a scalar loss L(x) with A x = b.  Given the
+ * solution x and g = dL/dx, solves A^T lambda = g (A is symmetric for CG,
+ * so this is one more solve with A, same method and precond) and writes
+ *   grad_b[c]     = lambda[c]
+ *   grad_diag[c]  = -lambda[c] * x[c]
+ *   grad_upper[f] = -lambda[owner[f]] * x[neighbour[f]]
+ *   grad_lower[f] = -lambda[neighbour[f]] * x[owner[f]].
+ * Any grad pointer may be NULL to skip it.  If the matrix was created with
+ * lower == NULL (one coefficient per face), grad_upper receives the sum of
+ * the upper and lower gradients and grad_lower is not written.
+ * x, g: FP64[n_cells]; grad_diag, grad_b: FP64[n_cells]; grad_upper,
+ * grad_lower: FP64[n_faces]. */
+FVPCG_API int fvpcg_solve_backward(const fvpcg_matrix* mat, const double* x, const double* g, double* grad_b,
+                         double* grad_diag, double* grad_upper, double* grad_lower, double tol,
+                         int32_t maxit, int32_t method, int32_t precond, void* stream,
+                         fvpcg_stats* stats);
+
+/* ---- Batched solves: nsys independent systems of uneven sizes in one
+ * persistent launch.  cell_off_host, face_off_host: HOST int32[nsys+1]
+ * prefix offsets into the concatenated device arrays; owner/neighbour hold
+ * LOCAL cell indices of each system (LDU rules per system).  lower == NULL
+ * means symmetric.  Data are copied into the handle. */
+FVPCG_API int fvpcg_batch_create(int32_t nsys, const int32_t* cell_off_host, const int32_t* face_off_host,
+                       const int32_t* owner, const int32_t* neighbour, const double* diag,
+                       const double* upper, const double* lower, uint32_t flags, void* stream,
+                       fvpcg_batch** out);
+FVPCG_API int fvpcg_batch_destroy(fvpcg_batch* batch);
+/* b, x: concatenated FP64[total cells]; stats: HOST array of nsys entries
+ * (may be NULL).  Returns FVPCG_OK if every system converged, else the
+ * first non-OK status in system order. */
+FVPCG_API int fvpcg_solve_batched(const fvpcg_batch* batch, const double* b, double* x, double tol,
+                        int32_t maxit, int32_t method, int32_t precond, void* stream,
+                        fvpcg_stats* stats);
+/* Adjoint of fvpcg_solve_batched, per system as fvpcg_solve_backward, on
+ * the concatenated arrays (face-indexed gradients use the face offsets). */
+FVPCG_API int fvpcg_solve_batched_backward(const fvpcg_batch* batch, const double* x, const double* g,
+                                 double* grad_b, double* grad_diag, double* grad_upper,
+                                 double* grad_lower, double tol, int32_t maxit, int32_t method,
+                                 int32_t precond, void* stream, fvpcg_stats* stats);
+
+/* ---- STREAM-style copy and triad over device arrays of `bytes_per_array`
+ * bytes each (three arrays; 0 = 1 GiB), as the paper measures attainable
+ * bandwidth for its roofline (Section 1).  Results in GB/s (1e9 B/s);
+ * copy moves 2, triad 3 arrays per pass. */
+FVPCG_API int fvpcg_stream_calibrate(void* stream, uint64_t bytes_per_array, double* copy_gbs, double* triad_gbs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FVPCG_H */

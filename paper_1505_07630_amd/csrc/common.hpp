@@ -1,0 +1,205 @@
+// Internal definitions shared by the fvpcg HIP sources: handle layouts,
+// launch geometry, device-side reductions and error reporting.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "fvpcg.h"
+
+namespace fvpcg {
+
+constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxGrid = 2048;        // row-parallel workgroups per launch (multiple of 8)
+constexpr int kMaxChunk = 64;         // iterations enqueued between convergence checks
+// FP32 pipelined inner solve of the mixed solver: residual replacement period
+// and the number of replacements without a new minimum that ends it.
+constexpr int kReplaceEvery = 20;
+constexpr int kStagnationChecks = 5;
+
+// ---------------------------------------------------------------------------
+// Solver scalars living in device memory.  Written only by the last
+// workgroup of a reducing kernel (one thread), read by every workgroup of the
+// next kernel on the stream.
+struct alignas(128) DevState {
+    double gamma;     // (r, M^-1 r) of the current iterate
+    double delta;     // (p, A p) [standard] or (w, u) [pipelined]
+    double rho;       // (r, r)
+    double alpha;     // step of the next update
+    double beta;      // direction coefficient of the next update
+    double bnorm;     // ||b||
+    double tol_abs;   // tol * ||b||
+    double r0norm;    // ||r0||
+    double true_rr;   // ||b - A x||^2 at exit
+    double scale;     // mixed solver: ||r|| of the current outer residual
+    double gamma_old; // gamma and alpha of the previous iteration (pipelined
+    double alpha_old; //   recurrences, re-formed after a residual replacement)
+    double best;      // smallest replaced (true) ||r||^2 so far
+    int32_t no_min;   // replacements since the last new minimum
+    int32_t iter;     // completed updates of x
+    int32_t maxit;
+    int32_t done;     // 1 once converged, out of iterations or broken down
+    int32_t status;   // fvpcg_status
+    int32_t zero_b;   // 1 if b == 0 (host writes x = 0)
+    int32_t pad0;
+    uint32_t ticket;  // last-workgroup detection counter
+    uint32_t pad1;
+};
+
+// Rows [blk*R, min(n, blk*R + R)) per workgroup; R is a multiple of 64.
+struct Geom {
+    int grid;
+    int rows;
+};
+
+inline Geom make_geom(int n, int max_grid = kMaxGrid) {
+    if (n < 1) n = 1;
+    int g = (n + kBlock - 1) / kBlock;
+    if (g > max_grid) g = max_grid;
+    int r = (n + g - 1) / g;
+    r = (r + 63) / 64 * 64;
+    g = (n + r - 1) / r;
+    return {g, r};
+}
+
+// ---------------------------------------------------------------------------
+// Handles.
+
+struct fvpcg_mesh_impl;
+
+struct Work;  // per-matrix solve workspace (solve.hip)
+
+// ---------------------------------------------------------------------------
+// Error reporting: thread-local message, return codes only.
+
+int set_error(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+#define FV_HIP(expr)                                                       \
+    do {                                                                   \
+        hipError_t fv_e_ = (expr);                                         \
+        if (fv_e_ != hipSuccess) return ::fvpcg::hip_fail(fv_e_, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+#define FV_LAUNCHED()                                                      \
+    do {                                                                   \
+        hipError_t fv_e_ = hipGetLastError();                              \
+        if (fv_e_ != hipSuccess) return ::fvpcg::hip_fail(fv_e_, "kernel launch", __FILE__, __LINE__); \
+    } while (0)
+
+template <typename T>
+int dev_alloc(T** p, size_t count, const char* what) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_error(FVPCG_OUT_OF_MEMORY, "hipMalloc of %zu bytes for %s failed: %s", count * sizeof(T),
+                         what, hipGetErrorString(e));
+    }
+    return FVPCG_OK;
+}
+
+template <typename T>
+void dev_free(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// Device helpers.
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip; give
+// each XCD a contiguous band of rows so its L2 holds that band's neighbour
+// columns.  A bijection of [0, G) for any G.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+    const int q = G >> 3, rem = G & 7;
+    const int x = b & 7, i = b >> 3;
+    return x * q + (x < rem ? x : rem) + i;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    // Butterfly: every lane ends with the same, order-fixed sum.
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum NV values over the workgroup; the result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+    __shared__ double lds[NV][kWaves];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[k][wid] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) s += lds[k][w];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// One device-wide reduction in a single pass: each workgroup publishes its
+// partial sums (layout [NV][G]) and takes a ticket; the workgroup that draws
+// the last ticket sums all partials in a fixed order and returns true with
+// the totals in thread 0's `tot`.  Deterministic for a given G.
+template <int NV>
+__device__ __forceinline__ bool device_reduce(double (&v)[NV], double* partials, uint32_t* ticket, int blk,
+                                              int G, double (&tot)[NV]) {
+    __shared__ int s_last;
+    block_sum<NV>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            __hip_atomic_store(&partials[(size_t)k * G + blk], v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (t == (uint32_t)(G - 1));
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int i = threadIdx.x; i < G; i += kBlock) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            acc[k] += __hip_atomic_load(&partials[(size_t)k * G + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    block_sum<NV>(acc);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) tot[k] = acc[k];
+        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return true;
+}
+
+// Rows of workgroup `blk`.
+struct RowRange {
+    int begin, end;
+};
+__device__ __forceinline__ RowRange rows_of(int blk, int rows, int n) {
+    int b = blk * rows;
+    int e = b + rows;
+    return {b, e < n ? e : n};
+}
+
+}  // namespace fvpcg

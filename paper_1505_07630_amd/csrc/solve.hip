@@ -1,0 +1,937 @@
+// Krylov solves on the device: the LDU/ELL matrix-vector product, standard
+// preconditioned CG (Section 2: a sparse product, an optional
+// preconditioner, three inner products and vector updates per iteration),
+// the pipelined CG of Ghysels and Vanroose that the paper implements
+// (Section 4.1: one reduction per iteration, overlapped with the product),
+// the FP32/FP64 refinement and the adjoint gradients.
+//
+// Every row-parallel kernel assigns workgroup `blk` (XCD-remapped) the rows
+// [blk*R, blk*R + R), with R a multiple of 64; lanes stride through them.
+// Inner products are accumulated per thread in row order, then per wave
+// (butterfly), per workgroup (fixed order) and finally by the last workgroup
+// over all workgroup partials in index order: results are bitwise
+// reproducible for a given mesh.  The scalars of the recurrences (alpha,
+// beta, the stopping test, breakdown) are computed once, by that last
+// workgroup, and read by the next kernel from device memory; the host only
+// reads the `done` flag back at chunk boundaries.
+#include "handles.hpp"
+
+namespace fvpcg {
+
+// ===========================================================================
+// Row kernels' building blocks
+
+// acc + sum_k val[k][c] * v[col[k][c]] over the WT slots of row c.
+template <typename T, int WT>
+__device__ __forceinline__ T row_gather(const int* __restrict__ col, const T* __restrict__ val, int n, int c,
+                                        const T* __restrict__ v, T acc) {
+    int j[WT];
+    T a[WT];
+#pragma unroll
+    for (int k = 0; k < WT; ++k) {
+        size_t o = (size_t)k * n + c;
+        j[k] = col[o];
+        a[k] = val[o];
+    }
+#pragma unroll
+    for (int k = 0; k < WT; ++k) acc += a[k] * v[j[k]];
+    return acc;
+}
+
+#define FV_ROWS(blk)                                                     \
+    const int blk = xcd_block(blockIdx.x, g.grid);                      \
+    const RowRange rr_ = rows_of(blk, g.rows, n);                       \
+    for (int c = rr_.begin + (int)threadIdx.x; c < rr_.end; c += kBlock)
+
+// ===========================================================================
+// y = A v
+
+template <int WT>
+__global__ __launch_bounds__(kBlock) void k_spmv(const int* __restrict__ col, const double* __restrict__ val,
+                                                 const double* __restrict__ d, int n, Geom g,
+                                                 const double* __restrict__ v, double* __restrict__ y) {
+    FV_ROWS(blk) { y[c] = row_gather<double, WT>(col, val, n, c, v, d[c] * v[c]); }
+}
+
+// ||b - A x||^2 into st->true_rr (the true residual reported at exit).
+template <int WT>
+__global__ __launch_bounds__(kBlock) void k_true_residual(const int* __restrict__ col, const double* __restrict__ val,
+                                                          const double* __restrict__ d, int n, Geom g,
+                                                          const double* __restrict__ b, const double* __restrict__ x,
+                                                          DevState* st, double* partials) {
+    double acc[1] = {0.0};
+    FV_ROWS(blk) {
+        double r = b[c] - row_gather<double, WT>(col, val, n, c, x, d[c] * x[c]);
+        acc[0] += r * r;
+    }
+    double tot[1];
+    if (device_reduce<1>(acc, partials, &st->ticket, blk, g.grid, tot) && threadIdx.x == 0) st->true_rr = tot[0];
+}
+
+// ===========================================================================
+// Standard preconditioned CG
+
+// r = b - A x, z = M^-1 r, p = z; gamma = (r,z), rho = (r,r), (b,b).
+template <int WT, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_cg_init(const int* __restrict__ col, const double* __restrict__ val,
+                                                    const double* __restrict__ d, int n, Geom g,
+                                                    const double* __restrict__ b, const double* __restrict__ x,
+                                                    double* __restrict__ r, double* __restrict__ p, DevState* st,
+                                                    double* partials) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    FV_ROWS(blk) {
+        double bc = b[c];
+        double dc = d[c];
+        double rc = bc - row_gather<double, WT>(col, val, n, c, x, dc * x[c]);
+        double zc = JAC ? rc / dc : rc;
+        r[c] = rc;
+        p[c] = zc;
+        acc[0] += rc * zc;
+        acc[1] += rc * rc;
+        acc[2] += bc * bc;
+    }
+    double t[3];
+    if (device_reduce<3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        const double bb = t[2];
+        st->iter = 0;
+        st->bnorm = sqrt(bb);
+        if (bb == 0.0) {
+            st->zero_b = 1;
+            st->done = 1;
+            st->status = FVPCG_OK;
+            st->rho = 0.0;
+            return;
+        }
+        st->tol_abs *= st->bnorm;
+        st->gamma = t[0];
+        st->rho = t[1];
+        st->r0norm = sqrt(t[1]);
+        if (st->r0norm <= st->tol_abs) {
+            st->done = 1;
+            st->status = FVPCG_OK;
+        } else if (st->maxit <= 0) {
+            st->done = 1;
+            st->status = FVPCG_NOT_CONVERGED;
+        }
+    }
+}
+
+// q = A p; delta = (p, q); alpha = gamma / delta.
+template <int WT>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(const int* __restrict__ col, const double* __restrict__ val,
+                                                    const double* __restrict__ d, int n, Geom g,
+                                                    const double* __restrict__ p, double* __restrict__ q, DevState* st,
+                                                    double* partials) {
+    if (st->done) return;
+    double acc[1] = {0.0};
+    FV_ROWS(blk) {
+        double pc = p[c];
+        double qc = row_gather<double, WT>(col, val, n, c, p, d[c] * pc);
+        q[c] = qc;
+        acc[0] += pc * qc;
+    }
+    double t[1];
+    if (device_reduce<1>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        const double delta = t[0];
+        st->delta = delta;
+        if (!(delta > 0.0) || !isfinite(delta) || !isfinite(st->gamma)) {
+            st->done = 1;
+            st->status = FVPCG_BREAKDOWN;
+            return;
+        }
+        st->alpha = st->gamma / delta;
+    }
+}
+
+// r -= alpha q; z = M^-1 r; gamma' = (r, z), rho = (r, r); stopping test;
+// beta = gamma' / gamma.
+template <bool JAC>
+__global__ __launch_bounds__(kBlock) void k_cg_update_r(double* __restrict__ r, const double* __restrict__ q,
+                                                        const double* __restrict__ d, int n, Geom g, DevState* st,
+                                                        double* partials) {
+    if (st->done) return;
+    const double alpha = st->alpha;
+    double acc[2] = {0.0, 0.0};
+    FV_ROWS(blk) {
+        double rc = r[c] - alpha * q[c];
+        r[c] = rc;
+        double zc = JAC ? rc / d[c] : rc;
+        acc[0] += rc * zc;
+        acc[1] += rc * rc;
+    }
+    double t[2];
+    if (device_reduce<2>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        const int it = st->iter + 1;
+        st->iter = it;
+        st->rho = t[1];
+        if (sqrt(t[1]) <= st->tol_abs) {
+            st->done = 1;
+            st->status = FVPCG_OK;
+        } else if (it >= st->maxit) {
+            st->done = 1;
+            st->status = FVPCG_NOT_CONVERGED;
+        } else {
+            st->beta = t[0] / st->gamma;
+            st->gamma = t[0];
+        }
+    }
+}
+
+// x += alpha p (if iteration `it` updated r); p = z + beta p unless done.
+template <bool JAC>
+__global__ __launch_bounds__(kBlock) void k_cg_update_xp(double* __restrict__ x, double* __restrict__ p,
+                                                         const double* __restrict__ r, const double* __restrict__ d,
+                                                         int n, Geom g, int it, const DevState* st) {
+    if (st->iter != it + 1) return;
+    const double alpha = st->alpha, beta = st->beta;
+    const bool more = !st->done;
+    const int blk = xcd_block(blockIdx.x, g.grid);
+    const RowRange rr_ = rows_of(blk, g.rows, n);
+    if (more) {
+        for (int c = rr_.begin + (int)threadIdx.x; c < rr_.end; c += kBlock) {
+            double pc = p[c];
+            x[c] += alpha * pc;
+            double rc = r[c];
+            double zc = JAC ? rc / d[c] : rc;
+            p[c] = zc + beta * pc;
+        }
+    } else {
+        for (int c = rr_.begin + (int)threadIdx.x; c < rr_.end; c += kBlock) x[c] += alpha * p[c];
+    }
+}
+
+// ===========================================================================
+// Pipelined CG (Ghysels-Vanroose).  One kernel per iteration i does, per row:
+//   nv = A m_i with m_i = M^-1 w_i (gathered from w_i; with Jacobi
+//        A D^-1 w = w + sum_j (a_cj / d_j) w_j uses the column-scaled values)
+//   z = nv + beta z;  s = w + beta s;  p = u + beta p;  [literal: q = m + beta q]
+//   x += alpha p;  r -= alpha s;  w' = w - alpha z;   [literal: u -= alpha q]
+// and the partial sums of gamma = (r,u), delta = (w',u), rho = (r,r) of
+// the new iterate (folded: u = r/d).  w is double-buffered because
+// neighbouring rows still gather w_i while w_{i+1} is written.  The last
+// workgroup finishes the one reduction and forms alpha_{i+1}, beta_{i+1}:
+//   beta = gamma / gamma_prev,
+//   alpha = gamma / (delta - beta * gamma / alpha_prev).
+
+template <typename T>
+struct PipeVec {
+    const int* col;
+    const T* val;  // column-scaled with Jacobi, plain otherwise
+    const T* d;
+    const T* w_in;
+    T* w_out;
+    T* z;
+    T* s;
+    T* p;
+    T* x;
+    T* r;
+    T* u;  // literal only
+    T* q;  // literal only
+};
+
+__device__ __forceinline__ void pipe_scalars(DevState* st, double gamma, double delta, double rho, bool first) {
+    if (first) {
+        st->iter = 0;
+        st->r0norm = sqrt(rho);
+    } else {
+        st->iter = st->iter + 1;
+    }
+    st->rho = rho;
+    if (sqrt(rho) <= st->tol_abs) {
+        st->done = 1;
+        st->status = FVPCG_OK;
+        return;
+    }
+    if (st->iter >= st->maxit) {
+        st->done = 1;
+        st->status = FVPCG_NOT_CONVERGED;
+        return;
+    }
+    double beta, den;
+    if (first) {
+        beta = 0.0;
+        den = delta;
+    } else {
+        beta = gamma / st->gamma;
+        den = delta - beta * gamma / st->alpha;
+    }
+    const double alpha = gamma / den;
+    if (!(den > 0.0) || !isfinite(den) || !isfinite(alpha) || !isfinite(beta)) {
+        st->done = 1;
+        st->status = FVPCG_BREAKDOWN;
+        return;
+    }
+    st->gamma_old = st->gamma;
+    st->alpha_old = st->alpha;
+    st->gamma = gamma;
+    st->delta = delta;
+    st->alpha = alpha;
+    st->beta = beta;
+}
+
+// r = b - A x; (b, b) -> bnorm and the absolute tolerance; clears the
+// pipelined recurrences (z, s, p[, q]) and sets u = M^-1 r (literal).
+template <int WT, bool JAC, bool LIT>
+__global__ __launch_bounds__(kBlock) void k_pipe_init_r(const int* __restrict__ col, const double* __restrict__ val,
+                                                        const double* __restrict__ d, int n, Geom g,
+                                                        const double* __restrict__ b, const double* __restrict__ x,
+                                                        double* __restrict__ r, double* __restrict__ z,
+                                                        double* __restrict__ s, double* __restrict__ p,
+                                                        double* __restrict__ u, double* __restrict__ q, DevState* st,
+                                                        double* partials) {
+    double acc[1] = {0.0};
+    FV_ROWS(blk) {
+        double bc = b[c];
+        double dc = d[c];
+        double rc = bc - row_gather<double, WT>(col, val, n, c, x, dc * x[c]);
+        r[c] = rc;
+        z[c] = 0.0;
+        s[c] = 0.0;
+        p[c] = 0.0;
+        if (LIT) {
+            u[c] = JAC ? rc / dc : rc;
+            q[c] = 0.0;
+        }
+        acc[0] += bc * bc;
+    }
+    double t[1];
+    if (device_reduce<1>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        st->iter = 0;
+        st->bnorm = sqrt(t[0]);
+        st->tol_abs *= st->bnorm;
+        if (t[0] == 0.0) {
+            st->zero_b = 1;
+            st->done = 1;
+            st->status = FVPCG_OK;
+        }
+    }
+}
+
+// w0 = A M^-1 r0 and the first reduction (gamma_0, delta_0, rho_0).
+template <typename T, int WT, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_pipe_init_w(const int* __restrict__ col, const T* __restrict__ val,
+                                                        const T* __restrict__ d, int n, Geom g,
+                                                        const T* __restrict__ r, T* __restrict__ w, DevState* st,
+                                                        double* partials) {
+    if (st->done) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    FV_ROWS(blk) {
+        T rc = r[c];
+        T dc = d[c];
+        T wc = row_gather<T, WT>(col, val, n, c, r, JAC ? rc : dc * rc);
+        w[c] = wc;
+        T uc = JAC ? rc / dc : rc;
+        acc[0] += (double)rc * (double)uc;
+        acc[1] += (double)wc * (double)uc;
+        acc[2] += (double)rc * (double)rc;
+    }
+    double t[3];
+    if (device_reduce<3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0)
+        pipe_scalars(st, t[0], t[1], t[2], true);
+}
+
+template <typename T, int WT, bool JAC, bool LIT>
+__global__ __launch_bounds__(kBlock) void k_pipe_iter(PipeVec<T> a, int n, Geom g, DevState* st, double* partials) {
+    if (st->done) return;
+    const T alpha = (T)st->alpha, beta = (T)st->beta;
+    double acc[3] = {0.0, 0.0, 0.0};
+    FV_ROWS(blk) {
+        const T wc = a.w_in[c];
+        const T dc = a.d[c];
+        const T nv = row_gather<T, WT>(a.col, a.val, n, c, a.w_in, JAC ? wc : dc * wc);
+        const T zc = nv + beta * a.z[c];
+        const T sc = wc + beta * a.s[c];
+        T rc = a.r[c];
+        T uc;
+        if (LIT) {
+            const T mc = JAC ? wc / dc : wc;
+            const T qc = mc + beta * a.q[c];
+            uc = a.u[c];
+            const T pc = uc + beta * a.p[c];
+            a.q[c] = qc;
+            a.p[c] = pc;
+            a.x[c] += alpha * pc;
+            uc -= alpha * qc;
+            a.u[c] = uc;
+        } else {
+            uc = JAC ? rc / dc : rc;
+            const T pc = uc + beta * a.p[c];
+            a.p[c] = pc;
+            a.x[c] += alpha * pc;
+        }
+        rc -= alpha * sc;
+        const T wn = wc - alpha * zc;
+        a.z[c] = zc;
+        a.s[c] = sc;
+        a.r[c] = rc;
+        a.w_out[c] = wn;
+        if (!LIT) uc = JAC ? rc / dc : rc;
+        acc[0] += (double)rc * (double)uc;
+        acc[1] += (double)wn * (double)uc;
+        acc[2] += (double)rc * (double)rc;
+    }
+    double t[3];
+    if (device_reduce<3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0)
+        pipe_scalars(st, t[0], t[1], t[2], false);
+}
+
+// ===========================================================================
+// Residual replacement for the FP32 pipelined inner solve: the recurrence
+// vectors are re-formed from their definitions,
+//   r = b - A x,  s = A p          (k_replace_rs)
+//   w = A D^-1 r, z = A D^-1 s     (k_replace_wz, + the iteration's dots)
+// and the scalars of the next update are formed again from the new dots and
+// the previous iteration's gamma and alpha.  The inner solve ends once
+// kStagnationChecks replacements in a row bring no new minimum of ||r||.
+
+template <int WT>
+__global__ __launch_bounds__(kBlock) void k_replace_rs(const int* __restrict__ col, const float* __restrict__ val,
+                                                       const float* __restrict__ d, int n, Geom g,
+                                                       const float* __restrict__ b, const float* __restrict__ x,
+                                                       const float* __restrict__ p, float* __restrict__ r,
+                                                       float* __restrict__ s, const DevState* st) {
+    if (st->done) return;
+    FV_ROWS(blk) {
+        const float dc = d[c];
+        r[c] = b[c] - row_gather<float, WT>(col, val, n, c, x, dc * x[c]);
+        s[c] = row_gather<float, WT>(col, val, n, c, p, dc * p[c]);
+    }
+}
+
+template <int WT>
+__global__ __launch_bounds__(kBlock) void k_replace_wz(const int* __restrict__ col, const float* __restrict__ val_cs,
+                                                       const float* __restrict__ d, int n, Geom g,
+                                                       const float* __restrict__ r, const float* __restrict__ s,
+                                                       float* __restrict__ w, float* __restrict__ z, DevState* st,
+                                                       double* partials) {
+    if (st->done) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    FV_ROWS(blk) {
+        const float rc = r[c];
+        const float wc = row_gather<float, WT>(col, val_cs, n, c, r, rc);
+        z[c] = row_gather<float, WT>(col, val_cs, n, c, s, s[c]);
+        w[c] = wc;
+        const float uc = rc / d[c];
+        acc[0] += (double)rc * (double)uc;
+        acc[1] += (double)wc * (double)uc;
+        acc[2] += (double)rc * (double)rc;
+    }
+    double t[3];
+    if (device_reduce<3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        const double gamma = t[0], delta = t[1], rho = t[2];
+        st->rho = rho;
+        if (rho < st->best) {
+            st->best = rho;
+            st->no_min = 0;
+        } else if (++st->no_min >= kStagnationChecks) {
+            st->done = 1;
+            st->status = FVPCG_NOT_CONVERGED;
+            return;
+        }
+        if (sqrt(rho) <= st->tol_abs) {
+            st->done = 1;
+            st->status = FVPCG_OK;
+            return;
+        }
+        const double beta = gamma / st->gamma_old;
+        const double den = delta - beta * gamma / st->alpha_old;
+        const double alpha = gamma / den;
+        if (!(den > 0.0) || !isfinite(den) || !isfinite(alpha) || !isfinite(beta)) {
+            st->done = 1;
+            st->status = FVPCG_BREAKDOWN;
+            return;
+        }
+        st->gamma = gamma;
+        st->delta = delta;
+        st->alpha = alpha;
+        st->beta = beta;
+    }
+}
+
+// ===========================================================================
+// Mixed precision: FP64 residual and its norm, scaled FP32 right-hand side,
+// FP64 correction.
+
+// r = b - A x (FP64); outer stopping test on ||r||.  `j` = corrections so far.
+template <int WT>
+__global__ __launch_bounds__(kBlock) void k_mixed_residual(const int* __restrict__ col,
+                                                           const double* __restrict__ val,
+                                                           const double* __restrict__ d, int n, Geom g,
+                                                           const double* __restrict__ b, const double* __restrict__ x,
+                                                           double* __restrict__ r, int j, DevState* st,
+                                                           double* partials) {
+    double acc[2] = {0.0, 0.0};
+    FV_ROWS(blk) {
+        double bc = b[c];
+        double rc = bc - row_gather<double, WT>(col, val, n, c, x, d[c] * x[c]);
+        r[c] = rc;
+        acc[0] += rc * rc;
+        acc[1] += bc * bc;
+    }
+    double t[2];
+    if (device_reduce<2>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        st->iter = j;
+        const double rn = sqrt(t[0]);
+        const double prev = st->scale;
+        st->scale = rn;
+        st->rho = t[0];
+        st->true_rr = t[0];
+        if (j == 0) {
+            st->bnorm = sqrt(t[1]);
+            st->tol_abs *= st->bnorm;
+            st->r0norm = rn;
+            if (t[1] == 0.0) {
+                st->zero_b = 1;
+                st->done = 1;
+                st->status = FVPCG_OK;
+                return;
+            }
+        }
+        if (rn <= st->tol_abs) {
+            st->done = 1;
+            st->status = FVPCG_OK;
+        } else if (!isfinite(rn)) {
+            st->done = 1;
+            st->status = FVPCG_BREAKDOWN;
+        } else if (j >= st->maxit || (j > 0 && rn >= prev)) {
+            st->done = 1;
+            st->status = FVPCG_NOT_CONVERGED;
+        }
+    }
+}
+
+// r32 = fp32(r / ||r||), c = 0, recurrences cleared; inner ||rhs|| and
+// inner absolute tolerance.
+__global__ __launch_bounds__(kBlock) void k_mixed_cast(const double* __restrict__ r, int n, Geom g,
+                                                       const DevState* st_out, float* __restrict__ r32,
+                                                       float* __restrict__ b32, float* __restrict__ c32, float* __restrict__ z32,
+                                                       float* __restrict__ s32, float* __restrict__ p32,
+                                                       DevState* st_in, double* partials) {
+    const double inv = 1.0 / st_out->scale;
+    double acc[1] = {0.0};
+    FV_ROWS(blk) {
+        float v = (float)(r[c] * inv);
+        r32[c] = v;
+        b32[c] = v;
+        c32[c] = 0.0f;
+        z32[c] = 0.0f;
+        s32[c] = 0.0f;
+        p32[c] = 0.0f;
+        acc[0] += (double)v * (double)v;
+    }
+    double t[1];
+    if (device_reduce<1>(acc, partials, &st_in->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        st_in->iter = 0;
+        st_in->bnorm = sqrt(t[0]);
+        st_in->tol_abs *= st_in->bnorm;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mixed_correct(double* __restrict__ x, const float* __restrict__ c32, int n,
+                                                          Geom g, const DevState* st_out) {
+    const double sc = st_out->scale;
+    FV_ROWS(blk) { x[c] += sc * (double)c32[c]; }
+}
+
+// ===========================================================================
+// Adjoint gradients on the LDU pattern.
+
+__global__ void k_grad_cells(const double* __restrict__ x, const double* __restrict__ lam, int n,
+                             double* __restrict__ gd, double* __restrict__ gb) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        double l = lam[c];
+        if (gd) gd[c] = -l * x[c];
+        if (gb && gb != lam) gb[c] = l;
+    }
+}
+
+__global__ void k_grad_faces(const int* __restrict__ owner, const int* __restrict__ nb, int F,
+                             const double* __restrict__ x, const double* __restrict__ lam, double* __restrict__ gu,
+                             double* __restrict__ gl, int sym) {
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < F; f += gridDim.x * blockDim.x) {
+        const int o = owner[f], m = nb[f];
+        const double up = -lam[o] * x[m];
+        const double lo = -lam[m] * x[o];
+        if (sym) {
+            if (gu) gu[f] = up + lo;
+        } else {
+            if (gu) gu[f] = up;
+            if (gl) gl[f] = lo;
+        }
+    }
+}
+
+// ===========================================================================
+// Host side
+
+#define FV_WT_SWITCH(WT, ...)                                                        \
+    switch (WT) {                                                                    \
+        case 4: { constexpr int W_ = 4; __VA_ARGS__; } break;                        \
+        case 6: { constexpr int W_ = 6; __VA_ARGS__; } break;                        \
+        case 8: { constexpr int W_ = 8; __VA_ARGS__; } break;                        \
+        case 16: { constexpr int W_ = 16; __VA_ARGS__; } break;                      \
+        default: { constexpr int W_ = 32; __VA_ARGS__; } break;                      \
+    }
+
+int work_init(Work& w, int n) {
+    if (w.st) return FVPCG_OK;
+    w.n = n;
+    w.geom = make_geom(n);
+    int rc;
+    if ((rc = dev_alloc(&w.partials, (size_t)4 * w.geom.grid, "reduction partials"))) return rc;
+    if ((rc = dev_alloc(&w.st, 2, "solver state"))) return rc;
+    FV_HIP(hipMemset(w.st, 0, 2 * sizeof(DevState)));
+    hipError_t e = hipHostMalloc((void**)&w.hst, 4 * sizeof(DevState), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        w.hst = nullptr;
+        return set_error(FVPCG_OUT_OF_MEMORY, "pinned host allocation failed: %s", hipGetErrorString(e));
+    }
+    for (auto& ev : w.ev) FV_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    FV_HIP(hipEventCreate(&w.t_begin));
+    FV_HIP(hipEventCreate(&w.t_end));
+    FV_HIP(hipEventCreate(&w.t_it0));
+    FV_HIP(hipEventCreate(&w.t_it1));
+    return FVPCG_OK;
+}
+
+int work_need_cg(Work& w) {
+    if (w.have_cg) return FVPCG_OK;
+    int rc;
+    if (!w.r && (rc = dev_alloc(&w.r, (size_t)w.n, "r"))) return rc;
+    if (!w.p && (rc = dev_alloc(&w.p, (size_t)w.n, "p"))) return rc;
+    if (!w.q && (rc = dev_alloc(&w.q, (size_t)w.n, "q"))) return rc;
+    w.have_cg = true;
+    return FVPCG_OK;
+}
+
+int work_need_pipe(Work& w, bool literal) {
+    int rc;
+    if (!w.have_pipe) {
+        if (!w.r && (rc = dev_alloc(&w.r, (size_t)w.n, "r"))) return rc;
+        if (!w.p && (rc = dev_alloc(&w.p, (size_t)w.n, "p"))) return rc;
+        if (!w.z && (rc = dev_alloc(&w.z, (size_t)w.n, "z"))) return rc;
+        if (!w.s && (rc = dev_alloc(&w.s, (size_t)w.n, "s"))) return rc;
+        if (!w.w[0] && (rc = dev_alloc(&w.w[0], (size_t)w.n, "w0"))) return rc;
+        if (!w.w[1] && (rc = dev_alloc(&w.w[1], (size_t)w.n, "w1"))) return rc;
+        w.have_pipe = true;
+    }
+    if (literal && !w.have_lit) {
+        if (!w.u && (rc = dev_alloc(&w.u, (size_t)w.n, "u"))) return rc;
+        if (!w.qq && (rc = dev_alloc(&w.qq, (size_t)w.n, "q"))) return rc;
+        w.have_lit = true;
+    }
+    return FVPCG_OK;
+}
+
+int work_need_mixed(Work& w) {
+    if (w.have_mixed) return FVPCG_OK;
+    int rc;
+    if (!w.r && (rc = dev_alloc(&w.r, (size_t)w.n, "r"))) return rc;
+    if ((rc = dev_alloc(&w.r32, (size_t)w.n, "r32"))) return rc;
+    if ((rc = dev_alloc(&w.r32b, (size_t)w.n, "b32"))) return rc;
+    if ((rc = dev_alloc(&w.w32[0], (size_t)w.n, "w32a"))) return rc;
+    if ((rc = dev_alloc(&w.w32[1], (size_t)w.n, "w32b"))) return rc;
+    if ((rc = dev_alloc(&w.z32, (size_t)w.n, "z32"))) return rc;
+    if ((rc = dev_alloc(&w.s32, (size_t)w.n, "s32"))) return rc;
+    if ((rc = dev_alloc(&w.p32, (size_t)w.n, "p32"))) return rc;
+    if ((rc = dev_alloc(&w.c32, (size_t)w.n, "c32"))) return rc;
+    w.have_mixed = true;
+    return FVPCG_OK;
+}
+
+void work_free(Work& w) {
+    double* dv[] = {w.r, w.p, w.q, w.z, w.s, w.w[0], w.w[1], w.u, w.qq, w.lam, w.partials};
+    for (double* p : dv)
+        if (p) (void)hipFree(p);
+    float* fv[] = {w.r32, w.r32b, w.w32[0], w.w32[1], w.z32, w.s32, w.p32, w.c32};
+    for (float* p : fv)
+        if (p) (void)hipFree(p);
+    if (w.st) (void)hipFree(w.st);
+    if (w.hst) (void)hipHostFree(w.hst);
+    for (auto ev : w.ev)
+        if (ev) (void)hipEventDestroy(ev);
+    hipEvent_t te[] = {w.t_begin, w.t_end, w.t_it0, w.t_it1};
+    for (auto ev : te)
+        if (ev) (void)hipEventDestroy(ev);
+    w = Work();
+}
+
+namespace {
+
+// Reset the device state of slot `k` for a new solve.
+int state_reset(Work& w, int k, double tol_rel, int maxit, hipStream_t s) {
+    DevState* h = &w.hst[2 + k];
+    *h = DevState();
+    h->tol_abs = tol_rel;
+    h->maxit = maxit;
+    h->best = HUGE_VAL;
+    h->status = FVPCG_NOT_CONVERGED;
+    FV_HIP(hipMemcpyAsync(&w.st[k], h, sizeof(DevState), hipMemcpyHostToDevice, s));
+    return FVPCG_OK;
+}
+
+int state_read(Work& w, int k, DevState* out, hipStream_t s) {
+    FV_HIP(hipMemcpyAsync(&w.hst[k], &w.st[k], sizeof(DevState), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    *out = w.hst[k];
+    return FVPCG_OK;
+}
+
+// Enqueue iterations in growing chunks; after each chunk the state is copied
+// to pinned memory, and the previous chunk's copy is inspected while the
+// current chunk runs.  Kernels launched after convergence return at once.
+template <typename Launch>
+int iterate(Work& w, int k, int maxit, hipStream_t s, Launch&& launch_iter) {
+    int launched = 0, chunk = 2, pending = -1, slot = 0;
+    while (launched < maxit) {
+        int cnt = chunk < maxit - launched ? chunk : maxit - launched;
+        for (int i = 0; i < cnt; ++i) launch_iter(launched + i);
+        FV_LAUNCHED();
+        launched += cnt;
+        FV_HIP(hipMemcpyAsync(&w.hst[slot], &w.st[k], sizeof(DevState), hipMemcpyDeviceToHost, s));
+        FV_HIP(hipEventRecord(w.ev[slot], s));
+        if (pending >= 0) {
+            FV_HIP(hipEventSynchronize(w.ev[pending]));
+            if (w.hst[pending].done) break;
+        }
+        pending = slot;
+        slot ^= 1;
+        if (chunk < kMaxChunk) chunk *= 2;
+    }
+    return FVPCG_OK;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.f;
+    }
+    return ms;
+}
+
+}  // namespace
+
+int spmv(const fvpcg_matrix* A, const double* v, double* y, hipStream_t s) {
+    const fvpcg_mesh* m = A->mesh;
+    const Geom g = m->geom;
+    FV_WT_SWITCH(m->WT, hipLaunchKernelGGL(k_spmv<W_>, dim3(g.grid), dim3(kBlock), 0, s, m->col, A->val, A->d, m->n,
+                                           g, v, y));
+    FV_LAUNCHED();
+    return FVPCG_OK;
+}
+
+int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int maxit, int method, int precond,
+          hipStream_t s, fvpcg_stats* stats) {
+    const fvpcg_mesh* m = A->mesh;
+    const int n = m->n;
+    const bool jac = precond == FVPCG_PRECOND_JACOBI;
+    Work& w = *A->work;
+    int rc;
+    if ((rc = work_init(w, n))) return rc;
+    const Geom g = w.geom;
+    if (method == FVPCG_PIPECG_LITERAL && !jac) method = FVPCG_PIPECG;  // identical recurrences when M = I
+    if (method == FVPCG_CG) {
+        if ((rc = work_need_cg(w))) return rc;
+    } else {
+        if ((rc = work_need_pipe(w, method == FVPCG_PIPECG_LITERAL))) return rc;
+    }
+    FV_HIP(hipEventRecord(w.t_begin, s));
+    if ((rc = state_reset(w, 0, tol, maxit, s))) return rc;
+    DevState* st = &w.st[0];
+    double* part = w.partials;
+
+    if (method == FVPCG_CG) {
+        FV_WT_SWITCH(m->WT,
+                     if (jac) hipLaunchKernelGGL((k_cg_init<W_, true>), dim3(g.grid), dim3(kBlock), 0, s, m->col,
+                                                 A->val, A->d, n, g, b, x, w.r, w.p, st, part);
+                     else hipLaunchKernelGGL((k_cg_init<W_, false>), dim3(g.grid), dim3(kBlock), 0, s, m->col, A->val,
+                                             A->d, n, g, b, x, w.r, w.p, st, part));
+    } else {
+        const bool lit = method == FVPCG_PIPECG_LITERAL;
+        FV_WT_SWITCH(
+            m->WT,
+            if (jac && lit) hipLaunchKernelGGL((k_pipe_init_r<W_, true, true>), dim3(g.grid), dim3(kBlock), 0, s,
+                                               m->col, A->val, A->d, n, g, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st,
+                                               part);
+            else if (jac) hipLaunchKernelGGL((k_pipe_init_r<W_, true, false>), dim3(g.grid), dim3(kBlock), 0, s,
+                                             m->col, A->val, A->d, n, g, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st,
+                                             part);
+            else hipLaunchKernelGGL((k_pipe_init_r<W_, false, false>), dim3(g.grid), dim3(kBlock), 0, s, m->col,
+                                    A->val, A->d, n, g, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st, part);
+            if (jac) hipLaunchKernelGGL((k_pipe_init_w<double, W_, true>), dim3(g.grid), dim3(kBlock), 0, s, m->col,
+                                        A->val_cs, A->d, n, g, w.r, w.w[0], st, part);
+            else hipLaunchKernelGGL((k_pipe_init_w<double, W_, false>), dim3(g.grid), dim3(kBlock), 0, s, m->col,
+                                    A->val, A->d, n, g, w.r, w.w[0], st, part));
+    }
+    FV_LAUNCHED();
+    DevState h;
+    if ((rc = state_read(w, 0, &h, s))) return rc;
+    FV_HIP(hipEventRecord(w.t_it0, s));
+    if (h.zero_b) {
+        FV_HIP(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
+    } else if (!h.done) {
+        if (method == FVPCG_CG) {
+            rc = iterate(w, 0, maxit, s, [&](int it) {
+                FV_WT_SWITCH(m->WT, hipLaunchKernelGGL(k_cg_spmv<W_>, dim3(g.grid), dim3(kBlock), 0, s, m->col,
+                                                       A->val, A->d, n, g, w.p, w.q, st, part));
+                if (jac) {
+                    hipLaunchKernelGGL(k_cg_update_r<true>, dim3(g.grid), dim3(kBlock), 0, s, w.r, w.q, A->d, n, g,
+                                       st, part);
+                    hipLaunchKernelGGL(k_cg_update_xp<true>, dim3(g.grid), dim3(kBlock), 0, s, x, w.p, w.r, A->d, n,
+                                       g, it, st);
+                } else {
+                    hipLaunchKernelGGL(k_cg_update_r<false>, dim3(g.grid), dim3(kBlock), 0, s, w.r, w.q, A->d, n, g,
+                                       st, part);
+                    hipLaunchKernelGGL(k_cg_update_xp<false>, dim3(g.grid), dim3(kBlock), 0, s, x, w.p, w.r, A->d, n,
+                                       g, it, st);
+                }
+            });
+        } else {
+            const bool lit = method == FVPCG_PIPECG_LITERAL;
+            rc = iterate(w, 0, maxit, s, [&](int it) {
+                PipeVec<double> a{m->col, jac ? A->val_cs : A->val, A->d, w.w[it & 1], w.w[(it + 1) & 1], w.z,
+                                  w.s, w.p, x, w.r, w.u, w.qq};
+                FV_WT_SWITCH(
+                    m->WT,
+                    if (jac && lit) hipLaunchKernelGGL((k_pipe_iter<double, W_, true, true>), dim3(g.grid),
+                                                       dim3(kBlock), 0, s, a, n, g, st, part);
+                    else if (jac) hipLaunchKernelGGL((k_pipe_iter<double, W_, true, false>), dim3(g.grid),
+                                                     dim3(kBlock), 0, s, a, n, g, st, part);
+                    else hipLaunchKernelGGL((k_pipe_iter<double, W_, false, false>), dim3(g.grid), dim3(kBlock), 0,
+                                            s, a, n, g, st, part));
+            });
+        }
+        if (rc) return rc;
+    }
+    FV_HIP(hipEventRecord(w.t_it1, s));
+    FV_WT_SWITCH(m->WT, hipLaunchKernelGGL(k_true_residual<W_>, dim3(g.grid), dim3(kBlock), 0, s, m->col, A->val,
+                                           A->d, n, g, b, x, st, part));
+    FV_LAUNCHED();
+    FV_HIP(hipEventRecord(w.t_end, s));
+    if ((rc = state_read(w, 0, &h, s))) return rc;
+    if (stats) {
+        stats->iters = h.iter;
+        stats->outer_iters = 0;
+        stats->status = h.status;
+        stats->b_norm = h.bnorm;
+        stats->r0_norm = h.r0norm;
+        stats->rel_res = h.bnorm > 0 ? sqrt(h.rho) / h.bnorm : 0.0;
+        stats->true_rel_res = h.bnorm > 0 ? sqrt(h.true_rr) / h.bnorm : 0.0;
+        stats->device_ms = elapsed(w.t_begin, w.t_end);
+        stats->iter_ms = elapsed(w.t_it0, w.t_it1);
+    }
+    return h.status;
+}
+
+int solve_mixed(const fvpcg_matrix* A, const double* b, double* x, double outer_tol, double inner_tol, int max_outer,
+                int max_inner, hipStream_t s, fvpcg_stats* stats) {
+    const fvpcg_mesh* m = A->mesh;
+    const int n = m->n;
+    Work& w = *A->work;
+    int rc;
+    if ((rc = work_init(w, n)) || (rc = work_need_mixed(w))) return rc;
+    const Geom g = w.geom;
+    FV_HIP(hipEventRecord(w.t_begin, s));
+    if ((rc = state_reset(w, 0, outer_tol, max_outer, s))) return rc;
+    DevState* so = &w.st[0];
+    DevState* si = &w.st[1];
+    double* part = w.partials;
+    DevState h, hi;
+    int inner_total = 0, j = 0;
+    float iter_ms = 0.f;
+    for (j = 0;; ++j) {
+        FV_WT_SWITCH(m->WT, hipLaunchKernelGGL(k_mixed_residual<W_>, dim3(g.grid), dim3(kBlock), 0, s, m->col,
+                                               A->val, A->d, n, g, b, x, w.r, j, so, part));
+        FV_LAUNCHED();
+        if ((rc = state_read(w, 0, &h, s))) return rc;
+        if (h.done) break;
+        if ((rc = state_reset(w, 1, inner_tol, max_inner, s))) return rc;
+        FV_HIP(hipEventRecord(w.t_it0, s));
+        hipLaunchKernelGGL(k_mixed_cast, dim3(g.grid), dim3(kBlock), 0, s, w.r, n, g, so, w.r32, w.r32b, w.c32, w.z32, w.s32,
+                           w.p32, si, part);
+        FV_WT_SWITCH(m->WT, hipLaunchKernelGGL((k_pipe_init_w<float, W_, true>), dim3(g.grid), dim3(kBlock), 0, s,
+                                               m->col, A->val32_cs, A->d32, n, g, w.r32, w.w32[0], si, part));
+        FV_LAUNCHED();
+        rc = iterate(w, 1, max_inner, s, [&](int it) {
+            PipeVec<float> a{m->col, A->val32_cs, A->d32, w.w32[it & 1], w.w32[(it + 1) & 1], w.z32, w.s32,
+                             w.p32, w.c32, w.r32, nullptr, nullptr};
+            FV_WT_SWITCH(m->WT, hipLaunchKernelGGL((k_pipe_iter<float, W_, true, false>), dim3(g.grid), dim3(kBlock),
+                                                   0, s, a, n, g, si, part));
+            if ((it + 1) % kReplaceEvery == 0) {
+                float* w_cur = w.w32[(it + 1) & 1];
+                FV_WT_SWITCH(m->WT,
+                             hipLaunchKernelGGL(k_replace_rs<W_>, dim3(g.grid), dim3(kBlock), 0, s, m->col, A->val32,
+                                                A->d32, n, g, w.r32b, w.c32, w.p32, w.r32, w.s32, si);
+                             hipLaunchKernelGGL(k_replace_wz<W_>, dim3(g.grid), dim3(kBlock), 0, s, m->col,
+                                                A->val32_cs, A->d32, n, g, w.r32, w.s32, w_cur, w.z32, si, part));
+            }
+        });
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_mixed_correct, dim3(g.grid), dim3(kBlock), 0, s, x, w.c32, n, g, so);
+        FV_LAUNCHED();
+        FV_HIP(hipEventRecord(w.t_it1, s));
+        if ((rc = state_read(w, 1, &hi, s))) return rc;
+        iter_ms += elapsed(w.t_it0, w.t_it1);
+        inner_total += hi.iter;
+        if (hi.status == FVPCG_BREAKDOWN && hi.iter == 0) {
+            FV_HIP(hipEventRecord(w.t_end, s));
+            if ((rc = state_read(w, 0, &h, s))) return rc;
+            h.status = FVPCG_BREAKDOWN;
+            break;
+        }
+    }
+    if (h.zero_b) FV_HIP(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
+    FV_HIP(hipEventRecord(w.t_end, s));
+    FV_HIP(hipStreamSynchronize(s));
+    if (stats) {
+        stats->iters = inner_total;
+        stats->outer_iters = h.iter;
+        stats->status = h.status;
+        stats->b_norm = h.bnorm;
+        stats->r0_norm = h.r0norm;
+        stats->rel_res = h.bnorm > 0 ? h.scale / h.bnorm : 0.0;
+        stats->true_rel_res = stats->rel_res;
+        stats->device_ms = elapsed(w.t_begin, w.t_end);
+        stats->iter_ms = iter_ms;
+    }
+    return h.status;
+}
+
+int adjoint_grads(const fvpcg_matrix* A, const double* x, const double* lam, double* grad_b, double* grad_diag,
+                  double* grad_upper, double* grad_lower, hipStream_t s) {
+    const fvpcg_mesh* m = A->mesh;
+    int gc = (int)((m->n + kBlock - 1) / kBlock);
+    if (gc > 65536) gc = 65536;
+    int gf = (int)((m->F + kBlock - 1) / kBlock);
+    if (gf > 65536) gf = 65536;
+    if (gf < 1) gf = 1;
+    if (grad_diag || (grad_b && grad_b != lam))
+        hipLaunchKernelGGL(k_grad_cells, dim3(gc), dim3(kBlock), 0, s, x, lam, m->n, grad_diag, grad_b);
+    if ((grad_upper || grad_lower) && m->F > 0)
+        hipLaunchKernelGGL(k_grad_faces, dim3(gf), dim3(kBlock), 0, s, m->owner, m->nb, m->F, x, lam, grad_upper,
+                           grad_lower, A->sym ? 1 : 0);
+    FV_LAUNCHED();
+    return FVPCG_OK;
+}
+
+int solve_backward(const fvpcg_matrix* A, const double* x, const double* g, double* grad_b, double* grad_diag,
+                   double* grad_upper, double* grad_lower, double tol, int maxit, int method, int precond,
+                   hipStream_t s, fvpcg_stats* stats) {
+    Work& w = *A->work;
+    int rc;
+    if ((rc = work_init(w, A->mesh->n))) return rc;
+    double* lam = grad_b;
+    if (!lam) {
+        if (!w.lam && (rc = dev_alloc(&w.lam, (size_t)A->mesh->n, "adjoint solution"))) return rc;
+        lam = w.lam;
+    }
+    FV_HIP(hipMemsetAsync(lam, 0, sizeof(double) * (size_t)A->mesh->n, s));
+    int st = solve(A, g, lam, tol, maxit, method, precond, s, stats);
+    if (st < 0) return st;
+    if ((rc = adjoint_grads(A, x, lam, nullptr, grad_diag, grad_upper, grad_lower, s))) return rc;
+    FV_HIP(hipStreamSynchronize(s));
+    return st;
+}
+
+}  // namespace fvpcg

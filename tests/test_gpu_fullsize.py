@@ -1,0 +1,117 @@
+"""Full-size workloads in the launch configuration the benchmark times.
+
+The oracle cannot afford thousands of iterations at millions of cells, so at
+full size the checks are: the SpMV element by element against the oracle's
+product, the first iterations against the oracle at equal count, and
+properties of the converged solve that hold at any size (the FP64 true
+residual recomputed by the oracle's product)."""
+import numpy as np
+import pytest
+
+import fvcases as fc
+from tests.gpu_util import DevCase, rel, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fv():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1505_07630_amd as fv
+
+    fv.lib()
+    return fv
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+
+    oracle.build(force=False)
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def varcoef192():
+    say("generating varcoef192")
+    return fc.make("varcoef192")
+
+
+def _abs_bound(orc, case, v):
+    absc = fc.Case(case.name, case.shape, case.n, case.owner, case.neighbour, np.abs(case.diag), np.abs(case.upper),
+                   np.abs(case.lower), case.b)
+    return orc.spmv(absc, np.abs(v))
+
+
+def test_varcoef192_spmv_and_first_iterations(fv, orc, varcoef192):
+    case = varcoef192
+    say("varcoef192 spmv", case.n)
+    dc = DevCase(case)
+    v = np.random.default_rng(3).standard_normal(case.n)
+    y = fv.spmv(dc.A, to_dev(v)).cpu().numpy()
+    ref = orc.spmv(case, v)
+    assert np.all(np.abs(y - ref) <= 1e-14 * _abs_bound(orc, case, v))
+    say("varcoef192 first iterations")
+    for method in ("pipecg", "cg"):
+        x, st = fv.solve(dc.A, dc.b, tol=0.0, maxit=4, method=method)
+        assert st["iters"] == 4
+        if method == "cg":
+            xo, _ = orc.cg(case, case.b, tol=0.0, maxit=4)
+        else:
+            xo, _ = orc.pipecg(case, case.b, tol=0.0, maxit=4, folded=True)
+        assert rel(x.cpu().numpy(), xo) <= 1e-13
+    dc.close()
+
+
+def test_varcoef192_solve_to_tolerance(fv, orc, varcoef192):
+    case = varcoef192
+    say("varcoef192 pipecg solve")
+    dc = DevCase(case)
+    x, st = fv.solve(dc.A, dc.b, tol=1e-8, maxit=50000, method="pipecg")
+    assert st["status"] == 0
+    xg = x.cpu().numpy()
+    tr = np.linalg.norm(case.b - orc.spmv(case, xg)) / np.linalg.norm(case.b)
+    assert tr <= 1.5e-8
+    assert st["true_rel_res"] == pytest.approx(tr, rel=1e-6)
+    say("varcoef192 cg solve")
+    x2, s2 = fv.solve(dc.A, dc.b, tol=1e-8, maxit=50000, method="cg")
+    # the two forms take the same iterations up to rounding effects
+    assert abs(s2["iters"] - st["iters"]) <= max(2, 0.01 * st["iters"])
+    # both within the error bound of the same solution
+    assert rel(xg, x2.cpu().numpy()) <= 1e-4
+    dc.close()
+
+
+def test_varcoef192_mixed(fv, orc, varcoef192):
+    case = varcoef192
+    say("varcoef192 mixed")
+    dc = DevCase(case, fp32_copy=True)
+    x, st = fv.solve_mixed(dc.A, dc.b, outer_tol=1e-10, inner_tol=1e-5)
+    assert st["status"] == 0, st
+    xg = x.cpu().numpy()
+    tr = np.linalg.norm(case.b - orc.spmv(case, xg)) / np.linalg.norm(case.b)
+    assert tr <= 1.01e-10
+    say("varcoef192 fp64 reference solve")
+    xr, sr = fv.solve(dc.A, dc.b, tol=1e-12, maxit=50000, method="cg")
+    assert rel(xg, xr.cpu().numpy()) <= 1e-8
+    dc.close()
+
+
+def test_cavity256_pcg(fv, orc):
+    say("generating cavity256")
+    case = fc.make("cavity256")
+    dc = DevCase(case)
+    say("cavity256 first iterations")
+    x, st = fv.solve(dc.A, dc.b, tol=0.0, maxit=4, method="cg")
+    xo, _ = orc.cg(case, case.b, tol=0.0, maxit=4)
+    assert rel(x.cpu().numpy(), xo) <= 1e-13
+    say("cavity256 solve")
+    x, st = fv.solve(dc.A, dc.b, tol=1e-9, maxit=100000, method="cg")
+    assert st["status"] == 0
+    xg = x.cpu().numpy()
+    assert xg[0] == 0.0  # the pinned cell
+    tr = np.linalg.norm(case.b - orc.spmv(case, xg)) / np.linalg.norm(case.b)
+    assert tr <= 1.5e-9
+    dc.close()
