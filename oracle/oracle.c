@@ -369,7 +369,7 @@ static int32_t pipecg32_folded(int32_t n, int32_t nf, const int32_t* owner, cons
 /* ---- Mixed-precision iterative refinement (an extension beside the
  * paper's FP64 solver).  Outer loop in FP64 with the FP64 matrix:
  *   r = b - A x; stop when ||r|| <= outer_tol ||b||, or when ||r|| no longer
- *   decreases (NOT_CONVERGED);
+ *   decreases (NOT_CONVERGED, the last correction taken back);
  *   solve A32 c = fp32(r / ||r||) to inner_tol from c = 0;
  *   x += ||r|| * c. */
 int32_t or_refine(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
@@ -404,7 +404,13 @@ int32_t or_refine(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb
         if (j == 0 && st) st->r0_norm = rnorm;
         if (rnorm <= outer_tol * bnorm) { status = OR_OK; break; }
         if (!isfinite(rnorm)) { status = OR_BREAKDOWN; break; }
-        if (j == max_outer || rnorm >= prev) break;
+        if (rnorm >= prev) {
+            /* the last correction did not help: take it back */
+            for (int32_t c = 0; c < n; ++c) x[c] -= prev * (double)cor[c];
+            rnorm = prev;
+            break;
+        }
+        if (j == max_outer) break;
         prev = rnorm;
         for (int32_t c = 0; c < n; ++c) { rhs[c] = (float)(r[c] / rnorm); cor[c] = 0.0f; }
         int32_t it = 0;

@@ -3,22 +3,63 @@
 // (Section 1, Figure perf1); this is the same measurement on gfx950: copy
 // (c = a, 2 arrays moved) and triad (a = b + s*c, 3 arrays moved) over
 // FP64 arrays far larger than the 256 MB last-level cache, timed with HIP
-// events, best of several passes.
+// events: the best over several passes, grid sizes and kernel shapes (plain,
+// 4-way unrolled, non-temporal) is reported as attainable.
 #include "common.hpp"
 
 namespace fvpcg {
 
 namespace {
 
-__global__ __launch_bounds__(kBlock) void k_copy(const double2* __restrict__ a, double2* __restrict__ c, size_t n2) {
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n2; i += (size_t)gridDim.x * kBlock) c[i] = a[i];
+template <bool NT>
+__device__ __forceinline__ double2 ld2(const double2* p) {
+    if (NT) return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+    return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st2(double2* p, double2 v) {
+    if (NT) {
+        __builtin_nontemporal_store(v.x, &p->x);
+        __builtin_nontemporal_store(v.y, &p->y);
+    } else {
+        *p = v;
+    }
 }
 
+// Grid-stride copy / triad, U independent 16-byte accesses per thread per
+// step (more bytes in flight per wave), optionally non-temporal.
+template <int U, bool NT>
+__global__ __launch_bounds__(kBlock) void k_copy(const double2* __restrict__ a, double2* __restrict__ c, size_t n2) {
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + (U - 1) * stride < n2; i += U * stride) {
+        double2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = ld2<NT>(a + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < U; ++u) st2<NT>(c + i + u * stride, v[u]);
+    }
+    for (; i < n2; i += stride) st2<NT>(c + i, ld2<NT>(a + i));
+}
+
+template <int U, bool NT>
 __global__ __launch_bounds__(kBlock) void k_triad(double2* __restrict__ a, const double2* __restrict__ b,
                                                   const double2* __restrict__ c, double s, size_t n2) {
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n2; i += (size_t)gridDim.x * kBlock) {
-        double2 x = b[i], y = c[i];
-        a[i] = make_double2(x.x + s * y.x, x.y + s * y.y);
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + (U - 1) * stride < n2; i += U * stride) {
+        double2 x[U], y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            x[u] = ld2<NT>(b + i + u * stride);
+            y[u] = ld2<NT>(c + i + u * stride);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) st2<NT>(a + i + u * stride, make_double2(x[u].x + s * y[u].x, x[u].y + s * y[u].y));
+    }
+    for (; i < n2; i += stride) {
+        double2 x = ld2<NT>(b + i), y = ld2<NT>(c + i);
+        st2<NT>(a + i, make_double2(x.x + s * y.x, x.y + s * y.y));
     }
 }
 
@@ -57,20 +98,28 @@ int stream_calibrate(hipStream_t s, uint64_t bytes, double* copy_gbs, double* tr
         hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, s, c, n2, 0.5);
         FV_LAUNCHED();
         double best_copy = 0, best_triad = 0;
-        for (int rep = 0; rep < 6; ++rep) {
-            float ms = 0;
-            FV_HIP(hipEventRecord(e0, s));
-            hipLaunchKernelGGL(k_copy, dim3(grid), dim3(kBlock), 0, s, a, c, n2);
-            FV_HIP(hipEventRecord(e1, s));
-            FV_HIP(hipEventSynchronize(e1));
-            FV_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (rep > 0 && ms > 0) best_copy = std::fmax(best_copy, 2.0 * n2 * sizeof(double2) / (ms * 1e6));
-            FV_HIP(hipEventRecord(e0, s));
-            hipLaunchKernelGGL(k_triad, dim3(grid), dim3(kBlock), 0, s, a, b, c, 0.5, n2);
-            FV_HIP(hipEventRecord(e1, s));
-            FV_HIP(hipEventSynchronize(e1));
-            FV_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (rep > 0 && ms > 0) best_triad = std::fmax(best_triad, 3.0 * n2 * sizeof(double2) / (ms * 1e6));
+        float ms = 0;
+        auto timed = [&](auto&& launch, double bytes, double& best) -> int {
+            for (int rep = 0; rep < 4; ++rep) {
+                FV_HIP(hipEventRecord(e0, s));
+                launch();
+                FV_HIP(hipEventRecord(e1, s));
+                FV_HIP(hipEventSynchronize(e1));
+                FV_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0 && ms > 0) best = std::fmax(best, bytes / (ms * 1e6));
+            }
+            return FVPCG_OK;
+        };
+        const double b2 = 2.0 * n2 * sizeof(double2), b3 = 3.0 * n2 * sizeof(double2);
+        int rc2;
+        for (int gm : {4, 8, 16}) {
+            const int gg = cus * gm;
+            if ((rc2 = timed([&] { hipLaunchKernelGGL((k_copy<1, false>), dim3(gg), dim3(kBlock), 0, s, a, c, n2); }, b2, best_copy))) return rc2;
+            if ((rc2 = timed([&] { hipLaunchKernelGGL((k_copy<4, false>), dim3(gg), dim3(kBlock), 0, s, a, c, n2); }, b2, best_copy))) return rc2;
+            if ((rc2 = timed([&] { hipLaunchKernelGGL((k_copy<4, true>), dim3(gg), dim3(kBlock), 0, s, a, c, n2); }, b2, best_copy))) return rc2;
+            if ((rc2 = timed([&] { hipLaunchKernelGGL((k_triad<1, false>), dim3(gg), dim3(kBlock), 0, s, a, b, c, 0.5, n2); }, b3, best_triad))) return rc2;
+            if ((rc2 = timed([&] { hipLaunchKernelGGL((k_triad<4, false>), dim3(gg), dim3(kBlock), 0, s, a, b, c, 0.5, n2); }, b3, best_triad))) return rc2;
+            if ((rc2 = timed([&] { hipLaunchKernelGGL((k_triad<4, true>), dim3(gg), dim3(kBlock), 0, s, a, b, c, 0.5, n2); }, b3, best_triad))) return rc2;
         }
         FV_LAUNCHED();
         *copy_gbs = best_copy;

@@ -16,7 +16,10 @@ namespace fvpcg {
 
 constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kMaxGrid = 2048;        // row-parallel workgroups per launch (multiple of 8)
+#ifndef FVPCG_MAX_GRID
+#define FVPCG_MAX_GRID 1024
+#endif
+constexpr int kMaxGrid = FVPCG_MAX_GRID;  // row-parallel workgroups per launch
 constexpr int kMaxChunk = 64;         // iterations enqueued between convergence checks
 // FP32 pipelined inner solve of the mixed solver: residual replacement period
 // and the number of replacements without a new minimum that ends it.
@@ -41,13 +44,14 @@ struct alignas(128) DevState {
     double gamma_old; // gamma and alpha of the previous iteration (pipelined
     double alpha_old; //   recurrences, re-formed after a residual replacement)
     double best;      // smallest replaced (true) ||r||^2 so far
+    double scale_prev; // mixed solver: ||r|| before the last correction
     int32_t no_min;   // replacements since the last new minimum
     int32_t iter;     // completed updates of x
     int32_t maxit;
     int32_t done;     // 1 once converged, out of iterations or broken down
     int32_t status;   // fvpcg_status
     int32_t zero_b;   // 1 if b == 0 (host writes x = 0)
-    int32_t pad0;
+    int32_t undo;     // mixed solver: the last correction increased ||r||
     uint32_t ticket;  // last-workgroup detection counter
     uint32_t pad1;
 };
@@ -190,6 +194,45 @@ __device__ __forceinline__ bool device_reduce(double (&v)[NV], double* partials,
         __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return true;
+}
+
+// Loads and stores of data used once per kernel (matrix slots, the row's own
+// vector entries): marked non-temporal so they do not evict the gathered
+// neighbour values from L2.
+#ifndef FVPCG_NT_LOADS
+#define FVPCG_NT_LOADS 1
+#endif
+#ifndef FVPCG_NT_STORES
+#define FVPCG_NT_STORES 1
+#endif
+template <typename T>
+__device__ __forceinline__ T ld_once(const T* p) {
+#if FVPCG_NT_LOADS
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+template <typename T>
+__device__ __forceinline__ void st_once(T* p, T v) {
+#if FVPCG_NT_STORES
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+// Tiles of kBlock rows handled by workgroup b (see FV_ROWS).
+struct TileRange {
+    int first, end, step;
+};
+__device__ __forceinline__ TileRange xcd_tiles(int b, int G, int n) {
+    const int T = (n + kBlock - 1) / kBlock;
+    const int x = b & 7, j = b >> 3;
+    const int gx = (G >> 3) + (x < (G & 7) ? 1 : 0);
+    const int t0 = x * (T >> 3) + (x < (T & 7) ? x : (T & 7));
+    const int t1 = t0 + (T >> 3) + (x < (T & 7) ? 1 : 0);
+    return {t0 + j, t1, gx};
 }
 
 // Rows of workgroup `blk`.

@@ -30,18 +30,35 @@ __device__ __forceinline__ T row_gather(const int* __restrict__ col, const T* __
 #pragma unroll
     for (int k = 0; k < WT; ++k) {
         size_t o = (size_t)k * n + c;
-        j[k] = col[o];
-        a[k] = val[o];
+        j[k] = ld_once(col + o);
+        a[k] = ld_once(val + o);
     }
 #pragma unroll
     for (int k = 0; k < WT; ++k) acc += a[k] * v[j[k]];
     return acc;
 }
 
+#ifndef FVPCG_TILING
+#define FVPCG_TILING 1
+#endif
+
+#if FVPCG_TILING == 0
+// Contiguous chunk of g.rows rows per (XCD-remapped) workgroup.
 #define FV_ROWS(blk)                                                     \
     const int blk = xcd_block(blockIdx.x, g.grid);                      \
     const RowRange rr_ = rows_of(blk, g.rows, n);                       \
     for (int c = rr_.begin + (int)threadIdx.x; c < rr_.end; c += kBlock)
+#else
+// Tiles of kBlock rows.  XCD x (workgroups b with b % 8 == x) owns a
+// contiguous range of tiles; its Gx workgroups take tiles t0 + j, t0 + j + Gx,
+// ... so the workgroups resident on one XCD always work on a compact window
+// of rows and the neighbour columns they gather stay in that XCD's L2.
+#define FV_ROWS(blk)                                                          \
+    const int blk = (int)blockIdx.x;                                         \
+    const TileRange tr_ = xcd_tiles(blk, g.grid, n);                         \
+    for (int t_ = tr_.first; t_ < tr_.end; t_ += tr_.step)                   \
+        for (int c = t_ * kBlock + (int)threadIdx.x; c < n && c < (t_ + 1) * kBlock; c += n)
+#endif
 
 // ===========================================================================
 // y = A v
@@ -185,18 +202,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_xp(double* __restrict__ x,
     if (st->iter != it + 1) return;
     const double alpha = st->alpha, beta = st->beta;
     const bool more = !st->done;
-    const int blk = xcd_block(blockIdx.x, g.grid);
-    const RowRange rr_ = rows_of(blk, g.rows, n);
-    if (more) {
-        for (int c = rr_.begin + (int)threadIdx.x; c < rr_.end; c += kBlock) {
-            double pc = p[c];
-            x[c] += alpha * pc;
-            double rc = r[c];
-            double zc = JAC ? rc / d[c] : rc;
+    FV_ROWS(blk) {
+        const double pc = p[c];
+        x[c] += alpha * pc;
+        if (more) {
+            const double rc = r[c];
+            const double zc = JAC ? rc / d[c] : rc;
             p[c] = zc + beta * pc;
         }
-    } else {
-        for (int c = rr_.begin + (int)threadIdx.x; c < rr_.end; c += kBlock) x[c] += alpha * p[c];
     }
 }
 
@@ -337,33 +350,33 @@ __global__ __launch_bounds__(kBlock) void k_pipe_iter(PipeVec<T> a, int n, Geom 
     double acc[3] = {0.0, 0.0, 0.0};
     FV_ROWS(blk) {
         const T wc = a.w_in[c];
-        const T dc = a.d[c];
+        const T dc = ld_once(a.d + c);
         const T nv = row_gather<T, WT>(a.col, a.val, n, c, a.w_in, JAC ? wc : dc * wc);
-        const T zc = nv + beta * a.z[c];
-        const T sc = wc + beta * a.s[c];
-        T rc = a.r[c];
+        const T zc = nv + beta * ld_once(a.z + c);
+        const T sc = wc + beta * ld_once(a.s + c);
+        T rc = ld_once(a.r + c);
         T uc;
         if (LIT) {
             const T mc = JAC ? wc / dc : wc;
-            const T qc = mc + beta * a.q[c];
-            uc = a.u[c];
-            const T pc = uc + beta * a.p[c];
-            a.q[c] = qc;
-            a.p[c] = pc;
-            a.x[c] += alpha * pc;
+            const T qc = mc + beta * ld_once(a.q + c);
+            uc = ld_once(a.u + c);
+            const T pc = uc + beta * ld_once(a.p + c);
+            st_once(a.q + c, qc);
+            st_once(a.p + c, pc);
+            st_once(a.x + c, ld_once(a.x + c) + alpha * pc);
             uc -= alpha * qc;
-            a.u[c] = uc;
+            st_once(a.u + c, uc);
         } else {
             uc = JAC ? rc / dc : rc;
-            const T pc = uc + beta * a.p[c];
-            a.p[c] = pc;
-            a.x[c] += alpha * pc;
+            const T pc = uc + beta * ld_once(a.p + c);
+            st_once(a.p + c, pc);
+            st_once(a.x + c, ld_once(a.x + c) + alpha * pc);
         }
         rc -= alpha * sc;
         const T wn = wc - alpha * zc;
-        a.z[c] = zc;
-        a.s[c] = sc;
-        a.r[c] = rc;
+        st_once(a.z + c, zc);
+        st_once(a.s + c, sc);
+        st_once(a.r + c, rc);
         a.w_out[c] = wn;
         if (!LIT) uc = JAC ? rc / dc : rc;
         acc[0] += (double)rc * (double)uc;
@@ -473,6 +486,7 @@ __global__ __launch_bounds__(kBlock) void k_mixed_residual(const int* __restrict
         st->iter = j;
         const double rn = sqrt(t[0]);
         const double prev = st->scale;
+        st->scale_prev = prev;
         st->scale = rn;
         st->rho = t[0];
         st->true_rr = t[0];
@@ -493,7 +507,11 @@ __global__ __launch_bounds__(kBlock) void k_mixed_residual(const int* __restrict
         } else if (!isfinite(rn)) {
             st->done = 1;
             st->status = FVPCG_BREAKDOWN;
-        } else if (j >= st->maxit || (j > 0 && rn >= prev)) {
+        } else if (j > 0 && rn >= prev) {
+            st->done = 1;
+            st->status = FVPCG_NOT_CONVERGED;
+            st->undo = 1;
+        } else if (j >= st->maxit) {
             st->done = 1;
             st->status = FVPCG_NOT_CONVERGED;
         }
@@ -527,9 +545,10 @@ __global__ __launch_bounds__(kBlock) void k_mixed_cast(const double* __restrict_
     }
 }
 
+// x += ||r|| c; with `undo`, x -= ||r_prev|| c takes the last correction back.
 __global__ __launch_bounds__(kBlock) void k_mixed_correct(double* __restrict__ x, const float* __restrict__ c32, int n,
-                                                          Geom g, const DevState* st_out) {
-    const double sc = st_out->scale;
+                                                          Geom g, const DevState* st_out, int undo) {
+    const double sc = undo ? -st_out->scale_prev : st_out->scale;
     FV_ROWS(blk) { x[c] += sc * (double)c32[c]; }
 }
 
@@ -845,6 +864,11 @@ int solve_mixed(const fvpcg_matrix* A, const double* b, double* x, double outer_
                                                A->val, A->d, n, g, b, x, w.r, j, so, part));
         FV_LAUNCHED();
         if ((rc = state_read(w, 0, &h, s))) return rc;
+        if (h.undo) {
+            hipLaunchKernelGGL(k_mixed_correct, dim3(g.grid), dim3(kBlock), 0, s, x, w.c32, n, g, so, 1);
+            FV_LAUNCHED();
+            h.scale = h.scale_prev;
+        }
         if (h.done) break;
         if ((rc = state_reset(w, 1, inner_tol, max_inner, s))) return rc;
         FV_HIP(hipEventRecord(w.t_it0, s));
@@ -868,7 +892,7 @@ int solve_mixed(const fvpcg_matrix* A, const double* b, double* x, double outer_
             }
         });
         if (rc) return rc;
-        hipLaunchKernelGGL(k_mixed_correct, dim3(g.grid), dim3(kBlock), 0, s, x, w.c32, n, g, so);
+        hipLaunchKernelGGL(k_mixed_correct, dim3(g.grid), dim3(kBlock), 0, s, x, w.c32, n, g, so, 0);
         FV_LAUNCHED();
         FV_HIP(hipEventRecord(w.t_it1, s));
         if ((rc = state_read(w, 1, &hi, s))) return rc;
