@@ -14,7 +14,10 @@
 
 namespace fvpcg {
 
-constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
+#ifndef FVPCG_BLOCK
+#define FVPCG_BLOCK 256
+#endif
+constexpr int kBlock = FVPCG_BLOCK;   // threads per workgroup (wave64s)
 constexpr int kWaves = kBlock / 64;
 #ifndef FVPCG_MAX_GRID
 #define FVPCG_MAX_GRID 1024

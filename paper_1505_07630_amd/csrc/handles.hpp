@@ -48,12 +48,14 @@ struct fvpcg_mesh {
     int device = 0;
     int n = 0;
     int F = 0;
-    int maxdeg = 0;  // largest row degree
+    int maxdeg = 0;     // largest row degree
+    int bandwidth = -1; // largest |column - row| (-1: not measured)
     int W = 0;       // slots per row: maxdeg rounded up to a kernel width
     int WT = 0;      // kernel specialisation width (== W)
     int* owner = nullptr;
     int* nb = nullptr;
     int* col = nullptr;  // [W][n] column of each slot; padding holds the row itself
+    int16_t* col16 = nullptr;  // [W][n] column - row, when every offset fits in int16 (else NULL)
     int* ref = nullptr;  // [W][n] 2*face + (0 upper | 1 lower); -1 for padding
     fvpcg::Geom geom{1, 64};
 };

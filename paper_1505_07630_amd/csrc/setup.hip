@@ -9,6 +9,8 @@
 // owner[f], coefficient lower[f]), padded with (column c, value 0).  Element
 // (k, c) lives at k*n + c, so the 64 lanes of a wave read 64 consecutive
 // entries of a slot: every matrix stream is coalesced.
+#include <cstdlib>
+
 #include "handles.hpp"
 
 namespace fvpcg {
@@ -79,6 +81,25 @@ __global__ void k_sort_pad(const int* __restrict__ deg, int n, int W, int* col, 
     }
 }
 
+// Largest |column - row| over all slots (the matrix bandwidth).
+__global__ void k_max_offset(const int* __restrict__ col, int n, int W, int* out) {
+    int m = 0;
+    const size_t total = (size_t)W * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % (size_t)n);
+        m = max(m, abs(col[i] - c));
+    }
+    atomicMax(out, m);
+}
+
+__global__ void k_make_col16(const int* __restrict__ col, int n, int W, int16_t* col16) {
+    const size_t total = (size_t)W * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % (size_t)n);
+        col16[i] = (int16_t)(col[i] - c);
+    }
+}
+
 // Coefficients into the slot layout; also the column-scaled copy
 // A[c][j] / d[j] used by the Jacobi-folded pipelined kernels, and the FP32
 // copies when requested.
@@ -124,6 +145,7 @@ void mesh_free(fvpcg_mesh* m) {
     dev_free(m->owner);
     dev_free(m->nb);
     dev_free(m->col);
+    dev_free(m->col16);
     dev_free(m->ref);
     delete m;
 }
@@ -230,6 +252,24 @@ int mesh_create(int32_t n, int32_t F, const int32_t* owner, const int32_t* nb, h
     }
     hipLaunchKernelGGL(k_sort_pad, dim3(grid_for(n)), dim3(kBlock), 0, s, deg, n, W, m->col, m->ref);
     CK(hipGetLastError());
+    // 16-bit column offsets when the bandwidth allows (FVPCG_COL16=0 keeps int32)
+    {
+        const char* env = getenv("FVPCG_COL16");
+        if (!(env && env[0] == '0')) {
+            CK(hipMemsetAsync(dmax, 0, sizeof(int), s));
+            hipLaunchKernelGGL(k_max_offset, dim3(grid_for((size_t)W * n)), dim3(kBlock), 0, s, m->col, n, W, dmax);
+            CK(hipGetLastError());
+            int band = 0;
+            if ((rc = read_back(s, &band, dmax, sizeof(int)))) return fail(rc);
+            m->bandwidth = band;
+            if (band <= 32767) {
+                if ((rc = dev_alloc(&m->col16, (size_t)W * n, "ELL column offsets"))) return fail(rc);
+                hipLaunchKernelGGL(k_make_col16, dim3(grid_for((size_t)W * n)), dim3(kBlock), 0, s, m->col, n, W,
+                                   m->col16);
+                CK(hipGetLastError());
+            }
+        }
+    }
     CK(hipStreamSynchronize(s));
 #undef CK
     dev_free(deg);

@@ -21,16 +21,21 @@ namespace fvpcg {
 // ===========================================================================
 // Row kernels' building blocks
 
+// Column of slot (k, c): int32 column, or int16 offset from the row when the
+// mesh's bandwidth fits (12 fewer bytes per hexahedral row per product).
+__device__ __forceinline__ int slot_col(const int* p, size_t o, int) { return ld_once(p + o); }
+__device__ __forceinline__ int slot_col(const int16_t* p, size_t o, int c) { return c + (int)ld_once(p + o); }
+
 // acc + sum_k val[k][c] * v[col[k][c]] over the WT slots of row c.
-template <typename T, int WT>
-__device__ __forceinline__ T row_gather(const int* __restrict__ col, const T* __restrict__ val, int n, int c,
+template <typename T, int WT, typename CI>
+__device__ __forceinline__ T row_gather(const CI* __restrict__ col, const T* __restrict__ val, int n, int c,
                                         const T* __restrict__ v, T acc) {
     int j[WT];
     T a[WT];
 #pragma unroll
     for (int k = 0; k < WT; ++k) {
         size_t o = (size_t)k * n + c;
-        j[k] = ld_once(col + o);
+        j[k] = slot_col(col, o, c);
         a[k] = ld_once(val + o);
     }
 #pragma unroll
@@ -63,22 +68,22 @@ __device__ __forceinline__ T row_gather(const int* __restrict__ col, const T* __
 // ===========================================================================
 // y = A v
 
-template <int WT>
-__global__ __launch_bounds__(kBlock) void k_spmv(const int* __restrict__ col, const double* __restrict__ val,
+template <int WT, typename CI>
+__global__ __launch_bounds__(kBlock) void k_spmv(const CI* __restrict__ col, const double* __restrict__ val,
                                                  const double* __restrict__ d, int n, Geom g,
                                                  const double* __restrict__ v, double* __restrict__ y) {
-    FV_ROWS(blk) { y[c] = row_gather<double, WT>(col, val, n, c, v, d[c] * v[c]); }
+    FV_ROWS(blk) { y[c] = row_gather<double, WT, CI>(col, val, n, c, v, d[c] * v[c]); }
 }
 
 // ||b - A x||^2 into st->true_rr (the true residual reported at exit).
-template <int WT>
-__global__ __launch_bounds__(kBlock) void k_true_residual(const int* __restrict__ col, const double* __restrict__ val,
+template <int WT, typename CI>
+__global__ __launch_bounds__(kBlock) void k_true_residual(const CI* __restrict__ col, const double* __restrict__ val,
                                                           const double* __restrict__ d, int n, Geom g,
                                                           const double* __restrict__ b, const double* __restrict__ x,
                                                           DevState* st, double* partials) {
     double acc[1] = {0.0};
     FV_ROWS(blk) {
-        double r = b[c] - row_gather<double, WT>(col, val, n, c, x, d[c] * x[c]);
+        double r = b[c] - row_gather<double, WT, CI>(col, val, n, c, x, d[c] * x[c]);
         acc[0] += r * r;
     }
     double tot[1];
@@ -89,8 +94,8 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(const int* __restrict_
 // Standard preconditioned CG
 
 // r = b - A x, z = M^-1 r, p = z; gamma = (r,z), rho = (r,r), (b,b).
-template <int WT, bool JAC>
-__global__ __launch_bounds__(kBlock) void k_cg_init(const int* __restrict__ col, const double* __restrict__ val,
+template <int WT, typename CI, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_cg_init(const CI* __restrict__ col, const double* __restrict__ val,
                                                     const double* __restrict__ d, int n, Geom g,
                                                     const double* __restrict__ b, const double* __restrict__ x,
                                                     double* __restrict__ r, double* __restrict__ p, DevState* st,
@@ -99,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const int* __restrict__ col,
     FV_ROWS(blk) {
         double bc = b[c];
         double dc = d[c];
-        double rc = bc - row_gather<double, WT>(col, val, n, c, x, dc * x[c]);
+        double rc = bc - row_gather<double, WT, CI>(col, val, n, c, x, dc * x[c]);
         double zc = JAC ? rc / dc : rc;
         r[c] = rc;
         p[c] = zc;
@@ -134,8 +139,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const int* __restrict__ col,
 }
 
 // q = A p; delta = (p, q); alpha = gamma / delta.
-template <int WT>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(const int* __restrict__ col, const double* __restrict__ val,
+template <int WT, typename CI>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(const CI* __restrict__ col, const double* __restrict__ val,
                                                     const double* __restrict__ d, int n, Geom g,
                                                     const double* __restrict__ p, double* __restrict__ q, DevState* st,
                                                     double* partials) {
@@ -143,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const int* __restrict__ col,
     double acc[1] = {0.0};
     FV_ROWS(blk) {
         double pc = p[c];
-        double qc = row_gather<double, WT>(col, val, n, c, p, d[c] * pc);
+        double qc = row_gather<double, WT, CI>(col, val, n, c, p, d[c] * pc);
         q[c] = qc;
         acc[0] += pc * qc;
     }
@@ -228,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_xp(double* __restrict__ x,
 
 template <typename T>
 struct PipeVec {
-    const int* col;
+    const void* col;  // int32 columns or int16 offsets (the kernel's CI)
     const T* val;  // column-scaled with Jacobi, plain otherwise
     const T* d;
     const T* w_in;
@@ -284,8 +289,8 @@ __device__ __forceinline__ void pipe_scalars(DevState* st, double gamma, double 
 
 // r = b - A x; (b, b) -> bnorm and the absolute tolerance; clears the
 // pipelined recurrences (z, s, p[, q]) and sets u = M^-1 r (literal).
-template <int WT, bool JAC, bool LIT>
-__global__ __launch_bounds__(kBlock) void k_pipe_init_r(const int* __restrict__ col, const double* __restrict__ val,
+template <int WT, typename CI, bool JAC, bool LIT>
+__global__ __launch_bounds__(kBlock) void k_pipe_init_r(const CI* __restrict__ col, const double* __restrict__ val,
                                                         const double* __restrict__ d, int n, Geom g,
                                                         const double* __restrict__ b, const double* __restrict__ x,
                                                         double* __restrict__ r, double* __restrict__ z,
@@ -296,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_init_r(const int* __restrict__ 
     FV_ROWS(blk) {
         double bc = b[c];
         double dc = d[c];
-        double rc = bc - row_gather<double, WT>(col, val, n, c, x, dc * x[c]);
+        double rc = bc - row_gather<double, WT, CI>(col, val, n, c, x, dc * x[c]);
         r[c] = rc;
         z[c] = 0.0;
         s[c] = 0.0;
@@ -321,8 +326,8 @@ __global__ __launch_bounds__(kBlock) void k_pipe_init_r(const int* __restrict__ 
 }
 
 // w0 = A M^-1 r0 and the first reduction (gamma_0, delta_0, rho_0).
-template <typename T, int WT, bool JAC>
-__global__ __launch_bounds__(kBlock) void k_pipe_init_w(const int* __restrict__ col, const T* __restrict__ val,
+template <typename T, int WT, typename CI, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_pipe_init_w(const CI* __restrict__ col, const T* __restrict__ val,
                                                         const T* __restrict__ d, int n, Geom g,
                                                         const T* __restrict__ r, T* __restrict__ w, DevState* st,
                                                         double* partials) {
@@ -331,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_init_w(const int* __restrict__ 
     FV_ROWS(blk) {
         T rc = r[c];
         T dc = d[c];
-        T wc = row_gather<T, WT>(col, val, n, c, r, JAC ? rc : dc * rc);
+        T wc = row_gather<T, WT, CI>(col, val, n, c, r, JAC ? rc : dc * rc);
         w[c] = wc;
         T uc = JAC ? rc / dc : rc;
         acc[0] += (double)rc * (double)uc;
@@ -343,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_init_w(const int* __restrict__ 
         pipe_scalars(st, t[0], t[1], t[2], true);
 }
 
-template <typename T, int WT, bool JAC, bool LIT>
+template <typename T, int WT, typename CI, bool JAC, bool LIT>
 __global__ __launch_bounds__(kBlock) void k_pipe_iter(PipeVec<T> a, int n, Geom g, DevState* st, double* partials) {
     if (st->done) return;
     const T alpha = (T)st->alpha, beta = (T)st->beta;
@@ -351,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_iter(PipeVec<T> a, int n, Geom 
     FV_ROWS(blk) {
         const T wc = a.w_in[c];
         const T dc = ld_once(a.d + c);
-        const T nv = row_gather<T, WT>(a.col, a.val, n, c, a.w_in, JAC ? wc : dc * wc);
+        const T nv = row_gather<T, WT, CI>((const CI*)a.col, a.val, n, c, a.w_in, JAC ? wc : dc * wc);
         const T zc = nv + beta * ld_once(a.z + c);
         const T sc = wc + beta * ld_once(a.s + c);
         T rc = ld_once(a.r + c);
@@ -397,8 +402,8 @@ __global__ __launch_bounds__(kBlock) void k_pipe_iter(PipeVec<T> a, int n, Geom 
 // the previous iteration's gamma and alpha.  The inner solve ends once
 // kStagnationChecks replacements in a row bring no new minimum of ||r||.
 
-template <int WT>
-__global__ __launch_bounds__(kBlock) void k_replace_rs(const int* __restrict__ col, const float* __restrict__ val,
+template <int WT, typename CI>
+__global__ __launch_bounds__(kBlock) void k_replace_rs(const CI* __restrict__ col, const float* __restrict__ val,
                                                        const float* __restrict__ d, int n, Geom g,
                                                        const float* __restrict__ b, const float* __restrict__ x,
                                                        const float* __restrict__ p, float* __restrict__ r,
@@ -406,13 +411,13 @@ __global__ __launch_bounds__(kBlock) void k_replace_rs(const int* __restrict__ c
     if (st->done) return;
     FV_ROWS(blk) {
         const float dc = d[c];
-        r[c] = b[c] - row_gather<float, WT>(col, val, n, c, x, dc * x[c]);
-        s[c] = row_gather<float, WT>(col, val, n, c, p, dc * p[c]);
+        r[c] = b[c] - row_gather<float, WT, CI>(col, val, n, c, x, dc * x[c]);
+        s[c] = row_gather<float, WT, CI>(col, val, n, c, p, dc * p[c]);
     }
 }
 
-template <int WT>
-__global__ __launch_bounds__(kBlock) void k_replace_wz(const int* __restrict__ col, const float* __restrict__ val_cs,
+template <int WT, typename CI>
+__global__ __launch_bounds__(kBlock) void k_replace_wz(const CI* __restrict__ col, const float* __restrict__ val_cs,
                                                        const float* __restrict__ d, int n, Geom g,
                                                        const float* __restrict__ r, const float* __restrict__ s,
                                                        float* __restrict__ w, float* __restrict__ z, DevState* st,
@@ -421,8 +426,8 @@ __global__ __launch_bounds__(kBlock) void k_replace_wz(const int* __restrict__ c
     double acc[3] = {0.0, 0.0, 0.0};
     FV_ROWS(blk) {
         const float rc = r[c];
-        const float wc = row_gather<float, WT>(col, val_cs, n, c, r, rc);
-        z[c] = row_gather<float, WT>(col, val_cs, n, c, s, s[c]);
+        const float wc = row_gather<float, WT, CI>(col, val_cs, n, c, r, rc);
+        z[c] = row_gather<float, WT, CI>(col, val_cs, n, c, s, s[c]);
         w[c] = wc;
         const float uc = rc / d[c];
         acc[0] += (double)rc * (double)uc;
@@ -466,8 +471,8 @@ __global__ __launch_bounds__(kBlock) void k_replace_wz(const int* __restrict__ c
 // FP64 correction.
 
 // r = b - A x (FP64); outer stopping test on ||r||.  `j` = corrections so far.
-template <int WT>
-__global__ __launch_bounds__(kBlock) void k_mixed_residual(const int* __restrict__ col,
+template <int WT, typename CI>
+__global__ __launch_bounds__(kBlock) void k_mixed_residual(const CI* __restrict__ col,
                                                            const double* __restrict__ val,
                                                            const double* __restrict__ d, int n, Geom g,
                                                            const double* __restrict__ b, const double* __restrict__ x,
@@ -476,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_mixed_residual(const int* __restrict
     double acc[2] = {0.0, 0.0};
     FV_ROWS(blk) {
         double bc = b[c];
-        double rc = bc - row_gather<double, WT>(col, val, n, c, x, d[c] * x[c]);
+        double rc = bc - row_gather<double, WT, CI>(col, val, n, c, x, d[c] * x[c]);
         r[c] = rc;
         acc[0] += rc * rc;
         acc[1] += bc * bc;
@@ -591,6 +596,25 @@ __global__ void k_grad_faces(const int* __restrict__ owner, const int* __restric
         case 16: { constexpr int W_ = 16; __VA_ARGS__; } break;                      \
         default: { constexpr int W_ = 32; __VA_ARGS__; } break;                      \
     }
+
+// Dispatch on the mesh layout: W_ = slot count, CI_ = column type, cols_ =
+// the column array (int16 offsets when the bandwidth fits, else int32).
+#define FV_LAYOUT(M, ...)                                                            \
+    if ((M)->col16) {                                                                \
+        using CI_ = int16_t;                                                         \
+        const CI_* cols_ = (M)->col16;                                               \
+        (void)cols_;                                                                 \
+        FV_WT_SWITCH((M)->WT, __VA_ARGS__);                                          \
+    } else {                                                                         \
+        using CI_ = int;                                                             \
+        const CI_* cols_ = (M)->col;                                                 \
+        (void)cols_;                                                                 \
+        FV_WT_SWITCH((M)->WT, __VA_ARGS__);                                          \
+    }
+
+inline const void* mesh_cols(const fvpcg_mesh* m) {
+    return m->col16 ? (const void*)m->col16 : (const void*)m->col;
+}
 
 int work_init(Work& w, int n) {
     if (w.st) return FVPCG_OK;
@@ -734,7 +758,7 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 int spmv(const fvpcg_matrix* A, const double* v, double* y, hipStream_t s) {
     const fvpcg_mesh* m = A->mesh;
     const Geom g = m->geom;
-    FV_WT_SWITCH(m->WT, hipLaunchKernelGGL(k_spmv<W_>, dim3(g.grid), dim3(kBlock), 0, s, m->col, A->val, A->d, m->n,
+    FV_LAYOUT(m, hipLaunchKernelGGL((k_spmv<W_, CI_>), dim3(g.grid), dim3(kBlock), 0, s, cols_, A->val, A->d, m->n,
                                            g, v, y));
     FV_LAUNCHED();
     return FVPCG_OK;
@@ -761,26 +785,26 @@ int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int max
     double* part = w.partials;
 
     if (method == FVPCG_CG) {
-        FV_WT_SWITCH(m->WT,
-                     if (jac) hipLaunchKernelGGL((k_cg_init<W_, true>), dim3(g.grid), dim3(kBlock), 0, s, m->col,
+        FV_LAYOUT(m,
+                     if (jac) hipLaunchKernelGGL((k_cg_init<W_, CI_, true>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
                                                  A->val, A->d, n, g, b, x, w.r, w.p, st, part);
-                     else hipLaunchKernelGGL((k_cg_init<W_, false>), dim3(g.grid), dim3(kBlock), 0, s, m->col, A->val,
+                     else hipLaunchKernelGGL((k_cg_init<W_, CI_, false>), dim3(g.grid), dim3(kBlock), 0, s, cols_, A->val,
                                              A->d, n, g, b, x, w.r, w.p, st, part));
     } else {
         const bool lit = method == FVPCG_PIPECG_LITERAL;
-        FV_WT_SWITCH(
-            m->WT,
-            if (jac && lit) hipLaunchKernelGGL((k_pipe_init_r<W_, true, true>), dim3(g.grid), dim3(kBlock), 0, s,
-                                               m->col, A->val, A->d, n, g, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st,
+        FV_LAYOUT(
+            m,
+            if (jac && lit) hipLaunchKernelGGL((k_pipe_init_r<W_, CI_, true, true>), dim3(g.grid), dim3(kBlock), 0, s,
+                                               cols_, A->val, A->d, n, g, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st,
                                                part);
-            else if (jac) hipLaunchKernelGGL((k_pipe_init_r<W_, true, false>), dim3(g.grid), dim3(kBlock), 0, s,
-                                             m->col, A->val, A->d, n, g, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st,
+            else if (jac) hipLaunchKernelGGL((k_pipe_init_r<W_, CI_, true, false>), dim3(g.grid), dim3(kBlock), 0, s,
+                                             cols_, A->val, A->d, n, g, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st,
                                              part);
-            else hipLaunchKernelGGL((k_pipe_init_r<W_, false, false>), dim3(g.grid), dim3(kBlock), 0, s, m->col,
+            else hipLaunchKernelGGL((k_pipe_init_r<W_, CI_, false, false>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
                                     A->val, A->d, n, g, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st, part);
-            if (jac) hipLaunchKernelGGL((k_pipe_init_w<double, W_, true>), dim3(g.grid), dim3(kBlock), 0, s, m->col,
+            if (jac) hipLaunchKernelGGL((k_pipe_init_w<double, W_, CI_, true>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
                                         A->val_cs, A->d, n, g, w.r, w.w[0], st, part);
-            else hipLaunchKernelGGL((k_pipe_init_w<double, W_, false>), dim3(g.grid), dim3(kBlock), 0, s, m->col,
+            else hipLaunchKernelGGL((k_pipe_init_w<double, W_, CI_, false>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
                                     A->val, A->d, n, g, w.r, w.w[0], st, part));
     }
     FV_LAUNCHED();
@@ -792,39 +816,39 @@ int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int max
     } else if (!h.done) {
         if (method == FVPCG_CG) {
             rc = iterate(w, 0, maxit, s, [&](int it) {
-                FV_WT_SWITCH(m->WT, hipLaunchKernelGGL(k_cg_spmv<W_>, dim3(g.grid), dim3(kBlock), 0, s, m->col,
+                FV_LAYOUT(m, hipLaunchKernelGGL((k_cg_spmv<W_, CI_>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
                                                        A->val, A->d, n, g, w.p, w.q, st, part));
                 if (jac) {
-                    hipLaunchKernelGGL(k_cg_update_r<true>, dim3(g.grid), dim3(kBlock), 0, s, w.r, w.q, A->d, n, g,
+                    hipLaunchKernelGGL((k_cg_update_r<true>), dim3(g.grid), dim3(kBlock), 0, s, w.r, w.q, A->d, n, g,
                                        st, part);
-                    hipLaunchKernelGGL(k_cg_update_xp<true>, dim3(g.grid), dim3(kBlock), 0, s, x, w.p, w.r, A->d, n,
+                    hipLaunchKernelGGL((k_cg_update_xp<true>), dim3(g.grid), dim3(kBlock), 0, s, x, w.p, w.r, A->d, n,
                                        g, it, st);
                 } else {
-                    hipLaunchKernelGGL(k_cg_update_r<false>, dim3(g.grid), dim3(kBlock), 0, s, w.r, w.q, A->d, n, g,
+                    hipLaunchKernelGGL((k_cg_update_r<false>), dim3(g.grid), dim3(kBlock), 0, s, w.r, w.q, A->d, n, g,
                                        st, part);
-                    hipLaunchKernelGGL(k_cg_update_xp<false>, dim3(g.grid), dim3(kBlock), 0, s, x, w.p, w.r, A->d, n,
+                    hipLaunchKernelGGL((k_cg_update_xp<false>), dim3(g.grid), dim3(kBlock), 0, s, x, w.p, w.r, A->d, n,
                                        g, it, st);
                 }
             });
         } else {
             const bool lit = method == FVPCG_PIPECG_LITERAL;
             rc = iterate(w, 0, maxit, s, [&](int it) {
-                PipeVec<double> a{m->col, jac ? A->val_cs : A->val, A->d, w.w[it & 1], w.w[(it + 1) & 1], w.z,
+                PipeVec<double> a{mesh_cols(m), jac ? A->val_cs : A->val, A->d, w.w[it & 1], w.w[(it + 1) & 1], w.z,
                                   w.s, w.p, x, w.r, w.u, w.qq};
-                FV_WT_SWITCH(
-                    m->WT,
-                    if (jac && lit) hipLaunchKernelGGL((k_pipe_iter<double, W_, true, true>), dim3(g.grid),
+                FV_LAYOUT(
+                    m,
+                    if (jac && lit) hipLaunchKernelGGL((k_pipe_iter<double, W_, CI_, true, true>), dim3(g.grid),
                                                        dim3(kBlock), 0, s, a, n, g, st, part);
-                    else if (jac) hipLaunchKernelGGL((k_pipe_iter<double, W_, true, false>), dim3(g.grid),
+                    else if (jac) hipLaunchKernelGGL((k_pipe_iter<double, W_, CI_, true, false>), dim3(g.grid),
                                                      dim3(kBlock), 0, s, a, n, g, st, part);
-                    else hipLaunchKernelGGL((k_pipe_iter<double, W_, false, false>), dim3(g.grid), dim3(kBlock), 0,
+                    else hipLaunchKernelGGL((k_pipe_iter<double, W_, CI_, false, false>), dim3(g.grid), dim3(kBlock), 0,
                                             s, a, n, g, st, part));
             });
         }
         if (rc) return rc;
     }
     FV_HIP(hipEventRecord(w.t_it1, s));
-    FV_WT_SWITCH(m->WT, hipLaunchKernelGGL(k_true_residual<W_>, dim3(g.grid), dim3(kBlock), 0, s, m->col, A->val,
+    FV_LAYOUT(m, hipLaunchKernelGGL((k_true_residual<W_, CI_>), dim3(g.grid), dim3(kBlock), 0, s, cols_, A->val,
                                            A->d, n, g, b, x, st, part));
     FV_LAUNCHED();
     FV_HIP(hipEventRecord(w.t_end, s));
@@ -860,7 +884,7 @@ int solve_mixed(const fvpcg_matrix* A, const double* b, double* x, double outer_
     int inner_total = 0, j = 0;
     float iter_ms = 0.f;
     for (j = 0;; ++j) {
-        FV_WT_SWITCH(m->WT, hipLaunchKernelGGL(k_mixed_residual<W_>, dim3(g.grid), dim3(kBlock), 0, s, m->col,
+        FV_LAYOUT(m, hipLaunchKernelGGL((k_mixed_residual<W_, CI_>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
                                                A->val, A->d, n, g, b, x, w.r, j, so, part));
         FV_LAUNCHED();
         if ((rc = state_read(w, 0, &h, s))) return rc;
@@ -874,20 +898,20 @@ int solve_mixed(const fvpcg_matrix* A, const double* b, double* x, double outer_
         FV_HIP(hipEventRecord(w.t_it0, s));
         hipLaunchKernelGGL(k_mixed_cast, dim3(g.grid), dim3(kBlock), 0, s, w.r, n, g, so, w.r32, w.r32b, w.c32, w.z32, w.s32,
                            w.p32, si, part);
-        FV_WT_SWITCH(m->WT, hipLaunchKernelGGL((k_pipe_init_w<float, W_, true>), dim3(g.grid), dim3(kBlock), 0, s,
-                                               m->col, A->val32_cs, A->d32, n, g, w.r32, w.w32[0], si, part));
+        FV_LAYOUT(m, hipLaunchKernelGGL((k_pipe_init_w<float, W_, CI_, true>), dim3(g.grid), dim3(kBlock), 0, s,
+                                               cols_, A->val32_cs, A->d32, n, g, w.r32, w.w32[0], si, part));
         FV_LAUNCHED();
         rc = iterate(w, 1, max_inner, s, [&](int it) {
-            PipeVec<float> a{m->col, A->val32_cs, A->d32, w.w32[it & 1], w.w32[(it + 1) & 1], w.z32, w.s32,
+            PipeVec<float> a{mesh_cols(m), A->val32_cs, A->d32, w.w32[it & 1], w.w32[(it + 1) & 1], w.z32, w.s32,
                              w.p32, w.c32, w.r32, nullptr, nullptr};
-            FV_WT_SWITCH(m->WT, hipLaunchKernelGGL((k_pipe_iter<float, W_, true, false>), dim3(g.grid), dim3(kBlock),
+            FV_LAYOUT(m, hipLaunchKernelGGL((k_pipe_iter<float, W_, CI_, true, false>), dim3(g.grid), dim3(kBlock),
                                                    0, s, a, n, g, si, part));
             if ((it + 1) % kReplaceEvery == 0) {
                 float* w_cur = w.w32[(it + 1) & 1];
-                FV_WT_SWITCH(m->WT,
-                             hipLaunchKernelGGL(k_replace_rs<W_>, dim3(g.grid), dim3(kBlock), 0, s, m->col, A->val32,
+                FV_LAYOUT(m,
+                             hipLaunchKernelGGL((k_replace_rs<W_, CI_>), dim3(g.grid), dim3(kBlock), 0, s, cols_, A->val32,
                                                 A->d32, n, g, w.r32b, w.c32, w.p32, w.r32, w.s32, si);
-                             hipLaunchKernelGGL(k_replace_wz<W_>, dim3(g.grid), dim3(kBlock), 0, s, m->col,
+                             hipLaunchKernelGGL((k_replace_wz<W_, CI_>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
                                                 A->val32_cs, A->d32, n, g, w.r32, w.s32, w_cur, w.z32, si, part));
             }
         });

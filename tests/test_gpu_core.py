@@ -343,3 +343,22 @@ def test_stream_calibrate(fv):
     say("calibrate")
     r = fv.stream_calibrate(256 << 20)
     assert r["copy_gbs"] > 500 and r["triad_gbs"] > 500
+
+
+def test_int16_and_int32_columns_agree_bitwise(fv, monkeypatch):
+    """The 16-bit column-offset layout (used when the bandwidth fits) and the
+    32-bit layout encode the same columns: identical results, bit for bit."""
+    say("int16 vs int32 columns")
+    case = fc.varcoef((20, 18, 16), seed=4)
+    out = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("FVPCG_COL16", flag)
+        dc = DevCase(case, fp32_copy=True)
+        x1, s1 = fv.solve(dc.A, dc.b, tol=1e-9, method="pipecg")
+        x2, s2 = fv.solve(dc.A, dc.b, tol=1e-9, method="cg")
+        x3, s3 = fv.solve_mixed(dc.A, dc.b)
+        y = fv.spmv(dc.A, dc.b)
+        out[flag] = [t.cpu().numpy() for t in (x1, x2, x3, y)] + [s1["iters"], s2["iters"], s3["iters"]]
+        dc.close()
+    for a, b in zip(out["1"], out["0"]):
+        assert np.array_equal(a, b)
