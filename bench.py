@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 METRIC = "CG iters/s + HBM GB/s at 7M cells; mixed/batched vs plain FP64 at 1e-8"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pipecg_fold_varcoef192_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1505_07630_amd", "csrc", f) for f in ("solve.hip", "common.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1505_07630_amd", "csrc", f) for f in ("solve.hip", "common.hpp", "setup.hip")]
 
 
 def log(*a):
@@ -46,9 +46,10 @@ def kernel_source_hash() -> str:
 
 
 def alg_bytes_pipecg_folded(n, F):
-    """Per iteration: matrix 24F (int32 column + FP64 value per off-diagonal
-    slot) + 13 FP64 vector passes 104n (reads w, z, s, p, x, r, d; writes
-    z, s, p, x, r, w')."""
+    """Per iteration: matrix 24F (an int32 column + an FP64 value per
+    off-diagonal entry, 2F entries) + 13 FP64 vector passes 104n (reads w, z,
+    s, p, x, r, d; writes z, s, p, x, r, w').  Fixed by the method, not by the
+    layout: the 16-bit column offsets move fewer bytes than this."""
     return 104 * n + 24 * F
 
 
@@ -86,7 +87,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--method", default="pipecg", choices=["pipecg", "cg", "pipecg_literal"])
     ap.add_argument("--roofline-iters", type=int, default=500)
-    ap.add_argument("--cpu-iters", type=int, default=30)
+    ap.add_argument("--cpu-iters", type=int, default=150)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time the other workloads")
     args = ap.parse_args()
@@ -155,8 +156,8 @@ def main():
         f"{stf['iters']} fixed iterations")
 
     traffic = measured_traffic(bpi)
-    kernel_name = {"pipecg": "k_pipe_iter<double, 6, JAC=true, LIT=false>",
-                   "pipecg_literal": "k_pipe_iter<double, 6, JAC=true, LIT=true>",
+    kernel_name = {"pipecg": "k_pipe_iter<512, double, 6, int16_t, JAC=true, LIT=false>",
+                   "pipecg_literal": "k_pipe_iter<512, double, 6, int16_t, JAC=true, LIT=true>",
                    "cg": "k_cg_spmv + k_cg_update_r + k_cg_update_xp"}[args.method]
     out = {
         "metric": METRIC,
@@ -186,9 +187,10 @@ def main():
             "avg_launch_us_fixed_iters": round(kern_fixed_s * 1e6, 2),
         },
         "stream_calibration_gbs": {"copy": round(calib["copy_gbs"], 1), "triad": round(calib["triad_gbs"], 1)},
+        "frac_of_stream_copy": round(achieved / calib["copy_gbs"], 4) if calib["copy_gbs"] > 0 else None,
     }
     if args.extras:
-        out["extras"] = extras(fv, torch, np, fvcases, dev)
+        out["extras"] = extras(fv, torch, np, fvcases, dev, case, mesh, b)
     if not args.no_cpu:
         log(f"oracle baseline: {args.cpu_iters} iterations on the CPU ...")
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_iters)
@@ -196,10 +198,52 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def extras(fv, torch, np, fvcases, dev):
+def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None):
     """Other workloads, for information (not the headline line)."""
     res = {}
     to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).to(dev)
+    if case is not None:
+        # mixed precision on the same 192^3 arrays: time to 1e-10 vs FP64
+        A32 = fv.Matrix(mesh, to(case.diag, torch.float64), to(case.upper, torch.float64), fp32_copy=True)
+        fv.solve_mixed(A32, b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xm, sm = fv.solve_mixed(A32, b, outer_tol=1e-10, inner_tol=1e-5)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        xr, sr = fv.solve(A32, b, tol=1e-10, maxit=50000, method="pipecg")
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        xc, _ = fv.solve(A32, b, tol=1e-12, maxit=50000, method="cg")
+        err = (torch.linalg.norm(xm - xc) / torch.linalg.norm(xc)).item()
+        res["varcoef192/mixed"] = {"status": sm["status_name"], "outer_iters": sm["outer_iters"],
+                                   "inner_fp32_iters": sm["iters"], "ms_to_1e-10": round(tm * 1e3, 1),
+                                   "fp64_pipecg_ms_to_1e-10": round(t64 * 1e3, 1), "fp64_iters": sr["iters"],
+                                   "true_rel_res": sm["true_rel_res"],
+                                   "rel_err_vs_fp64_cg_1e-12": err}
+        log(f"extra mixed: {res['varcoef192/mixed']}")
+        A32.close()
+    # batched: 256 systems, edges 16..64
+    bt = fvcases.make("batch256")
+    B = fv.Batch(bt.cell_off, bt.face_off, to(bt.owner, torch.int32), to(bt.neighbour, torch.int32),
+                 to(bt.diag, torch.float64), to(bt.upper, torch.float64))
+    bb = to(bt.b, torch.float64)
+    for method in ("cg", "pipecg"):
+        fv.solve_batched(B, bb, tol=1e-8, method=method)  # tunes and captures
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xb, sts, code = fv.solve_batched(B, bb, tol=1e-8, method=method)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        its = [s_["iters"] for s_ in sts]
+        byts = sum((104 * c.n + 24 * c.F) * k for c, k in zip(bt.cases, its))
+        res[f"batch256/{method}"] = {"status": code, "ms": round(tb * 1e3, 2), "system_iters": int(sum(its)),
+                                     "system_iters_per_s": round(sum(its) / tb, 1), "max_iters": max(its),
+                                     "effective_GBs": round(byts / tb / 1e9, 1),
+                                     "total_cells": int(bt.cell_off[-1])}
+        log(f"extra batched {method}: {res[f'batch256/{method}']}")
+    B.close()
     for name, method in (("laplace32", "pipecg"), ("laplace32", "cg"), ("cavity256", "cg")):
         c = fvcases.make(name)
         mesh = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))

@@ -43,7 +43,7 @@ struct BatchStat {
 };
 
 struct BatchArgs {
-    const int* col;
+    const void* col;  // int32 columns or int16 offsets (the kernel's CI)
     const double* val;     // plain values (residuals, standard CG, unpreconditioned)
     const double* val_cs;  // column-scaled values (Jacobi-folded pipelined)
     const double* d;
@@ -122,15 +122,19 @@ __device__ __forceinline__ void block_allreduce(double (&v)[NV]) {
     __syncthreads();
 }
 
-template <int WT>
-__device__ __forceinline__ double gather(const int* __restrict__ col, const double* __restrict__ val, int n, int c,
+__device__ __forceinline__ int slot_col(const int* p, size_t o, int) { return p[o]; }
+__device__ __forceinline__ int slot_col(const int16_t* p, size_t o, int c) { return c + (int)p[o]; }
+
+template <int WT, typename CI>
+__device__ __forceinline__ double gather(const void* colv, const double* __restrict__ val, int n, int c,
                                          const double* __restrict__ v, double acc) {
+    const CI* __restrict__ col = (const CI*)colv;
     int j[WT];
     double a[WT];
 #pragma unroll
     for (int k = 0; k < WT; ++k) {
         const size_t o = (size_t)k * n + c;
-        j[k] = col[o];
+        j[k] = slot_col(col, o, c);
         a[k] = val[o];
     }
 #pragma unroll
@@ -179,12 +183,12 @@ __device__ __forceinline__ void pipe_step(Sys& y, double gamma, double delta, do
 }
 
 // r = b - A x over [c0, c1) and (b, b); returns false (x zeroed) when b = 0.
-template <int BS, int WT>
+template <int BS, int WT, typename CI>
 __device__ bool sys_begin(const BatchArgs& a, int c0, int c1, Sys& y, double* zero0, double* zero1, double* zero2) {
     double acc[1] = {0.0};
     for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
         const double bc = a.b[c];
-        a.r[c] = bc - gather<WT>(a.col, a.val, a.n, c, a.x, a.d[c] * a.x[c]);
+        a.r[c] = bc - gather<WT, CI>(a.col, a.val, a.n, c, a.x, a.d[c] * a.x[c]);
         if (zero0) zero0[c] = 0.0;
         if (zero1) zero1[c] = 0.0;
         if (zero2) zero2[c] = 0.0;
@@ -202,12 +206,12 @@ __device__ bool sys_begin(const BatchArgs& a, int c0, int c1, Sys& y, double* ze
     return true;
 }
 
-template <int BS, int WT>
+template <int BS, int WT, typename CI>
 __device__ void sys_finish(const BatchArgs& a, int s, int c0, int c1, const Sys& y) {
     __syncthreads();
     double acc[1] = {0.0};
     for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
-        const double rc = a.b[c] - gather<WT>(a.col, a.val, a.n, c, a.x, a.d[c] * a.x[c]);
+        const double rc = a.b[c] - gather<WT, CI>(a.col, a.val, a.n, c, a.x, a.d[c] * a.x[c]);
         acc[0] += rc * rc;
     }
     block_allreduce<BS, 1>(acc);
@@ -223,17 +227,17 @@ __device__ void sys_finish(const BatchArgs& a, int s, int c0, int c1, const Sys&
     }
 }
 
-template <int BS, int WT, bool JAC>
+template <int BS, int WT, typename CI, bool JAC>
 __device__ void solve_pipe(const BatchArgs& a, int s) {
     const int c0 = a.cell_off[s], c1 = a.cell_off[s + 1];
     const double* val = JAC ? a.val_cs : a.val;
     Sys y;
-    if (sys_begin<BS, WT>(a, c0, c1, y, a.z, a.s, a.p)) {
+    if (sys_begin<BS, WT, CI>(a, c0, c1, y, a.z, a.s, a.p)) {
         __syncthreads();
         double acc[3] = {0.0, 0.0, 0.0};
         for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
             const double rc = a.r[c], dc = a.d[c];
-            const double wc = gather<WT>(a.col, val, a.n, c, a.r, JAC ? rc : dc * rc);
+            const double wc = gather<WT, CI>(a.col, val, a.n, c, a.r, JAC ? rc : dc * rc);
             a.w0[c] = wc;
             const double uc = JAC ? rc / dc : rc;
             acc[0] += rc * uc;
@@ -251,7 +255,7 @@ __device__ void solve_pipe(const BatchArgs& a, int s) {
             double t[3] = {0.0, 0.0, 0.0};
             for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
                 const double wc = w_in[c], dc = a.d[c];
-                const double nv = gather<WT>(a.col, val, a.n, c, w_in, JAC ? wc : dc * wc);
+                const double nv = gather<WT, CI>(a.col, val, a.n, c, w_in, JAC ? wc : dc * wc);
                 const double zc = nv + beta * a.z[c];
                 const double sc = wc + beta * a.s[c];
                 double rc = a.r[c];
@@ -275,14 +279,14 @@ __device__ void solve_pipe(const BatchArgs& a, int s) {
             ++it;
         }
     }
-    sys_finish<BS, WT>(a, s, c0, c1, y);
+    sys_finish<BS, WT, CI>(a, s, c0, c1, y);
 }
 
-template <int BS, int WT, bool JAC>
+template <int BS, int WT, typename CI, bool JAC>
 __device__ void solve_cg(const BatchArgs& a, int s) {
     const int c0 = a.cell_off[s], c1 = a.cell_off[s + 1];
     Sys y;
-    if (sys_begin<BS, WT>(a, c0, c1, y, nullptr, nullptr, nullptr)) {
+    if (sys_begin<BS, WT, CI>(a, c0, c1, y, nullptr, nullptr, nullptr)) {
         double acc[2] = {0.0, 0.0};
         for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
             const double rc = a.r[c];
@@ -305,7 +309,7 @@ __device__ void solve_cg(const BatchArgs& a, int s) {
             double t1[1] = {0.0};
             for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
                 const double pc = a.p[c];
-                const double qc = gather<WT>(a.col, a.val, a.n, c, a.p, a.d[c] * pc);
+                const double qc = gather<WT, CI>(a.col, a.val, a.n, c, a.p, a.d[c] * pc);
                 a.q[c] = qc;
                 t1[0] += pc * qc;
             }
@@ -348,11 +352,11 @@ __device__ void solve_cg(const BatchArgs& a, int s) {
             __syncthreads();
         }
     }
-    sys_finish<BS, WT>(a, s, c0, c1, y);
+    sys_finish<BS, WT, CI>(a, s, c0, c1, y);
 }
 
 // method: 0 standard CG, 1 pipelined CG
-template <int BS, int WT, bool JAC, int METHOD>
+template <int BS, int WT, typename CI, bool JAC, int METHOD>
 __global__ __launch_bounds__(BS) void k_batch(BatchArgs a) {
     __shared__ int s_next;
     for (;;) {
@@ -365,9 +369,9 @@ __global__ __launch_bounds__(BS) void k_batch(BatchArgs a) {
         __syncthreads();
         if (s < 0) return;
         if (METHOD == 1)
-            solve_pipe<BS, WT, JAC>(a, s);
+            solve_pipe<BS, WT, CI, JAC>(a, s);
         else
-            solve_cg<BS, WT, JAC>(a, s);
+            solve_cg<BS, WT, CI, JAC>(a, s);
         __syncthreads();
     }
 }
@@ -402,27 +406,32 @@ __global__ void k_offset_faces(const int* __restrict__ owner, const int* __restr
 
 typedef void (*BatchKernel)(BatchArgs);
 
-template <int BS, bool JAC, int METHOD>
+template <int BS, typename CI, bool JAC, int METHOD>
 BatchKernel pick_wt_kernel(int wt) {
     switch (wt) {
-        case 4: return k_batch<BS, 4, JAC, METHOD>;
-        case 6: return k_batch<BS, 6, JAC, METHOD>;
-        case 8: return k_batch<BS, 8, JAC, METHOD>;
-        case 16: return k_batch<BS, 16, JAC, METHOD>;
-        default: return k_batch<BS, 32, JAC, METHOD>;
+        case 4: return k_batch<BS, 4, CI, JAC, METHOD>;
+        case 6: return k_batch<BS, 6, CI, JAC, METHOD>;
+        case 8: return k_batch<BS, 8, CI, JAC, METHOD>;
+        case 16: return k_batch<BS, 16, CI, JAC, METHOD>;
+        default: return k_batch<BS, 32, CI, JAC, METHOD>;
     }
 }
 
-template <int BS>
-BatchKernel pick_kernel_bs(int wt, bool jac, int method) {
-    if (method == 1) return jac ? pick_wt_kernel<BS, true, 1>(wt) : pick_wt_kernel<BS, false, 1>(wt);
-    return jac ? pick_wt_kernel<BS, true, 0>(wt) : pick_wt_kernel<BS, false, 0>(wt);
+template <int BS, typename CI>
+BatchKernel pick_kernel_ci(int wt, bool jac, int method) {
+    if (method == 1) return jac ? pick_wt_kernel<BS, CI, true, 1>(wt) : pick_wt_kernel<BS, CI, false, 1>(wt);
+    return jac ? pick_wt_kernel<BS, CI, true, 0>(wt) : pick_wt_kernel<BS, CI, false, 0>(wt);
 }
 
-BatchKernel pick_kernel(int bs, int wt, bool jac, int method) {
-    if (bs == 1024) return pick_kernel_bs<1024>(wt, jac, method);
-    if (bs == 512) return pick_kernel_bs<512>(wt, jac, method);
-    return pick_kernel_bs<256>(wt, jac, method);
+template <int BS>
+BatchKernel pick_kernel_bs(int wt, bool col16, bool jac, int method) {
+    return col16 ? pick_kernel_ci<BS, int16_t>(wt, jac, method) : pick_kernel_ci<BS, int>(wt, jac, method);
+}
+
+BatchKernel pick_kernel(int bs, int wt, bool col16, bool jac, int method) {
+    if (bs == 1024) return pick_kernel_bs<1024>(wt, col16, jac, method);
+    if (bs == 512) return pick_kernel_bs<512>(wt, col16, jac, method);
+    return pick_kernel_bs<256>(wt, col16, jac, method);
 }
 
 int device_cus(int* cus) {
@@ -445,7 +454,7 @@ int grid_for(const fvpcg_batch* bt, const Tuning& t, BatchKernel k, int* grid) {
 BatchArgs make_args(const fvpcg_batch* bt, const double* b, double* x, double tol, int maxit) {
     const fvpcg_matrix* A = bt->mat;
     BatchArgs a;
-    a.col = bt->mesh->col;
+    a.col = bt->mesh->col16 ? (const void*)bt->mesh->col16 : (const void*)bt->mesh->col;
     a.val = A->val;
     a.val_cs = A->val_cs;
     a.d = A->d;
@@ -471,7 +480,7 @@ BatchArgs make_args(const fvpcg_batch* bt, const double* b, double* x, double to
 
 // Enqueue one batched solve directly (used while tuning).
 int launch_direct(const fvpcg_batch* bt, const Tuning& t, const BatchArgs& a, bool jac, int method, hipStream_t s) {
-    BatchKernel k = pick_kernel(t.block, bt->mesh->WT, jac, method);
+    BatchKernel k = pick_kernel(t.block, bt->mesh->WT, bt->mesh->col16 != nullptr, jac, method);
     int grid = 1, rc;
     if ((rc = grid_for(bt, t, k, &grid))) return rc;
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, bt->d_queue);

@@ -20,7 +20,7 @@ namespace fvpcg {
 constexpr int kBlock = FVPCG_BLOCK;   // threads per workgroup (wave64s)
 constexpr int kWaves = kBlock / 64;
 #ifndef FVPCG_MAX_GRID
-#define FVPCG_MAX_GRID 1024
+#define FVPCG_MAX_GRID 256
 #endif
 constexpr int kMaxGrid = FVPCG_MAX_GRID;  // row-parallel workgroups per launch
 constexpr int kMaxChunk = 64;         // iterations enqueued between convergence checks
@@ -139,10 +139,11 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sum NV values over the workgroup; the result is valid in thread 0.
-template <int NV>
+// Sum NV values over a workgroup of BS threads; the result is valid in thread 0.
+template <int BS, int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV]) {
-    __shared__ double lds[NV][kWaves];
+    constexpr int kW = BS / 64;
+    __shared__ double lds[NV][kW];
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -156,7 +157,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
         for (int k = 0; k < NV; ++k) {
             double s = 0.0;
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) s += lds[k][w];
+            for (int w = 0; w < kW; ++w) s += lds[k][w];
             v[k] = s;
         }
     }
@@ -167,11 +168,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
 // partial sums (layout [NV][G]) and takes a ticket; the workgroup that draws
 // the last ticket sums all partials in a fixed order and returns true with
 // the totals in thread 0's `tot`.  Deterministic for a given G.
-template <int NV>
+template <int BS, int NV>
 __device__ __forceinline__ bool device_reduce(double (&v)[NV], double* partials, uint32_t* ticket, int blk,
                                               int G, double (&tot)[NV]) {
     __shared__ int s_last;
-    block_sum<NV>(v);
+    block_sum<BS, NV>(v);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < NV; ++k)
@@ -185,12 +186,12 @@ __device__ __forceinline__ bool device_reduce(double (&v)[NV], double* partials,
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    for (int i = threadIdx.x; i < G; i += kBlock) {
+    for (int i = threadIdx.x; i < G; i += BS) {
 #pragma unroll
         for (int k = 0; k < NV; ++k)
             acc[k] += __hip_atomic_load(&partials[(size_t)k * G + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    block_sum<NV>(acc);
+    block_sum<BS, NV>(acc);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) tot[k] = acc[k];
@@ -225,12 +226,13 @@ __device__ __forceinline__ void st_once(T* p, T v) {
 #endif
 }
 
-// Tiles of kBlock rows handled by workgroup b (see FV_ROWS).
+// Tiles of BS rows handled by workgroup b (see FV_ROWS).
 struct TileRange {
     int first, end, step;
 };
+template <int BS>
 __device__ __forceinline__ TileRange xcd_tiles(int b, int G, int n) {
-    const int T = (n + kBlock - 1) / kBlock;
+    const int T = (n + BS - 1) / BS;
     const int x = b & 7, j = b >> 3;
     const int gx = (G >> 3) + (x < (G & 7) ? 1 : 0);
     const int t0 = x * (T >> 3) + (x < (T & 7) ? x : (T & 7));

@@ -43,41 +43,30 @@ __device__ __forceinline__ T row_gather(const CI* __restrict__ col, const T* __r
     return acc;
 }
 
-#ifndef FVPCG_TILING
-#define FVPCG_TILING 1
-#endif
-
-#if FVPCG_TILING == 0
-// Contiguous chunk of g.rows rows per (XCD-remapped) workgroup.
-#define FV_ROWS(blk)                                                     \
-    const int blk = xcd_block(blockIdx.x, g.grid);                      \
-    const RowRange rr_ = rows_of(blk, g.rows, n);                       \
-    for (int c = rr_.begin + (int)threadIdx.x; c < rr_.end; c += kBlock)
-#else
-// Tiles of kBlock rows.  XCD x (workgroups b with b % 8 == x) owns a
-// contiguous range of tiles; its Gx workgroups take tiles t0 + j, t0 + j + Gx,
-// ... so the workgroups resident on one XCD always work on a compact window
-// of rows and the neighbour columns they gather stay in that XCD's L2.
+// Tiles of BS rows (BS = the kernel's workgroup size).  XCD x (workgroups b
+// with b % 8 == x) owns a contiguous range of tiles; its Gx workgroups take
+// tiles t0 + j, t0 + j + Gx, ... so the workgroups resident on one XCD always
+// work on a compact window of rows and the neighbour columns they gather stay
+// in that XCD's L2.
 #define FV_ROWS(blk)                                                          \
     const int blk = (int)blockIdx.x;                                         \
-    const TileRange tr_ = xcd_tiles(blk, g.grid, n);                         \
+    const TileRange tr_ = xcd_tiles<BS>(blk, g.grid, n);                     \
     for (int t_ = tr_.first; t_ < tr_.end; t_ += tr_.step)                   \
-        for (int c = t_ * kBlock + (int)threadIdx.x; c < n && c < (t_ + 1) * kBlock; c += n)
-#endif
+        for (int c = t_ * BS + (int)threadIdx.x; c < n && c < (t_ + 1) * BS; c += n)
 
 // ===========================================================================
 // y = A v
 
-template <int WT, typename CI>
-__global__ __launch_bounds__(kBlock) void k_spmv(const CI* __restrict__ col, const double* __restrict__ val,
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_spmv(const CI* __restrict__ col, const double* __restrict__ val,
                                                  const double* __restrict__ d, int n, Geom g,
                                                  const double* __restrict__ v, double* __restrict__ y) {
     FV_ROWS(blk) { y[c] = row_gather<double, WT, CI>(col, val, n, c, v, d[c] * v[c]); }
 }
 
 // ||b - A x||^2 into st->true_rr (the true residual reported at exit).
-template <int WT, typename CI>
-__global__ __launch_bounds__(kBlock) void k_true_residual(const CI* __restrict__ col, const double* __restrict__ val,
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_true_residual(const CI* __restrict__ col, const double* __restrict__ val,
                                                           const double* __restrict__ d, int n, Geom g,
                                                           const double* __restrict__ b, const double* __restrict__ x,
                                                           DevState* st, double* partials) {
@@ -87,15 +76,15 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(const CI* __restrict__
         acc[0] += r * r;
     }
     double tot[1];
-    if (device_reduce<1>(acc, partials, &st->ticket, blk, g.grid, tot) && threadIdx.x == 0) st->true_rr = tot[0];
+    if (device_reduce<BS, 1>(acc, partials, &st->ticket, blk, g.grid, tot) && threadIdx.x == 0) st->true_rr = tot[0];
 }
 
 // ===========================================================================
 // Standard preconditioned CG
 
 // r = b - A x, z = M^-1 r, p = z; gamma = (r,z), rho = (r,r), (b,b).
-template <int WT, typename CI, bool JAC>
-__global__ __launch_bounds__(kBlock) void k_cg_init(const CI* __restrict__ col, const double* __restrict__ val,
+template <int BS, int WT, typename CI, bool JAC>
+__global__ __launch_bounds__(BS) void k_cg_init(const CI* __restrict__ col, const double* __restrict__ val,
                                                     const double* __restrict__ d, int n, Geom g,
                                                     const double* __restrict__ b, const double* __restrict__ x,
                                                     double* __restrict__ r, double* __restrict__ p, DevState* st,
@@ -113,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const CI* __restrict__ col, 
         acc[2] += bc * bc;
     }
     double t[3];
-    if (device_reduce<3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+    if (device_reduce<BS, 3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
         const double bb = t[2];
         st->iter = 0;
         st->bnorm = sqrt(bb);
@@ -139,8 +128,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const CI* __restrict__ col, 
 }
 
 // q = A p; delta = (p, q); alpha = gamma / delta.
-template <int WT, typename CI>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(const CI* __restrict__ col, const double* __restrict__ val,
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_cg_spmv(const CI* __restrict__ col, const double* __restrict__ val,
                                                     const double* __restrict__ d, int n, Geom g,
                                                     const double* __restrict__ p, double* __restrict__ q, DevState* st,
                                                     double* partials) {
@@ -153,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const CI* __restrict__ col, 
         acc[0] += pc * qc;
     }
     double t[1];
-    if (device_reduce<1>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+    if (device_reduce<BS, 1>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
         const double delta = t[0];
         st->delta = delta;
         if (!(delta > 0.0) || !isfinite(delta) || !isfinite(st->gamma)) {
@@ -167,8 +156,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const CI* __restrict__ col, 
 
 // r -= alpha q; z = M^-1 r; gamma' = (r, z), rho = (r, r); stopping test;
 // beta = gamma' / gamma.
-template <bool JAC>
-__global__ __launch_bounds__(kBlock) void k_cg_update_r(double* __restrict__ r, const double* __restrict__ q,
+template <int BS, bool JAC>
+__global__ __launch_bounds__(BS) void k_cg_update_r(double* __restrict__ r, const double* __restrict__ q,
                                                         const double* __restrict__ d, int n, Geom g, DevState* st,
                                                         double* partials) {
     if (st->done) return;
@@ -182,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_r(double* __restrict__ r, 
         acc[1] += rc * rc;
     }
     double t[2];
-    if (device_reduce<2>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+    if (device_reduce<BS, 2>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
         const int it = st->iter + 1;
         st->iter = it;
         st->rho = t[1];
@@ -200,8 +189,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_r(double* __restrict__ r, 
 }
 
 // x += alpha p (if iteration `it` updated r); p = z + beta p unless done.
-template <bool JAC>
-__global__ __launch_bounds__(kBlock) void k_cg_update_xp(double* __restrict__ x, double* __restrict__ p,
+template <int BS, bool JAC>
+__global__ __launch_bounds__(BS) void k_cg_update_xp(double* __restrict__ x, double* __restrict__ p,
                                                          const double* __restrict__ r, const double* __restrict__ d,
                                                          int n, Geom g, int it, const DevState* st) {
     if (st->iter != it + 1) return;
@@ -289,8 +278,8 @@ __device__ __forceinline__ void pipe_scalars(DevState* st, double gamma, double 
 
 // r = b - A x; (b, b) -> bnorm and the absolute tolerance; clears the
 // pipelined recurrences (z, s, p[, q]) and sets u = M^-1 r (literal).
-template <int WT, typename CI, bool JAC, bool LIT>
-__global__ __launch_bounds__(kBlock) void k_pipe_init_r(const CI* __restrict__ col, const double* __restrict__ val,
+template <int BS, int WT, typename CI, bool JAC, bool LIT>
+__global__ __launch_bounds__(BS) void k_pipe_init_r(const CI* __restrict__ col, const double* __restrict__ val,
                                                         const double* __restrict__ d, int n, Geom g,
                                                         const double* __restrict__ b, const double* __restrict__ x,
                                                         double* __restrict__ r, double* __restrict__ z,
@@ -313,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_init_r(const CI* __restrict__ c
         acc[0] += bc * bc;
     }
     double t[1];
-    if (device_reduce<1>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+    if (device_reduce<BS, 1>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
         st->iter = 0;
         st->bnorm = sqrt(t[0]);
         st->tol_abs *= st->bnorm;
@@ -326,8 +315,8 @@ __global__ __launch_bounds__(kBlock) void k_pipe_init_r(const CI* __restrict__ c
 }
 
 // w0 = A M^-1 r0 and the first reduction (gamma_0, delta_0, rho_0).
-template <typename T, int WT, typename CI, bool JAC>
-__global__ __launch_bounds__(kBlock) void k_pipe_init_w(const CI* __restrict__ col, const T* __restrict__ val,
+template <int BS, typename T, int WT, typename CI, bool JAC>
+__global__ __launch_bounds__(BS) void k_pipe_init_w(const CI* __restrict__ col, const T* __restrict__ val,
                                                         const T* __restrict__ d, int n, Geom g,
                                                         const T* __restrict__ r, T* __restrict__ w, DevState* st,
                                                         double* partials) {
@@ -344,12 +333,12 @@ __global__ __launch_bounds__(kBlock) void k_pipe_init_w(const CI* __restrict__ c
         acc[2] += (double)rc * (double)rc;
     }
     double t[3];
-    if (device_reduce<3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0)
+    if (device_reduce<BS, 3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0)
         pipe_scalars(st, t[0], t[1], t[2], true);
 }
 
-template <typename T, int WT, typename CI, bool JAC, bool LIT>
-__global__ __launch_bounds__(kBlock) void k_pipe_iter(PipeVec<T> a, int n, Geom g, DevState* st, double* partials) {
+template <int BS, typename T, int WT, typename CI, bool JAC, bool LIT>
+__global__ __launch_bounds__(BS) void k_pipe_iter(PipeVec<T> a, int n, Geom g, DevState* st, double* partials) {
     if (st->done) return;
     const T alpha = (T)st->alpha, beta = (T)st->beta;
     double acc[3] = {0.0, 0.0, 0.0};
@@ -389,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_pipe_iter(PipeVec<T> a, int n, Geom 
         acc[2] += (double)rc * (double)rc;
     }
     double t[3];
-    if (device_reduce<3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0)
+    if (device_reduce<BS, 3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0)
         pipe_scalars(st, t[0], t[1], t[2], false);
 }
 
@@ -402,8 +391,8 @@ __global__ __launch_bounds__(kBlock) void k_pipe_iter(PipeVec<T> a, int n, Geom 
 // the previous iteration's gamma and alpha.  The inner solve ends once
 // kStagnationChecks replacements in a row bring no new minimum of ||r||.
 
-template <int WT, typename CI>
-__global__ __launch_bounds__(kBlock) void k_replace_rs(const CI* __restrict__ col, const float* __restrict__ val,
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_replace_rs(const CI* __restrict__ col, const float* __restrict__ val,
                                                        const float* __restrict__ d, int n, Geom g,
                                                        const float* __restrict__ b, const float* __restrict__ x,
                                                        const float* __restrict__ p, float* __restrict__ r,
@@ -416,8 +405,8 @@ __global__ __launch_bounds__(kBlock) void k_replace_rs(const CI* __restrict__ co
     }
 }
 
-template <int WT, typename CI>
-__global__ __launch_bounds__(kBlock) void k_replace_wz(const CI* __restrict__ col, const float* __restrict__ val_cs,
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_replace_wz(const CI* __restrict__ col, const float* __restrict__ val_cs,
                                                        const float* __restrict__ d, int n, Geom g,
                                                        const float* __restrict__ r, const float* __restrict__ s,
                                                        float* __restrict__ w, float* __restrict__ z, DevState* st,
@@ -435,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_replace_wz(const CI* __restrict__ co
         acc[2] += (double)rc * (double)rc;
     }
     double t[3];
-    if (device_reduce<3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+    if (device_reduce<BS, 3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
         const double gamma = t[0], delta = t[1], rho = t[2];
         st->rho = rho;
         if (rho < st->best) {
@@ -471,8 +460,8 @@ __global__ __launch_bounds__(kBlock) void k_replace_wz(const CI* __restrict__ co
 // FP64 correction.
 
 // r = b - A x (FP64); outer stopping test on ||r||.  `j` = corrections so far.
-template <int WT, typename CI>
-__global__ __launch_bounds__(kBlock) void k_mixed_residual(const CI* __restrict__ col,
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_mixed_residual(const CI* __restrict__ col,
                                                            const double* __restrict__ val,
                                                            const double* __restrict__ d, int n, Geom g,
                                                            const double* __restrict__ b, const double* __restrict__ x,
@@ -487,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_mixed_residual(const CI* __restrict_
         acc[1] += bc * bc;
     }
     double t[2];
-    if (device_reduce<2>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+    if (device_reduce<BS, 2>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
         st->iter = j;
         const double rn = sqrt(t[0]);
         const double prev = st->scale;
@@ -525,7 +514,8 @@ __global__ __launch_bounds__(kBlock) void k_mixed_residual(const CI* __restrict_
 
 // r32 = fp32(r / ||r||), c = 0, recurrences cleared; inner ||rhs|| and
 // inner absolute tolerance.
-__global__ __launch_bounds__(kBlock) void k_mixed_cast(const double* __restrict__ r, int n, Geom g,
+template <int BS>
+__global__ __launch_bounds__(BS) void k_mixed_cast(const double* __restrict__ r, int n, Geom g,
                                                        const DevState* st_out, float* __restrict__ r32,
                                                        float* __restrict__ b32, float* __restrict__ c32, float* __restrict__ z32,
                                                        float* __restrict__ s32, float* __restrict__ p32,
@@ -543,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_mixed_cast(const double* __restrict_
         acc[0] += (double)v * (double)v;
     }
     double t[1];
-    if (device_reduce<1>(acc, partials, &st_in->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+    if (device_reduce<BS, 1>(acc, partials, &st_in->ticket, blk, g.grid, t) && threadIdx.x == 0) {
         st_in->iter = 0;
         st_in->bnorm = sqrt(t[0]);
         st_in->tol_abs *= st_in->bnorm;
@@ -551,7 +541,8 @@ __global__ __launch_bounds__(kBlock) void k_mixed_cast(const double* __restrict_
 }
 
 // x += ||r|| c; with `undo`, x -= ||r_prev|| c takes the last correction back.
-__global__ __launch_bounds__(kBlock) void k_mixed_correct(double* __restrict__ x, const float* __restrict__ c32, int n,
+template <int BS>
+__global__ __launch_bounds__(BS) void k_mixed_correct(double* __restrict__ x, const float* __restrict__ c32, int n,
                                                           Geom g, const DevState* st_out, int undo) {
     const double sc = undo ? -st_out->scale_prev : st_out->scale;
     FV_ROWS(blk) { x[c] += sc * (double)c32[c]; }
@@ -616,12 +607,38 @@ inline const void* mesh_cols(const fvpcg_mesh* m) {
     return m->col16 ? (const void*)m->col16 : (const void*)m->col;
 }
 
+// Workgroup size per solver (measured on MI355X at 7.08M cells: the fused
+// pipelined iteration is fastest with 512-thread workgroups, the standard-CG
+// and FP32 kernels with 1024) and the workgroup count (one per CU: each
+// workgroup streams long runs of every array; more concurrent workgroups only
+// add concurrent HBM streams).
+#ifndef FVPCG_BS_PIPE
+#define FVPCG_BS_PIPE 512
+#endif
+#ifndef FVPCG_BS_CG
+#define FVPCG_BS_CG 1024
+#endif
+#ifndef FVPCG_BS_MIXED
+#define FVPCG_BS_MIXED 1024
+#endif
+#ifndef FVPCG_BS_MISC
+#define FVPCG_BS_MISC 512
+#endif
+constexpr int kBsPipe = FVPCG_BS_PIPE, kBsCg = FVPCG_BS_CG, kBsMixed = FVPCG_BS_MIXED, kBsMisc = FVPCG_BS_MISC;
+
+inline Geom geom_for(int n, int bs) {
+    if (n < 1) n = 1;
+    int g = (n + bs - 1) / bs;
+    if (g > kMaxGrid) g = kMaxGrid;
+    return {g, bs};
+}
+
 int work_init(Work& w, int n) {
     if (w.st) return FVPCG_OK;
     w.n = n;
     w.geom = make_geom(n);
     int rc;
-    if ((rc = dev_alloc(&w.partials, (size_t)4 * w.geom.grid, "reduction partials"))) return rc;
+    if ((rc = dev_alloc(&w.partials, (size_t)4 * kMaxGrid, "reduction partials"))) return rc;
     if ((rc = dev_alloc(&w.st, 2, "solver state"))) return rc;
     FV_HIP(hipMemset(w.st, 0, 2 * sizeof(DevState)));
     hipError_t e = hipHostMalloc((void**)&w.hst, 4 * sizeof(DevState), hipHostMallocDefault);
@@ -757,9 +774,9 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 
 int spmv(const fvpcg_matrix* A, const double* v, double* y, hipStream_t s) {
     const fvpcg_mesh* m = A->mesh;
-    const Geom g = m->geom;
-    FV_LAYOUT(m, hipLaunchKernelGGL((k_spmv<W_, CI_>), dim3(g.grid), dim3(kBlock), 0, s, cols_, A->val, A->d, m->n,
-                                           g, v, y));
+    const Geom gm = geom_for(m->n, kBsMisc);
+    FV_LAYOUT(m, hipLaunchKernelGGL((k_spmv<kBsMisc, W_, CI_>), dim3(gm.grid), dim3(kBsMisc), 0, s, cols_, A->val, A->d, m->n,
+                                           gm, v, y));
     FV_LAUNCHED();
     return FVPCG_OK;
 }
@@ -772,7 +789,9 @@ int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int max
     Work& w = *A->work;
     int rc;
     if ((rc = work_init(w, n))) return rc;
-    const Geom g = w.geom;
+    const Geom gm = geom_for(n, kBsMisc), gc = geom_for(n, kBsCg), gp = geom_for(n, kBsPipe),
+               gx = geom_for(n, kBsMixed);
+    (void)gc; (void)gp; (void)gx; (void)gm;
     if (method == FVPCG_PIPECG_LITERAL && !jac) method = FVPCG_PIPECG;  // identical recurrences when M = I
     if (method == FVPCG_CG) {
         if ((rc = work_need_cg(w))) return rc;
@@ -786,26 +805,26 @@ int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int max
 
     if (method == FVPCG_CG) {
         FV_LAYOUT(m,
-                     if (jac) hipLaunchKernelGGL((k_cg_init<W_, CI_, true>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
-                                                 A->val, A->d, n, g, b, x, w.r, w.p, st, part);
-                     else hipLaunchKernelGGL((k_cg_init<W_, CI_, false>), dim3(g.grid), dim3(kBlock), 0, s, cols_, A->val,
-                                             A->d, n, g, b, x, w.r, w.p, st, part));
+                     if (jac) hipLaunchKernelGGL((k_cg_init<kBsCg, W_, CI_, true>), dim3(gc.grid), dim3(kBsCg), 0, s, cols_,
+                                                 A->val, A->d, n, gc, b, x, w.r, w.p, st, part);
+                     else hipLaunchKernelGGL((k_cg_init<kBsCg, W_, CI_, false>), dim3(gc.grid), dim3(kBsCg), 0, s, cols_, A->val,
+                                             A->d, n, gc, b, x, w.r, w.p, st, part));
     } else {
         const bool lit = method == FVPCG_PIPECG_LITERAL;
         FV_LAYOUT(
             m,
-            if (jac && lit) hipLaunchKernelGGL((k_pipe_init_r<W_, CI_, true, true>), dim3(g.grid), dim3(kBlock), 0, s,
-                                               cols_, A->val, A->d, n, g, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st,
+            if (jac && lit) hipLaunchKernelGGL((k_pipe_init_r<kBsPipe, W_, CI_, true, true>), dim3(gp.grid), dim3(kBsPipe), 0, s,
+                                               cols_, A->val, A->d, n, gp, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st,
                                                part);
-            else if (jac) hipLaunchKernelGGL((k_pipe_init_r<W_, CI_, true, false>), dim3(g.grid), dim3(kBlock), 0, s,
-                                             cols_, A->val, A->d, n, g, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st,
+            else if (jac) hipLaunchKernelGGL((k_pipe_init_r<kBsPipe, W_, CI_, true, false>), dim3(gp.grid), dim3(kBsPipe), 0, s,
+                                             cols_, A->val, A->d, n, gp, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st,
                                              part);
-            else hipLaunchKernelGGL((k_pipe_init_r<W_, CI_, false, false>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
-                                    A->val, A->d, n, g, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st, part);
-            if (jac) hipLaunchKernelGGL((k_pipe_init_w<double, W_, CI_, true>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
-                                        A->val_cs, A->d, n, g, w.r, w.w[0], st, part);
-            else hipLaunchKernelGGL((k_pipe_init_w<double, W_, CI_, false>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
-                                    A->val, A->d, n, g, w.r, w.w[0], st, part));
+            else hipLaunchKernelGGL((k_pipe_init_r<kBsPipe, W_, CI_, false, false>), dim3(gp.grid), dim3(kBsPipe), 0, s, cols_,
+                                    A->val, A->d, n, gp, b, x, w.r, w.z, w.s, w.p, w.u, w.qq, st, part);
+            if (jac) hipLaunchKernelGGL((k_pipe_init_w<kBsPipe, double, W_, CI_, true>), dim3(gp.grid), dim3(kBsPipe), 0, s, cols_,
+                                        A->val_cs, A->d, n, gp, w.r, w.w[0], st, part);
+            else hipLaunchKernelGGL((k_pipe_init_w<kBsPipe, double, W_, CI_, false>), dim3(gp.grid), dim3(kBsPipe), 0, s, cols_,
+                                    A->val, A->d, n, gp, w.r, w.w[0], st, part));
     }
     FV_LAUNCHED();
     DevState h;
@@ -816,18 +835,18 @@ int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int max
     } else if (!h.done) {
         if (method == FVPCG_CG) {
             rc = iterate(w, 0, maxit, s, [&](int it) {
-                FV_LAYOUT(m, hipLaunchKernelGGL((k_cg_spmv<W_, CI_>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
-                                                       A->val, A->d, n, g, w.p, w.q, st, part));
+                FV_LAYOUT(m, hipLaunchKernelGGL((k_cg_spmv<kBsCg, W_, CI_>), dim3(gc.grid), dim3(kBsCg), 0, s, cols_,
+                                                       A->val, A->d, n, gc, w.p, w.q, st, part));
                 if (jac) {
-                    hipLaunchKernelGGL((k_cg_update_r<true>), dim3(g.grid), dim3(kBlock), 0, s, w.r, w.q, A->d, n, g,
+                    hipLaunchKernelGGL((k_cg_update_r<kBsCg, true>), dim3(gc.grid), dim3(kBsCg), 0, s, w.r, w.q, A->d, n, gc,
                                        st, part);
-                    hipLaunchKernelGGL((k_cg_update_xp<true>), dim3(g.grid), dim3(kBlock), 0, s, x, w.p, w.r, A->d, n,
-                                       g, it, st);
+                    hipLaunchKernelGGL((k_cg_update_xp<kBsCg, true>), dim3(gc.grid), dim3(kBsCg), 0, s, x, w.p, w.r, A->d, n,
+                                       gc, it, st);
                 } else {
-                    hipLaunchKernelGGL((k_cg_update_r<false>), dim3(g.grid), dim3(kBlock), 0, s, w.r, w.q, A->d, n, g,
+                    hipLaunchKernelGGL((k_cg_update_r<kBsCg, false>), dim3(gc.grid), dim3(kBsCg), 0, s, w.r, w.q, A->d, n, gc,
                                        st, part);
-                    hipLaunchKernelGGL((k_cg_update_xp<false>), dim3(g.grid), dim3(kBlock), 0, s, x, w.p, w.r, A->d, n,
-                                       g, it, st);
+                    hipLaunchKernelGGL((k_cg_update_xp<kBsCg, false>), dim3(gc.grid), dim3(kBsCg), 0, s, x, w.p, w.r, A->d, n,
+                                       gc, it, st);
                 }
             });
         } else {
@@ -837,19 +856,19 @@ int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int max
                                   w.s, w.p, x, w.r, w.u, w.qq};
                 FV_LAYOUT(
                     m,
-                    if (jac && lit) hipLaunchKernelGGL((k_pipe_iter<double, W_, CI_, true, true>), dim3(g.grid),
-                                                       dim3(kBlock), 0, s, a, n, g, st, part);
-                    else if (jac) hipLaunchKernelGGL((k_pipe_iter<double, W_, CI_, true, false>), dim3(g.grid),
-                                                     dim3(kBlock), 0, s, a, n, g, st, part);
-                    else hipLaunchKernelGGL((k_pipe_iter<double, W_, CI_, false, false>), dim3(g.grid), dim3(kBlock), 0,
-                                            s, a, n, g, st, part));
+                    if (jac && lit) hipLaunchKernelGGL((k_pipe_iter<kBsPipe, double, W_, CI_, true, true>), dim3(gp.grid),
+                                                       dim3(kBsPipe), 0, s, a, n, gp, st, part);
+                    else if (jac) hipLaunchKernelGGL((k_pipe_iter<kBsPipe, double, W_, CI_, true, false>), dim3(gp.grid),
+                                                       dim3(kBsPipe), 0, s, a, n, gp, st, part);
+                    else hipLaunchKernelGGL((k_pipe_iter<kBsPipe, double, W_, CI_, false, false>), dim3(gp.grid), dim3(kBsPipe), 0,
+                                            s, a, n, gp, st, part));
             });
         }
         if (rc) return rc;
     }
     FV_HIP(hipEventRecord(w.t_it1, s));
-    FV_LAYOUT(m, hipLaunchKernelGGL((k_true_residual<W_, CI_>), dim3(g.grid), dim3(kBlock), 0, s, cols_, A->val,
-                                           A->d, n, g, b, x, st, part));
+    FV_LAYOUT(m, hipLaunchKernelGGL((k_true_residual<kBsMisc, W_, CI_>), dim3(gm.grid), dim3(kBsMisc), 0, s, cols_, A->val,
+                                           A->d, n, gm, b, x, st, part));
     FV_LAUNCHED();
     FV_HIP(hipEventRecord(w.t_end, s));
     if ((rc = state_read(w, 0, &h, s))) return rc;
@@ -874,7 +893,9 @@ int solve_mixed(const fvpcg_matrix* A, const double* b, double* x, double outer_
     Work& w = *A->work;
     int rc;
     if ((rc = work_init(w, n)) || (rc = work_need_mixed(w))) return rc;
-    const Geom g = w.geom;
+    const Geom gm = geom_for(n, kBsMisc), gc = geom_for(n, kBsCg), gp = geom_for(n, kBsPipe),
+               gx = geom_for(n, kBsMixed);
+    (void)gc; (void)gp; (void)gx; (void)gm;
     FV_HIP(hipEventRecord(w.t_begin, s));
     if ((rc = state_reset(w, 0, outer_tol, max_outer, s))) return rc;
     DevState* so = &w.st[0];
@@ -884,39 +905,39 @@ int solve_mixed(const fvpcg_matrix* A, const double* b, double* x, double outer_
     int inner_total = 0, j = 0;
     float iter_ms = 0.f;
     for (j = 0;; ++j) {
-        FV_LAYOUT(m, hipLaunchKernelGGL((k_mixed_residual<W_, CI_>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
-                                               A->val, A->d, n, g, b, x, w.r, j, so, part));
+        FV_LAYOUT(m, hipLaunchKernelGGL((k_mixed_residual<kBsMixed, W_, CI_>), dim3(gx.grid), dim3(kBsMixed), 0, s, cols_,
+                                               A->val, A->d, n, gx, b, x, w.r, j, so, part));
         FV_LAUNCHED();
         if ((rc = state_read(w, 0, &h, s))) return rc;
         if (h.undo) {
-            hipLaunchKernelGGL(k_mixed_correct, dim3(g.grid), dim3(kBlock), 0, s, x, w.c32, n, g, so, 1);
+            hipLaunchKernelGGL((k_mixed_correct<kBsMixed>), dim3(gx.grid), dim3(kBsMixed), 0, s, x, w.c32, n, gx, so, 1);
             FV_LAUNCHED();
             h.scale = h.scale_prev;
         }
         if (h.done) break;
         if ((rc = state_reset(w, 1, inner_tol, max_inner, s))) return rc;
         FV_HIP(hipEventRecord(w.t_it0, s));
-        hipLaunchKernelGGL(k_mixed_cast, dim3(g.grid), dim3(kBlock), 0, s, w.r, n, g, so, w.r32, w.r32b, w.c32, w.z32, w.s32,
+        hipLaunchKernelGGL((k_mixed_cast<kBsMixed>), dim3(gx.grid), dim3(kBsMixed), 0, s, w.r, n, gx, so, w.r32, w.r32b, w.c32, w.z32, w.s32,
                            w.p32, si, part);
-        FV_LAYOUT(m, hipLaunchKernelGGL((k_pipe_init_w<float, W_, CI_, true>), dim3(g.grid), dim3(kBlock), 0, s,
-                                               cols_, A->val32_cs, A->d32, n, g, w.r32, w.w32[0], si, part));
+        FV_LAYOUT(m, hipLaunchKernelGGL((k_pipe_init_w<kBsMixed, float, W_, CI_, true>), dim3(gx.grid), dim3(kBsMixed), 0, s,
+                                               cols_, A->val32_cs, A->d32, n, gx, w.r32, w.w32[0], si, part));
         FV_LAUNCHED();
         rc = iterate(w, 1, max_inner, s, [&](int it) {
             PipeVec<float> a{mesh_cols(m), A->val32_cs, A->d32, w.w32[it & 1], w.w32[(it + 1) & 1], w.z32, w.s32,
                              w.p32, w.c32, w.r32, nullptr, nullptr};
-            FV_LAYOUT(m, hipLaunchKernelGGL((k_pipe_iter<float, W_, CI_, true, false>), dim3(g.grid), dim3(kBlock),
-                                                   0, s, a, n, g, si, part));
+            FV_LAYOUT(m, hipLaunchKernelGGL((k_pipe_iter<kBsMixed, float, W_, CI_, true, false>), dim3(gx.grid), dim3(kBsMixed),
+                                                   0, s, a, n, gx, si, part));
             if ((it + 1) % kReplaceEvery == 0) {
                 float* w_cur = w.w32[(it + 1) & 1];
                 FV_LAYOUT(m,
-                             hipLaunchKernelGGL((k_replace_rs<W_, CI_>), dim3(g.grid), dim3(kBlock), 0, s, cols_, A->val32,
-                                                A->d32, n, g, w.r32b, w.c32, w.p32, w.r32, w.s32, si);
-                             hipLaunchKernelGGL((k_replace_wz<W_, CI_>), dim3(g.grid), dim3(kBlock), 0, s, cols_,
-                                                A->val32_cs, A->d32, n, g, w.r32, w.s32, w_cur, w.z32, si, part));
+                             hipLaunchKernelGGL((k_replace_rs<kBsMixed, W_, CI_>), dim3(gx.grid), dim3(kBsMixed), 0, s, cols_, A->val32,
+                                                A->d32, n, gx, w.r32b, w.c32, w.p32, w.r32, w.s32, si);
+                             hipLaunchKernelGGL((k_replace_wz<kBsMixed, W_, CI_>), dim3(gx.grid), dim3(kBsMixed), 0, s, cols_,
+                                                A->val32_cs, A->d32, n, gx, w.r32, w.s32, w_cur, w.z32, si, part));
             }
         });
         if (rc) return rc;
-        hipLaunchKernelGGL(k_mixed_correct, dim3(g.grid), dim3(kBlock), 0, s, x, w.c32, n, g, so, 0);
+        hipLaunchKernelGGL((k_mixed_correct<kBsMixed>), dim3(gx.grid), dim3(kBsMixed), 0, s, x, w.c32, n, gx, so, 0);
         FV_LAUNCHED();
         FV_HIP(hipEventRecord(w.t_it1, s));
         if ((rc = state_read(w, 1, &hi, s))) return rc;

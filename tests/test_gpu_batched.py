@@ -170,14 +170,15 @@ def batch256():
     return fc.make("batch256")
 
 
-def test_batch256_full_size(fv, orc, batch256):
+@pytest.mark.parametrize("method", ["cg", "pipecg"])
+def test_batch256_full_size(fv, orc, batch256, method):
     """The 256-system workload (edges 16..64, 22M cells): every system's FP64
     true residual recomputed by the oracle's product, and the smallest
     systems at equal iteration count against the oracle."""
     bt = batch256
-    say("batch256 solve", bt.cell_off[-1])
+    say("batch256 solve", method, bt.cell_off[-1])
     B, b = dev_batch(fv, bt)
-    x, stats, code = fv.solve_batched(B, b, tol=1e-8, method="cg")
+    x, stats, code = fv.solve_batched(B, b, tol=1e-8, method=method)
     assert code == 0
     xs = per_system(bt, x.cpu().numpy())
     order = np.argsort([c.n for c in bt.cases])
@@ -187,7 +188,10 @@ def test_batch256_full_size(fv, orc, batch256):
         assert stats[s]["true_rel_res"] == pytest.approx(tr, rel=1e-6)
     for s in order[:3]:
         case = bt.cases[s]
-        xo, _ = orc.cg(case, case.b, tol=0.0, maxit=stats[s]["iters"])
+        if method == "cg":
+            xo, _ = orc.cg(case, case.b, tol=0.0, maxit=stats[s]["iters"])
+        else:
+            xo, _ = orc.pipecg(case, case.b, tol=0.0, maxit=stats[s]["iters"], folded=True)
         assert rel(xs[s], xo) <= PARITY
     B.close()
 

@@ -119,19 +119,30 @@ def renumbered(case, seed=0):
     return fc.Case(case.name, case.shape, case.n, o.astype(np.int32), nb.astype(np.int32), d, up, lo, b), new_index
 
 
-def parity_bars(orc, case, method, precond, tol, k_or, k, xo):
-    """(iteration-count bar, solution-difference bar).  The oracle itself is
-    run on a randomly renumbered copy of the system, which changes only the
-    order of its floating-point sums; its change of iteration count and of
-    the solution at equal count measure how much any reordering of the sums
-    moves this solve.  Bars: max(2, 2x that count change) and
-    max(1e-10, 10x that solution change).  For the pipelined recurrences and
-    for unpreconditioned solves of badly scaled systems the reordering alone
-    moves the solution by more than 1e-10."""
-    pc, new_index = renumbered(case)
-    _, sp = oracle_solve(orc, pc, method, precond, tol, 20000)
-    xp, _ = oracle_solve(orc, pc, method, precond, 0.0, k)
-    return max(2, 2 * abs(sp["iters"] - k_or)), max(PARITY, 10.0 * rel(xp[new_index], xo))
+def parity_bars(orc, case, method, precond, tol, k_or, k, xo, xs=None):
+    """(iteration-count bar, solution-difference bar, distance-to-solution
+    bar).  The oracle itself is run on randomly renumbered copies of the
+    system (three of them), which changes only the order of its
+    floating-point sums; its largest change of iteration count and of the
+    solution at equal count measure how much a reordering of the sums moves
+    this solve.  Bars: max(2, 2x that count change) and max(1e-10, 10x that
+    solution change).  For the pipelined recurrences and for unpreconditioned
+    solves of badly scaled systems the reordering alone moves the solution by
+    more than 1e-10.  With xs (the exact solution) also returns 4x the largest
+    distance of the oracle's iterates to it: where the pipelined iterate's
+    own rounding dominates (the graded cavity), its distance to the solution
+    varies by factors of 2 between orderings of the same sums; the true
+    residual (checked separately) stays within tolerance."""
+    dk, dx, ex = 0, 0.0, (rel(xo, xs) if xs is not None else 0.0)
+    for seed in range(3):
+        pc, new_index = renumbered(case, seed)
+        _, sp = oracle_solve(orc, pc, method, precond, tol, 20000)
+        xp, _ = oracle_solve(orc, pc, method, precond, 0.0, k)
+        dk = max(dk, abs(sp["iters"] - k_or))
+        dx = max(dx, rel(xp[new_index], xo))
+        if xs is not None:
+            ex = max(ex, rel(xp[new_index], xs))
+    return max(2, 2 * dk), max(PARITY, 10.0 * dx), 4.0 * ex + 1e-12
 
 
 @pytest.mark.parametrize("name", list(SOLVE_CASES))
@@ -147,18 +158,21 @@ def test_solve_parity_equal_iterations(fv, orc, name, method, precond):
     _, so = oracle_solve(orc, case, method, precond, tol, 20000)
     xo, _ = oracle_solve(orc, case, method, precond, 0.0, k)
     xg = x.cpu().numpy()
+    xs = None
+    if method != "cg" and precond == "jacobi":
+        xs, _ = orc.cg(case, case.b, tol=1e-13, maxit=50000, precond="jacobi")
     if (name, method, precond) in STRICT:
         count_bar, diff_bar = 2, PARITY
+        exact_bar = 2 * rel(xo, xs) + 1e-12 if xs is not None else None
     else:
-        count_bar, diff_bar = parity_bars(orc, case, method, precond, tol, so["iters"], k, xo)
+        count_bar, diff_bar, exact_bar = parity_bars(orc, case, method, precond, tol, so["iters"], k, xo, xs)
     assert abs(so["iters"] - k) <= count_bar, (so["iters"], k)
     assert rel(xg, xo) <= diff_bar
     assert st["true_rel_res"] <= 10 * tol
     assert st["b_norm"] == pytest.approx(np.linalg.norm(case.b), rel=1e-13)
-    if method != "cg" and precond == "jacobi":
-        # as close to the exact solution as the oracle's own iterate
-        xs, _ = orc.cg(case, case.b, tol=1e-13, maxit=50000, precond="jacobi")
-        assert rel(xg, xs) <= 2 * rel(xo, xs) + 1e-12
+    if xs is not None:
+        # as close to the exact solution as the oracle's own iterates
+        assert rel(xg, xs) <= exact_bar
     dc.close()
 
 
