@@ -9,7 +9,7 @@ solve: initial residual, every iteration, stopping test and the true residual
 at exit, with inputs resident in HBM.
 
 Prints ONE JSON line.  value = iterations/s over the timed solves.  roofline:
-the fused pipelined kernel, algorithmic bytes per launch (104n + 24F) divided
+the fused pipelined kernel, algorithmic bytes per launch (96n + 24F) divided
 by its average launch time from HIP events on the solve stream, against the
 8 TB/s HBM peak.  cpu_baseline: the plain-C oracle (single thread) on a
 bounded sample of the same workload.
@@ -45,11 +45,25 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def alg_bytes_pipecg_folded(n, F):
-    """Per iteration: matrix 24F (an int32 column + an FP64 value per
-    off-diagonal entry, 2F entries) + 13 FP64 vector passes 104n (reads w, z,
-    s, p, x, r, d; writes z, s, p, x, r, w').  Fixed by the method, not by the
-    layout: the 16-bit column offsets move fewer bytes than this."""
+def alg_bytes_pipecg_folded(n, F, iters):
+    """Average bytes per fused launch over a solve of `iters` iterations.
+    Every iteration: matrix 24F (an int32 column + an FP64 value per
+    off-diagonal entry, 2F entries) + 11 FP64 vector passes 88n (reads w, z,
+    s, p, r, d; writes z, s, p, r, w').  x is updated every second iteration
+    (x += alpha_{i-1} p_{i-1} + alpha_i p_i on odd i): 16n more on those, and
+    a final x += alpha p (24n) after an odd count.  Averages 96n + 24F,
+    against 104n + 24F for an x update every iteration.  Fixed by the method,
+    not by the layout: the 16-bit column offsets move fewer bytes than this."""
+    total = iters * (88 * n + 24 * F) + (iters // 2) * 16 * n + (iters % 2) * 24 * n
+    return total / max(iters, 1)
+
+
+def alg_bytes_per_iter(method, n, F, iters):
+    if method == "pipecg":
+        return alg_bytes_pipecg_folded(n, F, iters)
+    if method == "pipecg_literal":
+        return 136 * n + 24 * F  # also carries u and q: 4 more vector passes
+    # standard form: SpMV 24n + 24F, r update 32n, x/p update 48n
     return 104 * n + 24 * F
 
 
@@ -141,7 +155,7 @@ def main():
     assert all(s["status"] == 0 for s in stats), stats
 
     n, F = case.n, case.F
-    bpi = alg_bytes_pipecg_folded(n, F) if args.method != "cg" else 104 * n + 24 * F
+    bpi = sum(alg_bytes_per_iter(args.method, n, F, s_["iters"]) * s_["iters"] for s_ in stats) / total_iters
     its = total_iters / elapsed
     # dominant kernel: average duration of one fused iteration over the timed
     # solves (HIP events around the iteration launches on the solve stream)
@@ -229,20 +243,31 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None):
     B = fv.Batch(bt.cell_off, bt.face_off, to(bt.owner, torch.int32), to(bt.neighbour, torch.int32),
                  to(bt.diag, torch.float64), to(bt.upper, torch.float64))
     bb = to(bt.b, torch.float64)
+    saved = os.environ.get("FVPCG_BATCH_TEAMS")
     for method in ("cg", "pipecg"):
-        fv.solve_batched(B, bb, tol=1e-8, method=method)  # tunes and captures
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        xb, sts, code = fv.solve_batched(B, bb, tol=1e-8, method=method)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t0
-        its = [s_["iters"] for s_ in sts]
-        byts = sum((104 * c.n + 24 * c.F) * k for c, k in zip(bt.cases, its))
-        res[f"batch256/{method}"] = {"status": code, "ms": round(tb * 1e3, 2), "system_iters": int(sum(its)),
-                                     "system_iters_per_s": round(sum(its) / tb, 1), "max_iters": max(its),
-                                     "effective_GBs": round(byts / tb / 1e9, 1),
-                                     "total_cells": int(bt.cell_off[-1])}
-        log(f"extra batched {method}: {res[f'batch256/{method}']}")
+        # teams off, teams forced on, and the autotuner's choice between them
+        for mode, label in (("0", "/single"), ("1", "/teams"), (None, "")):
+            if mode is None:
+                os.environ.pop("FVPCG_BATCH_TEAMS", None)
+            else:
+                os.environ["FVPCG_BATCH_TEAMS"] = mode
+            fv.solve_batched(B, bb, tol=1e-8, method=method)  # tunes and captures
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xb, sts, code = fv.solve_batched(B, bb, tol=1e-8, method=method)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t0
+            its = [s_["iters"] for s_ in sts]
+            byts = sum((104 * c.n + 24 * c.F) * k for c, k in zip(bt.cases, its))
+            key = f"batch256/{method}{label}"
+            res[key] = {"status": code, "ms": round(tb * 1e3, 2), "system_iters": int(sum(its)),
+                        "system_iters_per_s": round(sum(its) / tb, 1), "max_iters": max(its),
+                        "effective_GBs": round(byts / tb / 1e9, 1), "total_cells": int(bt.cell_off[-1])}
+            log(f"extra batched {method}{label}: {res[key]}")
+    if saved is None:
+        os.environ.pop("FVPCG_BATCH_TEAMS", None)
+    else:
+        os.environ["FVPCG_BATCH_TEAMS"] = saved
     B.close()
     for name, method in (("laplace32", "pipecg"), ("laplace32", "cg"), ("cavity256", "cg")):
         c = fvcases.make(name)

@@ -222,6 +222,12 @@ def batch(nsys=256, edge_lo=16, edge_hi=64, seed=5, tol=1e-8, name="batch"):
         xt = R.uniform(gtgt, n)
         cases.append(_finish(f"{name}[{s}]", shape, n, owner, nb, diag, upper, lower, b, tol, seed,
                              {"edge": e, "ordering": "natural"}, x_target=xt))
+    return concat(cases, name=name, tol=tol, seed=seed)
+
+
+def concat(cases, name="batch", tol=1e-8, seed=0):
+    """Batch of the given systems, in order (a missing x_target reads as 0)."""
+    nsys = len(cases)
     cell_off = np.zeros(nsys + 1, dtype=np.int64)
     face_off = np.zeros(nsys + 1, dtype=np.int64)
     cell_off[1:] = np.cumsum([c.n for c in cases])
@@ -229,9 +235,11 @@ def batch(nsys=256, edge_lo=16, edge_hi=64, seed=5, tol=1e-8, name="batch"):
     if cell_off[-1] >= 2 ** 31 or face_off[-1] >= 2 ** 31:
         raise ValueError("batch too large for int32 offsets")
     cat = lambda attr: np.concatenate([getattr(c, attr) for c in cases])
-    return Batch(name=name, cases=cases, cell_off=cell_off.astype(np.int32), face_off=face_off.astype(np.int32),
-                 owner=cat("owner"), neighbour=cat("neighbour"), diag=cat("diag"), upper=cat("upper"),
-                 lower=cat("lower"), b=cat("b"), x_target=cat("x_target"), tol=tol, seed=seed)
+    xt = np.concatenate([c.x_target if c.x_target is not None else np.zeros(c.n) for c in cases])
+    return Batch(name=name, cases=list(cases), cell_off=cell_off.astype(np.int32),
+                 face_off=face_off.astype(np.int32), owner=cat("owner"), neighbour=cat("neighbour"),
+                 diag=cat("diag"), upper=cat("upper"), lower=cat("lower"), b=cat("b"), x_target=xt, tol=tol,
+                 seed=seed)
 
 
 # ---------------------------------------------------------------------------

@@ -179,7 +179,15 @@ FVPCG_API int fvpcg_batch_create(int32_t nsys, const int32_t* cell_off_host, con
 FVPCG_API int fvpcg_batch_destroy(fvpcg_batch* batch);
 /* b, x: concatenated FP64[total cells]; stats: HOST array of nsys entries
  * (may be NULL).  Returns FVPCG_OK if every system converged, else the
- * first non-OK status in system order. */
+ * first non-OK status in system order.  Systems far larger than a
+ * workgroup's share of the batch may be solved by a team of workgroups that
+ * synchronise through device memory; each such wait is bounded
+ * (FVPCG_BATCH_BARRIER_TIMEOUT_MS, default 5000): on a timeout every
+ * workgroup leaves, x and stats are invalid and FVPCG_DEVICE_ERROR is
+ * returned.  The first call per batch shape times the launch candidates
+ * (block size, workgroups per CU, teams on/off) and caches the choice in
+ * $FVPCG_TUNE_CACHE (FVPCG_TUNE=0: fixed defaults; FVPCG_BATCH_TEAMS=0/1:
+ * never/always form teams).  Calls on one batch handle must not overlap. */
 FVPCG_API int fvpcg_solve_batched(const fvpcg_batch* batch, const double* b, double* x, double tol,
                         int32_t maxit, int32_t method, int32_t precond, void* stream,
                         fvpcg_stats* stats);

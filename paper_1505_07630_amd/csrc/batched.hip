@@ -3,18 +3,21 @@
 //
 // The systems are stored as one block-diagonal matrix (their addressing
 // offset by each system's first cell), so the ELL layout, validation and
-// coefficient handling are the single-system ones.  One workgroup solves one
-// system from start to finish: its rows, its reductions (wave butterfly +
-// LDS, fixed order) and its scalars stay inside the workgroup, so no
-// workgroup ever waits for another.  Workgroups take systems from a device
-// queue ordered by decreasing size (largest first, the list-scheduling rule
-// that keeps the tail short); a launch uses min(nsys, resident capacity)
-// workgroups.  Block size and workgroups per CU are chosen per batch by a
-// small autotuner that times the candidates on the batch itself and caches
-// the choice in a JSON file.
+// coefficient handling are the single-system ones.  A system is solved from
+// start to finish either by one workgroup (its rows, reductions and scalars
+// stay inside the workgroup; no waiting on anyone) or, when it costs much more
+// than a workgroup's fair share of the batch, by a team of workgroups that
+// split its row tiles and combine their reductions through device memory and
+// a bounded team barrier.  Teams are assigned statically at launch; the other
+// systems go to a device queue ordered by decreasing size (largest first, the
+// list-scheduling rule that keeps the tail short), which team members join
+// once their system is done.  Block size, workgroups per CU and teams on/off
+// are chosen per batch by a small autotuner that times the candidates on the
+// batch itself and caches the choice in a JSON file.
 #include <sys/stat.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <fstream>
 #include <map>
@@ -48,8 +51,8 @@ struct BatchArgs {
     const double* val_cs;  // column-scaled values (Jacobi-folded pipelined)
     const double* d;
     const int* cell_off;
-    const int* order;  // systems, largest first
-    int nsys;
+    const int* order;  // queued systems, largest first
+    int nsys;          // queue length
     int n;  // total cells (slot stride)
     const double* b;
     double* x;
@@ -58,11 +61,18 @@ struct BatchArgs {
     int maxit;
     unsigned* queue;
     BatchStat* stats;
+    // workgroup teams for systems larger than a workgroup's fair share
+    const int4* tasks;            // [grid] (system, rank, team size, partials offset); system -1: none
+    unsigned long long* arrive;   // [nsys] team barrier counters, zeroed per launch
+    double* team_part;            // team partial sums, [2][size][3] per team system
+    int* abort_flag;              // set when a team barrier times out; every workgroup then exits
+    unsigned long long spin_ticks;  // team barrier timeout, wall-clock ticks
 };
 
 struct Tuning {
     int block = 256;
     int per_cu = 4;
+    int teams = 0;
 };
 
 }  // namespace fvpcg
@@ -85,9 +95,21 @@ struct fvpcg_batch {
     hipStream_t capture = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::map<std::string, fvpcg::Tuning> tuned;
+    // teams: per-launch work table, barrier counters, partials, abort flag
+    int pmax = 0;
+    int4* d_tasks = nullptr;
+    unsigned long long* d_arrive = nullptr;
+    double* d_team_part = nullptr;
+    int* d_abort = nullptr;
+    int4* h_tasks = nullptr;   // pinned staging
+    int* h_order = nullptr;    // pinned staging
+    int* h_abort = nullptr;    // pinned
+    unsigned long long spin_ticks = 0;
     // cached graph
     hipGraphExec_t gexec = nullptr;
     std::string gkey;
+    // which work table the device holds now
+    int plan_grid = -1, plan_block = 0, plan_teams = 0, plan_queue = 0;
 };
 
 namespace fvpcg {
@@ -142,6 +164,91 @@ __device__ __forceinline__ double gather(const void* colv, const double* __restr
     return acc;
 }
 
+// A team: the workgroups that solve one system together (size 1 = one
+// workgroup, no cross-workgroup synchronisation at all).
+struct Team {
+    int rank, size;
+    unsigned long long* arrive;
+    double* part;
+    int* abort_flag;
+    unsigned long long ticks;
+    int nbar;  // barriers passed so far
+    int par;   // which half of the double-buffered partials
+};
+
+// Barrier among the team's workgroups: a monotonic arrival counter (barrier k
+// completes when it reaches k * size), agent-scope release before arriving
+// and acquire after, so every member sees the others' vector writes.  The wait
+// is bounded: past the timeout (or when another workgroup has timed out) the
+// abort flag is set and false returned, and every workgroup leaves.
+__device__ bool team_barrier(Team& t) {
+    t.nbar += 1;
+    if (t.size == 1) {
+        __syncthreads();
+        return true;
+    }
+    __shared__ int s_ok;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long target = (unsigned long long)t.nbar * (unsigned long long)t.size;
+        __hip_atomic_fetch_add(t.arrive, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        const unsigned long long t0 = (unsigned long long)wall_clock64();
+        while (__hip_atomic_load(t.arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(t.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            if ((unsigned long long)wall_clock64() - t0 > t.ticks) {
+                __hip_atomic_store(t.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        s_ok = ok;
+    }
+    __syncthreads();
+    const bool ok = s_ok != 0;
+    __threadfence();
+    __syncthreads();
+    return ok;
+}
+
+// Sum NV values over the team: workgroup totals, then (size > 1) each member
+// publishes its totals, waits at the barrier and adds all members' totals in
+// rank order, so every member holds identical sums.
+template <int BS, int NV>
+__device__ bool team_allreduce(double (&v)[NV], Team& t) {
+    block_allreduce<BS, NV>(v);
+    if (t.size == 1) return true;
+    double* mine = t.part + ((size_t)t.par * t.size + t.rank) * 3;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) mine[k] = v[k];
+    }
+    const bool ok = team_barrier(t);
+    double tot[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) tot[k] = 0.0;
+    for (int r = 0; r < t.size; ++r) {
+        const double* q = t.part + ((size_t)t.par * t.size + r) * 3;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) tot[k] += q[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = tot[k];
+    t.par ^= 1;
+    return ok;
+}
+
+// Rows of system [c0, c1) handled by this team member: tiles of BS rows,
+// member r takes tiles r, r + size, ...  (size 1: every row, in order).
+#define TEAM_ROWS(c)                                                             \
+    for (int t_ = tm.rank; c0 + t_ * BS < c1; t_ += tm.size)                     \
+        for (int c = c0 + t_ * BS + (int)threadIdx.x; c < c1 && c < c0 + (t_ + 1) * BS; c += BS)
+
 // Scalar state of one system, identical in every thread of its workgroup.
 struct Sys {
     double gamma = 0, alpha = 0, beta = 0, bnorm = 0, tol_abs = 0, r0norm = 0, rho = 0;
@@ -182,11 +289,13 @@ __device__ __forceinline__ void pipe_step(Sys& y, double gamma, double delta, do
     y.beta = beta;
 }
 
-// r = b - A x over [c0, c1) and (b, b); returns false (x zeroed) when b = 0.
+// r = b - A x over the member's rows and (b, b); returns false (x zeroed)
+// when b = 0.
 template <int BS, int WT, typename CI>
-__device__ bool sys_begin(const BatchArgs& a, int c0, int c1, Sys& y, double* zero0, double* zero1, double* zero2) {
+__device__ bool sys_begin(const BatchArgs& a, int c0, int c1, Sys& y, Team& tm, double* zero0, double* zero1,
+                          double* zero2) {
     double acc[1] = {0.0};
-    for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
+    TEAM_ROWS(c) {
         const double bc = a.b[c];
         a.r[c] = bc - gather<WT, CI>(a.col, a.val, a.n, c, a.x, a.d[c] * a.x[c]);
         if (zero0) zero0[c] = 0.0;
@@ -194,11 +303,15 @@ __device__ bool sys_begin(const BatchArgs& a, int c0, int c1, Sys& y, double* ze
         if (zero2) zero2[c] = 0.0;
         acc[0] += bc * bc;
     }
-    block_allreduce<BS, 1>(acc);
+    if (!team_allreduce<BS, 1>(acc, tm)) {
+        y.done = true;
+        y.status = FVPCG_DEVICE_ERROR;
+        return false;
+    }
     y.bnorm = sqrt(acc[0]);
     y.tol_abs = a.tol * y.bnorm;
     if (acc[0] == 0.0) {
-        for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) a.x[c] = 0.0;
+        TEAM_ROWS(c) { a.x[c] = 0.0; }
         y.done = true;
         y.status = FVPCG_OK;
         return false;
@@ -207,15 +320,16 @@ __device__ bool sys_begin(const BatchArgs& a, int c0, int c1, Sys& y, double* ze
 }
 
 template <int BS, int WT, typename CI>
-__device__ void sys_finish(const BatchArgs& a, int s, int c0, int c1, const Sys& y) {
-    __syncthreads();
+__device__ void sys_finish(const BatchArgs& a, int s, int c0, int c1, Sys& y, Team& tm) {
     double acc[1] = {0.0};
-    for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
+    // the last updates of x must be complete in every member before the gather
+    if (!team_barrier(tm)) y.status = FVPCG_DEVICE_ERROR;
+    TEAM_ROWS(c) {
         const double rc = a.b[c] - gather<WT, CI>(a.col, a.val, a.n, c, a.x, a.d[c] * a.x[c]);
         acc[0] += rc * rc;
     }
-    block_allreduce<BS, 1>(acc);
-    if (threadIdx.x == 0) {
+    if (!team_allreduce<BS, 1>(acc, tm)) y.status = FVPCG_DEVICE_ERROR;
+    if (tm.rank == 0 && threadIdx.x == 0) {
         BatchStat st;
         st.iters = y.iter;
         st.status = y.status;
@@ -228,14 +342,13 @@ __device__ void sys_finish(const BatchArgs& a, int s, int c0, int c1, const Sys&
 }
 
 template <int BS, int WT, typename CI, bool JAC>
-__device__ void solve_pipe(const BatchArgs& a, int s) {
+__device__ void solve_pipe(const BatchArgs& a, int s, Team& tm) {
     const int c0 = a.cell_off[s], c1 = a.cell_off[s + 1];
     const double* val = JAC ? a.val_cs : a.val;
     Sys y;
-    if (sys_begin<BS, WT, CI>(a, c0, c1, y, a.z, a.s, a.p)) {
-        __syncthreads();
+    if (sys_begin<BS, WT, CI>(a, c0, c1, y, tm, a.z, a.s, a.p)) {
         double acc[3] = {0.0, 0.0, 0.0};
-        for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
+        TEAM_ROWS(c) {
             const double rc = a.r[c], dc = a.d[c];
             const double wc = gather<WT, CI>(a.col, val, a.n, c, a.r, JAC ? rc : dc * rc);
             a.w0[c] = wc;
@@ -244,16 +357,20 @@ __device__ void solve_pipe(const BatchArgs& a, int s) {
             acc[1] += wc * uc;
             acc[2] += rc * rc;
         }
-        block_allreduce<BS, 3>(acc);
-        y.r0norm = sqrt(acc[2]);
-        pipe_step(y, acc[0], acc[1], acc[2], true, a.maxit);
+        if (!team_allreduce<BS, 3>(acc, tm)) {
+            y.done = true;
+            y.status = FVPCG_DEVICE_ERROR;
+        } else {
+            y.r0norm = sqrt(acc[2]);
+            pipe_step(y, acc[0], acc[1], acc[2], true, a.maxit);
+        }
         int it = 0;
         while (!y.done) {
             const double* w_in = (it & 1) ? a.w1 : a.w0;
             double* w_out = (it & 1) ? a.w0 : a.w1;
             const double alpha = y.alpha, beta = y.beta;
             double t[3] = {0.0, 0.0, 0.0};
-            for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
+            TEAM_ROWS(c) {
                 const double wc = w_in[c], dc = a.d[c];
                 const double nv = gather<WT, CI>(a.col, val, a.n, c, w_in, JAC ? wc : dc * wc);
                 const double zc = nv + beta * a.z[c];
@@ -274,46 +391,58 @@ __device__ void solve_pipe(const BatchArgs& a, int s) {
                 t[1] += wn * un;
                 t[2] += rc * rc;
             }
-            block_allreduce<BS, 3>(t);
+            if (!team_allreduce<BS, 3>(t, tm)) {
+                y.done = true;
+                y.status = FVPCG_DEVICE_ERROR;
+                break;
+            }
             pipe_step(y, t[0], t[1], t[2], false, a.maxit);
             ++it;
         }
     }
-    sys_finish<BS, WT, CI>(a, s, c0, c1, y);
+    sys_finish<BS, WT, CI>(a, s, c0, c1, y, tm);
 }
 
 template <int BS, int WT, typename CI, bool JAC>
-__device__ void solve_cg(const BatchArgs& a, int s) {
+__device__ void solve_cg(const BatchArgs& a, int s, Team& tm) {
     const int c0 = a.cell_off[s], c1 = a.cell_off[s + 1];
     Sys y;
-    if (sys_begin<BS, WT, CI>(a, c0, c1, y, nullptr, nullptr, nullptr)) {
+    if (sys_begin<BS, WT, CI>(a, c0, c1, y, tm, nullptr, nullptr, nullptr)) {
         double acc[2] = {0.0, 0.0};
-        for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
+        TEAM_ROWS(c) {
             const double rc = a.r[c];
             const double zc = JAC ? rc / a.d[c] : rc;
             a.p[c] = zc;
             acc[0] += rc * zc;
             acc[1] += rc * rc;
         }
-        block_allreduce<BS, 2>(acc);
-        y.gamma = acc[0];
-        y.rho = acc[1];
-        y.r0norm = sqrt(acc[1]);
-        if (y.r0norm <= y.tol_abs) {
+        if (!team_allreduce<BS, 2>(acc, tm)) {
             y.done = true;
-            y.status = FVPCG_OK;
-        } else if (a.maxit <= 0) {
-            y.done = true;
+            y.status = FVPCG_DEVICE_ERROR;
+        } else {
+            y.gamma = acc[0];
+            y.rho = acc[1];
+            y.r0norm = sqrt(acc[1]);
+            if (y.r0norm <= y.tol_abs) {
+                y.done = true;
+                y.status = FVPCG_OK;
+            } else if (a.maxit <= 0) {
+                y.done = true;
+            }
         }
         while (!y.done) {
             double t1[1] = {0.0};
-            for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
+            TEAM_ROWS(c) {
                 const double pc = a.p[c];
                 const double qc = gather<WT, CI>(a.col, a.val, a.n, c, a.p, a.d[c] * pc);
                 a.q[c] = qc;
                 t1[0] += pc * qc;
             }
-            block_allreduce<BS, 1>(t1);
+            if (!team_allreduce<BS, 1>(t1, tm)) {
+                y.done = true;
+                y.status = FVPCG_DEVICE_ERROR;
+                break;
+            }
             const double delta = t1[0];
             if (!(delta > 0.0) || !isfinite(delta) || !isfinite(y.gamma)) {
                 y.done = true;
@@ -322,7 +451,7 @@ __device__ void solve_cg(const BatchArgs& a, int s) {
             }
             const double alpha = y.gamma / delta;
             double t2[2] = {0.0, 0.0};
-            for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
+            TEAM_ROWS(c) {
                 a.x[c] += alpha * a.p[c];
                 const double rc = a.r[c] - alpha * a.q[c];
                 a.r[c] = rc;
@@ -330,7 +459,11 @@ __device__ void solve_cg(const BatchArgs& a, int s) {
                 t2[0] += rc * zc;
                 t2[1] += rc * rc;
             }
-            block_allreduce<BS, 2>(t2);
+            if (!team_allreduce<BS, 2>(t2, tm)) {
+                y.done = true;
+                y.status = FVPCG_DEVICE_ERROR;
+                break;
+            }
             y.iter += 1;
             y.rho = t2[1];
             if (sqrt(t2[1]) <= y.tol_abs) {
@@ -344,40 +477,67 @@ __device__ void solve_cg(const BatchArgs& a, int s) {
             }
             const double beta = t2[0] / y.gamma;
             y.gamma = t2[0];
-            for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) {
+            TEAM_ROWS(c) {
                 const double rc = a.r[c];
                 const double zc = JAC ? rc / a.d[c] : rc;
                 a.p[c] = zc + beta * a.p[c];
             }
-            __syncthreads();
+            if (!team_barrier(tm)) {
+                y.done = true;
+                y.status = FVPCG_DEVICE_ERROR;
+                break;
+            }
         }
     }
-    sys_finish<BS, WT, CI>(a, s, c0, c1, y);
+    sys_finish<BS, WT, CI>(a, s, c0, c1, y, tm);
 }
 
-// method: 0 standard CG, 1 pipelined CG
+template <int BS, int WT, typename CI, bool JAC, int METHOD>
+__device__ __forceinline__ void solve_one(const BatchArgs& a, int s, Team& tm) {
+    if (METHOD == 1)
+        solve_pipe<BS, WT, CI, JAC>(a, s, tm);
+    else
+        solve_cg<BS, WT, CI, JAC>(a, s, tm);
+}
+
+// method: 0 standard CG, 1 pipelined CG.  A workgroup first does its static
+// team task (if any), then takes single-workgroup systems from the queue.
 template <int BS, int WT, typename CI, bool JAC, int METHOD>
 __global__ __launch_bounds__(BS) void k_batch(BatchArgs a) {
     __shared__ int s_next;
+    const int4 task = a.tasks[blockIdx.x];
+    if (task.x >= 0) {
+        Team tm{task.y, task.z, a.arrive + task.x, a.team_part + task.w, a.abort_flag, a.spin_ticks, 0, 0};
+        solve_one<BS, WT, CI, JAC, METHOD>(a, task.x, tm);
+        __syncthreads();
+    }
     for (;;) {
         if (threadIdx.x == 0) {
-            const unsigned k = atomicAdd(a.queue, 1u);
-            s_next = (k < (unsigned)a.nsys) ? a.order[k] : -1;
+            int next = -1;
+            if (!__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                const unsigned k = atomicAdd(a.queue, 1u);
+                next = (k < (unsigned)a.nsys) ? a.order[k] : -1;
+            }
+            s_next = next;
         }
         __syncthreads();
         const int s = s_next;
         __syncthreads();
         if (s < 0) return;
-        if (METHOD == 1)
-            solve_pipe<BS, WT, CI, JAC>(a, s);
-        else
-            solve_cg<BS, WT, CI, JAC>(a, s);
+        Team tm{0, 1, nullptr, nullptr, a.abort_flag, a.spin_ticks, 0, 0};
+        solve_one<BS, WT, CI, JAC, METHOD>(a, s, tm);
         __syncthreads();
     }
 }
 
-__global__ void k_queue_reset(unsigned* q) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0u;
+// Per launch: queue head, team barrier counters and the abort flag to zero
+// (a kernel, not a memset, so the captured graph replays it faithfully).
+__global__ void k_queue_reset(unsigned* q, unsigned long long* arrive, int nsys, int* abort_flag) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nsys; i += gridDim.x * blockDim.x) arrive[i] = 0ull;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *q = 0u;
+        *abort_flag = 0;
+    }
 }
 
 __global__ void k_offset_faces(const int* __restrict__ owner, const int* __restrict__ nb, const int* __restrict__ face_off,
@@ -441,17 +601,94 @@ int device_cus(int* cus) {
     return FVPCG_OK;
 }
 
+// Workgroups of one launch: all resident at once (occupancy-limited), which
+// the team barriers rely on; without teams, no more than there are systems.
 int grid_for(const fvpcg_batch* bt, const Tuning& t, BatchKernel k, int* grid) {
     int cus = 0, occ = 0;
     int rc;
     if ((rc = device_cus(&cus))) return rc;
     FV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k, t.block, 0));
     const int per_cu = std::max(1, std::min(occ, t.per_cu));
-    *grid = std::max(1, std::min(bt->nsys, cus * per_cu));
+    int g = cus * per_cu;
+    if (!t.teams) g = std::min(g, bt->nsys);
+    *grid = std::max(1, std::min(g, bt->pmax));
     return FVPCG_OK;
 }
 
-BatchArgs make_args(const fvpcg_batch* bt, const double* b, double* x, double tol, int maxit) {
+// Work table for a launch of P workgroups.  Cost of a system ~ n^(4/3)
+// (cells times iterations, and CG iterations grow like the mesh edge for
+// these Laplacians).  A system costing at least twice a workgroup's fair share
+// C/P gets a team of about cost/share workgroups (at most one per tile), taken
+// from one XCD's workgroups (b % 8) where they fit so the team shares an L2;
+// the others go to the queue, largest first.  Returns the queue length.
+int plan(fvpcg_batch* bt, int P, int bs, bool teams) {
+    const int ns = bt->nsys;
+    std::vector<double> cost(ns);
+    double C = 0.0;
+    for (int i = 0; i < ns; ++i) {
+        cost[i] = std::pow((double)(bt->cell_off[i + 1] - bt->cell_off[i]), 4.0 / 3.0);
+        C += cost[i];
+    }
+    const double share = C / P;
+    std::vector<int> g(ns, 1);
+    std::vector<int> team;
+    if (teams) {
+        for (int i = 0; i < ns; ++i) {
+            const int tiles = (bt->cell_off[i + 1] - bt->cell_off[i] + bs - 1) / bs;
+            if (cost[i] >= 2.0 * share && tiles >= 2) {
+                g[i] = std::max(2, std::min({(int)std::lround(cost[i] / share), tiles, 64}));
+                team.push_back(i);
+            }
+        }
+        std::sort(team.begin(), team.end(), [&](int x, int y) { return cost[x] > cost[y] || (cost[x] == cost[y] && x < y); });
+        double small = 0.0;
+        for (int i = 0; i < ns; ++i)
+            if (g[i] == 1) small += cost[i];
+        const int reserve = small > 0 ? std::max(1, (int)std::ceil(small / share)) : 0;
+        auto used = [&]() { int u = 0; for (int i : team) u += g[i]; return u; };
+        while (!team.empty() && used() + reserve > P) {
+            int big = team[0];
+            for (int i : team)
+                if (g[i] > g[big]) big = i;
+            if (g[big] > 2) {
+                g[big] -= 1;
+            } else {  // drop the cheapest team back to the queue
+                g[team.back()] = 1;
+                team.pop_back();
+            }
+        }
+    }
+    for (int b = 0; b < P; ++b) bt->h_tasks[b] = make_int4(-1, 0, 0, 0);
+    std::vector<std::vector<int>> free_slots(8);
+    for (int b = P - 1; b >= 0; --b) free_slots[b & 7].push_back(b);
+    int part = 0;
+    for (int i : team) {
+        int rank = 0;
+        while (rank < g[i]) {
+            int x = 0;
+            for (int k = 1; k < 8; ++k)
+                if (free_slots[k].size() > free_slots[x].size()) x = k;
+            if (free_slots[x].empty()) break;  // cannot happen: sum of team sizes <= P
+            while (rank < g[i] && !free_slots[x].empty()) {
+                const int b = free_slots[x].back();
+                free_slots[x].pop_back();
+                bt->h_tasks[b] = make_int4(i, rank++, g[i], part);
+            }
+        }
+        part += 6 * g[i];
+    }
+    int nq = 0;
+    std::vector<int> order;
+    for (int i = 0; i < ns; ++i)
+        if (g[i] == 1) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (bt->cell_off[x + 1] - bt->cell_off[x]) > (bt->cell_off[y + 1] - bt->cell_off[y]);
+    });
+    for (int i : order) bt->h_order[nq++] = i;
+    return nq;
+}
+
+BatchArgs make_args(const fvpcg_batch* bt, const double* b, double* x, double tol, int maxit, int nqueue) {
     const fvpcg_matrix* A = bt->mat;
     BatchArgs a;
     a.col = bt->mesh->col16 ? (const void*)bt->mesh->col16 : (const void*)bt->mesh->col;
@@ -460,7 +697,7 @@ BatchArgs make_args(const fvpcg_batch* bt, const double* b, double* x, double to
     a.d = A->d;
     a.cell_off = bt->d_cell_off;
     a.order = bt->d_order;
-    a.nsys = bt->nsys;
+    a.nsys = nqueue;
     a.n = bt->ncells;
     a.b = b;
     a.x = x;
@@ -475,18 +712,47 @@ BatchArgs make_args(const fvpcg_batch* bt, const double* b, double* x, double to
     a.maxit = maxit;
     a.queue = bt->d_queue;
     a.stats = bt->d_stats;
+    a.tasks = bt->d_tasks;
+    a.arrive = bt->d_arrive;
+    a.team_part = bt->d_team_part;
+    a.abort_flag = bt->d_abort;
+    a.spin_ticks = bt->spin_ticks;
     return a;
 }
 
-// Enqueue one batched solve directly (used while tuning).
-int launch_direct(const fvpcg_batch* bt, const Tuning& t, const BatchArgs& a, bool jac, int method, hipStream_t s) {
+// Plan the launch and upload its tables on `s` (stream-ordered before the
+// launch that uses them).
+int prepare(fvpcg_batch* bt, const Tuning& t, bool jac, int method, hipStream_t s, int* grid, int* nqueue) {
     BatchKernel k = pick_kernel(t.block, bt->mesh->WT, bt->mesh->col16 != nullptr, jac, method);
-    int grid = 1, rc;
-    if ((rc = grid_for(bt, t, k, &grid))) return rc;
-    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, bt->d_queue);
+    int rc;
+    if ((rc = grid_for(bt, t, k, grid))) return rc;
+    *nqueue = plan(bt, *grid, t.block, t.teams != 0);
+    FV_HIP(hipMemcpyAsync(bt->d_tasks, bt->h_tasks, sizeof(int4) * (size_t)*grid, hipMemcpyHostToDevice, s));
+    if (*nqueue > 0)
+        FV_HIP(hipMemcpyAsync(bt->d_order, bt->h_order, sizeof(int) * (size_t)*nqueue, hipMemcpyHostToDevice, s));
+    // the staging buffers are reused by the next plan: wait for the copies
+    FV_HIP(hipStreamSynchronize(s));
+    return FVPCG_OK;
+}
+
+// Enqueue one batched solve (reset + persistent kernel) on `s`.
+int launch_direct(const fvpcg_batch* bt, const Tuning& t, const BatchArgs& a, bool jac, int method, int grid,
+                  hipStream_t s) {
+    BatchKernel k = pick_kernel(t.block, bt->mesh->WT, bt->mesh->col16 != nullptr, jac, method);
+    hipLaunchKernelGGL(k_queue_reset, dim3(std::max(1, std::min(64, (bt->nsys + 255) / 256))), dim3(256), 0, s,
+                       bt->d_queue, bt->d_arrive, bt->nsys, bt->d_abort);
     hipLaunchKernelGGL(k, dim3(grid), dim3(t.block), 0, s, a);
     FV_LAUNCHED();
     return FVPCG_OK;
+}
+
+// FVPCG_BATCH_TEAMS: "0" never forms teams, "1" always offers them, unset
+// lets the autotuner decide.
+char teams_mode() {
+    const char* e = getenv("FVPCG_BATCH_TEAMS");
+    if (e && e[0] == '0') return '0';
+    if (e && e[0] == '1') return '1';
+    return 'a';
 }
 
 std::string tune_key(const fvpcg_batch* bt, bool jac, int method) {
@@ -498,7 +764,7 @@ std::string tune_key(const fvpcg_batch* bt, bool jac, int method) {
     }
     std::ostringstream os;
     os << "gfx950/nsys" << bt->nsys << "/cells" << bt->ncells << "/W" << bt->mesh->WT << "/m" << method << "/j"
-       << (jac ? 1 : 0) << "/h" << std::hex << h;
+       << (jac ? 1 : 0) << "/t" << teams_mode() << "/h" << std::hex << h;
     return os.str();
 }
 
@@ -509,7 +775,7 @@ std::string cache_path() {
     return std::string(home ? home : "/tmp") + "/.cache/fvpcg_batched_tuning.json";
 }
 
-// The cache is a flat JSON object {"key": [block, per_cu], ...}.
+// The cache is a flat JSON object {"key": [block, per_cu, teams], ...}.
 std::map<std::string, Tuning> load_cache() {
     std::map<std::string, Tuning> m;
     std::ifstream f(cache_path());
@@ -525,8 +791,9 @@ std::map<std::string, Tuning> load_cache() {
         const size_t lb = s.find('[', j), rb = s.find(']', j);
         if (lb == std::string::npos || rb == std::string::npos) break;
         Tuning t;
-        if (sscanf(s.c_str() + lb + 1, "%d , %d", &t.block, &t.per_cu) == 2 &&
-            (t.block == 256 || t.block == 512 || t.block == 1024) && t.per_cu >= 1 && t.per_cu <= 32)
+        if (sscanf(s.c_str() + lb + 1, "%d , %d , %d", &t.block, &t.per_cu, &t.teams) == 3 &&
+            (t.block == 256 || t.block == 512 || t.block == 1024) && t.per_cu >= 1 && t.per_cu <= 16 &&
+            (t.teams == 0 || t.teams == 1))
             m[key] = t;
         i = rb + 1;
     }
@@ -552,15 +819,44 @@ void store_cache(const std::string& key, const Tuning& t) {
     if (!f) return;
     f << "{\n";
     size_t k = 0;
-    for (auto& kv : m) f << "  \"" << kv.first << "\": [" << kv.second.block << ", " << kv.second.per_cu << "]"
-                          << (++k < m.size() ? ",\n" : "\n");
+    for (auto& kv : m)
+        f << "  \"" << kv.first << "\": [" << kv.second.block << ", " << kv.second.per_cu << ", " << kv.second.teams
+          << "]" << (++k < m.size() ? ",\n" : "\n");
     f << "}\n";
     f.close();
     (void)rename(tmp.c_str(), path.c_str());
 }
 
-// Pick block size and workgroups per CU by timing each candidate on this
-// batch (a copy of x0, the caller's tolerance), fastest wins.
+// Upload the work table for tuning t unless the device already holds it.
+int ensure_plan(fvpcg_batch* bt, const Tuning& t, bool jac, int method, hipStream_t s, int* grid, int* nqueue) {
+    BatchKernel k = pick_kernel(t.block, bt->mesh->WT, bt->mesh->col16 != nullptr, jac, method);
+    int rc, g = 0;
+    if ((rc = grid_for(bt, t, k, &g))) return rc;
+    if (bt->plan_grid == g && bt->plan_block == t.block && bt->plan_teams == t.teams) {
+        *grid = g;
+        *nqueue = bt->plan_queue;
+        return FVPCG_OK;
+    }
+    bt->plan_grid = -1;
+    if ((rc = prepare(bt, t, jac, method, s, grid, nqueue))) return rc;
+    bt->plan_grid = *grid;
+    bt->plan_block = t.block;
+    bt->plan_teams = t.teams;
+    bt->plan_queue = *nqueue;
+    return FVPCG_OK;
+}
+
+int check_abort(fvpcg_batch* bt, hipStream_t s) {
+    FV_HIP(hipMemcpyAsync(bt->h_abort, bt->d_abort, sizeof(int), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    if (*bt->h_abort)
+        return set_error(FVPCG_DEVICE_ERROR, "batched solve: a workgroup team barrier timed out (results invalid)");
+    return FVPCG_OK;
+}
+
+// Pick block size, workgroups per CU and teams on/off by timing each
+// candidate on this batch (a copy of x0, the caller's tolerance), fastest
+// wins.
 int autotune(fvpcg_batch* bt, const double* b, const double* x0, double tol, int maxit, bool jac, int method,
              hipStream_t s, Tuning* out) {
     const std::string key = tune_key(bt, jac, method);
@@ -569,9 +865,11 @@ int autotune(fvpcg_batch* bt, const double* b, const double* x0, double tol, int
         *out = it->second;
         return FVPCG_OK;
     }
+    const char mode = teams_mode();
     const char* env = getenv("FVPCG_TUNE");
     if (env && env[0] == '0') {
         *out = Tuning();
+        out->teams = mode == '1' ? 1 : 0;
         bt->tuned[key] = *out;
         return FVPCG_OK;
     }
@@ -584,19 +882,34 @@ int autotune(fvpcg_batch* bt, const double* b, const double* x0, double tol, int
     }
     int rc;
     if (!bt->xscratch && (rc = dev_alloc(&bt->xscratch, (size_t)bt->ncells, "batched tuning x"))) return rc;
-    const Tuning cands[] = {{256, 4}, {256, 8}, {512, 2}, {512, 4}, {1024, 1}, {1024, 2}};
+    std::vector<Tuning> cands;
+    const int shapes[][2] = {{256, 4}, {256, 8}, {512, 2}, {512, 4}, {1024, 1}, {1024, 2}};
+    for (int tm = 0; tm < 2; ++tm) {
+        if ((mode == '0' && tm == 1) || (mode == '1' && tm == 0)) continue;
+        for (auto& sh : shapes) {
+            Tuning t;
+            t.block = sh[0];
+            t.per_cu = sh[1];
+            t.teams = tm;
+            cands.push_back(t);
+        }
+    }
     float best = 1e30f;
-    Tuning pick;
+    Tuning pick = cands[0];
     for (const Tuning& t : cands) {
+        int grid = 0, nq = 0;
+        if ((rc = ensure_plan(bt, t, jac, method, s, &grid, &nq))) return rc;
         float ms = 0;
         for (int rep = 0; rep < 2; ++rep) {
             FV_HIP(hipMemcpyAsync(bt->xscratch, x0, sizeof(double) * (size_t)bt->ncells, hipMemcpyDeviceToDevice, s));
             FV_HIP(hipEventRecord(bt->e0, s));
-            if ((rc = launch_direct(bt, t, make_args(bt, b, bt->xscratch, tol, maxit), jac, method, s))) return rc;
+            if ((rc = launch_direct(bt, t, make_args(bt, b, bt->xscratch, tol, maxit, nq), jac, method, grid, s)))
+                return rc;
             FV_HIP(hipEventRecord(bt->e1, s));
             FV_HIP(hipEventSynchronize(bt->e1));
             FV_HIP(hipEventElapsedTime(&ms, bt->e0, bt->e1));
         }
+        if ((rc = check_abort(bt, s))) return rc;
         if (ms < best) {
             best = ms;
             pick = t;
@@ -617,9 +930,16 @@ void batch_free(fvpcg_batch* bt) {
     dev_free(bt->d_order);
     dev_free(bt->d_queue);
     dev_free(bt->d_stats);
+    dev_free(bt->d_tasks);
+    dev_free(bt->d_arrive);
+    dev_free(bt->d_team_part);
+    dev_free(bt->d_abort);
     double** vs[] = {&bt->r, &bt->p, &bt->q, &bt->z, &bt->s, &bt->w0, &bt->w1, &bt->xscratch, &bt->lam};
     for (double** v : vs) dev_free(*v);
     if (bt->h_stats) (void)hipHostFree(bt->h_stats);
+    if (bt->h_tasks) (void)hipHostFree(bt->h_tasks);
+    if (bt->h_order) (void)hipHostFree(bt->h_order);
+    if (bt->h_abort) (void)hipHostFree(bt->h_abort);
     if (bt->capture) (void)hipStreamDestroy(bt->capture);
     if (bt->e0) (void)hipEventDestroy(bt->e0);
     if (bt->e1) (void)hipEventDestroy(bt->e1);
@@ -678,22 +998,36 @@ int batch_create(int32_t nsys, const int32_t* cell_off, const int32_t* face_off,
     dev_free(dfo);
     dev_free(bad);
     if ((rc = matrix_create(bt->mesh, diag, upper, lower, 0, s, &bt->mat))) return fail(rc);
-    // largest systems first
-    std::vector<int> order(nsys);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return (cell_off[a + 1] - cell_off[a]) > (cell_off[b + 1] - cell_off[b]);
-    });
+    // launch tables: at most 16 workgroups per CU are ever resident
+    int cus = 0;
+    if ((rc = device_cus(&cus))) return fail(rc);
+    bt->pmax = 16 * cus;
     if ((rc = dev_alloc(&bt->d_order, (size_t)nsys, "system order")) || (rc = dev_alloc(&bt->d_queue, 1, "queue")) ||
-        (rc = dev_alloc(&bt->d_stats, (size_t)nsys, "system stats")))
+        (rc = dev_alloc(&bt->d_stats, (size_t)nsys, "system stats")) ||
+        (rc = dev_alloc(&bt->d_tasks, (size_t)bt->pmax, "team tasks")) ||
+        (rc = dev_alloc(&bt->d_arrive, (size_t)nsys, "team barriers")) ||
+        (rc = dev_alloc(&bt->d_team_part, (size_t)6 * bt->pmax, "team partials")) ||
+        (rc = dev_alloc(&bt->d_abort, 1, "abort flag")))
         return fail(rc);
-    CK(hipMemcpyAsync(bt->d_order, order.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, s));
     double** vs[] = {&bt->r, &bt->p, &bt->q, &bt->z, &bt->s, &bt->w0, &bt->w1};
     for (double** v : vs)
         if ((rc = dev_alloc(v, n, "batched vector"))) return fail(rc);
-    if (hipHostMalloc((void**)&bt->h_stats, sizeof(BatchStat) * nsys, hipHostMallocDefault) != hipSuccess) {
-        bt->h_stats = nullptr;
+    if (hipHostMalloc((void**)&bt->h_stats, sizeof(BatchStat) * nsys, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&bt->h_tasks, sizeof(int4) * bt->pmax, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&bt->h_order, sizeof(int) * nsys, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&bt->h_abort, sizeof(int), hipHostMallocDefault) != hipSuccess)
         return fail(set_error(FVPCG_OUT_OF_MEMORY, "pinned allocation failed"));
+    *bt->h_abort = 0;
+    // team barrier timeout (FVPCG_BATCH_BARRIER_TIMEOUT_MS, default 5 s) in
+    // wall-clock ticks
+    {
+        int dev = 0, khz = 0;
+        CK(hipGetDevice(&dev));
+        CK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        const char* e = getenv("FVPCG_BATCH_BARRIER_TIMEOUT_MS");
+        double ms = 5000.0;
+        if (e && *e) ms = std::max(0.0, atof(e));
+        bt->spin_ticks = (unsigned long long)((double)std::max(khz, 1) * ms);
     }
     CK(hipStreamCreateWithFlags(&bt->capture, hipStreamNonBlocking));
     CK(hipEventCreate(&bt->e0));
@@ -726,10 +1060,12 @@ int solve_batched(const fvpcg_batch* cbt, const double* b, double* x, double tol
     int rc;
     Tuning t;
     if ((rc = autotune(bt, b, x, tol, maxit, jac, m, s, &t))) return rc;
+    int grid = 0, nq = 0;
+    if ((rc = ensure_plan(bt, t, jac, m, s, &grid, &nq))) return rc;
     // graph of (queue reset, persistent solve) for these arguments
     std::ostringstream os;
     os << (const void*)b << '/' << (const void*)x << '/' << tol << '/' << maxit << '/' << m << '/' << jac << '/'
-       << t.block << '/' << t.per_cu;
+       << t.block << '/' << t.per_cu << '/' << t.teams << '/' << grid << '/' << nq;
     if (!bt->gexec || bt->gkey != os.str()) {
         if (bt->gexec) {
             (void)hipGraphExecDestroy(bt->gexec);
@@ -737,7 +1073,7 @@ int solve_batched(const fvpcg_batch* cbt, const double* b, double* x, double tol
         }
         hipGraph_t graph = nullptr;
         FV_HIP(hipStreamBeginCapture(bt->capture, hipStreamCaptureModeThreadLocal));
-        int lrc = launch_direct(bt, t, make_args(bt, b, x, tol, maxit), jac, m, bt->capture);
+        int lrc = launch_direct(bt, t, make_args(bt, b, x, tol, maxit, nq), jac, m, grid, bt->capture);
         hipError_t e = hipStreamEndCapture(bt->capture, &graph);
         if (lrc) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -756,7 +1092,7 @@ int solve_batched(const fvpcg_batch* cbt, const double* b, double* x, double tol
     FV_HIP(hipGraphLaunch(bt->gexec, s));
     FV_HIP(hipEventRecord(bt->e1, s));
     FV_HIP(hipMemcpyAsync(bt->h_stats, bt->d_stats, sizeof(BatchStat) * bt->nsys, hipMemcpyDeviceToHost, s));
-    FV_HIP(hipStreamSynchronize(s));
+    if ((rc = check_abort(bt, s))) return rc;
     float ms = 0;
     (void)hipEventElapsedTime(&ms, bt->e0, bt->e1);
     int overall = FVPCG_OK;

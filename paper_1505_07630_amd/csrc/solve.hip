@@ -337,10 +337,23 @@ __global__ __launch_bounds__(BS) void k_pipe_init_w(const CI* __restrict__ col, 
         pipe_scalars(st, t[0], t[1], t[2], true);
 }
 
+// FP64 folded form: x is needed only at exit, so it is updated every second
+// iteration: on odd iterations x += alpha_{i-1} p_{i-1} + alpha_i p_i (p_{i-1}
+// is read anyway; the two products are added in order, giving the same x as
+// two separate updates); k_x_fixup adds a pending alpha_i p_i after an even
+// last iteration.  Saves two vector passes every other iteration.
+template <typename T, bool LIT>
+struct PairX {
+    static constexpr bool value = !LIT && sizeof(T) == 8;
+};
+
 template <int BS, typename T, int WT, typename CI, bool JAC, bool LIT>
 __global__ __launch_bounds__(BS) void k_pipe_iter(PipeVec<T> a, int n, Geom g, DevState* st, double* partials) {
     if (st->done) return;
+    constexpr bool PAIR = PairX<T, LIT>::value;
     const T alpha = (T)st->alpha, beta = (T)st->beta;
+    const T alpha_prev = (T)st->alpha_old;
+    const bool odd = (st->iter & 1) != 0;
     double acc[3] = {0.0, 0.0, 0.0};
     FV_ROWS(blk) {
         const T wc = a.w_in[c];
@@ -362,9 +375,15 @@ __global__ __launch_bounds__(BS) void k_pipe_iter(PipeVec<T> a, int n, Geom g, D
             st_once(a.u + c, uc);
         } else {
             uc = JAC ? rc / dc : rc;
-            const T pc = uc + beta * ld_once(a.p + c);
+            const T pold = ld_once(a.p + c);
+            const T pc = uc + beta * pold;
             st_once(a.p + c, pc);
-            st_once(a.x + c, ld_once(a.x + c) + alpha * pc);
+            if (!PAIR) {
+                st_once(a.x + c, ld_once(a.x + c) + alpha * pc);
+            } else if (odd) {
+                const T xa = ld_once(a.x + c) + alpha_prev * pold;
+                st_once(a.x + c, xa + alpha * pc);
+            }
         }
         rc -= alpha * sc;
         const T wn = wc - alpha * zc;
@@ -380,6 +399,16 @@ __global__ __launch_bounds__(BS) void k_pipe_iter(PipeVec<T> a, int n, Geom g, D
     double t[3];
     if (device_reduce<BS, 3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0)
         pipe_scalars(st, t[0], t[1], t[2], false);
+}
+
+// x += alpha p when the last pipelined iteration (an even one) left its
+// update pending (see PairX).
+template <int BS>
+__global__ __launch_bounds__(BS) void k_x_fixup(double* __restrict__ x, const double* __restrict__ p, int n, Geom g,
+                                                const DevState* st) {
+    if ((st->iter & 1) == 0) return;
+    const double alpha = st->alpha;
+    FV_ROWS(blk) { x[c] += alpha * p[c]; }
 }
 
 // ===========================================================================
@@ -865,6 +894,10 @@ int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int max
             });
         }
         if (rc) return rc;
+    }
+    if (method == FVPCG_PIPECG && !h.zero_b && !h.done) {
+        hipLaunchKernelGGL((k_x_fixup<kBsPipe>), dim3(gp.grid), dim3(kBsPipe), 0, s, x, w.p, n, gp, st);
+        FV_LAUNCHED();
     }
     FV_HIP(hipEventRecord(w.t_it1, s));
     FV_LAYOUT(m, hipLaunchKernelGGL((k_true_residual<kBsMisc, W_, CI_>), dim3(gm.grid), dim3(kBsMisc), 0, s, cols_, A->val,

@@ -162,6 +162,67 @@ def test_autotune_cache_written(fv, tmp_path):
     B.close()
 
 
+# ------------------------------------------------------------------ workgroup teams
+
+@pytest.mark.parametrize("method", ["pipecg", "cg"])
+def test_batched_teams_match_oracle(fv, orc, monkeypatch, method):
+    """Teams forced on: one 40^3 system far above a workgroup's fair share
+    (split over many workgroups) beside small queued systems; every system
+    against the oracle at its iteration count, bitwise reproducible."""
+    say("batched teams", method)
+    import torch
+
+    monkeypatch.setenv("FVPCG_TUNE", "0")
+    monkeypatch.setenv("FVPCG_BATCH_TEAMS", "1")
+    big = fc.varcoef((40, 40, 40), seed=4)
+    small = fc.batch(12, 3, 12, seed=6).cases
+    bt = fc.concat([big] + small)
+    B, b = dev_batch(fv, bt)
+    runs = []
+    for _ in range(2):
+        x, stats, code = fv.solve_batched(B, b, x=torch.zeros_like(b), tol=1e-9, method=method)
+        assert code == 0 and all(st["status"] == 0 for st in stats)
+        runs.append(x.cpu().numpy())
+    assert np.array_equal(runs[0], runs[1])
+    xs = per_system(bt, runs[0])
+    for s, case in enumerate(bt.cases):
+        k = stats[s]["iters"]
+        if method == "cg":
+            _, so = orc.cg(case, case.b, tol=1e-9, maxit=20000)
+            xo, _ = orc.cg(case, case.b, tol=0.0, maxit=k)
+        else:
+            _, so = orc.pipecg(case, case.b, tol=1e-9, maxit=20000, folded=True)
+            xo, _ = orc.pipecg(case, case.b, tol=0.0, maxit=k, folded=True)
+        assert abs(so["iters"] - k) <= 2, (s, so["iters"], k)
+        assert rel(xs[s], xo) <= PARITY, s
+        tr = np.linalg.norm(case.b - orc.spmv(case, xs[s])) / np.linalg.norm(case.b)
+        assert stats[s]["true_rel_res"] == pytest.approx(tr, rel=1e-6)
+    B.close()
+
+
+def test_batched_team_barrier_timeout_reports_error(fv, monkeypatch):
+    """A zero barrier timeout (set from the host) makes a team's bounded wait
+    give up: every workgroup leaves and the call reports DEVICE_ERROR; a batch
+    with the normal timeout then solves."""
+    say("batched team timeout")
+    import torch
+
+    monkeypatch.setenv("FVPCG_TUNE", "0")
+    monkeypatch.setenv("FVPCG_BATCH_TEAMS", "1")
+    monkeypatch.setenv("FVPCG_BATCH_BARRIER_TIMEOUT_MS", "0")
+    bt = fc.concat([fc.varcoef((32, 32, 32), seed=4)])
+    B, b = dev_batch(fv, bt)
+    with pytest.raises(fv.FVPCGError) as e:
+        fv.solve_batched(B, b, tol=1e-9, method="pipecg")
+    assert e.value.code == fv.DEVICE_ERROR and "barrier" in str(e.value)
+    B.close()
+    monkeypatch.delenv("FVPCG_BATCH_BARRIER_TIMEOUT_MS")
+    B, b = dev_batch(fv, bt)
+    x, stats, code = fv.solve_batched(B, b, x=torch.zeros_like(b), tol=1e-9, method="pipecg")
+    assert code == 0 and stats[0]["true_rel_res"] <= 1e-8
+    B.close()
+
+
 # ------------------------------------------------------------------ full size
 
 @pytest.fixture(scope="module")
