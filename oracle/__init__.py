@@ -65,6 +65,8 @@ def lib():
         L.or_pipecg.restype = i32
         L.or_refine.argtypes = [i32, i32, P, P, P, P, P, P, P, d, d, i32, i32, P]
         L.or_refine.restype = i32
+        L.or_mixed_reliable.argtypes = [i32, i32, P, P, P, P, P, P, P, d, i32, i32, P]
+        L.or_mixed_reliable.restype = i32
         L.or_adjoint_grads.argtypes = [i32, i32, P, P, P, P, P, P, P]
         L.or_adjoint_grads.restype = None
         _lib = L
@@ -162,6 +164,15 @@ def refine(A, b, x0=None, outer_tol=1e-10, inner_tol=1e-5, max_outer=50, max_inn
     st = Stats()
     lib().or_refine(*A.args(), _p(b), _p(x), float(outer_tol), float(inner_tol), int(max_outer), int(max_inner),
                     ctypes.byref(st))
+    return x, st.asdict()
+
+
+def mixed_reliable(A, b, x0=None, tol=1e-10, update_every=20, maxit=100000):
+    A = _as_sys(A)
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    st = Stats()
+    lib().or_mixed_reliable(*A.args(), _p(b), _p(x), float(tol), int(update_every), int(maxit), ctypes.byref(st))
     return x, st.asdict()
 
 

@@ -431,6 +431,134 @@ int32_t or_refine(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb
     return status;
 }
 
+/* ---- Mixed precision with reliable updates (an extension beside the
+ * paper's FP64 solver; the residual-replacement idea of van der Vorst and
+ * Ye, applied to the pipelined recurrences as by Cools et al.).  One FP32
+ * folded pipelined Jacobi-CG iteration runs on the FP32-rounded matrix for
+ * the scaled system A c = (b - A x0) / s, s = ||b - A x0||, with FP64
+ * inner-product accumulation; its Krylov recurrences are never restarted.
+ * Every `update_every` iterations (and at maxit) the FP64 side takes over:
+ *   x += s * c, c = 0                         (solution accumulation, FP64)
+ *   r64 = b - A x with the FP64 matrix        (outer residual, FP64)
+ *   stop if ||r64|| <= tol ||b||, at maxit, or once ||r64|| has had no
+ *   new minimum for max(OR_RU_STAGNATION, 10 update_every) iterations
+ *   (NOT_CONVERGED; CG residual norms are not monotone, so the window is
+ *   long);
+ *   r = fp32(r64 / s), then s_ = A32 p, w = A32 D^-1 r, z = A32 D^-1 s_
+ *   re-formed from their definitions (p is kept), and the next step's
+ *   alpha, beta from the new dots and the previous gamma, alpha.
+ * A breakdown of the FP32 recurrences (p'Ap <= 0 or a non-finite scalar)
+ * also triggers an update, after which the recurrences restart from the
+ * replaced residual (p = s = z = 0); a breakdown in the first iteration after
+ * a restart ends the solve with BREAKDOWN.  st->iters counts FP32
+ * iterations, st->outer_iters FP64 updates. */
+enum { OR_RU_STAGNATION = 500 };
+
+int32_t or_mixed_reliable(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                          const double* diag, const double* upper, const double* lower,
+                          const double* b, double* x, double tol, int32_t update_every,
+                          int32_t maxit, or_stats* st)
+{
+    if (st) memset(st, 0, sizeof(*st));
+    double bnorm = sqrt(or_dot(n, b, b));
+    if (bnorm == 0.0) {
+        for (int32_t c = 0; c < n; ++c) x[c] = 0.0;
+        return OR_OK;
+    }
+    if (!diag_positive(n, diag)) {
+        if (st) st->status = OR_BREAKDOWN;
+        return OR_BREAKDOWN;
+    }
+    if (update_every < 1) update_every = 1;
+    double* r64 = alloc_vec(n);
+    residual(n, nf, owner, nb, diag, upper, lower, b, x, r64);
+    double rnorm = sqrt(or_dot(n, r64, r64));
+    const double scale = rnorm;
+    if (st) { st->r0_norm = rnorm; st->b_norm = bnorm; }
+    int32_t status = OR_NOT_CONVERGED, it = 0, updates = 0;
+    if (rnorm <= tol * bnorm) {
+        free(r64);
+        if (st) { st->status = OR_OK; st->rel_res = st->true_rel_res = rnorm / bnorm; }
+        return OR_OK;
+    }
+    float* d32 = malloc(sizeof(float) * (size_t)n);
+    float* u32 = malloc(sizeof(float) * (size_t)(nf > 0 ? nf : 1));
+    float* l32 = malloc(sizeof(float) * (size_t)(nf > 0 ? nf : 1));
+    for (int32_t c = 0; c < n; ++c) d32[c] = (float)diag[c];
+    for (int32_t f = 0; f < nf; ++f) { u32[f] = (float)upper[f]; l32[f] = (float)lower[f]; }
+    float *r = calloc((size_t)n, 4), *u = calloc((size_t)n, 4), *w = calloc((size_t)n, 4);
+    float *m = calloc((size_t)n, 4), *nv = calloc((size_t)n, 4), *z = calloc((size_t)n, 4);
+    float *s = calloc((size_t)n, 4), *p = calloc((size_t)n, 4), *cc = calloc((size_t)n, 4);
+
+    for (int32_t c = 0; c < n; ++c) r[c] = (float)(r64[c] / scale);
+    spmv32_scaled(n, nf, owner, nb, d32, u32, l32, r, m, w);
+    double gamma_prev = 0.0, alpha_prev = 0.0, best = rnorm;
+    int32_t first = 1, since = 0, it_best = 0;
+    const int32_t window = OR_RU_STAGNATION > 10 * update_every ? OR_RU_STAGNATION : 10 * update_every;
+    for (;;) {
+        /* one FP32 pipelined iteration (Section 4.1 recurrences, folded Jacobi) */
+        for (int32_t c = 0; c < n; ++c) u[c] = r[c] / d32[c];
+        double gamma = dot32(n, r, u);
+        double delta = dot32(n, w, u);
+        double beta, den;
+        if (first) { beta = 0.0; den = delta; }
+        else { beta = gamma / gamma_prev; den = delta - beta * gamma / alpha_prev; }
+        double alpha = gamma / den;
+        int broke = !(den > 0.0) || !isfinite(alpha) || !isfinite(beta);
+        if (broke && first) { status = OR_BREAKDOWN; break; }
+        if (!broke) {
+            for (int32_t c = 0; c < n; ++c) m[c] = w[c] / d32[c];
+            spmv32(n, nf, owner, nb, d32, u32, l32, m, nv);
+            float a32 = (float)alpha, b32 = (float)beta;
+            for (int32_t c = 0; c < n; ++c) {
+                z[c] = nv[c] + b32 * z[c];
+                s[c] = w[c] + b32 * s[c];
+                p[c] = u[c] + b32 * p[c];
+                cc[c] += a32 * p[c];
+                r[c] -= a32 * s[c];
+                w[c] -= a32 * z[c];
+            }
+            gamma_prev = gamma;
+            alpha_prev = alpha;
+            first = 0;
+            ++it;
+            ++since;
+        }
+        if (!broke && since < update_every && it < maxit) continue;
+        /* reliable update: FP64 accumulation and outer residual */
+        since = 0;
+        ++updates;
+        for (int32_t c = 0; c < n; ++c) { x[c] += scale * (double)cc[c]; cc[c] = 0.0f; }
+        residual(n, nf, owner, nb, diag, upper, lower, b, x, r64);
+        rnorm = sqrt(or_dot(n, r64, r64));
+        if (rnorm <= tol * bnorm) { status = OR_OK; break; }
+        if (!isfinite(rnorm)) { status = OR_BREAKDOWN; break; }
+        if (it >= maxit) break;
+        if (rnorm < best) { best = rnorm; it_best = it; }
+        else if (it - it_best >= window) break;
+        for (int32_t c = 0; c < n; ++c) r[c] = (float)(r64[c] / scale);
+        if (broke) {
+            for (int32_t c = 0; c < n; ++c) { p[c] = 0.0f; s[c] = 0.0f; z[c] = 0.0f; }
+            spmv32_scaled(n, nf, owner, nb, d32, u32, l32, r, m, w);
+            first = 1;
+        } else {
+            spmv32(n, nf, owner, nb, d32, u32, l32, p, s);
+            spmv32_scaled(n, nf, owner, nb, d32, u32, l32, r, m, w);
+            spmv32_scaled(n, nf, owner, nb, d32, u32, l32, s, m, z);
+        }
+    }
+    if (st) {
+        st->iters = it;
+        st->outer_iters = updates;
+        st->status = status;
+        st->rel_res = rnorm / bnorm;
+        st->true_rel_res = rnorm / bnorm;
+    }
+    free(d32); free(u32); free(l32); free(r); free(u); free(w); free(m); free(nv); free(z); free(s); free(p);
+    free(cc); free(r64);
+    return status;
+}
+
 /* ---- Adjoint gradients on the sparsity pattern.  For L(x) with A x = b and
  * lambda = A^-T dL/dx: dL/db = lambda and dL/dA_ij = -lambda_i x_j, so the
  * diagonal gets -lambda_c x_c, upper[f] (row owner, column neighbour) gets

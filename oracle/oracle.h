@@ -68,6 +68,15 @@ int32_t or_refine(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb
                   const double* b, double* x, double outer_tol, double inner_tol,
                   int32_t max_outer, int32_t max_inner, or_stats* st);
 
+/* Mixed precision with reliable updates: FP32 folded pipelined Jacobi-CG
+ * whose recurrences are never restarted, with the FP64 solution
+ * accumulation, FP64 outer residual and residual replacement every
+ * update_every iterations. */
+int32_t or_mixed_reliable(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                          const double* diag, const double* upper, const double* lower,
+                          const double* b, double* x, double tol, int32_t update_every,
+                          int32_t maxit, or_stats* st);
+
 /* Gradients of a scalar loss L(x) with A x = b on the LDU pattern, given x
  * and lambda = A^-T dL/dx:  dL/ddiag = -lambda*x, dL/dupper[f] =
  * -lambda[owner]*x[nb], dL/dlower[f] = -lambda[nb]*x[owner]. */

@@ -9,6 +9,8 @@ P8  CG error bound in the A-norm          P9  pipelined CG == CG
 P10 adjoint gradients vs dense solves and finite differences
 P11 Table pcgs2 iteration counts (loose; parity unpinned: norm unstated)
 P12 mixed-precision refinement reaches the FP64 solution
+P13 mixed precision with reliable updates: dense solutions, the iteration
+    count of FP64 Jacobi-CG (SciPy), edge cases
 """
 import json
 import os
@@ -308,6 +310,98 @@ def test_p12_refinement_reaches_fp64_solution(oracle_lib):
     assert st["true_rel_res"] <= 1e-10
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-8
     assert st["outer_iters"] >= 2
+
+
+# ---------------------------------------------------------------- P13
+def _csr(c):
+    import scipy.sparse as sp
+
+    rows = np.concatenate([np.arange(c.n), c.owner, c.neighbour])
+    cols = np.concatenate([np.arange(c.n), c.neighbour, c.owner])
+    return sp.csr_matrix((np.concatenate([c.diag, c.upper, c.lower]), (rows, cols)), shape=(c.n, c.n))
+
+
+@pytest.mark.parametrize("make", [lambda: fc.laplace((8, 8, 8)), lambda: fc.varcoef((9, 8, 7), seed=6),
+                                  lambda: fc.cavity((10, 10, 4))])
+def test_p13_reliable_reaches_dense_solution(oracle_lib, make):
+    """FP64-level result from FP32 recurrences: the dense LU solution to 1e-8
+    and an FP64 residual (recomputed densely) below 1e-10, far below the
+    ~1e-7 * kappa an FP32 solve alone can reach."""
+    c = make()
+    A = dense(c)
+    xs = np.linalg.solve(A, c.b)
+    x, st = oracle_lib.mixed_reliable(c, c.b, tol=1e-10, update_every=20)
+    assert st["status"] == 0
+    assert np.linalg.norm(c.b - A @ x) / np.linalg.norm(c.b) <= 1e-10
+    assert st["true_rel_res"] == pytest.approx(np.linalg.norm(c.b - A @ x) / np.linalg.norm(c.b), rel=1e-6)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-8
+    assert st["outer_iters"] == -(-st["iters"] // 20) or st["outer_iters"] == st["iters"] // 20
+
+
+@pytest.mark.parametrize("make", [lambda: fc.laplace((16, 16, 16)), lambda: fc.laplace((32, 32, 32)),
+                                  lambda: fc.varcoef((20, 20, 20), seed=2)])
+def test_p13_reliable_tracks_fp64_iteration_count(oracle_lib, make):
+    """With the FP32 recurrences re-anchored to the FP64 residual every 10
+    iterations the Krylov process is not restarted: the FP32 iteration count
+    stays within 30% (+ one update period) of FP64 Jacobi-CG run by SciPy to
+    the same relative residual."""
+    import scipy.sparse.linalg as spl
+
+    c = make()
+    A = _csr(c)
+    its = [0]
+    Minv = spl.LinearOperator(A.shape, matvec=lambda v: v / c.diag)
+    spl.cg(A, c.b, rtol=1e-10, M=Minv, maxiter=100000, callback=lambda xk: its.__setitem__(0, its[0] + 1))
+    x, st = oracle_lib.mixed_reliable(c, c.b, tol=1e-10, update_every=10)
+    assert st["status"] == 0
+    assert its[0] * 0.9 <= st["iters"] <= 1.3 * its[0] + 10, (st["iters"], its[0])
+    # restarting from r at every FP64 correction (classical refinement) costs more
+    _, sr = oracle_lib.refine(c, c.b, outer_tol=1e-10, inner_tol=1e-5)
+    assert sr["iters"] > st["iters"]
+
+
+def test_p13_reliable_long_period_needs_re_formed_recurrences(oracle_lib):
+    """Between updates the FP32 recurrences drift; the update re-forms r, s,
+    w and z from their definitions.  With updates only every 40 iterations on
+    the variable-coefficient 32^3 system this keeps the count within 1.5x of
+    FP64 Jacobi-CG (SciPy); re-forming r and w but not s = A p roughly
+    doubles it."""
+    import scipy.sparse.linalg as spl
+
+    c = fc.varcoef((32, 32, 32), seed=2)
+    A = _csr(c)
+    its = [0]
+    Minv = spl.LinearOperator(A.shape, matvec=lambda v: v / c.diag)
+    spl.cg(A, c.b, rtol=1e-10, M=Minv, maxiter=100000, callback=lambda xk: its.__setitem__(0, its[0] + 1))
+    x, st = oracle_lib.mixed_reliable(c, c.b, tol=1e-10, update_every=40)
+    assert st["status"] == 0
+    assert st["iters"] <= 1.5 * its[0] + 40, (st["iters"], its[0])
+
+
+def test_p13_reliable_edge_cases(oracle_lib):
+    c = fc.varcoef((6, 5, 4), seed=3)
+    A = dense(c)
+    x, st = oracle_lib.mixed_reliable(c, np.zeros(c.n), x0=np.ones(c.n))
+    assert st["status"] == 0 and st["iters"] == 0 and np.all(x == 0)
+    xs = np.linalg.solve(A, c.b)
+    x, st = oracle_lib.mixed_reliable(c, c.b, x0=xs, tol=1e-8)
+    assert st["status"] == 0 and st["iters"] == 0 and st["outer_iters"] == 0
+    # iteration limit: NOT_CONVERGED after exactly maxit FP32 iterations
+    x, st = oracle_lib.mixed_reliable(c, c.b, tol=1e-14, update_every=4, maxit=10)
+    assert st["status"] == 1 and st["iters"] == 10 and st["outer_iters"] == 3
+    # an FP64 update after every iteration still converges
+    x, st = oracle_lib.mixed_reliable(c, c.b, tol=1e-10, update_every=1)
+    assert st["status"] == 0 and st["outer_iters"] == st["iters"]
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-8
+    # unattainable tolerance: ends by stagnation of the FP64 residual
+    x, st = oracle_lib.mixed_reliable(c, c.b, tol=1e-30, update_every=5, maxit=100000)
+    assert st["status"] == 1 and st["iters"] < 100000
+    assert np.linalg.norm(c.b - A @ x) / np.linalg.norm(c.b) <= 1e-13
+    # indefinite diagonal under Jacobi
+    c.diag = c.diag.copy()
+    c.diag[3] = -1.0
+    _, st = oracle_lib.mixed_reliable(c, c.b)
+    assert st["status"] == -3
 
 
 # ---------------------------------------------------------------- edge cases
