@@ -29,6 +29,7 @@ if ROOT not in sys.path:
 
 METRIC = "CG iters/s + HBM GB/s at 7M cells; mixed/batched vs plain FP64 at 1e-8"
 HBM_PEAK_GBS = 8000.0
+RELIABLE_PERIOD = 16  # FP32 iterations between FP64 updates in the reliable-update mixed solve
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pipecg_fold_varcoef192_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1505_07630_amd", "csrc", f) for f in ("solve.hip", "common.hpp", "setup.hip")]
 
@@ -217,26 +218,38 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None):
     res = {}
     to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).to(dev)
     if case is not None:
-        # mixed precision on the same 192^3 arrays: time to 1e-10 vs FP64
+        # mixed precision on the same 192^3 arrays against plain FP64, to 1e-8
+        # and to 1e-10: restarted refinement (FP32 inner to 1e-5) and reliable
+        # updates (FP32 recurrences re-anchored to the FP64 residual)
         A32 = fv.Matrix(mesh, to(case.diag, torch.float64), to(case.upper, torch.float64), fp32_copy=True)
-        fv.solve_mixed(A32, b)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        xm, sm = fv.solve_mixed(A32, b, outer_tol=1e-10, inner_tol=1e-5)
-        torch.cuda.synchronize()
-        tm = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        xr, sr = fv.solve(A32, b, tol=1e-10, maxit=50000, method="pipecg")
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t0
         xc, _ = fv.solve(A32, b, tol=1e-12, maxit=50000, method="cg")
-        err = (torch.linalg.norm(xm - xc) / torch.linalg.norm(xc)).item()
-        res["varcoef192/mixed"] = {"status": sm["status_name"], "outer_iters": sm["outer_iters"],
-                                   "inner_fp32_iters": sm["iters"], "ms_to_1e-10": round(tm * 1e3, 1),
-                                   "fp64_pipecg_ms_to_1e-10": round(t64 * 1e3, 1), "fp64_iters": sr["iters"],
-                                   "true_rel_res": sm["true_rel_res"],
-                                   "rel_err_vs_fp64_cg_1e-12": err}
-        log(f"extra mixed: {res['varcoef192/mixed']}")
+
+        def timed(f):
+            f()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x_, st_ = f()
+            torch.cuda.synchronize()
+            ms_ = (time.perf_counter() - t0) * 1e3
+            err_ = (torch.linalg.norm(x_ - xc) / torch.linalg.norm(xc)).item()
+            return st_, ms_, err_
+
+        for tol in (1e-8, 1e-10):
+            s64, t64, e64 = timed(lambda: fv.solve(A32, b, tol=tol, maxit=50000, method="pipecg"))
+            sm, tm, em = timed(lambda: fv.solve_mixed(A32, b, outer_tol=tol, inner_tol=1e-5))
+            sr, tr, er = timed(lambda: fv.solve_mixed_reliable(A32, b, tol=tol, update_every=RELIABLE_PERIOD))
+            key = f"varcoef192/mixed_to_{tol:g}"
+            res[key] = {
+                "fp64_pipecg": {"ms": round(t64, 1), "iters": s64["iters"], "rel_err_vs_fp64_cg_1e-12": e64},
+                "refinement": {"ms": round(tm, 1), "status": sm["status_name"], "outer_iters": sm["outer_iters"],
+                               "fp32_iters": sm["iters"], "true_rel_res": sm["true_rel_res"],
+                               "rel_err_vs_fp64_cg_1e-12": em, "speedup_vs_fp64": round(t64 / tm, 3)},
+                "reliable": {"ms": round(tr, 1), "status": sr["status_name"], "fp64_updates": sr["outer_iters"],
+                             "update_every": RELIABLE_PERIOD, "fp32_iters": sr["iters"],
+                             "true_rel_res": sr["true_rel_res"], "rel_err_vs_fp64_cg_1e-12": er,
+                             "speedup_vs_fp64": round(t64 / tr, 3)},
+            }
+            log(f"extra mixed to {tol:g}: {res[key]}")
         A32.close()
     # batched: 256 systems, edges 16..64
     bt = fvcases.make("batch256")
@@ -269,6 +282,31 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None):
     else:
         os.environ["FVPCG_BATCH_TEAMS"] = saved
     B.close()
+    # the same 256 systems solved one after another by the single-system
+    # FP64 solver (setup outside the timed region)
+    singles = []
+    for c in bt.cases:
+        m_ = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
+        singles.append((m_, fv.Matrix(m_, to(c.diag, torch.float64), to(c.upper, torch.float64)),
+                        to(c.b, torch.float64)))
+    for method in ("cg", "pipecg"):
+        for m_, A_, b_ in singles[:4]:
+            fv.solve(A_, b_, tol=1e-8, method=method)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = 0
+        for m_, A_, b_ in singles:
+            _, st_ = fv.solve(A_, b_, tol=1e-8, maxit=100000, method=method)
+            its += st_["iters"]
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        key = f"batch256/{method}/one_solve_per_system"
+        res[key] = {"ms": round(ts * 1e3, 1), "system_iters": its, "system_iters_per_s": round(its / ts, 1),
+                    "batched_speedup": round(ts * 1e3 / res[f"batch256/{method}"]["ms"], 2)}
+        log(f"extra {key}: {res[key]}")
+    for m_, A_, b_ in singles:
+        A_.close()
+        m_.close()
     for name, method in (("laplace32", "pipecg"), ("laplace32", "cg"), ("cavity256", "cg")):
         c = fvcases.make(name)
         mesh = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))

@@ -73,7 +73,7 @@ enum {
 enum { FVPCG_PRECOND_NONE = 0, FVPCG_PRECOND_JACOBI = 1 };
 
 /* fvpcg_matrix_create flags */
-#define FVPCG_FP32_COPY 1u /* also keep an FP32 copy for fvpcg_solve_mixed */
+#define FVPCG_FP32_COPY 1u /* also keep an FP32 copy for the mixed-precision solves */
 
 #define FVPCG_MAX_ROW_DEGREE 32
 
@@ -149,6 +149,23 @@ FVPCG_API int fvpcg_solve(const fvpcg_matrix* mat, const double* b, double* x, d
 FVPCG_API int fvpcg_solve_mixed(const fvpcg_matrix* mat, const double* b, double* x, double outer_tol,
                       double inner_tol, int32_t max_outer, int32_t max_inner, void* stream,
                       fvpcg_stats* stats);
+
+/* ---- Mixed precision with reliable updates (needs FVPCG_FP32_COPY; Jacobi).
+ * The FP32 folded pipelined Jacobi-CG recurrences (Section 4.1) run on the
+ * FP32-rounded matrix for A c = (b - A x0)/s, s = ||b - A x0||, with FP64
+ * inner-product accumulation, and are never restarted.  Every update_every
+ * FP32 iterations the FP64 side accumulates x += s c (c = 0), recomputes
+ * r = b - A x with the FP64 matrix and re-forms the FP32 r = r/s, s = A p,
+ * w = A D^-1 r, z = A D^-1 s (residual replacement).  Stops when
+ * ||b - A x|| <= tol ||b|| (OK), after maxit FP32 iterations or once the FP64
+ * residual has not reached a new minimum for max(500, 10 update_every)
+ * iterations (NOT_CONVERGED), or on a breakdown of the FP32 recurrences right
+ * after a restart from the replaced residual (BREAKDOWN); any other FP32
+ * breakdown restarts them.  x holds x0 on entry (FP64[n_cells]).  Stats:
+ * iters = FP32 iterations, outer_iters = FP64 updates, true_rel_res = the
+ * last FP64 residual.  update_every >= 1, maxit >= 1. */
+FVPCG_API int fvpcg_solve_mixed_reliable(const fvpcg_matrix* mat, const double* b, double* x, double tol,
+                                         int32_t update_every, int32_t maxit, void* stream, fvpcg_stats* stats);
 
 /* ---- Adjoint of a solve, for a scalar loss L(x) with A x = b.  Given the
  * solution x and g = dL/dx, solves A^T lambda = g (A is symmetric for CG,

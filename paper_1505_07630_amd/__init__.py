@@ -233,6 +233,24 @@ def fvpcg_solve_mixed(A: Matrix, b, x=None, outer_tol=1e-10, inner_tol=1e-5, max
 solve_mixed = fvpcg_solve_mixed
 
 
+def fvpcg_solve_mixed_reliable(A: Matrix, b, x=None, tol=1e-10, update_every=10, maxit=100000, stream=None):
+    """FP32 pipelined Jacobi-CG whose recurrences are re-anchored to the FP64
+    residual every `update_every` iterations (reliable updates)."""
+    import torch
+
+    if x is None:
+        x = torch.zeros_like(b)
+    st = Stats()
+    code = lib().fvpcg_solve_mixed_reliable(A.handle, _ptr(b, torch.float64, A.n, "b"),
+                                            _ptr(x, torch.float64, A.n, "x"), float(tol), int(update_every),
+                                            int(maxit), _stream(stream), ctypes.byref(st))
+    _check(code, "fvpcg_solve_mixed_reliable")
+    return x, st.asdict()
+
+
+solve_mixed_reliable = fvpcg_solve_mixed_reliable
+
+
 def fvpcg_solve_backward(A: Matrix, x, g, want=("b", "diag", "upper", "lower"), tol=1e-10, maxit=10000,
                          method="pipecg", precond="jacobi", stream=None):
     """Adjoint of a solve: returns (dict of gradients, stats)."""

@@ -19,6 +19,8 @@ int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int max
           hipStream_t s, fvpcg_stats* stats);
 int solve_mixed(const fvpcg_matrix* A, const double* b, double* x, double outer_tol, double inner_tol, int max_outer,
                 int max_inner, hipStream_t s, fvpcg_stats* stats);
+int solve_mixed_reliable(const fvpcg_matrix* A, const double* b, double* x, double tol, int update_every, int maxit,
+                         hipStream_t s, fvpcg_stats* stats);
 int solve_backward(const fvpcg_matrix* A, const double* x, const double* g, double* grad_b, double* grad_diag,
                    double* grad_upper, double* grad_lower, double tol, int maxit, int method, int precond,
                    hipStream_t s, fvpcg_stats* stats);
@@ -251,6 +253,29 @@ int fvpcg_solve_mixed(const fvpcg_matrix* mat, const double* b, double* x, doubl
             return set_error(FVPCG_BREAKDOWN, "Jacobi preconditioner needs a finite positive diagonal");
         }
         return solve_mixed(mat, b, x, outer_tol, inner_tol, max_outer, max_inner, (hipStream_t)stream, stats);
+    });
+}
+
+int fvpcg_solve_mixed_reliable(const fvpcg_matrix* mat, const double* b, double* x, double tol, int32_t update_every,
+                               int32_t maxit, void* stream, fvpcg_stats* stats) {
+    return guard([&]() -> int {
+        stats_status(stats, FVPCG_INVALID_ARG);
+        if (!mat) return set_error(FVPCG_INVALID_ARG, "mat is NULL");
+        if (!mat->fp32) {
+            stats_status(stats, FVPCG_UNSUPPORTED);
+            return set_error(FVPCG_UNSUPPORTED, "matrix was created without FVPCG_FP32_COPY");
+        }
+        if (!(tol >= 0.0) || !std::isfinite(tol)) return set_error(FVPCG_INVALID_ARG, "need a finite tol >= 0");
+        if (update_every < 1 || maxit < 1) return set_error(FVPCG_INVALID_ARG, "need update_every >= 1, maxit >= 1");
+        size_t bytes = sizeof(double) * (size_t)mat->mesh->n;
+        FV_TRY(check_dev(b, bytes, "b"));
+        FV_TRY(check_dev(x, bytes, "x"));
+        if (overlap(b, bytes, x, bytes)) return set_error(FVPCG_INVALID_ARG, "b and x overlap");
+        if (!mat->diag_ok) {
+            stats_status(stats, FVPCG_BREAKDOWN);
+            return set_error(FVPCG_BREAKDOWN, "Jacobi preconditioner needs a finite positive diagonal");
+        }
+        return solve_mixed_reliable(mat, b, x, tol, update_every, maxit, (hipStream_t)stream, stats);
     });
 }
 

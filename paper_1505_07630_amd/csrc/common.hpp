@@ -28,6 +28,10 @@ constexpr int kMaxChunk = 64;         // iterations enqueued between convergence
 // and the number of replacements without a new minimum that ends it.
 constexpr int kReplaceEvery = 20;
 constexpr int kStagnationChecks = 5;
+// Reliable-update mixed solve: stop once the FP64 residual has had no new
+// minimum for max(kReliableWindow, 10 * update period) FP32 iterations (CG
+// residual norms are not monotone, so the window is long).
+constexpr int kReliableWindow = 500;
 
 // ---------------------------------------------------------------------------
 // Solver scalars living in device memory.  Written only by the last

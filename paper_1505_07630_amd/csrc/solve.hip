@@ -14,6 +14,10 @@
 // beta, the stopping test, breakdown) are computed once, by that last
 // workgroup, and read by the next kernel from device memory; the host only
 // reads the `done` flag back at chunk boundaries.
+#include <climits>
+
+#include <algorithm>
+
 #include "handles.hpp"
 
 namespace fvpcg {
@@ -434,13 +438,16 @@ __global__ __launch_bounds__(BS) void k_replace_rs(const CI* __restrict__ col, c
     }
 }
 
-template <int BS, int WT, typename CI>
+// RELIABLE: replacement within the reliable-update mixed solve (r comes from
+// the FP64 residual; no stagnation or tolerance test here: the FP64 side
+// decides, and `outer` done skips the kernel).
+template <int BS, int WT, typename CI, bool RELIABLE>
 __global__ __launch_bounds__(BS) void k_replace_wz(const CI* __restrict__ col, const float* __restrict__ val_cs,
                                                        const float* __restrict__ d, int n, Geom g,
                                                        const float* __restrict__ r, const float* __restrict__ s,
                                                        float* __restrict__ w, float* __restrict__ z, DevState* st,
-                                                       double* partials) {
-    if (st->done) return;
+                                                       const DevState* outer, double* partials) {
+    if (st->done || (RELIABLE && outer->done)) return;
     double acc[3] = {0.0, 0.0, 0.0};
     FV_ROWS(blk) {
         const float rc = r[c];
@@ -456,18 +463,20 @@ __global__ __launch_bounds__(BS) void k_replace_wz(const CI* __restrict__ col, c
     if (device_reduce<BS, 3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
         const double gamma = t[0], delta = t[1], rho = t[2];
         st->rho = rho;
-        if (rho < st->best) {
-            st->best = rho;
-            st->no_min = 0;
-        } else if (++st->no_min >= kStagnationChecks) {
-            st->done = 1;
-            st->status = FVPCG_NOT_CONVERGED;
-            return;
-        }
-        if (sqrt(rho) <= st->tol_abs) {
-            st->done = 1;
-            st->status = FVPCG_OK;
-            return;
+        if (!RELIABLE) {
+            if (rho < st->best) {
+                st->best = rho;
+                st->no_min = 0;
+            } else if (++st->no_min >= kStagnationChecks) {
+                st->done = 1;
+                st->status = FVPCG_NOT_CONVERGED;
+                return;
+            }
+            if (sqrt(rho) <= st->tol_abs) {
+                st->done = 1;
+                st->status = FVPCG_OK;
+                return;
+            }
         }
         const double beta = gamma / st->gamma_old;
         const double den = delta - beta * gamma / st->alpha_old;
@@ -575,6 +584,83 @@ __global__ __launch_bounds__(BS) void k_mixed_correct(double* __restrict__ x, co
                                                           Geom g, const DevState* st_out, int undo) {
     const double sc = undo ? -st_out->scale_prev : st_out->scale;
     FV_ROWS(blk) { x[c] += sc * (double)c32[c]; }
+}
+
+// ===========================================================================
+// Mixed precision with reliable updates (residual replacement in the sense
+// of van der Vorst and Ye, applied to the pipelined recurrences as by Cools
+// et al.): the FP32 pipelined recurrences are never restarted; every K
+// iterations the FP64 side accumulates x and recomputes b - A x, from which
+// the FP32 r is re-formed, with s = A p (here) and w, z (k_replace_wz).
+
+// x += scale * c; c = 0.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_ru_accumulate(double* __restrict__ x, float* __restrict__ c32, int n, Geom g,
+                                                          const DevState* so) {
+    if (so->done) return;
+    const double sc = so->scale;
+    FV_ROWS(blk) {
+        x[c] += sc * (double)c32[c];
+        c32[c] = 0.0f;
+    }
+}
+
+// r64 = b - A x with the FP64 matrix; r32 = fp32(r64 / scale); s32 = A32 p32,
+// or, when the FP32 recurrences have stopped (breakdown), p32 = s32 = z32 = 0
+// for a restart.  Outer tests on ||r64||: tolerance, non-finite, FP32
+// iteration limit, no new minimum for `window` iterations.
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_ru_residual(const CI* __restrict__ col, const double* __restrict__ val,
+                                                        const double* __restrict__ d, const float* __restrict__ val32,
+                                                        const float* __restrict__ d32, int n, Geom g,
+                                                        const double* __restrict__ b, const double* __restrict__ x,
+                                                        float* __restrict__ r32, float* __restrict__ s32,
+                                                        float* __restrict__ p32, float* __restrict__ z32,
+                                                        DevState* so, const DevState* si, int it_offset, int maxit,
+                                                        int window, int j, double* partials) {
+    if (so->done) return;
+    const double inv = 1.0 / so->scale;
+    const bool restart = si->done != 0;
+    double acc[1] = {0.0};
+    FV_ROWS(blk) {
+        const double rc = b[c] - row_gather<double, WT, CI>(col, val, n, c, x, d[c] * x[c]);
+        r32[c] = (float)(rc * inv);
+        if (restart) {
+            s32[c] = 0.0f;
+            p32[c] = 0.0f;
+            z32[c] = 0.0f;
+        } else {
+            s32[c] = row_gather<float, WT, CI>(col, val32, n, c, p32, d32[c] * p32[c]);
+        }
+        acc[0] += rc * rc;
+    }
+    double t[1];
+    if (device_reduce<BS, 1>(acc, partials, &so->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        const double rn = sqrt(t[0]);
+        const int total = it_offset + si->iter;
+        so->iter = j;
+        so->rho = t[0];
+        so->true_rr = t[0];
+        if (rn <= so->tol_abs) {
+            so->done = 1;
+            so->status = FVPCG_OK;
+        } else if (!isfinite(rn)) {
+            so->done = 1;
+            so->status = FVPCG_BREAKDOWN;
+        } else if (total >= maxit) {
+            so->done = 1;
+            so->status = FVPCG_NOT_CONVERGED;
+        } else {
+            const double best = so->best < so->r0norm ? so->best : so->r0norm;
+            if (rn < best) {
+                so->best = rn;
+                so->no_min = total;
+            } else if (total - so->no_min >= window) {
+                so->done = 1;
+                so->status = FVPCG_NOT_CONVERGED;
+            }
+        }
+    }
 }
 
 // ===========================================================================
@@ -763,6 +849,15 @@ int state_read(Work& w, int k, DevState* out, hipStream_t s) {
     FV_HIP(hipMemcpyAsync(&w.hst[k], &w.st[k], sizeof(DevState), hipMemcpyDeviceToHost, s));
     FV_HIP(hipStreamSynchronize(s));
     *out = w.hst[k];
+    return FVPCG_OK;
+}
+
+// Both states (outer, inner) with one copy and one wait.
+int state_read_both(Work& w, DevState* h0, DevState* h1, hipStream_t s) {
+    FV_HIP(hipMemcpyAsync(&w.hst[0], &w.st[0], 2 * sizeof(DevState), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    *h0 = w.hst[0];
+    *h1 = w.hst[1];
     return FVPCG_OK;
 }
 
@@ -965,8 +1060,8 @@ int solve_mixed(const fvpcg_matrix* A, const double* b, double* x, double outer_
                 FV_LAYOUT(m,
                              hipLaunchKernelGGL((k_replace_rs<kBsMixed, W_, CI_>), dim3(gx.grid), dim3(kBsMixed), 0, s, cols_, A->val32,
                                                 A->d32, n, gx, w.r32b, w.c32, w.p32, w.r32, w.s32, si);
-                             hipLaunchKernelGGL((k_replace_wz<kBsMixed, W_, CI_>), dim3(gx.grid), dim3(kBsMixed), 0, s, cols_,
-                                                A->val32_cs, A->d32, n, gx, w.r32, w.s32, w_cur, w.z32, si, part));
+                             hipLaunchKernelGGL((k_replace_wz<kBsMixed, W_, CI_, false>), dim3(gx.grid), dim3(kBsMixed), 0, s, cols_,
+                                                A->val32_cs, A->d32, n, gx, w.r32, w.s32, w_cur, w.z32, si, nullptr, part));
             }
         });
         if (rc) return rc;
@@ -996,6 +1091,91 @@ int solve_mixed(const fvpcg_matrix* A, const double* b, double* x, double outer_
         stats->true_rel_res = stats->rel_res;
         stats->device_ms = elapsed(w.t_begin, w.t_end);
         stats->iter_ms = iter_ms;
+    }
+    return h.status;
+}
+
+// Mixed precision with reliable updates.  Stats: iters = FP32 iterations,
+// outer_iters = FP64 updates; status as the FP64 side decides it.
+int solve_mixed_reliable(const fvpcg_matrix* A, const double* b, double* x, double tol, int update_every, int maxit,
+                         hipStream_t s, fvpcg_stats* stats) {
+    const fvpcg_mesh* m = A->mesh;
+    const int n = m->n;
+    Work& w = *A->work;
+    int rc;
+    if ((rc = work_init(w, n)) || (rc = work_need_mixed(w))) return rc;
+    const Geom gx = geom_for(n, kBsMixed);
+    const int K = update_every;
+    const int window = std::max(kReliableWindow, 10 * K);
+    FV_HIP(hipEventRecord(w.t_begin, s));
+    if ((rc = state_reset(w, 0, tol, INT_MAX, s)) || (rc = state_reset(w, 1, 0.0, maxit, s))) return rc;
+    DevState* so = &w.st[0];
+    DevState* si = &w.st[1];
+    double* part = w.partials;
+    DevState h, hi;
+    // r = b - A x0, ||b||, scale = ||r0||; r32 = fp32(r / scale), c = z = s = p = 0
+    FV_LAYOUT(m, hipLaunchKernelGGL((k_mixed_residual<kBsMixed, W_, CI_>), dim3(gx.grid), dim3(kBsMixed), 0, s, cols_,
+                                    A->val, A->d, n, gx, b, x, w.r, 0, so, part));
+    FV_LAUNCHED();
+    if ((rc = state_read(w, 0, &h, s))) return rc;
+    int offset = 0, updates = 0, wi = 0;
+    FV_HIP(hipEventRecord(w.t_it0, s));
+    if (!h.done) {
+        hipLaunchKernelGGL((k_mixed_cast<kBsMixed>), dim3(gx.grid), dim3(kBsMixed), 0, s, w.r, n, gx, so, w.r32, w.r32b,
+                           w.c32, w.z32, w.s32, w.p32, si, part);
+        FV_LAYOUT(m, hipLaunchKernelGGL((k_pipe_init_w<kBsMixed, float, W_, CI_, true>), dim3(gx.grid), dim3(kBsMixed), 0,
+                                        s, cols_, A->val32_cs, A->d32, n, gx, w.r32, w.w32[wi], si, part));
+        FV_LAUNCHED();
+        for (;;) {
+            for (int k = 0; k < K; ++k) {
+                PipeVec<float> a{mesh_cols(m), A->val32_cs, A->d32, w.w32[wi], w.w32[wi ^ 1], w.z32, w.s32, w.p32,
+                                 w.c32, w.r32, nullptr, nullptr};
+                FV_LAYOUT(m, hipLaunchKernelGGL((k_pipe_iter<kBsMixed, float, W_, CI_, true, false>), dim3(gx.grid),
+                                                dim3(kBsMixed), 0, s, a, n, gx, si, part));
+                wi ^= 1;
+            }
+            ++updates;
+            hipLaunchKernelGGL((k_ru_accumulate<kBsMixed>), dim3(gx.grid), dim3(kBsMixed), 0, s, x, w.c32, n, gx, so);
+            FV_LAYOUT(m, hipLaunchKernelGGL((k_ru_residual<kBsMixed, W_, CI_>), dim3(gx.grid), dim3(kBsMixed), 0, s,
+                                            cols_, A->val, A->d, A->val32, A->d32, n, gx, b, x, w.r32, w.s32, w.p32,
+                                            w.z32, so, si, offset, maxit, window, updates, part);
+                         hipLaunchKernelGGL((k_replace_wz<kBsMixed, W_, CI_, true>), dim3(gx.grid), dim3(kBsMixed), 0,
+                                            s, cols_, A->val32_cs, A->d32, n, gx, w.r32, w.s32, w.w32[wi], w.z32, si,
+                                            so, part));
+            FV_LAUNCHED();
+            if ((rc = state_read_both(w, &h, &hi, s))) return rc;
+            if (h.done) break;
+            if (hi.done) {
+                // the FP32 recurrences stopped (breakdown): restart them from
+                // the replaced residual; a breakdown in a restart's first
+                // iteration ends the solve
+                if (hi.iter == 0) {
+                    h.status = FVPCG_BREAKDOWN;
+                    break;
+                }
+                offset += hi.iter;
+                if ((rc = state_reset(w, 1, 0.0, maxit - offset, s))) return rc;
+                FV_LAYOUT(m, hipLaunchKernelGGL((k_pipe_init_w<kBsMixed, float, W_, CI_, true>), dim3(gx.grid),
+                                                dim3(kBsMixed), 0, s, cols_, A->val32_cs, A->d32, n, gx, w.r32,
+                                                w.w32[wi], si, part));
+                FV_LAUNCHED();
+            }
+        }
+    }
+    if (h.zero_b) FV_HIP(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
+    FV_HIP(hipEventRecord(w.t_it1, s));
+    FV_HIP(hipEventRecord(w.t_end, s));
+    FV_HIP(hipStreamSynchronize(s));
+    if (stats) {
+        stats->iters = updates == 0 ? 0 : offset + hi.iter;
+        stats->outer_iters = updates;
+        stats->status = h.status;
+        stats->b_norm = h.bnorm;
+        stats->r0_norm = h.r0norm;
+        stats->rel_res = h.bnorm > 0 ? sqrt(h.rho) / h.bnorm : 0.0;
+        stats->true_rel_res = stats->rel_res;
+        stats->device_ms = elapsed(w.t_begin, w.t_end);
+        stats->iter_ms = elapsed(w.t_it0, w.t_it1);
     }
     return h.status;
 }

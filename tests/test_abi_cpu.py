@@ -32,10 +32,11 @@ def lib_path():
 
 def test_header_declares_the_boundary():
     names = declared()
-    for n in ["fvpcg_mesh_create", "fvpcg_matrix_create", "fvpcg_solve", "fvpcg_solve_mixed", "fvpcg_solve_batched",
+    for n in ["fvpcg_mesh_create", "fvpcg_matrix_create", "fvpcg_solve", "fvpcg_solve_mixed",
+              "fvpcg_solve_mixed_reliable", "fvpcg_solve_batched",
               "fvpcg_solve_backward", "fvpcg_spmv", "fvpcg_stream_calibrate", "fvpcg_last_error"]:
         assert n in names
-    assert len(names) == 17
+    assert len(names) == 18
 
 
 def test_library_exports_every_declared_symbol(lib_path):

@@ -105,6 +105,74 @@ def test_mixed_outer_limit(fv):
     dc.close()
 
 
+# ------------------------------------------------------------------ mixed, reliable updates
+
+# (case, tolerance): the graded cavity is ill-conditioned enough that a 1e-10
+# residual leaves an error above 1e-8, so it is solved to 1e-12
+RELIABLE_CASES = {k: (v, 1e-10) for k, v in MIXED_CASES.items()}
+RELIABLE_CASES["cavity_24x24x8"] = (lambda: fc.cavity((24, 24, 8)), 1e-12)
+
+
+@pytest.mark.parametrize("name", list(RELIABLE_CASES))
+def test_mixed_reliable_matches_fp64_solution(fv, orc, name):
+    """FP32 pipelined recurrences re-anchored to the FP64 residual every 10
+    iterations: error against the oracle's FP64 solution (standard CG to
+    1e-13) <= 1e-8, FP64 true residual (the oracle's product) <= tol, and an
+    FP32 iteration count within 3 update periods or 15% of the oracle running
+    the same algorithm (FP32 rounding orders differ)."""
+    say("mixed reliable", name)
+    make, tol = RELIABLE_CASES[name]
+    case = make()
+    dc = DevCase(case, fp32_copy=True)
+    x, st = fv.solve_mixed_reliable(dc.A, dc.b, tol=tol, update_every=10)
+    assert st["status"] == 0, st
+    xg = x.cpu().numpy()
+    xs, _ = orc.cg(case, case.b, tol=1e-13, maxit=100000)
+    assert rel(xg, xs) <= 1e-8
+    tr = np.linalg.norm(case.b - orc.spmv(case, xg)) / np.linalg.norm(case.b)
+    assert tr <= tol * 1.01
+    assert st["true_rel_res"] == pytest.approx(tr, rel=1e-6, abs=1e-15)
+    xo, so = orc.mixed_reliable(case, case.b, tol=tol, update_every=10)
+    assert so["status"] == 0
+    assert abs(st["iters"] - so["iters"]) <= max(30, 0.15 * so["iters"]), (st["iters"], so["iters"])
+    assert st["outer_iters"] >= -(-st["iters"] // 10)
+    dc.close()
+
+
+def test_mixed_reliable_edge_cases(fv, orc):
+    say("mixed reliable edge cases")
+    import torch
+
+    case = fc.varcoef((10, 10, 10), seed=3)
+    dc = DevCase(case, fp32_copy=True)
+    x = torch.ones(case.n, dtype=torch.float64, device="cuda")
+    x, st = fv.solve_mixed_reliable(dc.A, torch.zeros_like(dc.b), x=x)
+    assert st["status"] == 0 and torch.count_nonzero(x).item() == 0 and st["iters"] == 0
+    xs, _ = orc.cg(case, case.b, tol=1e-13, maxit=10000)
+    x, st = fv.solve_mixed_reliable(dc.A, dc.b, x=to_dev(xs), tol=1e-10)
+    assert st["status"] == 0 and st["iters"] == 0 and st["outer_iters"] == 0
+    # iteration limit, and an update after every iteration
+    x, st = fv.solve_mixed_reliable(dc.A, dc.b, tol=1e-14, update_every=4, maxit=10)
+    assert st["status"] == 1 and st["iters"] == 10 and st["outer_iters"] == 3
+    x, st = fv.solve_mixed_reliable(dc.A, dc.b, tol=1e-10, update_every=1)
+    assert st["status"] == 0 and st["outer_iters"] == st["iters"]
+    assert rel(x.cpu().numpy(), xs) <= 1e-8
+    # unattainable tolerance: the FP64 residual stagnates, the solve ends
+    x, st = fv.solve_mixed_reliable(dc.A, dc.b, tol=1e-30, update_every=5, maxit=100000)
+    assert st["status"] == 1 and st["iters"] < 100000
+    tr = np.linalg.norm(case.b - orc.spmv(case, x.cpu().numpy())) / np.linalg.norm(case.b)
+    assert tr <= 1e-13
+    with pytest.raises(fv.FVPCGError) as e:
+        fv.solve_mixed_reliable(dc.A, dc.b, update_every=0)
+    assert e.value.code == fv.INVALID_ARG
+    dc.close()
+    dc = DevCase(case)  # no FP32 copy
+    with pytest.raises(fv.FVPCGError) as e:
+        fv.solve_mixed_reliable(dc.A, dc.b)
+    assert e.value.code == fv.UNSUPPORTED
+    dc.close()
+
+
 # ------------------------------------------------------------------ adjoint
 
 def _loss_setup(orc, case):

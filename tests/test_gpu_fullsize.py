@@ -99,6 +99,26 @@ def test_varcoef192_mixed(fv, orc, varcoef192):
     dc.close()
 
 
+def test_varcoef192_mixed_reliable(fv, orc, varcoef192):
+    """The reliable-update mixed solve at full size: FP64 true residual (the
+    oracle's product) <= 1e-10 and the FP64 GPU solution to 1e-12 within
+    1e-8; FP32 iterations at most 1.3x the FP64 pipelined count to 1e-10."""
+    case = varcoef192
+    say("varcoef192 mixed reliable")
+    dc = DevCase(case, fp32_copy=True)
+    x, st = fv.solve_mixed_reliable(dc.A, dc.b, tol=1e-10, update_every=10)
+    assert st["status"] == 0, st
+    xg = x.cpu().numpy()
+    tr = np.linalg.norm(case.b - orc.spmv(case, xg)) / np.linalg.norm(case.b)
+    assert tr <= 1.01e-10
+    assert st["true_rel_res"] == pytest.approx(tr, rel=1e-6)
+    xr, sr = fv.solve(dc.A, dc.b, tol=1e-12, maxit=50000, method="cg")
+    assert rel(xg, xr.cpu().numpy()) <= 1e-8
+    _, sp = fv.solve(dc.A, dc.b, tol=1e-10, maxit=50000, method="pipecg")
+    assert st["iters"] <= 1.3 * sp["iters"] + 10, (st["iters"], sp["iters"])
+    dc.close()
+
+
 def test_cavity256_pcg(fv, orc):
     say("generating cavity256")
     case = fc.make("cavity256")
