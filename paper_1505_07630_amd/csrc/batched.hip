@@ -177,9 +177,15 @@ struct Team {
 };
 
 // Barrier among the team's workgroups: a monotonic arrival counter (barrier k
-// completes when it reaches k * size), agent-scope release before arriving
-// and acquire after, so every member sees the others' vector writes.  The wait
-// is bounded: past the timeout (or when another workgroup has timed out) the
+// completes when it reaches k * size).  The workgroup's threads meet at a
+// workgroup barrier; thread 0 then arrives with an agent-scope release,
+// polls the counter with relaxed loads and ends with one agent-scope acquire
+// fence before the closing workgroup barrier.  Under the HSA memory model
+// (HRF-indirect, inclusive scopes) happens-before is transitive through the
+// workgroup barriers and thread 0's agent-scope synchronisation, so every
+// member sees the other members' vector writes; a fence per thread would
+// only repeat the L2 write-back and invalidate once per wave.  The wait is
+// bounded: past the timeout (or when another workgroup has timed out) the
 // abort flag is set and false returned, and every workgroup leaves.
 __device__ bool team_barrier(Team& t) {
     t.nbar += 1;
@@ -188,14 +194,13 @@ __device__ bool team_barrier(Team& t) {
         return true;
     }
     __shared__ int s_ok;
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned long long target = (unsigned long long)t.nbar * (unsigned long long)t.size;
         __hip_atomic_fetch_add(t.arrive, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
         const unsigned long long t0 = (unsigned long long)wall_clock64();
-        while (__hip_atomic_load(t.arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(t.arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(t.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 ok = 0;
                 break;
@@ -207,13 +212,11 @@ __device__ bool team_barrier(Team& t) {
             }
             __builtin_amdgcn_s_sleep(1);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_ok = ok;
     }
     __syncthreads();
-    const bool ok = s_ok != 0;
-    __threadfence();
-    __syncthreads();
-    return ok;
+    return s_ok != 0;
 }
 
 // Sum NV values over the team: workgroup totals, then (size > 1) each member
