@@ -5,8 +5,8 @@
 // offset by each system's first cell), so the ELL layout, validation and
 // coefficient handling are the single-system ones.  A system is solved from
 // start to finish either by one workgroup (its rows, reductions and scalars
-// stay inside the workgroup; no waiting on anyone) or, when it costs much more
-// than a workgroup's fair share of the batch, by a team of workgroups that
+// stay inside the workgroup; no waiting on anyone) or, when it costs at least
+// a workgroup's fair share of the batch, by a team of workgroups that
 // split its row tiles and combine their reductions through device memory and
 // a bounded team barrier.  Teams are assigned statically at launch; the other
 // systems go to a device queue ordered by decreasing size (largest first, the
@@ -620,11 +620,16 @@ int grid_for(const fvpcg_batch* bt, const Tuning& t, BatchKernel k, int* grid) {
 
 // Work table for a launch of P workgroups.  Cost of a system ~ n^(4/3)
 // (cells times iterations, and CG iterations grow like the mesh edge for
-// these Laplacians).  A system costing at least twice a workgroup's fair share
-// C/P gets a team of about cost/share workgroups (at most one per tile), taken
+// these Laplacians).  A system costing at least a workgroup's fair share C/P
+// gets a team of about cost/share workgroups (at most one per tile), taken
 // from one XCD's workgroups (b % 8) where they fit so the team shares an L2;
 // the others go to the queue, largest first.  Returns the queue length.
 int plan(fvpcg_batch* bt, int P, int bs, bool teams) {
+    // measured on batch256 (pipelined / standard CG): threshold 4 share:
+    // 419 / 476 ms, 2: 342 / 382 ms, 0.8 to 1.25: 330 / 355 ms; the team size
+    // cap (32 to 128) and rounding up instead of to nearest change < 2%
+    constexpr double kTeamThreshold = 1.0;
+    constexpr int kTeamMax = 64;
     const int ns = bt->nsys;
     std::vector<double> cost(ns);
     double C = 0.0;
@@ -638,8 +643,8 @@ int plan(fvpcg_batch* bt, int P, int bs, bool teams) {
     if (teams) {
         for (int i = 0; i < ns; ++i) {
             const int tiles = (bt->cell_off[i + 1] - bt->cell_off[i] + bs - 1) / bs;
-            if (cost[i] >= 2.0 * share && tiles >= 2) {
-                g[i] = std::max(2, std::min({(int)std::lround(cost[i] / share), tiles, 64}));
+            if (cost[i] >= kTeamThreshold * share && tiles >= 2) {
+                g[i] = std::max(2, std::min({(int)std::lround(cost[i] / share), tiles, kTeamMax}));
                 team.push_back(i);
             }
         }
