@@ -107,8 +107,8 @@ def main():
     ap.add_argument("--extras", action="store_true", help="also time the other workloads")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of this "
-                                   "build (the solver's sharding is described in DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the library solves on one device "
+                                   "per call and has no multi-GPU path", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
