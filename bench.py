@@ -92,7 +92,21 @@ def cpu_baseline(case, iters):
     return {"value": st["iters"] / dt, "unit": "CG iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{st['iters']} fixed iterations (plus setup and final residual) of the folded pipelined "
                       f"Jacobi-CG on the full 192^3 workload, single thread, {dt:.1f} s",
-            "seconds": dt}
+            "seconds": dt, "host": host_cpu()}
+
+
+def host_cpu():
+    """CPU model and logical core count of the host the oracle ran on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cores": os.cpu_count()}
 
 
 def main():
@@ -307,23 +321,36 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None):
     for m_, A_, b_ in singles:
         A_.close()
         m_.close()
-    for name, method in (("laplace32", "pipecg"), ("laplace32", "cg"), ("cavity256", "cg")):
+    # small and graded cases: one warm-up solve, then repeated solves timed one
+    # by one with HIP events on the solve stream (median reported), and
+    # fixed-iteration runs (tol = 0) for the per-iteration rate: 32^3 in ten
+    # runs of 200 iterations (iterating far past convergence would end in a
+    # breakdown once the residual vanishes), the cavity in one run of 500
+    for name, method, reps, fixed in (("laplace32", "pipecg", 21, (200, 10)), ("laplace32", "cg", 21, (200, 10)),
+                                      ("cavity256", "cg", 3, (500, 1))):
         c = fvcases.make(name)
         mesh = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
         A = fv.Matrix(mesh, to(c.diag, torch.float64), to(c.upper, torch.float64))
         b = to(c.b, torch.float64)
         fv.solve(A, b, tol=c.tol, method=method)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        its = 0
-        for _ in range(3):
+        times = []
+        for _ in range(reps):
             _, st = fv.solve(A, b, tol=c.tol, method=method, maxit=100000)
-            its += st["iters"]
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        res[f"{name}/{method}"] = {"iters_per_solve": st["iters"], "iters_per_s": round(its / dt, 1),
-                                   "ms_per_solve": round(dt / 3 * 1e3, 3), "status": st["status_name"]}
+            times.append(st["device_ms"])
+        times.sort()
+        med = times[len(times) // 2]
+        f_its, f_ms = 0, 0.0
+        for _ in range(fixed[1]):
+            _, sf = fv.solve(A, b, tol=0.0, method=method, maxit=fixed[0])
+            f_its += sf["iters"]
+            f_ms += sf["iter_ms"]
+        res[f"{name}/{method}"] = {"iters_per_solve": st["iters"], "status": st["status_name"],
+                                   "median_ms_per_solve": round(med, 3), "solves": reps,
+                                   "iters_per_s": round(st["iters"] / med * 1e3, 1),
+                                   "fixed_iters": f_its, "fixed_iters_per_s": round(f_its / f_ms * 1e3, 1)}
         log(f"extra {name}/{method}: {res[f'{name}/{method}']}")
+        A.close()
+        mesh.close()
     return res
 
 

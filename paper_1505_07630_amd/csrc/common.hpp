@@ -136,11 +136,31 @@ __device__ __forceinline__ int xcd_block(int b, int G) {
     return x * q + (x < rem ? x : rem) + i;
 }
 
+// v from the lane K places lower in the same row of 16 lanes, 0 for the
+// first K lanes of each row (DPP row_shr:K with bound_ctrl zero fill; the
+// two 32-bit halves move separately).
+template <int K>
+__device__ __forceinline__ double row_shr(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x110 + K, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x110 + K, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum over the 64 lanes of a wave (all lanes active): an inclusive scan
+// within each row of 16 lanes by DPP row shifts (ALU cross-lane moves, no LDS
+// round trips), then the four row totals, read from lanes 15, 31, 47 and 63,
+// added in that order.  Every lane returns the same, order-fixed sum.
 __device__ __forceinline__ double wave_sum(double v) {
-    // Butterfly: every lane ends with the same, order-fixed sum.
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += row_shr<1>(v);
+    v += row_shr<2>(v);
+    v += row_shr<4>(v);
+    v += row_shr<8>(v);
+    return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
 }
 
 // Sum NV values over a workgroup of BS threads; the result is valid in thread 0.
