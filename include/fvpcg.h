@@ -198,7 +198,9 @@ FVPCG_API int fvpcg_batch_destroy(fvpcg_batch* batch);
  * (may be NULL).  Returns FVPCG_OK if every system converged, else the
  * first non-OK status in system order.  Systems far larger than a
  * workgroup's share of the batch may be solved by a team of workgroups that
- * synchronise through device memory; each such wait is bounded
+ * synchronise through device memory.  A launch with teams uses exactly the
+ * device's resident workgroup capacity, so kernels running at the same time
+ * on other streams can delay members; each wait is bounded
  * (FVPCG_BATCH_BARRIER_TIMEOUT_MS, default 5000): on a timeout every
  * workgroup leaves, x and stats are invalid and FVPCG_DEVICE_ERROR is
  * returned.  The first call per batch shape times the launch candidates

@@ -68,13 +68,17 @@ def _ptr(t, dtype, n, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def version() -> int:
+def fvpcg_version() -> int:
     return lib().fvpcg_version()
 
 
-def last_error() -> str:
+def fvpcg_last_error() -> str:
     m = lib().fvpcg_last_error()
     return m.decode() if m else ""
+
+
+version = fvpcg_version
+last_error = fvpcg_last_error
 
 
 # ---------------------------------------------------------------- C-ABI names
@@ -315,6 +319,17 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def fvpcg_batch_create(cell_off, face_off, owner, neighbour, diag, upper, lower=None, stream=None) -> Batch:
+    """The C-ABI name of `Batch(...)`: the handle is `.handle`, released by
+    `fvpcg_batch_destroy` (or `.close()`)."""
+    return Batch(cell_off, face_off, owner, neighbour, diag, upper, lower, stream)
+
+
+def fvpcg_batch_destroy(B: Batch):
+    B.close()
+    return OK
 
 
 def fvpcg_solve_batched(B: Batch, b, x=None, tol=1e-8, maxit=10000, method="pipecg", precond="jacobi",

@@ -85,3 +85,11 @@ def test_kernel_sources_build_for_gfx950_only():
     for src in build.SOURCES:
         text = open(os.path.join(build.CSRC, src)).read()
         assert "__CUDA" not in text and "__HIP_PLATFORM" not in text
+
+
+def test_binding_has_every_declared_name():
+    """The Python binding exposes each C-ABI entry point under the same name."""
+    import paper_1505_07630_amd as fv
+
+    for n in declared():
+        assert callable(getattr(fv, n, None)), n
