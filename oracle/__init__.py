@@ -21,14 +21,18 @@ OK, NOT_CONVERGED, BREAKDOWN = 0, 1, -3
 PRECOND = {"none": 0, "jacobi": 1}
 
 
+SOURCES = ("oracle.c", "amg.c")
+
+
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so (plain C99, gcc)."""
-    src = os.path.join(HERE, "oracle.c")
-    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(src):
+    """Compile oracle.c and amg.c into liboracle.so (plain C99, gcc)."""
+    srcs = [os.path.join(HERE, f) for f in SOURCES]
+    newest = max(os.path.getmtime(f) for f in srcs + [os.path.join(HERE, "oracle.h")])
+    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= newest:
         return LIB_PATH
     tmp = LIB_PATH + ".tmp"
     cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
+           "-Wall", "-Wextra", "-o", tmp, *srcs, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -67,6 +71,22 @@ def lib():
         L.or_refine.restype = i32
         L.or_mixed_reliable.argtypes = [i32, i32, P, P, P, P, P, P, P, d, i32, i32, P]
         L.or_mixed_reliable.restype = i32
+        L.or_amg_setup.argtypes = [i32, i32, P, P, P, P, P, d, i32, i32]
+        L.or_amg_setup.restype = P
+        L.or_amg_free.argtypes = [P]
+        L.or_amg_free.restype = None
+        L.or_amg_levels.argtypes = [P]
+        L.or_amg_levels.restype = i32
+        L.or_amg_level_info.argtypes = [P, i32, P, P, P, P]
+        L.or_amg_level_info.restype = None
+        L.or_amg_aggregates.argtypes = [P, i32, P]
+        L.or_amg_aggregates.restype = None
+        L.or_amg_export.argtypes = [P, i32, i32, P, P, P, P, P]
+        L.or_amg_export.restype = i32
+        L.or_amg_vcycle.argtypes = [P, P, P]
+        L.or_amg_vcycle.restype = None
+        L.or_amg_pcg.argtypes = [P, P, P, d, i32, P]
+        L.or_amg_pcg.restype = i32
         L.or_adjoint_grads.argtypes = [i32, i32, P, P, P, P, P, P, P]
         L.or_adjoint_grads.restype = None
         _lib = L
@@ -174,6 +194,64 @@ def mixed_reliable(A, b, x0=None, tol=1e-10, update_every=20, maxit=100000):
     st = Stats()
     lib().or_mixed_reliable(*A.args(), _p(b), _p(x), float(tol), int(update_every), int(maxit), ctypes.byref(st))
     return x, st.asdict()
+
+
+class AMG:
+    """Smoothed-aggregation AMG hierarchy built by the oracle (amg.c)."""
+
+    def __init__(self, A, theta=0.08, max_levels=12, coarse_size=64):
+        A = _as_sys(A)
+        self._sys = A
+        self.n = A.n
+        h = lib().or_amg_setup(*A.args(), float(theta), int(max_levels), int(coarse_size))
+        if not h:
+            raise ValueError("AMG setup failed: coarsest level not positive definite")
+        self._h = ctypes.c_void_p(h)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().or_amg_free(self._h)
+            self._h = None
+
+    @property
+    def levels(self):
+        return lib().or_amg_levels(self._h)
+
+    def level_info(self, l):
+        n, nnz, nc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        w = ctypes.c_double()
+        lib().or_amg_level_info(self._h, int(l), ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(nc),
+                                ctypes.byref(w))
+        return {"n": n.value, "nnz": nnz.value, "n_coarse": nc.value, "omega": w.value}
+
+    def aggregates(self, l):
+        out = np.empty(self.level_info(l)["n"], dtype=np.int32)
+        lib().or_amg_aggregates(self._h, int(l), _p(out))
+        return out
+
+    def export(self, l, which="A"):
+        """(indptr, indices, data, shape) of level l's A or P."""
+        w = 0 if which == "A" else 1
+        rows, cols = ctypes.c_int32(), ctypes.c_int32()
+        nnz = lib().or_amg_export(self._h, int(l), w, ctypes.byref(rows), ctypes.byref(cols), None, None, None)
+        ptr = np.empty(rows.value + 1, dtype=np.int32)
+        col = np.empty(nnz, dtype=np.int32)
+        val = np.empty(nnz)
+        lib().or_amg_export(self._h, int(l), w, ctypes.byref(rows), ctypes.byref(cols), _p(ptr), _p(col), _p(val))
+        return ptr, col, val, (rows.value, cols.value)
+
+    def vcycle(self, b):
+        b = _f64(b)
+        x = np.empty(self.n)
+        lib().or_amg_vcycle(self._h, _p(b), _p(x))
+        return x
+
+    def pcg(self, b, x0=None, tol=1e-8, maxit=1000):
+        b = _f64(b)
+        x = np.zeros(self.n) if x0 is None else _f64(x0).copy()
+        st = Stats()
+        lib().or_amg_pcg(self._h, _p(b), _p(x), float(tol), int(maxit), ctypes.byref(st))
+        return x, st.asdict()
 
 
 def adjoint_grads(A, x, lam):

@@ -1,0 +1,451 @@
+/*
+ * CPU oracle, smoothed-aggregation AMG preconditioner for CG -- TEST
+ * INFRASTRUCTURE.
+ *
+ * The paper compares its Jacobi-preconditioned solvers with aggregation-AMG
+ * preconditioned CG and pipelined CG (Section 5, Table pcgs2: 325 -> 28 CG
+ * iterations at 64^3).  It does not print the AMG it used; this file is the
+ * classical smoothed-aggregation method of Vanek, Mandel and Brezina written
+ * from its definition:
+ *   strength    j ~ i  iff  j != i and |a_ij| >= theta_l sqrt(a_ii a_jj),
+ *               theta_{l+1} = theta_l / 2;
+ *   aggregates  three greedy passes in index order: (1) i and all its strong
+ *               neighbours, if none is aggregated yet, form an aggregate;
+ *               (2) a remaining i joins the pass-1 aggregate of its strongest
+ *               strong neighbour (ties: lowest index); (3) what remains forms
+ *               aggregates of i and its still-free strong neighbours;
+ *   prolongator P = (I - omega D^-1 A) P_t, P_t the aggregate indicator,
+ *               omega = 4 / (3 lambda), lambda = max_i sum_j |a_ij| / a_ii
+ *               (Gershgorin bound of rho(D^-1 A));
+ *   coarse      A_c = P^T A P (Galerkin), R = P^T;
+ *   levels      until n <= coarse_size, the level limit, or an aggregation
+ *               that keeps more than 60% of the unknowns; the last level is
+ *               solved exactly (dense Cholesky);
+ *   cycle       V(1,1): x = omega D^-1 b; r = b - A x; x += P V(R r);
+ *               x += omega D^-1 (b - A x).
+ * The cycle is symmetric and positive definite for SPD A, so it is a valid
+ * preconditioner for standard CG.  Plain C, FP64, single thread.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t n, m;     /* rows, columns */
+    int32_t* ptr;     /* n + 1 */
+    int32_t* col;     /* sorted within each row */
+    double* val;
+} csr_t;
+
+struct or_amg {
+    int32_t nlev;
+    csr_t A[OR_AMG_MAX_LEVELS], P[OR_AMG_MAX_LEVELS], R[OR_AMG_MAX_LEVELS];
+    double* d[OR_AMG_MAX_LEVELS];
+    double omega[OR_AMG_MAX_LEVELS];
+    int32_t* agg[OR_AMG_MAX_LEVELS];
+    double* chol;   /* dense lower factor of the last level, row-major */
+    double *b[OR_AMG_MAX_LEVELS], *x[OR_AMG_MAX_LEVELS], *r[OR_AMG_MAX_LEVELS];
+};
+
+static void csr_free(csr_t* a)
+{
+    free(a->ptr); free(a->col); free(a->val);
+    memset(a, 0, sizeof(*a));
+}
+
+static void sort_row(int32_t* col, double* val, int32_t len)
+{
+    for (int32_t i = 1; i < len; ++i) {
+        int32_t c = col[i]; double v = val[i]; int32_t j = i - 1;
+        while (j >= 0 && col[j] > c) { col[j + 1] = col[j]; val[j + 1] = val[j]; --j; }
+        col[j + 1] = c; val[j + 1] = v;
+    }
+}
+
+/* The LDU matrix as CSR: row c holds its diagonal, upper[f] at column
+ * neighbour[f] for faces it owns and lower[f] at column owner[f] for faces
+ * it neighbours (Section 4.2's nnz = n + 2F). */
+static void csr_from_ldu(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                         const double* diag, const double* upper, const double* lower, csr_t* A)
+{
+    A->n = A->m = n;
+    A->ptr = calloc((size_t)n + 1, sizeof(int32_t));
+    for (int32_t c = 0; c < n; ++c) A->ptr[c + 1] = 1;
+    for (int32_t f = 0; f < nf; ++f) { A->ptr[owner[f] + 1]++; A->ptr[nb[f] + 1]++; }
+    for (int32_t c = 0; c < n; ++c) A->ptr[c + 1] += A->ptr[c];
+    int32_t nnz = A->ptr[n];
+    A->col = malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    A->val = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    int32_t* fill = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int32_t c = 0; c < n; ++c) {
+        fill[c] = A->ptr[c] + 1;
+        A->col[A->ptr[c]] = c;
+        A->val[A->ptr[c]] = diag[c];
+    }
+    for (int32_t f = 0; f < nf; ++f) {
+        int32_t o = owner[f], m = nb[f];
+        A->col[fill[o]] = m; A->val[fill[o]++] = upper[f];
+        A->col[fill[m]] = o; A->val[fill[m]++] = lower[f];
+    }
+    for (int32_t c = 0; c < n; ++c) sort_row(A->col + A->ptr[c], A->val + A->ptr[c], A->ptr[c + 1] - A->ptr[c]);
+    free(fill);
+}
+
+static void csr_diag(const csr_t* A, double* d)
+{
+    for (int32_t i = 0; i < A->n; ++i) {
+        d[i] = 0.0;
+        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p)
+            if (A->col[p] == i) d[i] = A->val[p];
+    }
+}
+
+/* y = A v */
+static void csr_mv(const csr_t* A, const double* v, double* y)
+{
+    for (int32_t i = 0; i < A->n; ++i) {
+        double s = 0.0;
+        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p) s += A->val[p] * v[A->col[p]];
+        y[i] = s;
+    }
+}
+
+static void csr_transpose(const csr_t* A, csr_t* T)
+{
+    T->n = A->m; T->m = A->n;
+    int32_t nnz = A->ptr[A->n];
+    T->ptr = calloc((size_t)T->n + 1, sizeof(int32_t));
+    T->col = malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    T->val = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    for (int32_t p = 0; p < nnz; ++p) T->ptr[A->col[p] + 1]++;
+    for (int32_t j = 0; j < T->n; ++j) T->ptr[j + 1] += T->ptr[j];
+    int32_t* fill = malloc(sizeof(int32_t) * (size_t)(T->n > 0 ? T->n : 1));
+    for (int32_t j = 0; j < T->n; ++j) fill[j] = T->ptr[j];
+    for (int32_t i = 0; i < A->n; ++i)  /* rows in order: columns of T come out sorted */
+        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p) {
+            int32_t q = fill[A->col[p]]++;
+            T->col[q] = i; T->val[q] = A->val[p];
+        }
+    free(fill);
+}
+
+/* C = X Y: row by row with a dense accumulator; within a row the products
+ * are added in the order of X's columns, then Y's columns. */
+static void csr_mm(const csr_t* X, const csr_t* Y, csr_t* C)
+{
+    C->n = X->n; C->m = Y->m;
+    C->ptr = calloc((size_t)C->n + 1, sizeof(int32_t));
+    double* acc = calloc((size_t)(Y->m > 0 ? Y->m : 1), sizeof(double));
+    int32_t* mark = malloc(sizeof(int32_t) * (size_t)(Y->m > 0 ? Y->m : 1));
+    for (int32_t k = 0; k < Y->m; ++k) mark[k] = -1;
+    int32_t* list = malloc(sizeof(int32_t) * (size_t)(Y->m > 0 ? Y->m : 1));
+    size_t cap = 16, nnz = 0;
+    C->col = malloc(sizeof(int32_t) * cap);
+    C->val = malloc(sizeof(double) * cap);
+    for (int32_t i = 0; i < X->n; ++i) {
+        int32_t len = 0;
+        for (int32_t p = X->ptr[i]; p < X->ptr[i + 1]; ++p) {
+            int32_t j = X->col[p];
+            double xv = X->val[p];
+            for (int32_t q = Y->ptr[j]; q < Y->ptr[j + 1]; ++q) {
+                int32_t k = Y->col[q];
+                if (mark[k] != i) { mark[k] = i; acc[k] = 0.0; list[len++] = k; }
+                acc[k] += xv * Y->val[q];
+            }
+        }
+        /* sort the touched columns */
+        for (int32_t a = 1; a < len; ++a) {
+            int32_t c = list[a], b = a - 1;
+            while (b >= 0 && list[b] > c) { list[b + 1] = list[b]; --b; }
+            list[b + 1] = c;
+        }
+        if (nnz + (size_t)len > cap) {
+            while (nnz + (size_t)len > cap) cap *= 2;
+            C->col = realloc(C->col, sizeof(int32_t) * cap);
+            C->val = realloc(C->val, sizeof(double) * cap);
+        }
+        for (int32_t a = 0; a < len; ++a) { C->col[nnz] = list[a]; C->val[nnz++] = acc[list[a]]; }
+        C->ptr[i + 1] = (int32_t)nnz;
+    }
+    free(acc); free(mark); free(list);
+}
+
+/* Strength and the three aggregation passes; returns the aggregate count. */
+static int32_t aggregate(const csr_t* A, const double* d, double theta, int32_t* agg)
+{
+    const int32_t n = A->n;
+    for (int32_t i = 0; i < n; ++i) agg[i] = -1;
+#define STRONG(i, p) (A->col[p] != (i) && fabs(A->val[p]) >= theta * sqrt(fabs(d[i] * d[A->col[p]])))
+    int32_t na = 0;
+    for (int32_t i = 0; i < n; ++i) {            /* pass 1 */
+        if (agg[i] >= 0) continue;
+        int free_nbhd = 1;
+        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p)
+            if (STRONG(i, p) && agg[A->col[p]] >= 0) { free_nbhd = 0; break; }
+        if (!free_nbhd) continue;
+        agg[i] = na;
+        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p)
+            if (STRONG(i, p)) agg[A->col[p]] = na;
+        ++na;
+    }
+    int32_t* pass1 = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    memcpy(pass1, agg, sizeof(int32_t) * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) {            /* pass 2 */
+        if (agg[i] >= 0) continue;
+        int32_t best = -1; double bw = -1.0;
+        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p) {
+            int32_t j = A->col[p];
+            if (STRONG(i, p) && pass1[j] >= 0 && fabs(A->val[p]) > bw) { bw = fabs(A->val[p]); best = j; }
+        }
+        if (best >= 0) agg[i] = pass1[best];
+    }
+    for (int32_t i = 0; i < n; ++i) {            /* pass 3 */
+        if (agg[i] >= 0) continue;
+        agg[i] = na;
+        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p)
+            if (STRONG(i, p) && agg[A->col[p]] < 0) agg[A->col[p]] = na;
+        ++na;
+    }
+#undef STRONG
+    free(pass1);
+    return na;
+}
+
+/* P = (I - omega D^-1 A) P_t, row i: 1 at agg[i], minus omega a_ij / a_ii at
+ * agg[j] for every stored a_ij (the diagonal included), in column order. */
+static void smoothed_prolongator(const csr_t* A, const double* d, const int32_t* agg, int32_t na, double omega,
+                                 csr_t* P)
+{
+    const int32_t n = A->n;
+    csr_t Pt = {n, na, NULL, NULL, NULL};
+    Pt.ptr = malloc(sizeof(int32_t) * ((size_t)n + 1));
+    Pt.col = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    Pt.val = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int32_t i = 0; i <= n; ++i) Pt.ptr[i] = i;
+    for (int32_t i = 0; i < n; ++i) { Pt.col[i] = agg[i]; Pt.val[i] = 1.0; }
+    /* S = I - omega D^-1 A as CSR, then P = S P_t */
+    csr_t S = {n, n, NULL, NULL, NULL};
+    int32_t nnz = A->ptr[n];
+    S.ptr = malloc(sizeof(int32_t) * ((size_t)n + 1));
+    S.col = malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    S.val = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    memcpy(S.ptr, A->ptr, sizeof(int32_t) * ((size_t)n + 1));
+    memcpy(S.col, A->col, sizeof(int32_t) * (size_t)nnz);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p)
+            S.val[p] = (A->col[p] == i ? 1.0 : 0.0) - omega * A->val[p] / d[i];
+    csr_mm(&S, &Pt, P);
+    csr_free(&S);
+    csr_free(&Pt);
+}
+
+static double gershgorin(const csr_t* A, const double* d)
+{
+    double lam = 0.0;
+    for (int32_t i = 0; i < A->n; ++i) {
+        double s = 0.0;
+        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p) s += fabs(A->val[p]);
+        s /= d[i];
+        if (s > lam) lam = s;
+    }
+    return lam;
+}
+
+static int dense_cholesky(const csr_t* A, double* L)
+{
+    const int32_t n = A->n;
+    memset(L, 0, sizeof(double) * (size_t)n * (size_t)n);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p) L[(size_t)i * n + A->col[p]] = A->val[p];
+    for (int32_t j = 0; j < n; ++j) {
+        double s = L[(size_t)j * n + j];
+        for (int32_t k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(s > 0.0)) return 0;
+        const double ljj = sqrt(s);
+        L[(size_t)j * n + j] = ljj;
+        for (int32_t i = j + 1; i < n; ++i) {
+            double t = L[(size_t)i * n + j];
+            for (int32_t k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = t / ljj;
+        }
+    }
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = i + 1; j < n; ++j) L[(size_t)i * n + j] = 0.0;
+    return 1;
+}
+
+or_amg* or_amg_setup(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                     const double* diag, const double* upper, const double* lower,
+                     double theta, int32_t max_levels, int32_t coarse_size)
+{
+    if (max_levels < 1) max_levels = 1;
+    if (max_levels > OR_AMG_MAX_LEVELS) max_levels = OR_AMG_MAX_LEVELS;
+    or_amg* h = calloc(1, sizeof(or_amg));
+    csr_from_ldu(n, nf, owner, nb, diag, upper, lower, &h->A[0]);
+    int32_t l = 0;
+    double th = theta;
+    for (;;) {
+        const csr_t* A = &h->A[l];
+        h->d[l] = malloc(sizeof(double) * (size_t)(A->n > 0 ? A->n : 1));
+        csr_diag(A, h->d[l]);
+        h->omega[l] = 4.0 / (3.0 * gershgorin(A, h->d[l]));
+        h->b[l] = calloc((size_t)(A->n > 0 ? A->n : 1), sizeof(double));
+        h->x[l] = calloc((size_t)(A->n > 0 ? A->n : 1), sizeof(double));
+        h->r[l] = calloc((size_t)(A->n > 0 ? A->n : 1), sizeof(double));
+        if (A->n <= coarse_size || l + 1 == max_levels) break;
+        int32_t* agg = malloc(sizeof(int32_t) * (size_t)A->n);
+        int32_t na = aggregate(A, h->d[l], th, agg);
+        if ((double)na > 0.6 * (double)A->n) { free(agg); break; }
+        h->agg[l] = agg;
+        smoothed_prolongator(A, h->d[l], agg, na, h->omega[l], &h->P[l]);
+        csr_transpose(&h->P[l], &h->R[l]);
+        csr_t AP;
+        csr_mm(A, &h->P[l], &AP);
+        csr_mm(&h->R[l], &AP, &h->A[l + 1]);
+        csr_free(&AP);
+        th *= 0.5;
+        ++l;
+    }
+    h->nlev = l + 1;
+    const int32_t nc = h->A[l].n;
+    h->chol = malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1) * (size_t)(nc > 0 ? nc : 1));
+    if (!dense_cholesky(&h->A[l], h->chol)) { or_amg_free(h); return NULL; }
+    return h;
+}
+
+void or_amg_free(or_amg* h)
+{
+    if (!h) return;
+    for (int32_t l = 0; l < OR_AMG_MAX_LEVELS; ++l) {
+        csr_free(&h->A[l]); csr_free(&h->P[l]); csr_free(&h->R[l]);
+        free(h->d[l]); free(h->agg[l]); free(h->b[l]); free(h->x[l]); free(h->r[l]);
+    }
+    free(h->chol);
+    free(h);
+}
+
+int32_t or_amg_levels(const or_amg* h) { return h->nlev; }
+
+void or_amg_level_info(const or_amg* h, int32_t l, int32_t* n, int32_t* nnz, int32_t* n_coarse, double* omega)
+{
+    *n = h->A[l].n;
+    *nnz = h->A[l].ptr[h->A[l].n];
+    *n_coarse = l + 1 < h->nlev ? h->A[l + 1].n : 0;
+    *omega = h->omega[l];
+}
+
+/* Copy out level l's aggregates (n_l entries), or its A / P as CSR
+ * (which = 0: A, 1: P); pass NULL arrays to query only the sizes. */
+void or_amg_aggregates(const or_amg* h, int32_t l, int32_t* out)
+{
+    memcpy(out, h->agg[l], sizeof(int32_t) * (size_t)h->A[l].n);
+}
+
+int32_t or_amg_export(const or_amg* h, int32_t l, int32_t which, int32_t* rows, int32_t* cols, int32_t* ptr,
+                      int32_t* col, double* val)
+{
+    const csr_t* M = which == 0 ? &h->A[l] : &h->P[l];
+    *rows = M->n;
+    *cols = M->m;
+    const int32_t nnz = M->ptr[M->n];
+    if (ptr) memcpy(ptr, M->ptr, sizeof(int32_t) * ((size_t)M->n + 1));
+    if (col) memcpy(col, M->col, sizeof(int32_t) * (size_t)nnz);
+    if (val) memcpy(val, M->val, sizeof(double) * (size_t)nnz);
+    return nnz;
+}
+
+static void vcycle(const or_amg* h, int32_t l, const double* b, double* x)
+{
+    const csr_t* A = &h->A[l];
+    const int32_t n = A->n;
+    if (l + 1 == h->nlev) {  /* exact: L L^T x = b */
+        const double* L = h->chol;
+        for (int32_t i = 0; i < n; ++i) {
+            double s = b[i];
+            for (int32_t k = 0; k < i; ++k) s -= L[(size_t)i * n + k] * x[k];
+            x[i] = s / L[(size_t)i * n + i];
+        }
+        for (int32_t i = n - 1; i >= 0; --i) {
+            double s = x[i];
+            for (int32_t k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * x[k];
+            x[i] = s / L[(size_t)i * n + i];
+        }
+        return;
+    }
+    const double* d = h->d[l];
+    const double w = h->omega[l];
+    double* r = h->r[l];
+    for (int32_t i = 0; i < n; ++i) x[i] = w * b[i] / d[i];            /* pre-smooth from 0 */
+    csr_mv(A, x, r);
+    for (int32_t i = 0; i < n; ++i) r[i] = b[i] - r[i];                /* residual */
+    double* bc = h->b[l + 1];
+    double* xc = h->x[l + 1];
+    csr_mv(&h->R[l], r, bc);                                            /* restrict */
+    vcycle(h, l + 1, bc, xc);
+    double* e = r;
+    csr_mv(&h->P[l], xc, e);                                            /* prolong */
+    for (int32_t i = 0; i < n; ++i) x[i] += e[i];
+    csr_mv(A, x, r);
+    for (int32_t i = 0; i < n; ++i) x[i] += w * (b[i] - r[i]) / d[i];  /* post-smooth */
+}
+
+void or_amg_vcycle(const or_amg* h, const double* b, double* x) { vcycle(h, 0, b, x); }
+
+/* Standard preconditioned CG (Section 2) with M^-1 = one V-cycle. */
+int32_t or_amg_pcg(const or_amg* h, const double* b, double* x, double tol, int32_t maxit, or_stats* st)
+{
+    const csr_t* A = &h->A[0];
+    const int32_t n = A->n;
+    if (st) memset(st, 0, sizeof(*st));
+    double* r = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* z = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* p = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* q = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    const double bnorm = sqrt(or_dot(n, b, b));
+    int32_t status = OR_NOT_CONVERGED, it = 0;
+    double rho = 0.0, gamma = 0.0;
+    if (bnorm == 0.0) {
+        for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+        status = OR_OK;
+        goto done;
+    }
+    csr_mv(A, x, r);
+    for (int32_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
+    rho = or_dot(n, r, r);
+    if (st) st->r0_norm = sqrt(rho);
+    if (sqrt(rho) <= tol * bnorm) { status = OR_OK; goto done; }
+    vcycle(h, 0, r, z);
+    gamma = or_dot(n, r, z);
+    memcpy(p, z, sizeof(double) * (size_t)n);
+    for (it = 0; it < maxit;) {
+        csr_mv(A, p, q);
+        const double delta = or_dot(n, p, q);
+        if (!(delta > 0.0) || !isfinite(delta)) { status = OR_BREAKDOWN; break; }
+        const double alpha = gamma / delta;
+        for (int32_t i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+        ++it;
+        rho = or_dot(n, r, r);
+        if (sqrt(rho) <= tol * bnorm) { status = OR_OK; break; }
+        if (it >= maxit) break;
+        vcycle(h, 0, r, z);
+        const double gnew = or_dot(n, r, z);
+        const double beta = gnew / gamma;
+        gamma = gnew;
+        for (int32_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+    }
+done:
+    if (st) {
+        st->iters = it;
+        st->status = status;
+        st->b_norm = bnorm;
+        st->rel_res = bnorm > 0 ? sqrt(rho) / bnorm : 0.0;
+        csr_mv(A, x, q);
+        double tr = 0.0;
+        for (int32_t i = 0; i < n; ++i) tr += (b[i] - q[i]) * (b[i] - q[i]);
+        st->true_rel_res = bnorm > 0 ? sqrt(tr) / bnorm : 0.0;
+    }
+    free(r); free(z); free(p); free(q);
+    return status;
+}

@@ -77,6 +77,28 @@ int32_t or_mixed_reliable(int32_t n, int32_t nf, const int32_t* owner, const int
                           const double* b, double* x, double tol, int32_t update_every,
                           int32_t maxit, or_stats* st);
 
+/* ---- Smoothed-aggregation AMG preconditioner (amg.c; the method is stated
+ * at the top of that file). */
+enum { OR_AMG_MAX_LEVELS = 16 };
+typedef struct or_amg or_amg;
+
+/* NULL if the coarsest level is not positive definite. */
+or_amg* or_amg_setup(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                     const double* diag, const double* upper, const double* lower,
+                     double theta, int32_t max_levels, int32_t coarse_size);
+void or_amg_free(or_amg* h);
+int32_t or_amg_levels(const or_amg* h);
+void or_amg_level_info(const or_amg* h, int32_t l, int32_t* n, int32_t* nnz, int32_t* n_coarse, double* omega);
+void or_amg_aggregates(const or_amg* h, int32_t l, int32_t* out);
+/* Level l's A (which = 0) or P (which = 1) as CSR; returns nnz; NULL arrays
+ * query the sizes only. */
+int32_t or_amg_export(const or_amg* h, int32_t l, int32_t which, int32_t* rows, int32_t* cols, int32_t* ptr,
+                      int32_t* col, double* val);
+/* x = M^-1 b, one V(1,1) cycle. */
+void or_amg_vcycle(const or_amg* h, const double* b, double* x);
+/* Standard PCG with the V-cycle; x holds x0 on entry. */
+int32_t or_amg_pcg(const or_amg* h, const double* b, double* x, double tol, int32_t maxit, or_stats* st);
+
 /* Gradients of a scalar loss L(x) with A x = b on the LDU pattern, given x
  * and lambda = A^-T dL/dx:  dL/ddiag = -lambda*x, dL/dupper[f] =
  * -lambda[owner]*x[nb], dL/dlower[f] = -lambda[nb]*x[owner]. */
