@@ -31,7 +31,8 @@ METRIC = "CG iters/s + HBM GB/s at 7M cells; mixed/batched vs plain FP64 at 1e-8
 HBM_PEAK_GBS = 8000.0
 RELIABLE_PERIOD = 16  # FP32 iterations between FP64 updates in the reliable-update mixed solve
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pipecg_fold_varcoef192_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1505_07630_amd", "csrc", f) for f in ("solve.hip", "common.hpp", "setup.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1505_07630_amd", "csrc", f)
+                  for f in ("solve.hip", "rows.hpp", "common.hpp", "setup.hip")]
 
 
 def log(*a):

@@ -80,6 +80,7 @@ enum { FVPCG_PRECOND_NONE = 0, FVPCG_PRECOND_JACOBI = 1 };
 typedef struct fvpcg_mesh fvpcg_mesh;
 typedef struct fvpcg_matrix fvpcg_matrix;
 typedef struct fvpcg_batch fvpcg_batch;
+typedef struct fvpcg_amg fvpcg_amg;
 
 typedef struct fvpcg_stats {
     int32_t iters;        /* updates of x (inner iterations summed for the mixed solver) */
@@ -216,6 +217,37 @@ FVPCG_API int fvpcg_solve_batched_backward(const fvpcg_batch* batch, const doubl
                                  double* grad_b, double* grad_diag, double* grad_upper,
                                  double* grad_lower, double tol, int32_t maxit, int32_t method,
                                  int32_t precond, void* stream, fvpcg_stats* stats);
+
+/* ---- Smoothed-aggregation AMG preconditioner (Section 5 and Table pcgs2
+ * compare the paper's Jacobi-preconditioned solvers with aggregation-AMG
+ * preconditioned CG; the paper does not print its AMG).  The method:
+ * strength |a_ij| >= theta_l sqrt(a_ii a_jj) with theta_l = theta / 2^l;
+ * three greedy aggregation passes in index order (i with all its free strong
+ * neighbours; leftovers join the first pass's aggregate of their strongest
+ * strong neighbour; what remains forms aggregates of i and its free
+ * neighbours); P = (I - omega D^-1 A) P_t with omega = 4 / (3 Gershgorin bound
+ * of D^-1 A); A_c = P^T A P; levels until n <= coarse_size, max_levels, or an
+ * aggregation keeping > 60% of the unknowns; the last level (at most 2048
+ * unknowns) solved exactly.  Cycle V(1,1) with damped Jacobi (the same
+ * omega).  The hierarchy is built on the host from the matrix's coefficients
+ * at creation (seconds for millions of cells) and uploaded; the matrix must
+ * outlive it and be symmetric; after fvpcg_matrix_update create it again.
+ * Calls on one handle must not overlap.  Typical: theta = 0.08,
+ * max_levels = 12, coarse_size = 64. */
+FVPCG_API int fvpcg_amg_create(const fvpcg_matrix* mat, double theta, int32_t max_levels, int32_t coarse_size,
+                               void* stream, fvpcg_amg** out);
+FVPCG_API int fvpcg_amg_destroy(fvpcg_amg* amg);
+/* Number of levels; rows and stored entries of `level` (n, nnz may be NULL). */
+FVPCG_API int fvpcg_amg_info(const fvpcg_amg* amg, int32_t level, int32_t* levels, int32_t* n, int64_t* nnz);
+/* Aggregate index of every row of `level` (a level with a coarser one) into a
+ * HOST int32 array of that level's row count. */
+FVPCG_API int fvpcg_amg_aggregates(const fvpcg_amg* amg, int32_t level, int32_t* host_out);
+/* z = M^-1 r, one cycle; r, z: FP64[n_cells] device arrays, not overlapping. */
+FVPCG_API int fvpcg_amg_apply(const fvpcg_amg* amg, const double* r, double* z, void* stream);
+/* Standard preconditioned CG (Section 2) with M^-1 = one cycle; stopping and
+ * stats as fvpcg_solve (x holds x0). */
+FVPCG_API int fvpcg_solve_amg(const fvpcg_amg* amg, const double* b, double* x, double tol, int32_t maxit,
+                              void* stream, fvpcg_stats* stats);
 
 /* ---- STREAM-style copy and triad over device arrays of `bytes_per_array`
  * bytes each (three arrays; 0 = 1 GiB), as the paper measures attainable

@@ -373,6 +373,103 @@ def fvpcg_solve_batched_backward(B: Batch, x, g, tol=1e-10, maxit=10000, method=
 solve_batched_backward = fvpcg_solve_batched_backward
 
 
+# ---------------------------------------------------------------- AMG
+
+class AMG:
+    """Smoothed-aggregation AMG hierarchy of a (symmetric) Matrix; the Matrix
+    must outlive it."""
+
+    def __init__(self, A: Matrix, theta=0.08, max_levels=12, coarse_size=64, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().fvpcg_amg_create(A.handle, float(theta), int(max_levels), int(coarse_size), _stream(stream),
+                                      ctypes.byref(h)), "fvpcg_amg_create")
+        self._h = h
+        self.A = A
+        self.n = A.n
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def levels(self):
+        lv = ctypes.c_int32()
+        _check(lib().fvpcg_amg_info(self._h, -1, ctypes.byref(lv), None, None), "fvpcg_amg_info")
+        return lv.value
+
+    def level_info(self, level):
+        lv, n, nnz = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().fvpcg_amg_info(self._h, int(level), ctypes.byref(lv), ctypes.byref(n), ctypes.byref(nnz)),
+               "fvpcg_amg_info")
+        return {"n": n.value, "nnz": nnz.value}
+
+    def aggregates(self, level):
+        import numpy as np
+
+        out = np.empty(self.level_info(level)["n"], dtype=np.int32)
+        _check(lib().fvpcg_amg_aggregates(self._h, int(level), out.ctypes.data_as(ctypes.c_void_p)),
+               "fvpcg_amg_aggregates")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fvpcg_amg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fvpcg_amg_create(A: Matrix, theta=0.08, max_levels=12, coarse_size=64, stream=None) -> AMG:
+    return AMG(A, theta, max_levels, coarse_size, stream)
+
+
+def fvpcg_amg_destroy(M: AMG):
+    M.close()
+    return OK
+
+
+def fvpcg_amg_info(M: AMG, level=0):
+    return dict(M.level_info(level), levels=M.levels)
+
+
+def fvpcg_amg_aggregates(M: AMG, level=0):
+    return M.aggregates(level)
+
+
+def fvpcg_amg_apply(M: AMG, r, z=None, stream=None):
+    """z = M^-1 r (one V-cycle)."""
+    import torch
+
+    if z is None:
+        z = torch.empty_like(r)
+    _check(lib().fvpcg_amg_apply(M.handle, _ptr(r, torch.float64, M.n, "r"), _ptr(z, torch.float64, M.n, "z"),
+                                 _stream(stream)), "fvpcg_amg_apply")
+    return z
+
+
+amg_apply = fvpcg_amg_apply
+
+
+def fvpcg_solve_amg(M: AMG, b, x=None, tol=1e-8, maxit=1000, stream=None):
+    """Standard CG preconditioned by one AMG cycle."""
+    import torch
+
+    if x is None:
+        x = torch.zeros_like(b)
+    st = Stats()
+    code = lib().fvpcg_solve_amg(M.handle, _ptr(b, torch.float64, M.n, "b"), _ptr(x, torch.float64, M.n, "x"),
+                                 float(tol), int(maxit), _stream(stream), ctypes.byref(st))
+    _check(code, "fvpcg_solve_amg")
+    return x, st.asdict()
+
+
+solve_amg = fvpcg_solve_amg
+
+
 def fvpcg_stream_calibrate(bytes_per_array=0, stream=None):
     c, t = ctypes.c_double(), ctypes.c_double()
     _check(lib().fvpcg_stream_calibrate(_stream(stream), int(bytes_per_array), ctypes.byref(c), ctypes.byref(t)),

@@ -1,0 +1,895 @@
+// Smoothed-aggregation AMG preconditioner and AMG-preconditioned CG.
+//
+// The paper compares its Jacobi-preconditioned CG and pipelined CG with
+// aggregation-AMG preconditioned versions (Section 5, Table pcgs2) without
+// printing the AMG.  This is the classical smoothed-aggregation method of
+// Vanek, Mandel and Brezina:
+//   strength    j ~ i iff j != i and |a_ij| >= theta_l sqrt(a_ii a_jj),
+//               theta_{l+1} = theta_l / 2;
+//   aggregates  three greedy passes in index order: (1) i and all its strong
+//               neighbours, when none of them is aggregated, form an
+//               aggregate; (2) a remaining i joins the pass-1 aggregate of its
+//               strongest strong neighbour (ties: lowest index); (3) what
+//               remains forms aggregates of i and its still-free neighbours;
+//   prolongator P = (I - omega D^-1 A) P_t, omega = 4 / (3 lambda), lambda
+//               the Gershgorin bound max_i sum_j |a_ij| / a_ii;
+//   coarse      A_c = P^T A P, R = P^T; stop at n <= coarse_size, at the
+//               level limit, or when aggregation keeps more than 60% of the
+//               unknowns; the last level is solved exactly (its inverse,
+//               formed from a Cholesky factor at setup);
+//   cycle       V(1,1): x = omega D^-1 b; r = b - A x; x += P V(R r);
+//               y = x + omega D^-1 (b - A x).
+// The hierarchy is built on the host at setup (sparse products with a dense
+// accumulator per row); the cycle runs on the device: level 0 uses the
+// matrix's ELL layout (the pre-smoothing and residual in one pass through
+// the column-scaled values), coarser levels CSR, one row per thread.  The
+// cycle is symmetric positive definite, so standard CG can use it as M^-1.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "handles.hpp"
+#include "rows.hpp"
+
+namespace fvpcg {
+
+constexpr int kAmgMaxLevels = 16;
+constexpr int kAmgMaxCoarse = 2048;  // largest exactly-solved last level
+constexpr int kAmgBs = 512;          // level-0 and PCG kernels
+constexpr int kAmgCsrBs = 256;       // CSR levels, one row per thread
+
+struct AmgLevel {
+    int n = 0, nc = 0;  // rows here and on the next level
+    long long nnz = 0;
+    double omega = 0.0;
+    int *a_ptr = nullptr, *a_col = nullptr;  // levels >= 1
+    double *a_val = nullptr, *d = nullptr;   // levels >= 1
+    int *p_ptr = nullptr, *p_col = nullptr;  // P: n x nc
+    double* p_val = nullptr;
+    int *r_ptr = nullptr, *r_col = nullptr;  // R = P^T: nc x n
+    double* r_val = nullptr;
+    double *b = nullptr, *x = nullptr, *r = nullptr, *y = nullptr;  // work
+    bool wave_a = false, wave_p = false, wave_r = false;             // one wavefront per row
+    std::vector<int> agg;
+};
+
+}  // namespace fvpcg
+
+struct fvpcg_amg {
+    const fvpcg_matrix* mat = nullptr;
+    int nlev = 0;
+    fvpcg::AmgLevel lev[fvpcg::kAmgMaxLevels];
+    double* cinv = nullptr;  // inverse of the last level, row-major
+    int nlast = 0;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;  // PCG vectors
+    fvpcg::DevState* st = nullptr;
+    fvpcg::DevState* hst = nullptr;  // pinned [2]
+    double* partials = nullptr;
+    hipEvent_t t_begin = nullptr, t_end = nullptr, t_it0 = nullptr, t_it1 = nullptr;
+};
+
+namespace fvpcg {
+
+namespace {
+
+// ---------------------------------------------------------------- host setup
+// Products and sums are rounded one operation at a time (no fused
+// multiply-add), in the orders stated, so the hierarchy does not depend on
+// the compiler's contraction choices.
+#pragma clang fp contract(off)
+
+struct Csr {
+    int n = 0, m = 0;
+    std::vector<int> ptr, col;
+    std::vector<double> val;
+};
+
+Csr transpose(const Csr& A) {
+    Csr T;
+    T.n = A.m;
+    T.m = A.n;
+    T.ptr.assign((size_t)T.n + 1, 0);
+    T.col.resize(A.col.size());
+    T.val.resize(A.val.size());
+    for (int c : A.col) T.ptr[(size_t)c + 1]++;
+    for (int j = 0; j < T.n; ++j) T.ptr[(size_t)j + 1] += T.ptr[j];
+    std::vector<int> fill(T.ptr.begin(), T.ptr.end() - 1);
+    for (int i = 0; i < A.n; ++i)
+        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k) {
+            const int q = fill[A.col[k]]++;
+            T.col[q] = i;
+            T.val[q] = A.val[k];
+        }
+    return T;
+}
+
+// C = X Y, row by row: products summed in the order of X's columns and then
+// Y's columns into a dense accumulator; columns sorted.
+Csr multiply(const Csr& X, const Csr& Y) {
+    Csr C;
+    C.n = X.n;
+    C.m = Y.m;
+    C.ptr.assign((size_t)C.n + 1, 0);
+    std::vector<double> acc((size_t)std::max(Y.m, 1), 0.0);
+    std::vector<int> mark((size_t)std::max(Y.m, 1), -1), touched;
+    for (int i = 0; i < X.n; ++i) {
+        touched.clear();
+        for (int a = X.ptr[i]; a < X.ptr[(size_t)i + 1]; ++a) {
+            const int j = X.col[a];
+            const double xv = X.val[a];
+            for (int b = Y.ptr[j]; b < Y.ptr[(size_t)j + 1]; ++b) {
+                const int k = Y.col[b];
+                if (mark[k] != i) {
+                    mark[k] = i;
+                    acc[k] = 0.0;
+                    touched.push_back(k);
+                }
+                acc[k] += xv * Y.val[b];
+            }
+        }
+        std::sort(touched.begin(), touched.end());
+        for (int k : touched) {
+            C.col.push_back(k);
+            C.val.push_back(acc[k]);
+        }
+        C.ptr[(size_t)i + 1] = (int)C.col.size();
+    }
+    return C;
+}
+
+std::vector<double> diagonal(const Csr& A) {
+    std::vector<double> d((size_t)A.n, 0.0);
+    for (int i = 0; i < A.n; ++i)
+        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k)
+            if (A.col[k] == i) d[i] = A.val[k];
+    return d;
+}
+
+int aggregate(const Csr& A, const std::vector<double>& d, double theta, std::vector<int>& agg) {
+    const int n = A.n;
+    agg.assign((size_t)n, -1);
+    auto strong = [&](int i, int k) {
+        const int j = A.col[k];
+        return j != i && std::fabs(A.val[k]) >= theta * std::sqrt(std::fabs(d[i] * d[j]));
+    };
+    int na = 0;
+    for (int i = 0; i < n; ++i) {  // pass 1
+        if (agg[i] >= 0) continue;
+        bool free_nbhd = true;
+        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1] && free_nbhd; ++k)
+            if (strong(i, k) && agg[A.col[k]] >= 0) free_nbhd = false;
+        if (!free_nbhd) continue;
+        agg[i] = na;
+        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k)
+            if (strong(i, k)) agg[A.col[k]] = na;
+        ++na;
+    }
+    const std::vector<int> first(agg);
+    for (int i = 0; i < n; ++i) {  // pass 2
+        if (agg[i] >= 0) continue;
+        int best = -1;
+        double bw = -1.0;
+        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k)
+            if (strong(i, k) && first[A.col[k]] >= 0 && std::fabs(A.val[k]) > bw) {
+                bw = std::fabs(A.val[k]);
+                best = A.col[k];
+            }
+        if (best >= 0) agg[i] = first[best];
+    }
+    for (int i = 0; i < n; ++i) {  // pass 3
+        if (agg[i] >= 0) continue;
+        agg[i] = na;
+        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k)
+            if (strong(i, k) && agg[A.col[k]] < 0) agg[A.col[k]] = na;
+        ++na;
+    }
+    return na;
+}
+
+double gershgorin(const Csr& A, const std::vector<double>& d) {
+    double lam = 0.0;
+    for (int i = 0; i < A.n; ++i) {
+        double s = 0.0;
+        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k) s += std::fabs(A.val[k]);
+        lam = std::max(lam, s / d[i]);
+    }
+    return lam;
+}
+
+// P = (I - omega D^-1 A) P_t
+Csr prolongator(const Csr& A, const std::vector<double>& d, const std::vector<int>& agg, int na, double omega) {
+    Csr S = A;
+    for (int i = 0; i < A.n; ++i)
+        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k)
+            S.val[k] = (A.col[k] == i ? 1.0 : 0.0) - omega * A.val[k] / d[i];
+    Csr Pt;
+    Pt.n = A.n;
+    Pt.m = na;
+    Pt.ptr.resize((size_t)A.n + 1);
+    for (int i = 0; i <= A.n; ++i) Pt.ptr[i] = i;
+    Pt.col = agg;
+    Pt.val.assign((size_t)A.n, 1.0);
+    return multiply(S, Pt);
+}
+
+// inverse of a small SPD matrix through its Cholesky factor; false if not SPD
+bool spd_inverse(const Csr& A, std::vector<double>& inv) {
+    const int n = A.n;
+    std::vector<double> L((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k) L[(size_t)i * n + A.col[k]] = A.val[k];
+    for (int j = 0; j < n; ++j) {
+        double s = L[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(s > 0.0)) return false;
+        const double ljj = std::sqrt(s);
+        L[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double t = L[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = t / ljj;
+        }
+    }
+    inv.assign((size_t)n * n, 0.0);
+    std::vector<double> e((size_t)n);
+    for (int c = 0; c < n; ++c) {  // column c of A^-1: L L^T v = e_c
+        for (int i = 0; i < n; ++i) {
+            double s = i == c ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) s -= L[(size_t)i * n + k] * e[k];
+            e[i] = s / L[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = e[i];
+            for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * e[k];
+            e[i] = s / L[(size_t)i * n + i];
+        }
+        for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = e[i];
+    }
+    return true;
+}
+
+// Level 0 as CSR from the device ELL layout: the diagonal plus every slot
+// whose column is not the row itself (padding repeats the row), sorted.
+int level0_from_device(const fvpcg_matrix* A, hipStream_t s, Csr& out) {
+    const fvpcg_mesh* m = A->mesh;
+    const int n = m->n, W = m->W;
+    std::vector<int> col((size_t)W * n);
+    std::vector<double> val((size_t)W * n), d((size_t)n);
+    FV_HIP(hipMemcpyAsync(col.data(), m->col, sizeof(int) * col.size(), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipMemcpyAsync(val.data(), A->val, sizeof(double) * val.size(), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipMemcpyAsync(d.data(), A->d, sizeof(double) * d.size(), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    out.n = out.m = n;
+    out.ptr.assign((size_t)n + 1, 0);
+    out.col.clear();
+    out.val.clear();
+    out.col.reserve((size_t)(W + 1) * n);
+    out.val.reserve((size_t)(W + 1) * n);
+    std::vector<std::pair<int, double>> row;
+    for (int c = 0; c < n; ++c) {
+        row.clear();
+        row.emplace_back(c, d[c]);
+        for (int k = 0; k < W; ++k) {
+            const size_t o = (size_t)k * n + c;
+            if (col[o] != c) row.emplace_back(col[o], val[o]);
+        }
+        std::sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+        for (auto& e : row) {
+            out.col.push_back(e.first);
+            out.val.push_back(e.second);
+        }
+        out.ptr[(size_t)c + 1] = (int)out.col.size();
+    }
+    return FVPCG_OK;
+}
+
+bool symmetric(const Csr& A) {
+    const Csr T = transpose(A);
+    return T.ptr == A.ptr && T.col == A.col && T.val == A.val;
+}
+
+template <typename T>
+int upload(T** dst, const std::vector<T>& src, const char* what, hipStream_t s) {
+    int rc;
+    if ((rc = dev_alloc(dst, std::max<size_t>(src.size(), 1), what))) return rc;
+    if (!src.empty()) FV_HIP(hipMemcpyAsync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s));
+    return FVPCG_OK;
+}
+
+#pragma clang fp contract(on)
+
+// ---------------------------------------------------------------- kernels
+
+// Level 0, from x = 0: x = omega b / d and r = b - A x in one pass.  With
+// x_j = omega b_j / d_j the product is omega (b_c + sum_j (a_cj / d_j) b_j),
+// the column-scaled values' gather of b.
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_amg_pre0(const CI* __restrict__ col, const double* __restrict__ val_cs,
+                                                  const double* __restrict__ d, int n, Geom g, double w,
+                                                  const double* __restrict__ b, double* __restrict__ x,
+                                                  double* __restrict__ r, const DevState* st) {
+    if (st->done) return;
+    FV_ROWS(blk) {
+        const double bc = b[c];
+        const double t = row_gather<double, WT, CI>(col, val_cs, n, c, b, bc);
+        x[c] = w * bc / d[c];
+        r[c] = bc - w * t;
+    }
+}
+
+// Level 0: y = x + omega (b - A x) / d; with DOT, also gamma' = (b, y) (b is
+// the CG residual, y the preconditioned one): the first cycle sets gamma and
+// beta = 0, later ones beta = gamma' / gamma.
+template <int BS, int WT, typename CI, bool DOT>
+__global__ __launch_bounds__(BS) void k_amg_post0(const CI* __restrict__ col, const double* __restrict__ val,
+                                                   const double* __restrict__ d, int n, Geom g, double w,
+                                                   const double* __restrict__ b, const double* __restrict__ x,
+                                                   double* __restrict__ y, int first, DevState* st,
+                                                   double* partials) {
+    if (st->done) return;
+    double acc[1] = {0.0};
+    FV_ROWS(blk) {
+        const double xc = x[c], dc = d[c], bc = b[c];
+        const double ax = row_gather<double, WT, CI>(col, val, n, c, x, dc * xc);
+        const double yc = xc + w * (bc - ax) / dc;
+        y[c] = yc;
+        if (DOT) acc[0] += bc * yc;
+    }
+    if (!DOT) return;
+    double t[1];
+    if (device_reduce<BS, 1>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        if (first) {
+            st->beta = 0.0;
+        } else {
+            st->beta = t[0] / st->gamma;
+        }
+        st->gamma = t[0];
+        if (!(t[0] > 0.0) || !isfinite(t[0])) {
+            st->done = 1;
+            st->status = FVPCG_BREAKDOWN;
+        }
+    }
+}
+
+// CSR levels, one row per thread.
+__global__ __launch_bounds__(kAmgCsrBs) void k_amg_pre(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                      const double* __restrict__ val, const double* __restrict__ d,
+                                                      int n, double w, const double* __restrict__ b,
+                                                      double* __restrict__ x, double* __restrict__ r,
+                                                      const DevState* st) {
+    if (st->done) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const int j = col[k];
+            s += val[k] * (w * b[j] / d[j]);
+        }
+        const double bi = b[i];
+        x[i] = w * bi / d[i];
+        r[i] = bi - s;
+    }
+}
+
+__global__ __launch_bounds__(kAmgCsrBs) void k_amg_post(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                       const double* __restrict__ val, const double* __restrict__ d,
+                                                       int n, double w, const double* __restrict__ b,
+                                                       const double* __restrict__ x, double* __restrict__ y,
+                                                       const DevState* st) {
+    if (st->done) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = ptr[i]; k < ptr[i + 1]; ++k) s += val[k] * x[col[k]];
+        y[i] = x[i] + w * (b[i] - s) / d[i];
+    }
+}
+
+// y = M v (restriction), or y += M v (prolongation, ADD)
+template <bool ADD>
+__global__ __launch_bounds__(kAmgCsrBs) void k_amg_csr_mv(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                         const double* __restrict__ val, int n,
+                                                         const double* __restrict__ v, double* __restrict__ y,
+                                                         const DevState* st) {
+    if (st->done) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = ptr[i]; k < ptr[i + 1]; ++k) s += val[k] * v[col[k]];
+        y[i] = ADD ? y[i] + s : s;
+    }
+}
+
+// The same CSR operations with one wavefront per row, for operators whose
+// rows are long (the coarse levels of smoothed aggregation hold tens to
+// hundreds of entries per row): the lanes stride through the row, coalesced,
+// and the row sum is a wave reduction.  The row loop is uniform per wave, so
+// every lane takes part in the reduction.
+__device__ __forceinline__ int wave_id() { return (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); }
+__device__ __forceinline__ int wave_count() { return (int)((gridDim.x * blockDim.x) >> 6); }
+
+__global__ __launch_bounds__(kAmgCsrBs) void k_amg_pre_w(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                        const double* __restrict__ val, const double* __restrict__ d,
+                                                        int n, double w, const double* __restrict__ b,
+                                                        double* __restrict__ x, double* __restrict__ r,
+                                                        const DevState* st) {
+    if (st->done) return;
+    const int lane = threadIdx.x & 63;
+    for (int i = wave_id(); i < n; i += wave_count()) {
+        double s = 0.0;
+        for (int k = ptr[i] + lane; k < ptr[i + 1]; k += 64) {
+            const int j = col[k];
+            s += val[k] * (w * b[j] / d[j]);
+        }
+        s = wave_sum(s);
+        if (lane == 0) {
+            const double bi = b[i];
+            x[i] = w * bi / d[i];
+            r[i] = bi - s;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kAmgCsrBs) void k_amg_post_w(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                         const double* __restrict__ val, const double* __restrict__ d,
+                                                         int n, double w, const double* __restrict__ b,
+                                                         const double* __restrict__ x, double* __restrict__ y,
+                                                         const DevState* st) {
+    if (st->done) return;
+    const int lane = threadIdx.x & 63;
+    for (int i = wave_id(); i < n; i += wave_count()) {
+        double s = 0.0;
+        for (int k = ptr[i] + lane; k < ptr[i + 1]; k += 64) s += val[k] * x[col[k]];
+        s = wave_sum(s);
+        if (lane == 0) y[i] = x[i] + w * (b[i] - s) / d[i];
+    }
+}
+
+template <bool ADD>
+__global__ __launch_bounds__(kAmgCsrBs) void k_amg_csr_mv_w(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                           const double* __restrict__ val, int n,
+                                                           const double* __restrict__ v, double* __restrict__ y,
+                                                           const DevState* st) {
+    if (st->done) return;
+    const int lane = threadIdx.x & 63;
+    for (int i = wave_id(); i < n; i += wave_count()) {
+        double s = 0.0;
+        for (int k = ptr[i] + lane; k < ptr[i + 1]; k += 64) s += val[k] * v[col[k]];
+        s = wave_sum(s);
+        if (lane == 0) y[i] = ADD ? y[i] + s : s;
+    }
+}
+
+// last level: y = A^-1 b with the dense inverse
+__global__ __launch_bounds__(kAmgCsrBs) void k_amg_coarse_w(const double* __restrict__ inv, int n,
+                                                           const double* __restrict__ b, double* __restrict__ y,
+                                                           const DevState* st) {
+    if (st->done) return;
+    const int lane = threadIdx.x & 63;
+    for (int i = wave_id(); i < n; i += wave_count()) {
+        double s = 0.0;
+        for (int k = lane; k < n; k += 64) s += inv[(size_t)i * n + k] * b[k];
+        s = wave_sum(s);
+        if (lane == 0) y[i] = s;
+    }
+}
+
+// gamma' = (r, z) when the hierarchy has a single level (no post-smoothing)
+template <int BS>
+__global__ __launch_bounds__(BS) void k_apcg_dot(const double* __restrict__ r, const double* __restrict__ z, int n,
+                                                 Geom g, int first, DevState* st, double* partials) {
+    if (st->done) return;
+    double acc[1] = {0.0};
+    FV_ROWS(blk) { acc[0] += r[c] * z[c]; }
+    double t[1];
+    if (device_reduce<BS, 1>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        st->beta = first ? 0.0 : t[0] / st->gamma;
+        st->gamma = t[0];
+        if (!(t[0] > 0.0) || !isfinite(t[0])) {
+            st->done = 1;
+            st->status = FVPCG_BREAKDOWN;
+        }
+    }
+}
+
+// r = b - A x; (b, b), (r, r); stopping test before the first iteration.
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_apcg_init(const CI* __restrict__ col, const double* __restrict__ val,
+                                                  const double* __restrict__ d, int n, Geom g,
+                                                  const double* __restrict__ b, const double* __restrict__ x,
+                                                  double* __restrict__ r, DevState* st, double* partials) {
+    double acc[2] = {0.0, 0.0};
+    FV_ROWS(blk) {
+        const double bc = b[c];
+        const double rc = bc - row_gather<double, WT, CI>(col, val, n, c, x, d[c] * x[c]);
+        r[c] = rc;
+        acc[0] += bc * bc;
+        acc[1] += rc * rc;
+    }
+    double t[2];
+    if (device_reduce<BS, 2>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        st->iter = 0;
+        st->bnorm = sqrt(t[0]);
+        st->rho = t[1];
+        st->r0norm = sqrt(t[1]);
+        if (t[0] == 0.0) {
+            st->zero_b = 1;
+            st->done = 1;
+            st->status = FVPCG_OK;
+            return;
+        }
+        st->tol_abs *= st->bnorm;
+        if (st->r0norm <= st->tol_abs) {
+            st->done = 1;
+            st->status = FVPCG_OK;
+        } else if (st->maxit <= 0) {
+            st->done = 1;
+            st->status = FVPCG_NOT_CONVERGED;
+        }
+    }
+}
+
+// p = z (first) or p = z + beta p
+template <int BS>
+__global__ __launch_bounds__(BS) void k_apcg_p(const double* __restrict__ z, double* __restrict__ p, int n, Geom g,
+                                               int first, const DevState* st) {
+    if (st->done) return;
+    const double beta = st->beta;
+    FV_ROWS(blk) { p[c] = first ? z[c] : z[c] + beta * p[c]; }
+}
+
+// q = A p; delta = (p, q); alpha = gamma / delta.
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_apcg_spmv(const CI* __restrict__ col, const double* __restrict__ val,
+                                                  const double* __restrict__ d, int n, Geom g,
+                                                  const double* __restrict__ p, double* __restrict__ q, DevState* st,
+                                                  double* partials) {
+    if (st->done) return;
+    double acc[1] = {0.0};
+    FV_ROWS(blk) {
+        const double pc = p[c];
+        const double qc = row_gather<double, WT, CI>(col, val, n, c, p, d[c] * pc);
+        q[c] = qc;
+        acc[0] += pc * qc;
+    }
+    double t[1];
+    if (device_reduce<BS, 1>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        st->delta = t[0];
+        if (!(t[0] > 0.0) || !isfinite(t[0])) {
+            st->done = 1;
+            st->status = FVPCG_BREAKDOWN;
+            return;
+        }
+        st->alpha = st->gamma / t[0];
+    }
+}
+
+// x += alpha p; r -= alpha q; rho = (r, r); iteration count and stopping test.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_apcg_xr(double* __restrict__ x, const double* __restrict__ p,
+                                                double* __restrict__ r, const double* __restrict__ q, int n, Geom g,
+                                                DevState* st, double* partials) {
+    if (st->done) return;
+    const double alpha = st->alpha;
+    double acc[1] = {0.0};
+    FV_ROWS(blk) {
+        x[c] += alpha * p[c];
+        const double rc = r[c] - alpha * q[c];
+        r[c] = rc;
+        acc[0] += rc * rc;
+    }
+    double t[1];
+    if (device_reduce<BS, 1>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
+        const int it = st->iter + 1;
+        st->iter = it;
+        st->rho = t[0];
+        if (sqrt(t[0]) <= st->tol_abs) {
+            st->done = 1;
+            st->status = FVPCG_OK;
+        } else if (it >= st->maxit) {
+            st->done = 1;
+            st->status = FVPCG_NOT_CONVERGED;
+        }
+    }
+}
+
+// ||b - A x||^2 at exit
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_apcg_true(const CI* __restrict__ col, const double* __restrict__ val,
+                                                  const double* __restrict__ d, int n, Geom g,
+                                                  const double* __restrict__ b, const double* __restrict__ x,
+                                                  DevState* st, double* partials) {
+    double acc[1] = {0.0};
+    FV_ROWS(blk) {
+        const double rc = b[c] - row_gather<double, WT, CI>(col, val, n, c, x, d[c] * x[c]);
+        acc[0] += rc * rc;
+    }
+    double t[1];
+    if (device_reduce<BS, 1>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) st->true_rr = t[0];
+}
+
+int csr_grid(int n) { return std::max(1, std::min((n + kAmgCsrBs - 1) / kAmgCsrBs, 4096)); }
+constexpr int kWavesPerBlock = kAmgCsrBs / 64;
+int wave_grid(int n) { return std::max(1, std::min((n + kWavesPerBlock - 1) / kWavesPerBlock, 8192)); }
+// one wavefront per row once rows average more than this many entries
+constexpr double kWaveRow = 12.0;
+
+// Enqueue one cycle y0 = M^-1 b0 on `s`; kernels skip once st->done.
+int enqueue_cycle(const fvpcg_amg* h, const double* b0, double* y0, bool dot, bool first, DevState* st,
+                  hipStream_t s) {
+    const fvpcg_matrix* A = h->mat;
+    const fvpcg_mesh* m = A->mesh;
+    const int n0 = m->n;
+    const Geom g0 = geom_for(n0, kAmgBs);
+    const int L = h->nlev;
+    if (L == 1) {
+        hipLaunchKernelGGL(k_amg_coarse_w, dim3(wave_grid(n0)), dim3(kAmgCsrBs), 0, s, h->cinv, n0, b0, y0, st);
+        if (dot)
+            hipLaunchKernelGGL((k_apcg_dot<kAmgBs>), dim3(g0.grid), dim3(kAmgBs), 0, s, b0, y0, n0, g0, first ? 1 : 0,
+                               st, h->partials);
+        FV_LAUNCHED();
+        return FVPCG_OK;
+    }
+    for (int l = 0; l + 1 < L; ++l) {
+        const AmgLevel& v = h->lev[l];
+        const double* b = l == 0 ? b0 : v.b;
+        if (l == 0) {
+            FV_LAYOUT(m, hipLaunchKernelGGL((k_amg_pre0<kAmgBs, W_, CI_>), dim3(g0.grid), dim3(kAmgBs), 0, s, cols_,
+                                            A->val_cs, A->d, n0, g0, v.omega, b, v.x, v.r, st));
+        } else if (v.wave_a) {
+            hipLaunchKernelGGL(k_amg_pre_w, dim3(wave_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col, v.a_val,
+                               v.d, v.n, v.omega, b, v.x, v.r, st);
+        } else {
+            hipLaunchKernelGGL(k_amg_pre, dim3(csr_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col, v.a_val, v.d,
+                               v.n, v.omega, b, v.x, v.r, st);
+        }
+        if (v.wave_r)
+            hipLaunchKernelGGL((k_amg_csr_mv_w<false>), dim3(wave_grid(v.nc)), dim3(kAmgCsrBs), 0, s, v.r_ptr,
+                               v.r_col, v.r_val, v.nc, v.r, h->lev[l + 1].b, st);
+        else
+            hipLaunchKernelGGL((k_amg_csr_mv<false>), dim3(csr_grid(v.nc)), dim3(kAmgCsrBs), 0, s, v.r_ptr, v.r_col,
+                               v.r_val, v.nc, v.r, h->lev[l + 1].b, st);
+    }
+    const AmgLevel& last = h->lev[L - 1];
+    hipLaunchKernelGGL(k_amg_coarse_w, dim3(wave_grid(last.n)), dim3(kAmgCsrBs), 0, s, h->cinv, last.n, last.b,
+                       last.y, st);
+    for (int l = L - 2; l >= 0; --l) {
+        const AmgLevel& v = h->lev[l];
+        if (v.wave_p)
+            hipLaunchKernelGGL((k_amg_csr_mv_w<true>), dim3(wave_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.p_ptr, v.p_col,
+                               v.p_val, v.n, h->lev[l + 1].y, v.x, st);
+        else
+            hipLaunchKernelGGL((k_amg_csr_mv<true>), dim3(csr_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.p_ptr, v.p_col,
+                               v.p_val, v.n, h->lev[l + 1].y, v.x, st);
+        if (l == 0) {
+            if (dot) {
+                FV_LAYOUT(m, hipLaunchKernelGGL((k_amg_post0<kAmgBs, W_, CI_, true>), dim3(g0.grid), dim3(kAmgBs), 0,
+                                                s, cols_, A->val, A->d, n0, g0, v.omega, b0, v.x, y0, first ? 1 : 0,
+                                                st, h->partials));
+            } else {
+                FV_LAYOUT(m, hipLaunchKernelGGL((k_amg_post0<kAmgBs, W_, CI_, false>), dim3(g0.grid), dim3(kAmgBs),
+                                                0, s, cols_, A->val, A->d, n0, g0, v.omega, b0, v.x, y0, 0, st,
+                                                h->partials));
+            }
+        } else if (v.wave_a) {
+            hipLaunchKernelGGL(k_amg_post_w, dim3(wave_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col, v.a_val,
+                               v.d, v.n, v.omega, v.b, v.x, v.y, st);
+        } else {
+            hipLaunchKernelGGL(k_amg_post, dim3(csr_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col, v.a_val,
+                               v.d, v.n, v.omega, v.b, v.x, v.y, st);
+        }
+    }
+    FV_LAUNCHED();
+    return FVPCG_OK;
+}
+
+int state_put(fvpcg_amg* h, double tol, int maxit, hipStream_t s) {
+    DevState* hs = &h->hst[1];
+    *hs = DevState();
+    hs->tol_abs = tol;
+    hs->maxit = maxit;
+    hs->status = FVPCG_NOT_CONVERGED;
+    FV_HIP(hipMemcpyAsync(h->st, hs, sizeof(DevState), hipMemcpyHostToDevice, s));
+    return FVPCG_OK;
+}
+
+int state_get(fvpcg_amg* h, DevState* out, hipStream_t s) {
+    FV_HIP(hipMemcpyAsync(&h->hst[0], h->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    *out = h->hst[0];
+    return FVPCG_OK;
+}
+
+}  // namespace
+
+void amg_free(fvpcg_amg* h) {
+    if (!h) return;
+    for (AmgLevel& v : h->lev) {
+        dev_free(v.a_ptr);
+        dev_free(v.a_col);
+        dev_free(v.a_val);
+        dev_free(v.d);
+        dev_free(v.p_ptr);
+        dev_free(v.p_col);
+        dev_free(v.p_val);
+        dev_free(v.r_ptr);
+        dev_free(v.r_col);
+        dev_free(v.r_val);
+        dev_free(v.b);
+        dev_free(v.x);
+        dev_free(v.r);
+        dev_free(v.y);
+    }
+    dev_free(h->cinv);
+    dev_free(h->r);
+    dev_free(h->z);
+    dev_free(h->p);
+    dev_free(h->q);
+    dev_free(h->st);
+    dev_free(h->partials);
+    if (h->hst) (void)hipHostFree(h->hst);
+    hipEvent_t* evs[] = {&h->t_begin, &h->t_end, &h->t_it0, &h->t_it1};
+    for (hipEvent_t* e : evs)
+        if (*e) (void)hipEventDestroy(*e);
+    delete h;
+}
+
+int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, hipStream_t s,
+               fvpcg_amg** out) {
+    fvpcg_amg* h = new (std::nothrow) fvpcg_amg();
+    if (!h) return set_error(FVPCG_OUT_OF_MEMORY, "host allocation failed");
+    h->mat = A;
+    auto fail = [&](int rc) {
+        amg_free(h);
+        return rc;
+    };
+    int rc;
+    Csr cur;
+    if ((rc = level0_from_device(A, s, cur))) return fail(rc);
+    if (!A->sym && !symmetric(cur))
+        return fail(set_error(FVPCG_UNSUPPORTED, "AMG needs a symmetric matrix (lower == upper on every face)"));
+    max_levels = std::max(1, std::min(max_levels, kAmgMaxLevels));
+    double th = theta;
+    int l = 0;
+    for (;;) {
+        AmgLevel& v = h->lev[l];
+        const std::vector<double> d = diagonal(cur);
+        v.n = cur.n;
+        v.nnz = (long long)cur.col.size();
+        v.omega = 4.0 / (3.0 * gershgorin(cur, d));
+        v.wave_a = (double)cur.col.size() > kWaveRow * (double)std::max(cur.n, 1);
+        if (l > 0) {
+            if ((rc = upload(&v.a_ptr, cur.ptr, "AMG level rows", s)) || (rc = upload(&v.a_col, cur.col, "AMG level columns", s)) ||
+                (rc = upload(&v.a_val, cur.val, "AMG level values", s)) || (rc = upload(&v.d, d, "AMG level diagonal", s)))
+                return fail(rc);
+        }
+        if ((rc = dev_alloc(&v.b, (size_t)std::max(v.n, 1), "AMG work")) ||
+            (rc = dev_alloc(&v.x, (size_t)std::max(v.n, 1), "AMG work")) ||
+            (rc = dev_alloc(&v.r, (size_t)std::max(v.n, 1), "AMG work")) ||
+            (rc = dev_alloc(&v.y, (size_t)std::max(v.n, 1), "AMG work")))
+            return fail(rc);
+        if (cur.n <= coarse_size || l + 1 == max_levels) break;
+        std::vector<int> agg;
+        const int na = aggregate(cur, d, th, agg);
+        if ((double)na > 0.6 * (double)cur.n) break;
+        const Csr P = prolongator(cur, d, agg, na, v.omega);
+        const Csr R = transpose(P);
+        Csr next = multiply(R, multiply(cur, P));
+        v.nc = na;
+        v.agg = std::move(agg);
+        v.wave_p = (double)P.col.size() > kWaveRow * (double)std::max(P.n, 1);
+        v.wave_r = (double)R.col.size() > kWaveRow * (double)std::max(R.n, 1);
+        if ((rc = upload(&v.p_ptr, P.ptr, "AMG prolongator", s)) || (rc = upload(&v.p_col, P.col, "AMG prolongator", s)) ||
+            (rc = upload(&v.p_val, P.val, "AMG prolongator", s)) || (rc = upload(&v.r_ptr, R.ptr, "AMG restriction", s)) ||
+            (rc = upload(&v.r_col, R.col, "AMG restriction", s)) || (rc = upload(&v.r_val, R.val, "AMG restriction", s)))
+            return fail(rc);
+        FV_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+        cur = std::move(next);
+        th *= 0.5;
+        ++l;
+    }
+    h->nlev = l + 1;
+    h->nlast = cur.n;
+    if (cur.n > kAmgMaxCoarse)
+        return fail(set_error(FVPCG_UNSUPPORTED, "AMG: last level has %d unknowns (at most %d are solved exactly)",
+                              cur.n, kAmgMaxCoarse));
+    std::vector<double> inv;
+    if (!spd_inverse(cur, inv))
+        return fail(set_error(FVPCG_BREAKDOWN, "AMG: the last level is not positive definite"));
+    if ((rc = upload(&h->cinv, inv, "AMG coarse inverse", s))) return fail(rc);
+    const size_t n0 = (size_t)std::max(A->mesh->n, 1);
+    if ((rc = dev_alloc(&h->r, n0, "AMG-PCG vectors")) || (rc = dev_alloc(&h->z, n0, "AMG-PCG vectors")) ||
+        (rc = dev_alloc(&h->p, n0, "AMG-PCG vectors")) || (rc = dev_alloc(&h->q, n0, "AMG-PCG vectors")) ||
+        (rc = dev_alloc(&h->st, 1, "AMG-PCG state")) || (rc = dev_alloc(&h->partials, (size_t)4 * kMaxGrid, "partials")))
+        return fail(rc);
+    if (hipHostMalloc((void**)&h->hst, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+        h->hst = nullptr;
+        return fail(set_error(FVPCG_OUT_OF_MEMORY, "pinned allocation failed"));
+    }
+    FV_HIP(hipMemsetAsync(h->st, 0, sizeof(DevState), s));
+    hipEvent_t* evs[] = {&h->t_begin, &h->t_end, &h->t_it0, &h->t_it1};
+    for (hipEvent_t* e : evs) FV_HIP(hipEventCreate(e));
+    FV_HIP(hipStreamSynchronize(s));
+    *out = h;
+    return FVPCG_OK;
+}
+
+int amg_levels(const fvpcg_amg* h) { return h->nlev; }
+int amg_level_n(const fvpcg_amg* h, int l) { return h->lev[l].n; }
+long long amg_level_nnz(const fvpcg_amg* h, int l) { return h->lev[l].nnz; }
+const int* amg_level_agg(const fvpcg_amg* h, int l) { return h->lev[l].agg.empty() ? nullptr : h->lev[l].agg.data(); }
+
+// z = M^-1 r (one cycle)
+int amg_apply(const fvpcg_amg* ch, const double* r, double* z, hipStream_t s) {
+    fvpcg_amg* h = const_cast<fvpcg_amg*>(ch);
+    int rc;
+    if ((rc = state_put(h, 0.0, 1, s))) return rc;
+    if ((rc = enqueue_cycle(h, r, z, false, false, h->st, s))) return rc;
+    FV_HIP(hipStreamSynchronize(s));
+    return FVPCG_OK;
+}
+
+// Standard PCG (Section 2) with one AMG cycle as M^-1.
+int solve_amg(const fvpcg_amg* ch, const double* b, double* x, double tol, int maxit, hipStream_t s,
+              fvpcg_stats* stats) {
+    fvpcg_amg* h = const_cast<fvpcg_amg*>(ch);
+    const fvpcg_matrix* A = h->mat;
+    const fvpcg_mesh* m = A->mesh;
+    const int n = m->n;
+    const Geom g = geom_for(n, kAmgBs);
+    DevState* st = h->st;
+    int rc;
+    FV_HIP(hipEventRecord(h->t_begin, s));
+    if ((rc = state_put(h, tol, maxit, s))) return rc;
+    FV_LAYOUT(m, hipLaunchKernelGGL((k_apcg_init<kAmgBs, W_, CI_>), dim3(g.grid), dim3(kAmgBs), 0, s, cols_, A->val,
+                                    A->d, n, g, b, x, h->r, st, h->partials));
+    FV_LAUNCHED();
+    DevState hs;
+    if ((rc = state_get(h, &hs, s))) return rc;
+    FV_HIP(hipEventRecord(h->t_it0, s));
+    if (!hs.done) {
+        // z = M^-1 r, gamma = (r, z), p = z
+        if ((rc = enqueue_cycle(h, h->r, h->z, true, true, st, s))) return rc;
+        hipLaunchKernelGGL((k_apcg_p<kAmgBs>), dim3(g.grid), dim3(kAmgBs), 0, s, h->z, h->p, n, g, 1, st);
+        FV_LAUNCHED();
+        int launched = 0, chunk = 1;
+        while (launched < maxit) {
+            const int cnt = std::min(chunk, maxit - launched);
+            for (int k = 0; k < cnt; ++k) {
+                FV_LAYOUT(m, hipLaunchKernelGGL((k_apcg_spmv<kAmgBs, W_, CI_>), dim3(g.grid), dim3(kAmgBs), 0, s,
+                                                cols_, A->val, A->d, n, g, h->p, h->q, st, h->partials));
+                hipLaunchKernelGGL((k_apcg_xr<kAmgBs>), dim3(g.grid), dim3(kAmgBs), 0, s, x, h->p, h->r, h->q, n, g,
+                                   st, h->partials);
+                if ((rc = enqueue_cycle(h, h->r, h->z, true, false, st, s))) return rc;
+                hipLaunchKernelGGL((k_apcg_p<kAmgBs>), dim3(g.grid), dim3(kAmgBs), 0, s, h->z, h->p, n, g, 0, st);
+                FV_LAUNCHED();
+            }
+            launched += cnt;
+            if ((rc = state_get(h, &hs, s))) return rc;
+            if (hs.done) break;
+            chunk = std::min(chunk * 2, 16);
+        }
+    }
+    FV_HIP(hipEventRecord(h->t_it1, s));
+    if (hs.zero_b) FV_HIP(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
+    FV_LAYOUT(m, hipLaunchKernelGGL((k_apcg_true<kAmgBs, W_, CI_>), dim3(g.grid), dim3(kAmgBs), 0, s, cols_, A->val,
+                                    A->d, n, g, b, x, st, h->partials));
+    FV_LAUNCHED();
+    FV_HIP(hipEventRecord(h->t_end, s));
+    if ((rc = state_get(h, &hs, s))) return rc;
+    if (stats) {
+        stats->iters = hs.iter;
+        stats->outer_iters = 0;
+        stats->status = hs.status;
+        stats->b_norm = hs.bnorm;
+        stats->r0_norm = hs.r0norm;
+        stats->rel_res = hs.bnorm > 0 ? sqrt(hs.rho) / hs.bnorm : 0.0;
+        stats->true_rel_res = hs.bnorm > 0 ? sqrt(hs.true_rr) / hs.bnorm : 0.0;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, h->t_begin, h->t_end);
+        stats->device_ms = ms;
+        (void)hipEventElapsedTime(&ms, h->t_it0, h->t_it1);
+        stats->iter_ms = ms;
+    }
+    return hs.status;
+}
+
+}  // namespace fvpcg

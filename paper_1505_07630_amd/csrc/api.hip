@@ -37,6 +37,15 @@ int solve_batched_backward(const fvpcg_batch* bt, const double* x, const double*
                            double* grad_diag, double* grad_upper, double* grad_lower, double tol, int maxit,
                            int method, int precond, hipStream_t s, fvpcg_stats* stats);
 int stream_calibrate(hipStream_t s, uint64_t bytes, double* copy_gbs, double* triad_gbs);
+int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, hipStream_t s, fvpcg_amg** out);
+void amg_free(fvpcg_amg* h);
+int amg_levels(const fvpcg_amg* h);
+int amg_level_n(const fvpcg_amg* h, int l);
+long long amg_level_nnz(const fvpcg_amg* h, int l);
+const int* amg_level_agg(const fvpcg_amg* h, int l);
+int amg_apply(const fvpcg_amg* h, const double* r, double* z, hipStream_t s);
+int solve_amg(const fvpcg_amg* h, const double* b, double* x, double tol, int maxit, hipStream_t s,
+              fvpcg_stats* stats);
 
 namespace {
 thread_local std::string g_last_error;
@@ -392,6 +401,77 @@ int fvpcg_solve_batched_backward(const fvpcg_batch* batch, const double* x, cons
         }
         return solve_batched_backward(batch, x, g, grad_b, grad_diag, grad_upper, grad_lower, tol, maxit, method,
                                       precond, (hipStream_t)stream, stats);
+    });
+}
+
+int fvpcg_amg_create(const fvpcg_matrix* mat, double theta, int32_t max_levels, int32_t coarse_size, void* stream,
+                     fvpcg_amg** out) {
+    return guard([&]() -> int {
+        if (!out) return set_error(FVPCG_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        if (!mat) return set_error(FVPCG_INVALID_ARG, "mat is NULL");
+        if (!(theta >= 0.0) || !std::isfinite(theta) || max_levels < 1 || coarse_size < 1)
+            return set_error(FVPCG_INVALID_ARG, "need theta >= 0, max_levels >= 1, coarse_size >= 1");
+        if (!mat->diag_ok) return set_error(FVPCG_BREAKDOWN, "AMG needs a finite positive diagonal");
+        return amg_create(mat, theta, max_levels, coarse_size, (hipStream_t)stream, out);
+    });
+}
+
+int fvpcg_amg_destroy(fvpcg_amg* amg) {
+    return guard([&]() -> int {
+        amg_free(amg);
+        return FVPCG_OK;
+    });
+}
+
+int fvpcg_amg_info(const fvpcg_amg* amg, int32_t level, int32_t* levels, int32_t* n, int64_t* nnz) {
+    return guard([&]() -> int {
+        if (!amg) return set_error(FVPCG_INVALID_ARG, "amg is NULL");
+        if (levels) *levels = amg_levels(amg);
+        if (level < 0 || level >= amg_levels(amg)) {
+            if (n || nnz) return set_error(FVPCG_INVALID_ARG, "level %d outside [0, %d)", level, amg_levels(amg));
+            return FVPCG_OK;
+        }
+        if (n) *n = amg_level_n(amg, level);
+        if (nnz) *nnz = amg_level_nnz(amg, level);
+        return FVPCG_OK;
+    });
+}
+
+int fvpcg_amg_aggregates(const fvpcg_amg* amg, int32_t level, int32_t* host_out) {
+    return guard([&]() -> int {
+        if (!amg || !host_out) return set_error(FVPCG_INVALID_ARG, "amg or host_out is NULL");
+        if (level < 0 || level + 1 >= amg_levels(amg))
+            return set_error(FVPCG_INVALID_ARG, "level %d has no coarser level", level);
+        const int* agg = amg_level_agg(amg, level);
+        std::memcpy(host_out, agg, sizeof(int32_t) * (size_t)amg_level_n(amg, level));
+        return FVPCG_OK;
+    });
+}
+
+int fvpcg_amg_apply(const fvpcg_amg* amg, const double* r, double* z, void* stream) {
+    return guard([&]() -> int {
+        if (!amg) return set_error(FVPCG_INVALID_ARG, "amg is NULL");
+        const size_t bytes = sizeof(double) * (size_t)amg_level_n(amg, 0);
+        FV_TRY(check_dev(r, bytes, "r"));
+        FV_TRY(check_dev(z, bytes, "z"));
+        if (overlap(r, bytes, z, bytes)) return set_error(FVPCG_INVALID_ARG, "r and z overlap");
+        return amg_apply(amg, r, z, (hipStream_t)stream);
+    });
+}
+
+int fvpcg_solve_amg(const fvpcg_amg* amg, const double* b, double* x, double tol, int32_t maxit, void* stream,
+                    fvpcg_stats* stats) {
+    return guard([&]() -> int {
+        stats_status(stats, FVPCG_INVALID_ARG);
+        if (!amg) return set_error(FVPCG_INVALID_ARG, "amg is NULL");
+        if (!(tol >= 0.0) || !std::isfinite(tol) || maxit < 0) return set_error(FVPCG_INVALID_ARG, "need tol >= 0, maxit >= 0");
+        if (tol == 0.0 && maxit == 0) return set_error(FVPCG_INVALID_ARG, "tol = maxit = 0");
+        const size_t bytes = sizeof(double) * (size_t)amg_level_n(amg, 0);
+        FV_TRY(check_dev(b, bytes, "b"));
+        FV_TRY(check_dev(x, bytes, "x"));
+        if (overlap(b, bytes, x, bytes)) return set_error(FVPCG_INVALID_ARG, "b and x overlap");
+        return solve_amg(amg, b, x, tol, maxit, (hipStream_t)stream, stats);
     });
 }
 
