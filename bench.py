@@ -322,6 +322,38 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None):
     for m_, A_, b_ in singles:
         A_.close()
         m_.close()
+    # AMG-preconditioned CG (smoothed aggregation, setup on the host, untimed)
+    # against the Jacobi solvers on the same systems and tolerances
+    for name in ("varcoef192", "cavity256", "laplace32"):
+        c = case if (name == "varcoef192" and case is not None) else fvcases.make(name)
+        m_ = mesh if (name == "varcoef192" and mesh is not None) else fv.Mesh(
+            c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
+        A_ = fv.Matrix(m_, to(c.diag, torch.float64), to(c.upper, torch.float64))
+        b_ = b if (name == "varcoef192" and b is not None) else to(c.b, torch.float64)
+        t0 = time.perf_counter()
+        M = fv.AMG(A_)
+        setup_s = time.perf_counter() - t0
+        fv.solve_amg(M, b_, tol=c.tol, maxit=1000)
+        sa = [fv.solve_amg(M, b_, tol=c.tol, maxit=1000)[1] for _ in range(3)]
+        sa.sort(key=lambda t: t["device_ms"])
+        st_a = sa[1]
+        jac = {}
+        for method in ("cg", "pipecg"):
+            fv.solve(A_, b_, tol=c.tol, maxit=100000, method=method)
+            sj = sorted((fv.solve(A_, b_, tol=c.tol, maxit=100000, method=method)[1] for _ in range(3)),
+                        key=lambda t: t["device_ms"])[1]
+            jac[method] = {"iters": sj["iters"], "ms": round(sj["device_ms"], 2)}
+        best_j = min(v["ms"] for v in jac.values())
+        res[f"{name}/amg_pcg_to_{c.tol:g}"] = {
+            "status": st_a["status_name"], "iters": st_a["iters"], "ms": round(st_a["device_ms"], 2),
+            "true_rel_res": st_a["true_rel_res"], "setup_s": round(setup_s, 2),
+            "levels": [M.level_info(l)["n"] for l in range(M.levels)],
+            "jacobi": jac, "speedup_vs_best_jacobi": round(best_j / st_a["device_ms"], 2)}
+        log(f"extra {name} amg: {res[f'{name}/amg_pcg_to_{c.tol:g}']}")
+        M.close()
+        A_.close()
+        if m_ is not mesh:
+            m_.close()
     # small and graded cases: one warm-up solve, then repeated solves timed one
     # by one with HIP events on the solve stream (median reported), and
     # fixed-iteration runs (tol = 0) for the per-iteration rate: 32^3 in ten

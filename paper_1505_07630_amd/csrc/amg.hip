@@ -45,12 +45,13 @@ struct AmgLevel {
     double omega = 0.0;
     int *a_ptr = nullptr, *a_col = nullptr;  // levels >= 1
     double *a_val = nullptr, *d = nullptr;   // levels >= 1
+    double* a_val_cs = nullptr;              // levels >= 1: a_ij / d_j
     int *p_ptr = nullptr, *p_col = nullptr;  // P: n x nc
     double* p_val = nullptr;
     int *r_ptr = nullptr, *r_col = nullptr;  // R = P^T: nc x n
     double* r_val = nullptr;
     double *b = nullptr, *x = nullptr, *r = nullptr, *y = nullptr;  // work
-    bool wave_a = false, wave_p = false, wave_r = false;             // one wavefront per row
+    int ga = 1, gp = 1, gr = 1;  // lanes per row for A, P, R (1, 16 or 64)
     std::vector<int> agg;
 };
 
@@ -354,20 +355,17 @@ __global__ __launch_bounds__(BS) void k_amg_post0(const CI* __restrict__ col, co
 
 // CSR levels, one row per thread.
 __global__ __launch_bounds__(kAmgCsrBs) void k_amg_pre(const int* __restrict__ ptr, const int* __restrict__ col,
-                                                      const double* __restrict__ val, const double* __restrict__ d,
+                                                      const double* __restrict__ val_cs, const double* __restrict__ d,
                                                       int n, double w, const double* __restrict__ b,
                                                       double* __restrict__ x, double* __restrict__ r,
                                                       const DevState* st) {
     if (st->done) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double s = 0.0;
-        for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
-            const int j = col[k];
-            s += val[k] * (w * b[j] / d[j]);
-        }
+        for (int k = ptr[i]; k < ptr[i + 1]; ++k) s += val_cs[k] * b[col[k]];
         const double bi = b[i];
         x[i] = w * bi / d[i];
-        r[i] = bi - s;
+        r[i] = bi - w * s;
     }
 }
 
@@ -398,77 +396,96 @@ __global__ __launch_bounds__(kAmgCsrBs) void k_amg_csr_mv(const int* __restrict_
     }
 }
 
-// The same CSR operations with one wavefront per row, for operators whose
-// rows are long (the coarse levels of smoothed aggregation hold tens to
-// hundreds of entries per row): the lanes stride through the row, coalesced,
-// and the row sum is a wave reduction.  The row loop is uniform per wave, so
-// every lane takes part in the reduction.
-__device__ __forceinline__ int wave_id() { return (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); }
-__device__ __forceinline__ int wave_count() { return (int)((gridDim.x * blockDim.x) >> 6); }
+// The same CSR operations with G lanes per row (G = 16: four rows per
+// wavefront; G = 64: one), for operators whose rows are long (the coarse
+// levels of smoothed aggregation hold tens to hundreds of entries per row):
+// the lanes stride through the row, coalesced, and the row sum is an
+// inclusive DPP scan within each 16-lane row of the wave (plus, for G = 64,
+// the sum of the four row totals).  Rows are taken in wave-uniform blocks so
+// every lane of a wave takes part in the scan.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    v += row_shr<1>(v);
+    v += row_shr<2>(v);
+    v += row_shr<4>(v);
+    v += row_shr<8>(v);
+    if (G == 64) return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
+    return v;  // the group's sum in its last lane
+}
 
-__global__ __launch_bounds__(kAmgCsrBs) void k_amg_pre_w(const int* __restrict__ ptr, const int* __restrict__ col,
-                                                        const double* __restrict__ val, const double* __restrict__ d,
-                                                        int n, double w, const double* __restrict__ b,
-                                                        double* __restrict__ x, double* __restrict__ r,
-                                                        const DevState* st) {
+#define AMG_GROUP_ROWS(G)                                                                  \
+    const int lane_ = threadIdx.x & 63, sub_ = lane_ / (G), gl_ = lane_ % (G);              \
+    const bool lead_ = (G) == 64 ? lane_ == 0 : gl_ == (G) - 1;                             \
+    const int wave_ = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);                  \
+    const int nwave_ = (int)((gridDim.x * blockDim.x) >> 6);                                \
+    for (int base_ = wave_ * (64 / (G)); base_ < n; base_ += nwave_ * (64 / (G)))
+
+// x = omega b / d; r = b - A x with A x = omega sum_j (a_ij / d_j) b_j
+template <int G>
+__global__ __launch_bounds__(kAmgCsrBs) void k_amg_pre_g(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                        const double* __restrict__ val_cs,
+                                                        const double* __restrict__ d, int n, double w,
+                                                        const double* __restrict__ b, double* __restrict__ x,
+                                                        double* __restrict__ r, const DevState* st) {
     if (st->done) return;
-    const int lane = threadIdx.x & 63;
-    for (int i = wave_id(); i < n; i += wave_count()) {
+    AMG_GROUP_ROWS(G) {
+        const int i = base_ + sub_;
         double s = 0.0;
-        for (int k = ptr[i] + lane; k < ptr[i + 1]; k += 64) {
-            const int j = col[k];
-            s += val[k] * (w * b[j] / d[j]);
-        }
-        s = wave_sum(s);
-        if (lane == 0) {
+        if (i < n)
+            for (int k = ptr[i] + gl_; k < ptr[i + 1]; k += G) s += val_cs[k] * b[col[k]];
+        s = group_sum<G>(s);
+        if (i < n && lead_) {
             const double bi = b[i];
             x[i] = w * bi / d[i];
-            r[i] = bi - s;
+            r[i] = bi - w * s;
         }
     }
 }
 
-__global__ __launch_bounds__(kAmgCsrBs) void k_amg_post_w(const int* __restrict__ ptr, const int* __restrict__ col,
+template <int G>
+__global__ __launch_bounds__(kAmgCsrBs) void k_amg_post_g(const int* __restrict__ ptr, const int* __restrict__ col,
                                                          const double* __restrict__ val, const double* __restrict__ d,
                                                          int n, double w, const double* __restrict__ b,
                                                          const double* __restrict__ x, double* __restrict__ y,
                                                          const DevState* st) {
     if (st->done) return;
-    const int lane = threadIdx.x & 63;
-    for (int i = wave_id(); i < n; i += wave_count()) {
+    AMG_GROUP_ROWS(G) {
+        const int i = base_ + sub_;
         double s = 0.0;
-        for (int k = ptr[i] + lane; k < ptr[i + 1]; k += 64) s += val[k] * x[col[k]];
-        s = wave_sum(s);
-        if (lane == 0) y[i] = x[i] + w * (b[i] - s) / d[i];
+        if (i < n)
+            for (int k = ptr[i] + gl_; k < ptr[i + 1]; k += G) s += val[k] * x[col[k]];
+        s = group_sum<G>(s);
+        if (i < n && lead_) y[i] = x[i] + w * (b[i] - s) / d[i];
     }
 }
 
-template <bool ADD>
-__global__ __launch_bounds__(kAmgCsrBs) void k_amg_csr_mv_w(const int* __restrict__ ptr, const int* __restrict__ col,
+template <int G, bool ADD>
+__global__ __launch_bounds__(kAmgCsrBs) void k_amg_csr_mv_g(const int* __restrict__ ptr, const int* __restrict__ col,
                                                            const double* __restrict__ val, int n,
                                                            const double* __restrict__ v, double* __restrict__ y,
                                                            const DevState* st) {
     if (st->done) return;
-    const int lane = threadIdx.x & 63;
-    for (int i = wave_id(); i < n; i += wave_count()) {
+    AMG_GROUP_ROWS(G) {
+        const int i = base_ + sub_;
         double s = 0.0;
-        for (int k = ptr[i] + lane; k < ptr[i + 1]; k += 64) s += val[k] * v[col[k]];
-        s = wave_sum(s);
-        if (lane == 0) y[i] = ADD ? y[i] + s : s;
+        if (i < n)
+            for (int k = ptr[i] + gl_; k < ptr[i + 1]; k += G) s += val[k] * v[col[k]];
+        s = group_sum<G>(s);
+        if (i < n && lead_) y[i] = ADD ? y[i] + s : s;
     }
 }
 
-// last level: y = A^-1 b with the dense inverse
+// last level: y = A^-1 b with the dense inverse, one wavefront per row
 __global__ __launch_bounds__(kAmgCsrBs) void k_amg_coarse_w(const double* __restrict__ inv, int n,
                                                            const double* __restrict__ b, double* __restrict__ y,
                                                            const DevState* st) {
     if (st->done) return;
-    const int lane = threadIdx.x & 63;
-    for (int i = wave_id(); i < n; i += wave_count()) {
+    AMG_GROUP_ROWS(64) {
+        const int i = base_;
         double s = 0.0;
-        for (int k = lane; k < n; k += 64) s += inv[(size_t)i * n + k] * b[k];
-        s = wave_sum(s);
-        if (lane == 0) y[i] = s;
+        for (int k = gl_; k < n; k += 64) s += inv[(size_t)i * n + k] * b[k];
+        s = group_sum<64>(s);
+        if (lead_) y[i] = s;
     }
 }
 
@@ -607,10 +624,55 @@ __global__ __launch_bounds__(BS) void k_apcg_true(const CI* __restrict__ col, co
 }
 
 int csr_grid(int n) { return std::max(1, std::min((n + kAmgCsrBs - 1) / kAmgCsrBs, 4096)); }
-constexpr int kWavesPerBlock = kAmgCsrBs / 64;
-int wave_grid(int n) { return std::max(1, std::min((n + kWavesPerBlock - 1) / kWavesPerBlock, 8192)); }
-// one wavefront per row once rows average more than this many entries
-constexpr double kWaveRow = 12.0;
+// blocks for G lanes per row: 64 / G rows per wavefront, 4 wavefronts per block
+int group_grid(int n, int G) {
+    const int rows_per_block = (kAmgCsrBs / 64) * (64 / G);
+    return std::max(1, std::min((n + rows_per_block - 1) / rows_per_block, 8192));
+}
+// lanes per row from the operator's mean row length (measured at 7M cells:
+// 44-entry rows run fastest with 16 lanes, hundreds with 64)
+int lanes_for(size_t nnz, int rows) {
+    const double avg = (double)nnz / (double)std::max(rows, 1);
+    return avg <= 6.0 ? 1 : (avg <= 48.0 ? 16 : 64);
+}
+
+void launch_pre(const AmgLevel& v, const double* b, const DevState* st, hipStream_t s) {
+    if (v.ga == 1)
+        hipLaunchKernelGGL(k_amg_pre, dim3(csr_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col, v.a_val_cs, v.d,
+                           v.n, v.omega, b, v.x, v.r, st);
+    else if (v.ga == 16)
+        hipLaunchKernelGGL((k_amg_pre_g<16>), dim3(group_grid(v.n, 16)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col,
+                           v.a_val_cs, v.d, v.n, v.omega, b, v.x, v.r, st);
+    else
+        hipLaunchKernelGGL((k_amg_pre_g<64>), dim3(group_grid(v.n, 64)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col,
+                           v.a_val_cs, v.d, v.n, v.omega, b, v.x, v.r, st);
+}
+
+void launch_post(const AmgLevel& v, const DevState* st, hipStream_t s) {
+    if (v.ga == 1)
+        hipLaunchKernelGGL(k_amg_post, dim3(csr_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col, v.a_val, v.d,
+                           v.n, v.omega, v.b, v.x, v.y, st);
+    else if (v.ga == 16)
+        hipLaunchKernelGGL((k_amg_post_g<16>), dim3(group_grid(v.n, 16)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col,
+                           v.a_val, v.d, v.n, v.omega, v.b, v.x, v.y, st);
+    else
+        hipLaunchKernelGGL((k_amg_post_g<64>), dim3(group_grid(v.n, 64)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col,
+                           v.a_val, v.d, v.n, v.omega, v.b, v.x, v.y, st);
+}
+
+template <bool ADD>
+void launch_mv(const int* ptr, const int* col, const double* val, int rows, int G, const double* in, double* out,
+               const DevState* st, hipStream_t s) {
+    if (G == 1)
+        hipLaunchKernelGGL((k_amg_csr_mv<ADD>), dim3(csr_grid(rows)), dim3(kAmgCsrBs), 0, s, ptr, col, val, rows, in,
+                           out, st);
+    else if (G == 16)
+        hipLaunchKernelGGL((k_amg_csr_mv_g<16, ADD>), dim3(group_grid(rows, 16)), dim3(kAmgCsrBs), 0, s, ptr, col,
+                           val, rows, in, out, st);
+    else
+        hipLaunchKernelGGL((k_amg_csr_mv_g<64, ADD>), dim3(group_grid(rows, 64)), dim3(kAmgCsrBs), 0, s, ptr, col,
+                           val, rows, in, out, st);
+}
 
 // Enqueue one cycle y0 = M^-1 b0 on `s`; kernels skip once st->done.
 int enqueue_cycle(const fvpcg_amg* h, const double* b0, double* y0, bool dot, bool first, DevState* st,
@@ -621,7 +683,7 @@ int enqueue_cycle(const fvpcg_amg* h, const double* b0, double* y0, bool dot, bo
     const Geom g0 = geom_for(n0, kAmgBs);
     const int L = h->nlev;
     if (L == 1) {
-        hipLaunchKernelGGL(k_amg_coarse_w, dim3(wave_grid(n0)), dim3(kAmgCsrBs), 0, s, h->cinv, n0, b0, y0, st);
+        hipLaunchKernelGGL(k_amg_coarse_w, dim3(group_grid(n0, 64)), dim3(kAmgCsrBs), 0, s, h->cinv, n0, b0, y0, st);
         if (dot)
             hipLaunchKernelGGL((k_apcg_dot<kAmgBs>), dim3(g0.grid), dim3(kAmgBs), 0, s, b0, y0, n0, g0, first ? 1 : 0,
                                st, h->partials);
@@ -634,31 +696,17 @@ int enqueue_cycle(const fvpcg_amg* h, const double* b0, double* y0, bool dot, bo
         if (l == 0) {
             FV_LAYOUT(m, hipLaunchKernelGGL((k_amg_pre0<kAmgBs, W_, CI_>), dim3(g0.grid), dim3(kAmgBs), 0, s, cols_,
                                             A->val_cs, A->d, n0, g0, v.omega, b, v.x, v.r, st));
-        } else if (v.wave_a) {
-            hipLaunchKernelGGL(k_amg_pre_w, dim3(wave_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col, v.a_val,
-                               v.d, v.n, v.omega, b, v.x, v.r, st);
         } else {
-            hipLaunchKernelGGL(k_amg_pre, dim3(csr_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col, v.a_val, v.d,
-                               v.n, v.omega, b, v.x, v.r, st);
+            launch_pre(v, b, st, s);
         }
-        if (v.wave_r)
-            hipLaunchKernelGGL((k_amg_csr_mv_w<false>), dim3(wave_grid(v.nc)), dim3(kAmgCsrBs), 0, s, v.r_ptr,
-                               v.r_col, v.r_val, v.nc, v.r, h->lev[l + 1].b, st);
-        else
-            hipLaunchKernelGGL((k_amg_csr_mv<false>), dim3(csr_grid(v.nc)), dim3(kAmgCsrBs), 0, s, v.r_ptr, v.r_col,
-                               v.r_val, v.nc, v.r, h->lev[l + 1].b, st);
+        launch_mv<false>(v.r_ptr, v.r_col, v.r_val, v.nc, v.gr, v.r, h->lev[l + 1].b, st, s);
     }
     const AmgLevel& last = h->lev[L - 1];
-    hipLaunchKernelGGL(k_amg_coarse_w, dim3(wave_grid(last.n)), dim3(kAmgCsrBs), 0, s, h->cinv, last.n, last.b,
+    hipLaunchKernelGGL(k_amg_coarse_w, dim3(group_grid(last.n, 64)), dim3(kAmgCsrBs), 0, s, h->cinv, last.n, last.b,
                        last.y, st);
     for (int l = L - 2; l >= 0; --l) {
         const AmgLevel& v = h->lev[l];
-        if (v.wave_p)
-            hipLaunchKernelGGL((k_amg_csr_mv_w<true>), dim3(wave_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.p_ptr, v.p_col,
-                               v.p_val, v.n, h->lev[l + 1].y, v.x, st);
-        else
-            hipLaunchKernelGGL((k_amg_csr_mv<true>), dim3(csr_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.p_ptr, v.p_col,
-                               v.p_val, v.n, h->lev[l + 1].y, v.x, st);
+        launch_mv<true>(v.p_ptr, v.p_col, v.p_val, v.n, v.gp, h->lev[l + 1].y, v.x, st, s);
         if (l == 0) {
             if (dot) {
                 FV_LAYOUT(m, hipLaunchKernelGGL((k_amg_post0<kAmgBs, W_, CI_, true>), dim3(g0.grid), dim3(kAmgBs), 0,
@@ -669,12 +717,8 @@ int enqueue_cycle(const fvpcg_amg* h, const double* b0, double* y0, bool dot, bo
                                                 0, s, cols_, A->val, A->d, n0, g0, v.omega, b0, v.x, y0, 0, st,
                                                 h->partials));
             }
-        } else if (v.wave_a) {
-            hipLaunchKernelGGL(k_amg_post_w, dim3(wave_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col, v.a_val,
-                               v.d, v.n, v.omega, v.b, v.x, v.y, st);
         } else {
-            hipLaunchKernelGGL(k_amg_post, dim3(csr_grid(v.n)), dim3(kAmgCsrBs), 0, s, v.a_ptr, v.a_col, v.a_val,
-                               v.d, v.n, v.omega, v.b, v.x, v.y, st);
+            launch_post(v, st, s);
         }
     }
     FV_LAUNCHED();
@@ -706,6 +750,7 @@ void amg_free(fvpcg_amg* h) {
         dev_free(v.a_ptr);
         dev_free(v.a_col);
         dev_free(v.a_val);
+        dev_free(v.a_val_cs);
         dev_free(v.d);
         dev_free(v.p_ptr);
         dev_free(v.p_col);
@@ -755,11 +800,15 @@ int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_s
         v.n = cur.n;
         v.nnz = (long long)cur.col.size();
         v.omega = 4.0 / (3.0 * gershgorin(cur, d));
-        v.wave_a = (double)cur.col.size() > kWaveRow * (double)std::max(cur.n, 1);
+        v.ga = lanes_for(cur.col.size(), cur.n);
         if (l > 0) {
+            std::vector<double> cs(cur.val.size());
+            for (size_t k = 0; k < cs.size(); ++k) cs[k] = cur.val[k] / d[cur.col[k]];
             if ((rc = upload(&v.a_ptr, cur.ptr, "AMG level rows", s)) || (rc = upload(&v.a_col, cur.col, "AMG level columns", s)) ||
-                (rc = upload(&v.a_val, cur.val, "AMG level values", s)) || (rc = upload(&v.d, d, "AMG level diagonal", s)))
+                (rc = upload(&v.a_val, cur.val, "AMG level values", s)) || (rc = upload(&v.d, d, "AMG level diagonal", s)) ||
+                (rc = upload(&v.a_val_cs, cs, "AMG level scaled values", s)))
                 return fail(rc);
+            FV_HIP(hipStreamSynchronize(s));  // cs goes out of scope
         }
         if ((rc = dev_alloc(&v.b, (size_t)std::max(v.n, 1), "AMG work")) ||
             (rc = dev_alloc(&v.x, (size_t)std::max(v.n, 1), "AMG work")) ||
@@ -775,8 +824,8 @@ int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_s
         Csr next = multiply(R, multiply(cur, P));
         v.nc = na;
         v.agg = std::move(agg);
-        v.wave_p = (double)P.col.size() > kWaveRow * (double)std::max(P.n, 1);
-        v.wave_r = (double)R.col.size() > kWaveRow * (double)std::max(R.n, 1);
+        v.gp = lanes_for(P.col.size(), P.n);
+        v.gr = lanes_for(R.col.size(), R.n);
         if ((rc = upload(&v.p_ptr, P.ptr, "AMG prolongator", s)) || (rc = upload(&v.p_col, P.col, "AMG prolongator", s)) ||
             (rc = upload(&v.p_val, P.val, "AMG prolongator", s)) || (rc = upload(&v.r_ptr, R.ptr, "AMG restriction", s)) ||
             (rc = upload(&v.r_col, R.col, "AMG restriction", s)) || (rc = upload(&v.r_val, R.val, "AMG restriction", s)))
