@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=150)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time the other workloads")
+    ap.add_argument("--extras-select", default="mixed,batched,amg,small",
+                    help="comma-separated groups of extras: mixed, batched, amg, small")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU: the library solves on one device "
@@ -220,7 +222,8 @@ def main():
         "frac_of_stream_copy": round(achieved / calib["copy_gbs"], 4) if calib["copy_gbs"] > 0 else None,
     }
     if args.extras:
-        out["extras"] = extras(fv, torch, np, fvcases, dev, case, mesh, b)
+        out["extras"] = extras(fv, torch, np, fvcases, dev, case, mesh, b,
+                               groups=set(args.extras_select.split(",")))
     if not args.no_cpu:
         log(f"oracle baseline: {args.cpu_iters} iterations on the CPU ...")
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_iters)
@@ -228,11 +231,11 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None):
+def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None, groups=("mixed", "batched", "amg", "small")):
     """Other workloads, for information (not the headline line)."""
     res = {}
     to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).to(dev)
-    if case is not None:
+    if case is not None and "mixed" in groups:
         # mixed precision on the same 192^3 arrays against plain FP64, to 1e-8
         # and to 1e-10: restarted refinement (FP32 inner to 1e-5) and reliable
         # updates (FP32 recurrences re-anchored to the FP64 residual)
@@ -266,124 +269,127 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None):
             }
             log(f"extra mixed to {tol:g}: {res[key]}")
         A32.close()
-    # batched: 256 systems, edges 16..64
-    bt = fvcases.make("batch256")
-    B = fv.Batch(bt.cell_off, bt.face_off, to(bt.owner, torch.int32), to(bt.neighbour, torch.int32),
-                 to(bt.diag, torch.float64), to(bt.upper, torch.float64))
-    bb = to(bt.b, torch.float64)
-    saved = os.environ.get("FVPCG_BATCH_TEAMS")
-    for method in ("cg", "pipecg"):
-        # teams off, teams forced on, and the autotuner's choice between them
-        for mode, label in (("0", "/single"), ("1", "/teams"), (None, "")):
-            if mode is None:
-                os.environ.pop("FVPCG_BATCH_TEAMS", None)
-            else:
-                os.environ["FVPCG_BATCH_TEAMS"] = mode
-            fv.solve_batched(B, bb, tol=1e-8, method=method)  # tunes and captures
+    if "batched" in groups:
+        # batched: 256 systems, edges 16..64
+        bt = fvcases.make("batch256")
+        B = fv.Batch(bt.cell_off, bt.face_off, to(bt.owner, torch.int32), to(bt.neighbour, torch.int32),
+                     to(bt.diag, torch.float64), to(bt.upper, torch.float64))
+        bb = to(bt.b, torch.float64)
+        saved = os.environ.get("FVPCG_BATCH_TEAMS")
+        for method in ("cg", "pipecg"):
+            # teams off, teams forced on, and the autotuner's choice between them
+            for mode, label in (("0", "/single"), ("1", "/teams"), (None, "")):
+                if mode is None:
+                    os.environ.pop("FVPCG_BATCH_TEAMS", None)
+                else:
+                    os.environ["FVPCG_BATCH_TEAMS"] = mode
+                fv.solve_batched(B, bb, tol=1e-8, method=method)  # tunes and captures
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                xb, sts, code = fv.solve_batched(B, bb, tol=1e-8, method=method)
+                torch.cuda.synchronize()
+                tb = time.perf_counter() - t0
+                its = [s_["iters"] for s_ in sts]
+                byts = sum((104 * c.n + 24 * c.F) * k for c, k in zip(bt.cases, its))
+                key = f"batch256/{method}{label}"
+                res[key] = {"status": code, "ms": round(tb * 1e3, 2), "system_iters": int(sum(its)),
+                            "system_iters_per_s": round(sum(its) / tb, 1), "max_iters": max(its),
+                            "effective_GBs": round(byts / tb / 1e9, 1), "total_cells": int(bt.cell_off[-1])}
+                log(f"extra batched {method}{label}: {res[key]}")
+        if saved is None:
+            os.environ.pop("FVPCG_BATCH_TEAMS", None)
+        else:
+            os.environ["FVPCG_BATCH_TEAMS"] = saved
+        B.close()
+        # the same 256 systems solved one after another by the single-system
+        # FP64 solver (setup outside the timed region)
+        singles = []
+        for c in bt.cases:
+            m_ = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
+            singles.append((m_, fv.Matrix(m_, to(c.diag, torch.float64), to(c.upper, torch.float64)),
+                            to(c.b, torch.float64)))
+        for method in ("cg", "pipecg"):
+            for m_, A_, b_ in singles[:4]:
+                fv.solve(A_, b_, tol=1e-8, method=method)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            xb, sts, code = fv.solve_batched(B, bb, tol=1e-8, method=method)
+            its = 0
+            for m_, A_, b_ in singles:
+                _, st_ = fv.solve(A_, b_, tol=1e-8, maxit=100000, method=method)
+                its += st_["iters"]
             torch.cuda.synchronize()
-            tb = time.perf_counter() - t0
-            its = [s_["iters"] for s_ in sts]
-            byts = sum((104 * c.n + 24 * c.F) * k for c, k in zip(bt.cases, its))
-            key = f"batch256/{method}{label}"
-            res[key] = {"status": code, "ms": round(tb * 1e3, 2), "system_iters": int(sum(its)),
-                        "system_iters_per_s": round(sum(its) / tb, 1), "max_iters": max(its),
-                        "effective_GBs": round(byts / tb / 1e9, 1), "total_cells": int(bt.cell_off[-1])}
-            log(f"extra batched {method}{label}: {res[key]}")
-    if saved is None:
-        os.environ.pop("FVPCG_BATCH_TEAMS", None)
-    else:
-        os.environ["FVPCG_BATCH_TEAMS"] = saved
-    B.close()
-    # the same 256 systems solved one after another by the single-system
-    # FP64 solver (setup outside the timed region)
-    singles = []
-    for c in bt.cases:
-        m_ = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
-        singles.append((m_, fv.Matrix(m_, to(c.diag, torch.float64), to(c.upper, torch.float64)),
-                        to(c.b, torch.float64)))
-    for method in ("cg", "pipecg"):
-        for m_, A_, b_ in singles[:4]:
-            fv.solve(A_, b_, tol=1e-8, method=method)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        its = 0
+            ts = time.perf_counter() - t0
+            key = f"batch256/{method}/one_solve_per_system"
+            res[key] = {"ms": round(ts * 1e3, 1), "system_iters": its, "system_iters_per_s": round(its / ts, 1),
+                        "batched_speedup": round(ts * 1e3 / res[f"batch256/{method}"]["ms"], 2)}
+            log(f"extra {key}: {res[key]}")
         for m_, A_, b_ in singles:
-            _, st_ = fv.solve(A_, b_, tol=1e-8, maxit=100000, method=method)
-            its += st_["iters"]
-        torch.cuda.synchronize()
-        ts = time.perf_counter() - t0
-        key = f"batch256/{method}/one_solve_per_system"
-        res[key] = {"ms": round(ts * 1e3, 1), "system_iters": its, "system_iters_per_s": round(its / ts, 1),
-                    "batched_speedup": round(ts * 1e3 / res[f"batch256/{method}"]["ms"], 2)}
-        log(f"extra {key}: {res[key]}")
-    for m_, A_, b_ in singles:
-        A_.close()
-        m_.close()
-    # AMG-preconditioned CG (smoothed aggregation, setup on the host, untimed)
-    # against the Jacobi solvers on the same systems and tolerances
-    for name in ("varcoef192", "cavity256", "laplace32"):
-        c = case if (name == "varcoef192" and case is not None) else fvcases.make(name)
-        m_ = mesh if (name == "varcoef192" and mesh is not None) else fv.Mesh(
-            c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
-        A_ = fv.Matrix(m_, to(c.diag, torch.float64), to(c.upper, torch.float64))
-        b_ = b if (name == "varcoef192" and b is not None) else to(c.b, torch.float64)
-        t0 = time.perf_counter()
-        M = fv.AMG(A_)
-        setup_s = time.perf_counter() - t0
-        fv.solve_amg(M, b_, tol=c.tol, maxit=1000)
-        sa = [fv.solve_amg(M, b_, tol=c.tol, maxit=1000)[1] for _ in range(3)]
-        sa.sort(key=lambda t: t["device_ms"])
-        st_a = sa[1]
-        jac = {}
-        for method in ("cg", "pipecg"):
-            fv.solve(A_, b_, tol=c.tol, maxit=100000, method=method)
-            sj = sorted((fv.solve(A_, b_, tol=c.tol, maxit=100000, method=method)[1] for _ in range(3)),
-                        key=lambda t: t["device_ms"])[1]
-            jac[method] = {"iters": sj["iters"], "ms": round(sj["device_ms"], 2)}
-        best_j = min(v["ms"] for v in jac.values())
-        res[f"{name}/amg_pcg_to_{c.tol:g}"] = {
-            "status": st_a["status_name"], "iters": st_a["iters"], "ms": round(st_a["device_ms"], 2),
-            "true_rel_res": st_a["true_rel_res"], "setup_s": round(setup_s, 2),
-            "levels": [M.level_info(l)["n"] for l in range(M.levels)],
-            "jacobi": jac, "speedup_vs_best_jacobi": round(best_j / st_a["device_ms"], 2)}
-        log(f"extra {name} amg: {res[f'{name}/amg_pcg_to_{c.tol:g}']}")
-        M.close()
-        A_.close()
-        if m_ is not mesh:
+            A_.close()
             m_.close()
-    # small and graded cases: one warm-up solve, then repeated solves timed one
-    # by one with HIP events on the solve stream (median reported), and
-    # fixed-iteration runs (tol = 0) for the per-iteration rate: 32^3 in ten
-    # runs of 200 iterations (iterating far past convergence would end in a
-    # breakdown once the residual vanishes), the cavity in one run of 500
-    for name, method, reps, fixed in (("laplace32", "pipecg", 21, (200, 10)), ("laplace32", "cg", 21, (200, 10)),
-                                      ("cavity256", "cg", 3, (500, 1))):
-        c = fvcases.make(name)
-        mesh = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
-        A = fv.Matrix(mesh, to(c.diag, torch.float64), to(c.upper, torch.float64))
-        b = to(c.b, torch.float64)
-        fv.solve(A, b, tol=c.tol, method=method)
-        times = []
-        for _ in range(reps):
-            _, st = fv.solve(A, b, tol=c.tol, method=method, maxit=100000)
-            times.append(st["device_ms"])
-        times.sort()
-        med = times[len(times) // 2]
-        f_its, f_ms = 0, 0.0
-        for _ in range(fixed[1]):
-            _, sf = fv.solve(A, b, tol=0.0, method=method, maxit=fixed[0])
-            f_its += sf["iters"]
-            f_ms += sf["iter_ms"]
-        res[f"{name}/{method}"] = {"iters_per_solve": st["iters"], "status": st["status_name"],
-                                   "median_ms_per_solve": round(med, 3), "solves": reps,
-                                   "iters_per_s": round(st["iters"] / med * 1e3, 1),
-                                   "fixed_iters": f_its, "fixed_iters_per_s": round(f_its / f_ms * 1e3, 1)}
-        log(f"extra {name}/{method}: {res[f'{name}/{method}']}")
-        A.close()
-        mesh.close()
+    if "amg" in groups:
+        # AMG-preconditioned CG (smoothed aggregation, setup on the host, untimed)
+        # against the Jacobi solvers on the same systems and tolerances
+        for name in ("varcoef192", "cavity256", "laplace32"):
+            c = case if (name == "varcoef192" and case is not None) else fvcases.make(name)
+            m_ = mesh if (name == "varcoef192" and mesh is not None) else fv.Mesh(
+                c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
+            A_ = fv.Matrix(m_, to(c.diag, torch.float64), to(c.upper, torch.float64))
+            b_ = b if (name == "varcoef192" and b is not None) else to(c.b, torch.float64)
+            t0 = time.perf_counter()
+            M = fv.AMG(A_)
+            setup_s = time.perf_counter() - t0
+            fv.solve_amg(M, b_, tol=c.tol, maxit=1000)
+            sa = [fv.solve_amg(M, b_, tol=c.tol, maxit=1000)[1] for _ in range(3)]
+            sa.sort(key=lambda t: t["device_ms"])
+            st_a = sa[1]
+            jac = {}
+            for method in ("cg", "pipecg"):
+                fv.solve(A_, b_, tol=c.tol, maxit=100000, method=method)
+                sj = sorted((fv.solve(A_, b_, tol=c.tol, maxit=100000, method=method)[1] for _ in range(3)),
+                            key=lambda t: t["device_ms"])[1]
+                jac[method] = {"iters": sj["iters"], "ms": round(sj["device_ms"], 2)}
+            best_j = min(v["ms"] for v in jac.values())
+            res[f"{name}/amg_pcg_to_{c.tol:g}"] = {
+                "status": st_a["status_name"], "iters": st_a["iters"], "ms": round(st_a["device_ms"], 2),
+                "true_rel_res": st_a["true_rel_res"], "setup_s": round(setup_s, 2),
+                "levels": [M.level_info(l)["n"] for l in range(M.levels)],
+                "jacobi": jac, "speedup_vs_best_jacobi": round(best_j / st_a["device_ms"], 2)}
+            log(f"extra {name} amg: {res[f'{name}/amg_pcg_to_{c.tol:g}']}")
+            M.close()
+            A_.close()
+            if m_ is not mesh:
+                m_.close()
+    if "small" in groups:
+        # small and graded cases: one warm-up solve, then repeated solves timed one
+        # by one with HIP events on the solve stream (median reported), and
+        # fixed-iteration runs (tol = 0) for the per-iteration rate: 32^3 in ten
+        # runs of 200 iterations (iterating far past convergence would end in a
+        # breakdown once the residual vanishes), the cavity in one run of 500
+        for name, method, reps, fixed in (("laplace32", "pipecg", 21, (200, 10)), ("laplace32", "cg", 21, (200, 10)),
+                                          ("cavity256", "cg", 3, (500, 1))):
+            c = fvcases.make(name)
+            mesh = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
+            A = fv.Matrix(mesh, to(c.diag, torch.float64), to(c.upper, torch.float64))
+            b = to(c.b, torch.float64)
+            fv.solve(A, b, tol=c.tol, method=method)
+            times = []
+            for _ in range(reps):
+                _, st = fv.solve(A, b, tol=c.tol, method=method, maxit=100000)
+                times.append(st["device_ms"])
+            times.sort()
+            med = times[len(times) // 2]
+            f_its, f_ms = 0, 0.0
+            for _ in range(fixed[1]):
+                _, sf = fv.solve(A, b, tol=0.0, method=method, maxit=fixed[0])
+                f_its += sf["iters"]
+                f_ms += sf["iter_ms"]
+            res[f"{name}/{method}"] = {"iters_per_solve": st["iters"], "status": st["status_name"],
+                                       "median_ms_per_solve": round(med, 3), "solves": reps,
+                                       "iters_per_s": round(st["iters"] / med * 1e3, 1),
+                                       "fixed_iters": f_its, "fixed_iters_per_s": round(f_its / f_ms * 1e3, 1)}
+            log(f"extra {name}/{method}: {res[f'{name}/{method}']}")
+            A.close()
+            mesh.close()
     return res
 
 

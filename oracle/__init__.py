@@ -87,6 +87,8 @@ def lib():
         L.or_amg_vcycle.restype = None
         L.or_amg_pcg.argtypes = [P, P, P, d, i32, P]
         L.or_amg_pcg.restype = i32
+        L.or_amg_pipecg.argtypes = [P, P, P, d, i32, P]
+        L.or_amg_pipecg.restype = i32
         L.or_adjoint_grads.argtypes = [i32, i32, P, P, P, P, P, P, P]
         L.or_adjoint_grads.restype = None
         _lib = L
@@ -246,11 +248,12 @@ class AMG:
         lib().or_amg_vcycle(self._h, _p(b), _p(x))
         return x
 
-    def pcg(self, b, x0=None, tol=1e-8, maxit=1000):
+    def pcg(self, b, x0=None, tol=1e-8, maxit=1000, pipelined=False):
         b = _f64(b)
         x = np.zeros(self.n) if x0 is None else _f64(x0).copy()
         st = Stats()
-        lib().or_amg_pcg(self._h, _p(b), _p(x), float(tol), int(maxit), ctypes.byref(st))
+        fn = lib().or_amg_pipecg if pipelined else lib().or_amg_pcg
+        fn(self._h, _p(b), _p(x), float(tol), int(maxit), ctypes.byref(st))
         return x, st.asdict()
 
 

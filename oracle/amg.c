@@ -449,3 +449,77 @@ done:
     free(r); free(z); free(p); free(q);
     return status;
 }
+
+/* Pipelined CG of Ghysels and Vanroose (Section 4.1) with M^-1 = one
+ * V-cycle, the literal recurrences (u = M^-1 r, m = M^-1 w, q = M^-1 s are
+ * carried):
+ *   r0 = b - A x0, u0 = M^-1 r0, w0 = A u0;  per iteration i:
+ *   gamma = (r, u), delta = (w, u); stop on ||r|| <= tol ||b||;
+ *   m = M^-1 w, n = A m;
+ *   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev)
+ *   (i = 0: beta = 0, alpha = gamma / delta);
+ *   z = n + beta z, q = m + beta q, s = w + beta s, p = u + beta p;
+ *   x += alpha p, r -= alpha s, u -= alpha q, w -= alpha z. */
+int32_t or_amg_pipecg(const or_amg* h, const double* b, double* x, double tol, int32_t maxit, or_stats* st)
+{
+    const csr_t* A = &h->A[0];
+    const int32_t n = A->n;
+    if (st) memset(st, 0, sizeof(*st));
+    const size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *r = malloc(sz), *u = malloc(sz), *w = malloc(sz), *m = malloc(sz), *nv = malloc(sz);
+    double *z = calloc((size_t)(n > 0 ? n : 1), sizeof(double)), *q = calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *s = calloc((size_t)(n > 0 ? n : 1), sizeof(double)), *p = calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    const double bnorm = sqrt(or_dot(n, b, b));
+    int32_t status = OR_NOT_CONVERGED, i = 0;
+    double rho = 0.0;
+    if (bnorm == 0.0) {
+        for (int32_t c = 0; c < n; ++c) x[c] = 0.0;
+        status = OR_OK;
+        goto done;
+    }
+    csr_mv(A, x, r);
+    for (int32_t c = 0; c < n; ++c) r[c] = b[c] - r[c];
+    vcycle(h, 0, r, u);
+    csr_mv(A, u, w);
+    double gamma_prev = 0.0, alpha_prev = 0.0;
+    for (i = 0;; ++i) {
+        const double gamma = or_dot(n, r, u);
+        const double delta = or_dot(n, w, u);
+        rho = or_dot(n, r, r);
+        if (i == 0 && st) st->r0_norm = sqrt(rho);
+        if (sqrt(rho) <= tol * bnorm) { status = OR_OK; break; }
+        if (i == maxit) break;
+        vcycle(h, 0, w, m);
+        csr_mv(A, m, nv);
+        double beta, den;
+        if (i == 0) { beta = 0.0; den = delta; }
+        else { beta = gamma / gamma_prev; den = delta - beta * gamma / alpha_prev; }
+        const double alpha = gamma / den;
+        if (!(den > 0.0) || !isfinite(alpha) || !isfinite(beta)) { status = OR_BREAKDOWN; break; }
+        for (int32_t c = 0; c < n; ++c) {
+            z[c] = nv[c] + beta * z[c];
+            q[c] = m[c] + beta * q[c];
+            s[c] = w[c] + beta * s[c];
+            p[c] = u[c] + beta * p[c];
+            x[c] += alpha * p[c];
+            r[c] -= alpha * s[c];
+            u[c] -= alpha * q[c];
+            w[c] -= alpha * z[c];
+        }
+        gamma_prev = gamma;
+        alpha_prev = alpha;
+    }
+done:
+    if (st) {
+        st->iters = i;
+        st->status = status;
+        st->b_norm = bnorm;
+        st->rel_res = bnorm > 0 ? sqrt(rho) / bnorm : 0.0;
+        csr_mv(A, x, nv);
+        double tr = 0.0;
+        for (int32_t c = 0; c < n; ++c) tr += (b[c] - nv[c]) * (b[c] - nv[c]);
+        st->true_rel_res = bnorm > 0 ? sqrt(tr) / bnorm : 0.0;
+    }
+    free(r); free(u); free(w); free(m); free(nv); free(z); free(q); free(s); free(p);
+    return status;
+}

@@ -98,6 +98,8 @@ int32_t or_amg_export(const or_amg* h, int32_t l, int32_t which, int32_t* rows, 
 void or_amg_vcycle(const or_amg* h, const double* b, double* x);
 /* Standard PCG with the V-cycle; x holds x0 on entry. */
 int32_t or_amg_pcg(const or_amg* h, const double* b, double* x, double tol, int32_t maxit, or_stats* st);
+/* Pipelined CG (literal recurrences) with the V-cycle; x holds x0 on entry. */
+int32_t or_amg_pipecg(const or_amg* h, const double* b, double* x, double tol, int32_t maxit, or_stats* st);
 
 /* Gradients of a scalar loss L(x) with A x = b on the LDU pattern, given x
  * and lambda = A^-T dL/dx:  dL/ddiag = -lambda*x, dL/dupper[f] =

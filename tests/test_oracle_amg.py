@@ -12,6 +12,8 @@ A7 the cycle is symmetric positive definite and its error propagator
 A8 AMG-PCG reaches the dense solution; iteration counts far below Jacobi-PCG
    and, at 64^3, no more than Table pcgs2's GPU AMG-CG count (loose: the
    paper's AMG, boundary conditions and right-hand side are not stated)
+A9 AMG-preconditioned pipelined CG: the same iterates as AMG-PCG in exact
+   arithmetic (equal at equal count up to rounding), the dense solution
 """
 import numpy as np
 import pytest
@@ -154,3 +156,21 @@ def test_a8_iteration_counts(oracle_lib):
     c = fc.laplace((64, 64, 64))
     _, st = oracle_lib.AMG(c).pcg(c.b, tol=1e-8, maxit=500)
     assert st["status"] == 0 and st["iters"] <= 28
+
+
+# ---------------------------------------------------------------- A9
+@pytest.mark.parametrize("make", [lambda: fc.laplace((12, 12, 12)), lambda: fc.varcoef((13, 11, 9), seed=6),
+                                  lambda: fc.cavity((14, 14, 5))])
+def test_a9_pipelined_equals_standard(oracle_lib, make):
+    c = make()
+    h = oracle_lib.AMG(c, coarse_size=16)
+    for k in (1, 3, 8):
+        xs, _ = h.pcg(c.b, tol=0.0, maxit=k)
+        xp, sp = h.pcg(c.b, tol=0.0, maxit=k, pipelined=True)
+        assert sp["iters"] == k
+        assert np.linalg.norm(xp - xs) / np.linalg.norm(xs) <= 1e-10
+    x, st = h.pcg(c.b, tol=1e-12, maxit=200, pipelined=True)
+    _, s2 = h.pcg(c.b, tol=1e-12, maxit=200)
+    assert st["status"] == 0 and abs(st["iters"] - s2["iters"]) <= 1
+    xd = np.linalg.solve(dense(c), c.b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 1e-9
