@@ -244,10 +244,12 @@ FVPCG_API int fvpcg_amg_info(const fvpcg_amg* amg, int32_t level, int32_t* level
 FVPCG_API int fvpcg_amg_aggregates(const fvpcg_amg* amg, int32_t level, int32_t* host_out);
 /* z = M^-1 r, one cycle; r, z: FP64[n_cells] device arrays, not overlapping. */
 FVPCG_API int fvpcg_amg_apply(const fvpcg_amg* amg, const double* r, double* z, void* stream);
-/* Standard preconditioned CG (Section 2) with M^-1 = one cycle; stopping and
- * stats as fvpcg_solve (x holds x0). */
+/* Preconditioned CG with M^-1 = one cycle: method FVPCG_CG (standard form,
+ * Section 2) or FVPCG_PIPECG (pipelined form of Section 4.1 with the literal
+ * recurrences u = M^-1 r, m = M^-1 w, q = M^-1 s; one cycle per iteration
+ * applied to w).  Stopping and stats as fvpcg_solve (x holds x0). */
 FVPCG_API int fvpcg_solve_amg(const fvpcg_amg* amg, const double* b, double* x, double tol, int32_t maxit,
-                              void* stream, fvpcg_stats* stats);
+                              int32_t method, void* stream, fvpcg_stats* stats);
 
 /* ---- STREAM-style copy and triad over device arrays of `bytes_per_array`
  * bytes each (three arrays; 0 = 1 GiB), as the paper measures attainable

@@ -454,15 +454,16 @@ def fvpcg_amg_apply(M: AMG, r, z=None, stream=None):
 amg_apply = fvpcg_amg_apply
 
 
-def fvpcg_solve_amg(M: AMG, b, x=None, tol=1e-8, maxit=1000, stream=None):
-    """Standard CG preconditioned by one AMG cycle."""
+def fvpcg_solve_amg(M: AMG, b, x=None, tol=1e-8, maxit=1000, method="cg", stream=None):
+    """CG preconditioned by one AMG cycle: method "cg" (standard form) or
+    "pipecg" (pipelined, literal recurrences)."""
     import torch
 
     if x is None:
         x = torch.zeros_like(b)
     st = Stats()
     code = lib().fvpcg_solve_amg(M.handle, _ptr(b, torch.float64, M.n, "b"), _ptr(x, torch.float64, M.n, "x"),
-                                 float(tol), int(maxit), _stream(stream), ctypes.byref(st))
+                                 float(tol), int(maxit), METHODS[method], _stream(stream), ctypes.byref(st))
     _check(code, "fvpcg_solve_amg")
     return x, st.asdict()
 

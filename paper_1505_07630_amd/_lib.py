@@ -67,7 +67,7 @@ SIGNATURES = {
     "fvpcg_amg_info": (ctypes.c_int, [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]),
     "fvpcg_amg_aggregates": (ctypes.c_int, [P, i32, P]),
     "fvpcg_amg_apply": (ctypes.c_int, [P, P, P, P]),
-    "fvpcg_solve_amg": (ctypes.c_int, [P, P, P, f64, i32, P, SPS]),
+    "fvpcg_solve_amg": (ctypes.c_int, [P, P, P, f64, i32, i32, P, SPS]),
 }
 
 _lib = None

@@ -64,6 +64,7 @@ struct fvpcg_amg {
     double* cinv = nullptr;  // inverse of the last level, row-major
     int nlast = 0;
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;  // PCG vectors
+    double *u = nullptr, *w = nullptr, *m = nullptr, *s = nullptr;  // pipelined CG, allocated on first use
     fvpcg::DevState* st = nullptr;
     fvpcg::DevState* hst = nullptr;  // pinned [2]
     double* partials = nullptr;
@@ -608,6 +609,84 @@ __global__ __launch_bounds__(BS) void k_apcg_xr(double* __restrict__ x, const do
     }
 }
 
+// Pipelined CG (Ghysels and Vanroose, Section 4.1) with the AMG cycle as
+// M^-1, literal recurrences: w0 = A u0 and the first reduction.
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_apipe_init_w(const CI* __restrict__ col, const double* __restrict__ val,
+                                                     const double* __restrict__ d, int n, Geom g,
+                                                     const double* __restrict__ r, const double* __restrict__ u,
+                                                     double* __restrict__ w, DevState* st, double* partials) {
+    if (st->done) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    FV_ROWS(blk) {
+        const double uc = u[c], rc = r[c];
+        const double wc = row_gather<double, WT, CI>(col, val, n, c, u, d[c] * uc);
+        w[c] = wc;
+        acc[0] += rc * uc;
+        acc[1] += wc * uc;
+        acc[2] += rc * rc;
+    }
+    double t[3];
+    if (device_reduce<BS, 3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0)
+        pipe_scalars(st, t[0], t[1], t[2], true);
+}
+
+// One iteration, m = M^-1 w already formed by a cycle:
+//   n = A m; z = n + beta z; q = m + beta q; s = w + beta s; p = u + beta p;
+//   x += alpha p; r -= alpha s; u -= alpha q; w -= alpha z;
+// and the reduction (r, u), (w, u), (r, r) of the new iterate.
+template <int BS, int WT, typename CI>
+__global__ __launch_bounds__(BS) void k_apipe_iter(const CI* __restrict__ col, const double* __restrict__ val,
+                                                   const double* __restrict__ d, int n, Geom g,
+                                                   const double* __restrict__ m, double* __restrict__ w,
+                                                   double* __restrict__ z, double* __restrict__ q,
+                                                   double* __restrict__ s, double* __restrict__ p,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ u, DevState* st, double* partials) {
+    if (st->done) return;
+    const double alpha = st->alpha, beta = st->beta;
+    double acc[3] = {0.0, 0.0, 0.0};
+    FV_ROWS(blk) {
+        const double mc = m[c];
+        const double nv = row_gather<double, WT, CI>(col, val, n, c, m, d[c] * mc);
+        const double zc = nv + beta * z[c];
+        const double qc = mc + beta * q[c];
+        const double wc = w[c];
+        const double sc = wc + beta * s[c];
+        double uc = u[c];
+        const double pc = uc + beta * p[c];
+        z[c] = zc;
+        q[c] = qc;
+        s[c] = sc;
+        p[c] = pc;
+        x[c] += alpha * pc;
+        const double rc = r[c] - alpha * sc;
+        r[c] = rc;
+        uc -= alpha * qc;
+        u[c] = uc;
+        const double wn = wc - alpha * zc;
+        w[c] = wn;
+        acc[0] += rc * uc;
+        acc[1] += wn * uc;
+        acc[2] += rc * rc;
+    }
+    double t[3];
+    if (device_reduce<BS, 3>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0)
+        pipe_scalars(st, t[0], t[1], t[2], false);
+}
+
+// zero the pipelined recurrences z, q, s, p before the first iteration
+template <int BS>
+__global__ __launch_bounds__(BS) void k_apipe_clear(double* __restrict__ z, double* __restrict__ q,
+                                                    double* __restrict__ s, double* __restrict__ p, int n, Geom g) {
+    FV_ROWS(blk) {
+        z[c] = 0.0;
+        q[c] = 0.0;
+        s[c] = 0.0;
+        p[c] = 0.0;
+    }
+}
+
 // ||b - A x||^2 at exit
 template <int BS, int WT, typename CI>
 __global__ __launch_bounds__(BS) void k_apcg_true(const CI* __restrict__ col, const double* __restrict__ val,
@@ -768,6 +847,10 @@ void amg_free(fvpcg_amg* h) {
     dev_free(h->z);
     dev_free(h->p);
     dev_free(h->q);
+    dev_free(h->u);
+    dev_free(h->w);
+    dev_free(h->m);
+    dev_free(h->s);
     dev_free(h->st);
     dev_free(h->partials);
     if (h->hst) (void)hipHostFree(h->hst);
@@ -877,7 +960,7 @@ int amg_apply(const fvpcg_amg* ch, const double* r, double* z, hipStream_t s) {
 }
 
 // Standard PCG (Section 2) with one AMG cycle as M^-1.
-int solve_amg(const fvpcg_amg* ch, const double* b, double* x, double tol, int maxit, hipStream_t s,
+int solve_amg(const fvpcg_amg* ch, const double* b, double* x, double tol, int maxit, int method, hipStream_t s,
               fvpcg_stats* stats) {
     fvpcg_amg* h = const_cast<fvpcg_amg*>(ch);
     const fvpcg_matrix* A = h->mat;
@@ -894,7 +977,36 @@ int solve_amg(const fvpcg_amg* ch, const double* b, double* x, double tol, int m
     DevState hs;
     if ((rc = state_get(h, &hs, s))) return rc;
     FV_HIP(hipEventRecord(h->t_it0, s));
-    if (!hs.done) {
+    const bool pipe = method == FVPCG_PIPECG;
+    if (pipe && !h->u) {
+        const size_t nn = (size_t)std::max(n, 1);
+        if ((rc = dev_alloc(&h->u, nn, "AMG pipelined vectors")) || (rc = dev_alloc(&h->w, nn, "AMG pipelined vectors")) ||
+            (rc = dev_alloc(&h->m, nn, "AMG pipelined vectors")) || (rc = dev_alloc(&h->s, nn, "AMG pipelined vectors")))
+            return rc;
+    }
+    if (!hs.done && pipe) {
+        // u = M^-1 r; z = q = s = p = 0; w = A u and the first reduction
+        if ((rc = enqueue_cycle(h, h->r, h->u, false, false, st, s))) return rc;
+        hipLaunchKernelGGL((k_apipe_clear<kAmgBs>), dim3(g.grid), dim3(kAmgBs), 0, s, h->z, h->q, h->s, h->p, n, g);
+        FV_LAYOUT(m, hipLaunchKernelGGL((k_apipe_init_w<kAmgBs, W_, CI_>), dim3(g.grid), dim3(kAmgBs), 0, s, cols_,
+                                        A->val, A->d, n, g, h->r, h->u, h->w, st, h->partials));
+        FV_LAUNCHED();
+        int launched = 0, chunk = 1;
+        while (launched < maxit) {
+            const int cnt = std::min(chunk, maxit - launched);
+            for (int k = 0; k < cnt; ++k) {
+                if ((rc = enqueue_cycle(h, h->w, h->m, false, false, st, s))) return rc;
+                FV_LAYOUT(m, hipLaunchKernelGGL((k_apipe_iter<kAmgBs, W_, CI_>), dim3(g.grid), dim3(kAmgBs), 0, s,
+                                                cols_, A->val, A->d, n, g, h->m, h->w, h->z, h->q, h->s, h->p, x,
+                                                h->r, h->u, st, h->partials));
+                FV_LAUNCHED();
+            }
+            launched += cnt;
+            if ((rc = state_get(h, &hs, s))) return rc;
+            if (hs.done) break;
+            chunk = std::min(chunk * 2, 16);
+        }
+    } else if (!hs.done) {
         // z = M^-1 r, gamma = (r, z), p = z
         if ((rc = enqueue_cycle(h, h->r, h->z, true, true, st, s))) return rc;
         hipLaunchKernelGGL((k_apcg_p<kAmgBs>), dim3(g.grid), dim3(kAmgBs), 0, s, h->z, h->p, n, g, 1, st);

@@ -44,7 +44,7 @@ int amg_level_n(const fvpcg_amg* h, int l);
 long long amg_level_nnz(const fvpcg_amg* h, int l);
 const int* amg_level_agg(const fvpcg_amg* h, int l);
 int amg_apply(const fvpcg_amg* h, const double* r, double* z, hipStream_t s);
-int solve_amg(const fvpcg_amg* h, const double* b, double* x, double tol, int maxit, hipStream_t s,
+int solve_amg(const fvpcg_amg* h, const double* b, double* x, double tol, int maxit, int method, hipStream_t s,
               fvpcg_stats* stats);
 
 namespace {
@@ -460,18 +460,20 @@ int fvpcg_amg_apply(const fvpcg_amg* amg, const double* r, double* z, void* stre
     });
 }
 
-int fvpcg_solve_amg(const fvpcg_amg* amg, const double* b, double* x, double tol, int32_t maxit, void* stream,
-                    fvpcg_stats* stats) {
+int fvpcg_solve_amg(const fvpcg_amg* amg, const double* b, double* x, double tol, int32_t maxit, int32_t method,
+                    void* stream, fvpcg_stats* stats) {
     return guard([&]() -> int {
         stats_status(stats, FVPCG_INVALID_ARG);
         if (!amg) return set_error(FVPCG_INVALID_ARG, "amg is NULL");
         if (!(tol >= 0.0) || !std::isfinite(tol) || maxit < 0) return set_error(FVPCG_INVALID_ARG, "need tol >= 0, maxit >= 0");
         if (tol == 0.0 && maxit == 0) return set_error(FVPCG_INVALID_ARG, "tol = maxit = 0");
+        if (method != FVPCG_CG && method != FVPCG_PIPECG)
+            return set_error(FVPCG_INVALID_ARG, "method must be FVPCG_CG or FVPCG_PIPECG");
         const size_t bytes = sizeof(double) * (size_t)amg_level_n(amg, 0);
         FV_TRY(check_dev(b, bytes, "b"));
         FV_TRY(check_dev(x, bytes, "x"));
         if (overlap(b, bytes, x, bytes)) return set_error(FVPCG_INVALID_ARG, "b and x overlap");
-        return solve_amg(amg, b, x, tol, maxit, (hipStream_t)stream, stats);
+        return solve_amg(amg, b, x, tol, maxit, method, (hipStream_t)stream, stats);
     });
 }
 

@@ -96,4 +96,49 @@ inline Geom geom_for(int n, int bs) {
 }
 
 
+// The pipelined recurrences' scalars, formed once by the workgroup that
+// finishes the reduction: the stopping test on rho = (r, r), then
+// beta = gamma / gamma_prev and alpha = gamma / (delta - beta gamma /
+// alpha_prev) (first: beta = 0, alpha = gamma / delta), with breakdown when
+// the denominator is not positive or a scalar is not finite.
+__device__ __forceinline__ void pipe_scalars(DevState* st, double gamma, double delta, double rho, bool first) {
+    if (first) {
+        st->iter = 0;
+        st->r0norm = sqrt(rho);
+    } else {
+        st->iter = st->iter + 1;
+    }
+    st->rho = rho;
+    if (sqrt(rho) <= st->tol_abs) {
+        st->done = 1;
+        st->status = FVPCG_OK;
+        return;
+    }
+    if (st->iter >= st->maxit) {
+        st->done = 1;
+        st->status = FVPCG_NOT_CONVERGED;
+        return;
+    }
+    double beta, den;
+    if (first) {
+        beta = 0.0;
+        den = delta;
+    } else {
+        beta = gamma / st->gamma;
+        den = delta - beta * gamma / st->alpha;
+    }
+    const double alpha = gamma / den;
+    if (!(den > 0.0) || !isfinite(den) || !isfinite(alpha) || !isfinite(beta)) {
+        st->done = 1;
+        st->status = FVPCG_BREAKDOWN;
+        return;
+    }
+    st->gamma_old = st->gamma;
+    st->alpha_old = st->alpha;
+    st->gamma = gamma;
+    st->delta = delta;
+    st->alpha = alpha;
+    st->beta = beta;
+}
+
 }  // namespace fvpcg

@@ -208,45 +208,6 @@ struct PipeVec {
     T* q;  // literal only
 };
 
-__device__ __forceinline__ void pipe_scalars(DevState* st, double gamma, double delta, double rho, bool first) {
-    if (first) {
-        st->iter = 0;
-        st->r0norm = sqrt(rho);
-    } else {
-        st->iter = st->iter + 1;
-    }
-    st->rho = rho;
-    if (sqrt(rho) <= st->tol_abs) {
-        st->done = 1;
-        st->status = FVPCG_OK;
-        return;
-    }
-    if (st->iter >= st->maxit) {
-        st->done = 1;
-        st->status = FVPCG_NOT_CONVERGED;
-        return;
-    }
-    double beta, den;
-    if (first) {
-        beta = 0.0;
-        den = delta;
-    } else {
-        beta = gamma / st->gamma;
-        den = delta - beta * gamma / st->alpha;
-    }
-    const double alpha = gamma / den;
-    if (!(den > 0.0) || !isfinite(den) || !isfinite(alpha) || !isfinite(beta)) {
-        st->done = 1;
-        st->status = FVPCG_BREAKDOWN;
-        return;
-    }
-    st->gamma_old = st->gamma;
-    st->alpha_old = st->alpha;
-    st->gamma = gamma;
-    st->delta = delta;
-    st->alpha = alpha;
-    st->beta = beta;
-}
 
 // r = b - A x; (b, b) -> bnorm and the absolute tolerance; clears the
 // pipelined recurrences (z, s, p[, q]) and sets u = M^-1 r (literal).

@@ -62,21 +62,23 @@ def test_amg_hierarchy_and_cycle_match_oracle(fv, orc, name):
     dc.close()
 
 
+@pytest.mark.parametrize("method", ["cg", "pipecg"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_amg_pcg_matches_oracle(fv, orc, name):
-    """AMG-PCG to 1e-10: iteration count within 1 of the oracle's, the
-    iterate within 1e-10 of the oracle's at the GPU's count, true residual
-    recomputed by the oracle's product."""
-    say("amg pcg", name)
+def test_amg_pcg_matches_oracle(fv, orc, name, method):
+    """AMG-preconditioned CG (standard or pipelined) to 1e-10: iteration
+    count within 1 of the oracle's, the iterate within 1e-10 of the oracle's
+    at the GPU's count, true residual recomputed by the oracle's product."""
+    say("amg", method, name)
+    pipe = method == "pipecg"
     case = CASES[name]()
     dc = DevCase(case)
     M = fv.AMG(dc.A, coarse_size=16)
     H = orc.AMG(case, coarse_size=16)
-    x, st = fv.solve_amg(M, dc.b, tol=1e-10, maxit=500)
+    x, st = fv.solve_amg(M, dc.b, tol=1e-10, maxit=500, method=method)
     assert st["status"] == 0, st
-    _, so = H.pcg(case.b, tol=1e-10, maxit=500)
+    _, so = H.pcg(case.b, tol=1e-10, maxit=500, pipelined=pipe)
     assert abs(st["iters"] - so["iters"]) <= 1, (st["iters"], so["iters"])
-    xo, _ = H.pcg(case.b, tol=0.0, maxit=st["iters"])
+    xo, _ = H.pcg(case.b, tol=0.0, maxit=st["iters"], pipelined=pipe)
     xg = x.cpu().numpy()
     assert rel(xg, xo) <= 1e-10
     tr = np.linalg.norm(case.b - orc.spmv(case, xg)) / np.linalg.norm(case.b)
@@ -103,11 +105,16 @@ def test_amg_edge_cases(fv, orc):
     xs, _ = orc.cg(case, case.b, tol=1e-13, maxit=10000)
     x, st = fv.solve_amg(M, dc.b, x=to_dev(xs), tol=1e-8)
     assert st["status"] == 0 and st["iters"] == 0
-    # iteration limit
-    x, st = fv.solve_amg(M, dc.b, tol=1e-15, maxit=3)
-    assert st["status"] == 1 and st["iters"] == 3
-    xo, _ = orc.AMG(case, coarse_size=16).pcg(case.b, tol=0.0, maxit=3)
-    assert rel(x.cpu().numpy(), xo) <= 1e-10
+    # iteration limit, both forms
+    H = orc.AMG(case, coarse_size=16)
+    for method in ("cg", "pipecg"):
+        x, st = fv.solve_amg(M, dc.b, tol=1e-15, maxit=3, method=method)
+        assert st["status"] == 1 and st["iters"] == 3
+        xo, _ = H.pcg(case.b, tol=0.0, maxit=3, pipelined=method == "pipecg")
+        assert rel(x.cpu().numpy(), xo) <= 1e-10
+    with pytest.raises(fv.FVPCGError) as e:
+        fv.solve_amg(M, dc.b, method="pipecg_literal")
+    assert e.value.code == fv.INVALID_ARG
     M.close()
     # one level: the cycle is the exact solve
     M1 = fv.AMG(dc.A, coarse_size=100000)
@@ -139,12 +146,13 @@ def test_amg_varcoef192(fv, orc):
     dc = DevCase(case)
     M = fv.AMG(dc.A)
     say("amg varcoef192 levels", [M.level_info(l)["n"] for l in range(M.levels)])
-    x, st = fv.solve_amg(M, dc.b, tol=1e-8, maxit=1000)
-    assert st["status"] == 0, st
-    xg = x.cpu().numpy()
-    tr = np.linalg.norm(case.b - orc.spmv(case, xg)) / np.linalg.norm(case.b)
-    assert tr <= 1.5e-8
-    assert st["true_rel_res"] == pytest.approx(tr, rel=1e-6)
-    assert st["iters"] <= 125
+    for method in ("cg", "pipecg"):
+        x, st = fv.solve_amg(M, dc.b, tol=1e-8, maxit=1000, method=method)
+        assert st["status"] == 0, st
+        xg = x.cpu().numpy()
+        tr = np.linalg.norm(case.b - orc.spmv(case, xg)) / np.linalg.norm(case.b)
+        assert tr <= 1.5e-8
+        assert st["true_rel_res"] == pytest.approx(tr, rel=1e-6)
+        assert st["iters"] <= 125
     M.close()
     dc.close()
