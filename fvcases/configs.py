@@ -242,6 +242,73 @@ def concat(cases, name="batch", tol=1e-8, seed=0):
                  seed=seed)
 
 
+@dataclasses.dataclass
+class Transient:
+    """Inputs of a transient diffusion run (laplacianFoam, implicit Euler):
+    per internal face a conductivity k_f and geometric weight w_f = |S_f|/|d_f|,
+    per cell a volume V_c, the Dirichlet contributions to the diagonal
+    (bdiag = sum of 2 k_b w_b over the cell's Dirichlet faces) and to the
+    right-hand side (bsrc = sum of 2 k_b w_b T_b plus a volumetric source),
+    the initial field T0 and the time step dt."""
+    name: str
+    shape: tuple
+    n: int
+    owner: np.ndarray
+    neighbour: np.ndarray
+    k_face: np.ndarray
+    w_face: np.ndarray
+    vol: np.ndarray
+    bdiag: np.ndarray
+    bsrc: np.ndarray
+    T0: np.ndarray
+    dt: float
+    tol: float = 1e-8
+
+    @property
+    def F(self) -> int:
+        return int(self.owner.shape[0])
+
+
+def transient(shape=(32, 32, 32), seed=7, dt=0.25, permute=False, tol=1e-8, name="transient"):
+    """Unit cubes (w_f = 1, V_c = 1), lognormal(0,1) conductivities (stream
+    coef, internal faces then the Dirichlet faces of x-min and x-max), T_b = 1
+    on x-min and 0 on x-max, a source U[0,1] per cell (stream src), T0 = 0;
+    optionally randomly permuted and RCM-renumbered (stream perm) like the
+    lognormal workload."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    owner, nb, _ = M.structured_faces(nx, ny, nz)
+    gcoef = R.stream(seed, "coef")
+    k_int = R.lognormal(gcoef, owner.shape[0])
+    bl = M.boundary_cells(shape, "xmin")
+    bh = M.boundary_cells(shape, "xmax")
+    k_b = R.lognormal(gcoef, bl.shape[0] + bh.shape[0])
+    bdiag = np.zeros(n)
+    np.add.at(bdiag, np.concatenate([bl, bh]), 2.0 * k_b)
+    bsrc = R.uniform(R.stream(seed, "src"), n) * 0.5 + 0.5
+    np.add.at(bsrc, bl, 2.0 * k_b[: bl.shape[0]] * 1.0)
+    w = np.ones(owner.shape[0])
+    vol = np.ones(n)
+    if permute:
+        p1 = R.stream(seed, "perm").permutation(n).astype(np.int64)
+        p2 = M.rcm_order(n, p1[owner], p1[nb])
+        new_index = p2[p1]
+        owner, nb, _, _, order = M.renumber(n, owner, nb, k_int, k_int, new_index)
+        k_int = k_int[order]
+        w = w[order]
+
+        def moved(a):
+            out = np.empty_like(a)
+            out[new_index] = a
+            return out
+
+        bdiag, bsrc, vol = moved(bdiag), moved(bsrc), moved(vol)
+    return Transient(name=name, shape=tuple(shape), n=n, owner=np.ascontiguousarray(owner, dtype=np.int32),
+                     neighbour=np.ascontiguousarray(nb, dtype=np.int32), k_face=np.ascontiguousarray(k_int),
+                     w_face=np.ascontiguousarray(w), vol=np.ascontiguousarray(vol), bdiag=bdiag, bsrc=bsrc,
+                     T0=np.zeros(n), dt=float(dt), tol=tol)
+
+
 # ---------------------------------------------------------------------------
 # Named full-size workloads, with an on-disk cache for the large ones.
 

@@ -21,6 +21,7 @@ STREAMS = {
     "fd": 7,
     "x0": 8,
     "test": 9,
+    "src": 10,
 }
 
 

@@ -21,7 +21,7 @@ OK, NOT_CONVERGED, BREAKDOWN = 0, 1, -3
 PRECOND = {"none": 0, "jacobi": 1}
 
 
-SOURCES = ("oracle.c", "amg.c")
+SOURCES = ("oracle.c", "amg.c", "transient.c")
 
 
 def build(force: bool = True) -> str:
@@ -89,6 +89,10 @@ def lib():
         L.or_amg_pcg.restype = i32
         L.or_amg_pipecg.argtypes = [P, P, P, d, i32, P]
         L.or_amg_pipecg.restype = i32
+        L.or_assemble_transient.argtypes = [i32, i32, P, P, P, P, P, P, P, d, P, P, P, P]
+        L.or_assemble_transient.restype = None
+        L.or_transient_run.argtypes = [i32, i32, P, P, P, P, P, P, P, d, i32, P, d, i32, P]
+        L.or_transient_run.restype = i32
         L.or_adjoint_grads.argtypes = [i32, i32, P, P, P, P, P, P, P]
         L.or_adjoint_grads.restype = None
         _lib = L
@@ -255,6 +259,28 @@ class AMG:
         fn = lib().or_amg_pipecg if pipelined else lib().or_amg_pcg
         fn(self._h, _p(b), _p(x), float(tol), int(maxit), ctypes.byref(st))
         return x, st.asdict()
+
+
+def assemble_transient(t, T_old, dt=None):
+    """(diag, upper, b) of one implicit-Euler step of a fvcases.Transient."""
+    keep = [_i32(t.owner), _i32(t.neighbour), _f64(t.k_face), _f64(t.w_face), _f64(t.vol), _f64(t.bdiag),
+            _f64(t.bsrc)]
+    T_old = _f64(T_old)
+    diag, upper, b = np.empty(t.n), np.empty(t.F), np.empty(t.n)
+    lib().or_assemble_transient(t.n, t.F, *[_p(a) for a in keep], float(t.dt if dt is None else dt), _p(T_old),
+                                _p(diag), _p(upper), _p(b))
+    return diag, upper, b
+
+
+def transient_run(t, nsteps, T0=None, tol=1e-10, maxit=100000, dt=None):
+    """Field after nsteps implicit-Euler steps, and the total CG iterations."""
+    keep = [_i32(t.owner), _i32(t.neighbour), _f64(t.k_face), _f64(t.w_face), _f64(t.vol), _f64(t.bdiag),
+            _f64(t.bsrc)]
+    T = (_f64(t.T0) if T0 is None else _f64(T0)).copy()
+    its = ctypes.c_int32()
+    status = lib().or_transient_run(t.n, t.F, *[_p(a) for a in keep], float(t.dt if dt is None else dt),
+                                    int(nsteps), _p(T), float(tol), int(maxit), ctypes.byref(its))
+    return T, {"status": status, "iters": its.value}
 
 
 def adjoint_grads(A, x, lam):

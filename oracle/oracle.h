@@ -101,6 +101,18 @@ int32_t or_amg_pcg(const or_amg* h, const double* b, double* x, double tol, int3
 /* Pipelined CG (literal recurrences) with the V-cycle; x holds x0 on entry. */
 int32_t or_amg_pipecg(const or_amg* h, const double* b, double* x, double tol, int32_t maxit, or_stats* st);
 
+/* ---- Transient diffusion (transient.c): implicit-Euler LDU assembly of
+ * laplacianFoam's heat equation and a run of nsteps steps (each solved by
+ * Jacobi-PCG from the previous field; T in/out). */
+void or_assemble_transient(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                           const double* k, const double* w, const double* vol, const double* bdiag,
+                           const double* bsrc, double dt, const double* T_old,
+                           double* diag, double* upper, double* b);
+int32_t or_transient_run(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                         const double* k, const double* w, const double* vol, const double* bdiag,
+                         const double* bsrc, double dt, int32_t nsteps, double* T, double tol, int32_t maxit,
+                         int32_t* total_iters);
+
 /* Gradients of a scalar loss L(x) with A x = b on the LDU pattern, given x
  * and lambda = A^-T dL/dx:  dL/ddiag = -lambda*x, dL/dupper[f] =
  * -lambda[owner]*x[nb], dL/dlower[f] = -lambda[nb]*x[owner]. */
