@@ -120,8 +120,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=150)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time the other workloads")
-    ap.add_argument("--extras-select", default="mixed,batched,amg,small",
-                    help="comma-separated groups of extras: mixed, batched, amg, small")
+    ap.add_argument("--extras-select", default="mixed,batched,amg,transient,small",
+                    help="comma-separated groups of extras: mixed, batched, amg, transient, small")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU: the library solves on one device "
@@ -231,7 +231,8 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None, groups=("mixed", "batched", "amg", "small")):
+def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None,
+           groups=("mixed", "batched", "amg", "transient", "small")):
     """Other workloads, for information (not the headline line)."""
     res = {}
     to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).to(dev)
@@ -364,6 +365,32 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None, groups=("m
             A_.close()
             if m_ is not mesh:
                 m_.close()
+    if "transient" in groups:
+        # laplacianFoam's repeated solve: 20 implicit-Euler steps at 192^3
+        # (lognormal conductivities, permuted + RCM), each step assembled on
+        # the device, the matrix refreshed and solved from the previous field
+        t = fvcases.transient((192, 192, 192), permute=True)
+        mt = fv.Mesh(t.n, to(t.owner, torch.int32), to(t.neighbour, torch.int32))
+        args_ = [to(a, torch.float64) for a in (t.k_face, t.w_face, t.vol, t.bdiag, t.bsrc)]
+        T0 = to(t.T0, torch.float64)
+        d0, u0, _ = fv.assemble_transient(mt, *args_, t.dt, T0)
+        At = fv.Matrix(mt, d0, u0)
+        for method in ("pipecg", "cg"):
+            T = T0.clone()
+            fv.transient_run(At, *args_, t.dt, 2, T, tol=1e-8, method=method)
+            T = T0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            T, st = fv.transient_run(At, *args_, t.dt, 20, T, tol=1e-8, method=method)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            key = f"transient192/{method}_20_steps"
+            res[key] = {"status": st["status_name"], "steps": st["outer_iters"], "cg_iters": st["iters"],
+                        "ms_per_step": round(st["device_ms"] / 20, 2), "wall_ms_per_step": round(wall * 1e3 / 20, 2),
+                        "iters_per_step": round(st["iters"] / 20, 1)}
+            log(f"extra {key}: {res[key]}")
+        At.close()
+        mt.close()
     if "small" in groups:
         # small and graded cases: one warm-up solve, then repeated solves timed one
         # by one with HIP events on the solve stream (median reported), and

@@ -218,6 +218,29 @@ FVPCG_API int fvpcg_solve_batched_backward(const fvpcg_batch* batch, const doubl
                                  double* grad_lower, double tol, int32_t maxit, int32_t method,
                                  int32_t precond, void* stream, fvpcg_stats* stats);
 
+/* ---- Transient diffusion, laplacianFoam's heat equation dT/dt = div(k grad T)
+ * (Section 2: the linear solver is called every time step), implicit Euler
+ * on the LDU addressing:
+ *   upper[f] = -k_face[f] w_face[f]            (w = |S_f| / |d_f|)
+ *   diag[c]  = vol[c] / dt + bdiag[c] + sum over the faces of c of k w
+ *   b[c]     = vol[c] / dt * T_old[c] + bsrc[c]
+ * (bdiag, bsrc: Dirichlet and source terms per cell).  All arrays are device
+ * FP64: k_face, w_face, upper [n_faces]; vol, bdiag, bsrc, T_old, diag, b
+ * [n_cells]; outputs must not overlap inputs. */
+FVPCG_API int fvpcg_assemble_transient(const fvpcg_mesh* mesh, const double* k_face, const double* w_face,
+                                       const double* vol, const double* bdiag, const double* bsrc, double dt,
+                                       const double* T_old, double* diag, double* upper, double* b,
+                                       void* stream);
+/* nsteps time steps on mat's mesh (mat created with lower == NULL; its
+ * coefficients are replaced every step): assemble, refresh the device layout
+ * (as fvpcg_matrix_update), solve with Jacobi and `method` from the previous
+ * field to tol.  T: the field, in/out.  Stats: iters = CG iterations over all
+ * steps, outer_iters = steps done, device_ms = the whole run; returns the
+ * status of the last solve (the run stops at the first non-OK one). */
+FVPCG_API int fvpcg_transient_run(fvpcg_matrix* mat, const double* k_face, const double* w_face, const double* vol,
+                                  const double* bdiag, const double* bsrc, double dt, int32_t nsteps, double* T,
+                                  double tol, int32_t maxit, int32_t method, void* stream, fvpcg_stats* stats);
+
 /* ---- Smoothed-aggregation AMG preconditioner (Section 5 and Table pcgs2
  * compare the paper's Jacobi-preconditioned solvers with aggregation-AMG
  * preconditioned CG; the paper does not print its AMG).  The method:

@@ -373,6 +373,48 @@ def fvpcg_solve_batched_backward(B: Batch, x, g, tol=1e-10, maxit=10000, method=
 solve_batched_backward = fvpcg_solve_batched_backward
 
 
+# ---------------------------------------------------------------- transient diffusion
+
+def fvpcg_assemble_transient(mesh: Mesh, k_face, w_face, vol, bdiag, bsrc, dt, T_old, diag=None, upper=None, b=None,
+                             stream=None):
+    """(diag, upper, b) of one implicit-Euler step of the heat equation."""
+    import torch
+
+    n, F = mesh.n, mesh.F
+    diag = torch.empty_like(vol) if diag is None else diag
+    upper = torch.empty_like(k_face) if upper is None else upper
+    b = torch.empty_like(vol) if b is None else b
+    _check(lib().fvpcg_assemble_transient(mesh.handle, _ptr(k_face, torch.float64, F, "k_face"),
+                                          _ptr(w_face, torch.float64, F, "w_face"), _ptr(vol, torch.float64, n, "vol"),
+                                          _ptr(bdiag, torch.float64, n, "bdiag"), _ptr(bsrc, torch.float64, n, "bsrc"),
+                                          float(dt), _ptr(T_old, torch.float64, n, "T_old"),
+                                          _ptr(diag, torch.float64, n, "diag"), _ptr(upper, torch.float64, F, "upper"),
+                                          _ptr(b, torch.float64, n, "b"), _stream(stream)), "fvpcg_assemble_transient")
+    return diag, upper, b
+
+
+assemble_transient = fvpcg_assemble_transient
+
+
+def fvpcg_transient_run(A: Matrix, k_face, w_face, vol, bdiag, bsrc, dt, nsteps, T, tol=1e-8, maxit=100000,
+                        method="pipecg", stream=None):
+    """Advance T (in place) by nsteps implicit-Euler steps; returns (T, stats)."""
+    import torch
+
+    n, F = A.n, A.mesh.F
+    st = Stats()
+    code = lib().fvpcg_transient_run(A.handle, _ptr(k_face, torch.float64, F, "k_face"),
+                                     _ptr(w_face, torch.float64, F, "w_face"), _ptr(vol, torch.float64, n, "vol"),
+                                     _ptr(bdiag, torch.float64, n, "bdiag"), _ptr(bsrc, torch.float64, n, "bsrc"),
+                                     float(dt), int(nsteps), _ptr(T, torch.float64, n, "T"), float(tol), int(maxit),
+                                     METHODS[method], _stream(stream), ctypes.byref(st))
+    _check(code, "fvpcg_transient_run")
+    return T, st.asdict()
+
+
+transient_run = fvpcg_transient_run
+
+
 # ---------------------------------------------------------------- AMG
 
 class AMG:

@@ -37,6 +37,12 @@ int solve_batched_backward(const fvpcg_batch* bt, const double* x, const double*
                            double* grad_diag, double* grad_upper, double* grad_lower, double tol, int maxit,
                            int method, int precond, hipStream_t s, fvpcg_stats* stats);
 int stream_calibrate(hipStream_t s, uint64_t bytes, double* copy_gbs, double* triad_gbs);
+int assemble_transient(const fvpcg_mesh* m, const double* k, const double* w, const double* vol, const double* bdiag,
+                       const double* bsrc, double dt, const double* T_old, double* diag, double* upper, double* b,
+                       hipStream_t s);
+int transient_run(fvpcg_matrix* A, const double* k, const double* w, const double* vol, const double* bdiag,
+                  const double* bsrc, double dt, int nsteps, double* T, double tol, int maxit, int method,
+                  hipStream_t s, fvpcg_stats* stats);
 int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, hipStream_t s, fvpcg_amg** out);
 void amg_free(fvpcg_amg* h);
 int amg_levels(const fvpcg_amg* h);
@@ -474,6 +480,69 @@ int fvpcg_solve_amg(const fvpcg_amg* amg, const double* b, double* x, double tol
         FV_TRY(check_dev(x, bytes, "x"));
         if (overlap(b, bytes, x, bytes)) return set_error(FVPCG_INVALID_ARG, "b and x overlap");
         return solve_amg(amg, b, x, tol, maxit, method, (hipStream_t)stream, stats);
+    });
+}
+
+int fvpcg_assemble_transient(const fvpcg_mesh* mesh, const double* k_face, const double* w_face, const double* vol,
+                             const double* bdiag, const double* bsrc, double dt, const double* T_old, double* diag,
+                             double* upper, double* b, void* stream) {
+    return guard([&]() -> int {
+        if (!mesh) return set_error(FVPCG_INVALID_ARG, "mesh is NULL");
+        if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(FVPCG_INVALID_ARG, "need a finite dt > 0");
+        const size_t nb = sizeof(double) * (size_t)mesh->n, fb = sizeof(double) * (size_t)mesh->F;
+        FV_TRY(check_dev(vol, nb, "vol"));
+        FV_TRY(check_dev(bdiag, nb, "bdiag"));
+        FV_TRY(check_dev(bsrc, nb, "bsrc"));
+        FV_TRY(check_dev(T_old, nb, "T_old"));
+        FV_TRY(check_dev(diag, nb, "diag"));
+        FV_TRY(check_dev(b, nb, "b"));
+        if (fb) {
+            FV_TRY(check_dev(k_face, fb, "k_face"));
+            FV_TRY(check_dev(w_face, fb, "w_face"));
+            FV_TRY(check_dev(upper, fb, "upper"));
+        }
+        const void* outs[] = {diag, b};
+        const size_t outsz[] = {nb, nb};
+        const void* ins[] = {vol, bdiag, bsrc, T_old, k_face, w_face};
+        const size_t insz[] = {nb, nb, nb, nb, fb, fb};
+        for (int o = 0; o < 2; ++o)
+            for (int i = 0; i < 6; ++i)
+                if (insz[i] && overlap(outs[o], outsz[o], ins[i], insz[i]))
+                    return set_error(FVPCG_INVALID_ARG, "an output overlaps an input");
+        if (fb)
+            for (int i = 0; i < 6; ++i)
+                if (insz[i] && overlap(upper, fb, ins[i], insz[i]))
+                    return set_error(FVPCG_INVALID_ARG, "an output overlaps an input");
+        return assemble_transient(mesh, k_face, w_face, vol, bdiag, bsrc, dt, T_old, diag, upper, b,
+                                  (hipStream_t)stream);
+    });
+}
+
+int fvpcg_transient_run(fvpcg_matrix* mat, const double* k_face, const double* w_face, const double* vol,
+                        const double* bdiag, const double* bsrc, double dt, int32_t nsteps, double* T, double tol,
+                        int32_t maxit, int32_t method, void* stream, fvpcg_stats* stats) {
+    return guard([&]() -> int {
+        stats_status(stats, FVPCG_INVALID_ARG);
+        if (!mat) return set_error(FVPCG_INVALID_ARG, "mat is NULL");
+        if (!mat->sym) return set_error(FVPCG_INVALID_ARG, "the matrix must have been created with lower == NULL");
+        if (!(dt > 0.0) || !std::isfinite(dt) || nsteps < 0) return set_error(FVPCG_INVALID_ARG, "need dt > 0, nsteps >= 0");
+        FV_TRY(check_solver_args(tol, maxit, method, FVPCG_PRECOND_JACOBI));
+        const fvpcg_mesh* m = mat->mesh;
+        const size_t nb = sizeof(double) * (size_t)m->n, fb = sizeof(double) * (size_t)m->F;
+        FV_TRY(check_dev(vol, nb, "vol"));
+        FV_TRY(check_dev(bdiag, nb, "bdiag"));
+        FV_TRY(check_dev(bsrc, nb, "bsrc"));
+        FV_TRY(check_dev(T, nb, "T"));
+        if (fb) {
+            FV_TRY(check_dev(k_face, fb, "k_face"));
+            FV_TRY(check_dev(w_face, fb, "w_face"));
+        }
+        const void* ins[] = {vol, bdiag, bsrc, k_face, w_face};
+        const size_t insz[] = {nb, nb, nb, fb, fb};
+        for (int i = 0; i < 5; ++i)
+            if (insz[i] && overlap(T, nb, ins[i], insz[i])) return set_error(FVPCG_INVALID_ARG, "T overlaps an input");
+        return transient_run(mat, k_face, w_face, vol, bdiag, bsrc, dt, nsteps, T, tol, maxit, method,
+                             (hipStream_t)stream, stats);
     });
 }
 
