@@ -18,6 +18,9 @@ Named workloads (full size; every builder also takes a smaller shape):
                   b = -div(U) of a random cell velocity, zero mean.
 * ``batch256``    256 independent cubes, edge uniform in {16..64}, as
                   varcoef but natural order, plus x_target ~ U[-1,1].
+* ``momentum192`` 192^3 non-symmetric momentum system (implicit Euler,
+                  upwind convection of a divergence-free flux, nu = 0.01,
+                  Courant 2), permuted + RCM like varcoef.
 """
 from __future__ import annotations
 
@@ -309,6 +312,79 @@ def transient(shape=(32, 32, 32), seed=7, dt=0.25, permute=False, tol=1e-8, name
                      T0=np.zeros(n), dt=float(dt), tol=tol)
 
 
+def momentum(shape=(192, 192, 192), seed=11, nu=0.01, co=2.0, permute=True, tol=1e-8, name="momentum"):
+    """Momentum-predictor stand-in for icoFoam (Section 2: its momentum
+    equation is solved with BiCGSTAB): the x-velocity equation of implicit
+    Euler with first-order upwind convection on cubes of side h = 1/nx in the
+    box [0,1] x [0, ny h] x [0, nz h].
+
+    Face fluxes are those of U = curl(psi e_z) with
+    psi = a sin(pi x) sin(pi y / Ly) (1 + 0.5 sin(2 pi z / Lz + theta)),
+    taken exactly as psi differences along each x- and y-face's edges (zero
+    on z-faces and walls), so every cell's net outflow is zero up to rounding;
+    a scales max |U| to 1 and theta ~ U[0, 2 pi) (stream vel).  Per internal
+    face (owner o -> neighbour m, flux F > 0 from o to m), D = nu h:
+        upper = -D - max(-F, 0),  lower = -D - max(F, 0);
+    diag = h^3/dt + sum over the cell's faces of (D + its outflow, if any)
+    + 2 nu h per wall face (no slip); the lid (y-max) moves at u = 1, adding
+    2 nu h to b there; b = h^3/dt u_old + h^3 g with u_old, g ~ U[-1,1]
+    (streams vel, src); dt = co h (Courant number co at |U| = 1).  Then,
+    as the lognormal workload, cells randomly permuted and RCM-renumbered
+    (stream perm).  Row sums are h^3/dt plus the wall terms: diagonally
+    dominant, lower != upper wherever the flux is non-zero."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    h = 1.0 / nx
+    Ly, Lz = ny * h, nz * h
+    owner, nb, direction = M.structured_faces(nx, ny, nz)
+    gvel = R.stream(seed, "vel")
+    theta = 2.0 * np.pi * gvel.random()
+    a = 1.0 / (1.5 * np.pi * max(1.0, 1.0 / Ly))
+
+    def psi(x, y, z):
+        return a * np.sin(np.pi * x) * np.sin(np.pi * y / Ly) * (1.0 + 0.5 * np.sin(2.0 * np.pi * z / Lz + theta))
+
+    i, j, k = M.cell_ijk(shape, owner)
+    zc = (k + 0.5) * h
+    flux = np.zeros(owner.shape[0])
+    m = direction == 0
+    xf = (i[m] + 1) * h
+    flux[m] = (psi(xf, (j[m] + 1) * h, zc[m]) - psi(xf, j[m] * h, zc[m])) * h
+    m = direction == 1
+    yf = (j[m] + 1) * h
+    flux[m] = -(psi((i[m] + 1) * h, yf, zc[m]) - psi(i[m] * h, yf, zc[m])) * h
+    D = nu * h
+    dt = co * h
+    vol = h ** 3
+    upper = -D - np.maximum(-flux, 0.0)
+    lower = -D - np.maximum(flux, 0.0)
+    diag = np.full(n, vol / dt)
+    np.add.at(diag, owner, D + np.maximum(flux, 0.0))
+    np.add.at(diag, nb, D + np.maximum(-flux, 0.0))
+    walls = ("xmin", "xmax", "ymin", "ymax", "zmin", "zmax")
+    for side in walls:
+        np.add.at(diag, M.boundary_cells(shape, side), 2.0 * nu * h)
+    u_old = R.uniform(gvel, n)
+    g = R.uniform(R.stream(seed, "src"), n)
+    b = vol / dt * u_old + vol * g
+    np.add.at(b, M.boundary_cells(shape, "ymax"), 2.0 * nu * h * 1.0)
+    meta = {"nu": nu, "courant": co, "dt": dt, "h": h, "theta": theta, "ordering": "natural",
+            "max_cell_peclet": float(np.abs(flux).max() / D) if flux.size else 0.0}
+    if permute:
+        p1 = R.stream(seed, "perm").permutation(n).astype(np.int64)
+        p2 = M.rcm_order(n, p1[owner], p1[nb])
+        new_index = p2[p1]
+        owner, nb, upper, lower, _ = M.renumber(n, owner, nb, upper, lower, new_index)
+        d2 = np.empty_like(diag)
+        d2[new_index] = diag
+        b2 = np.empty_like(b)
+        b2[new_index] = b
+        diag, b = d2, b2
+        meta["ordering"] = "random permutation, then reverse Cuthill-McKee"
+        meta["bandwidth"] = M.bandwidth(owner, nb)
+    return _finish(name, shape, n, owner, nb, diag, upper, lower, b, tol, seed, meta)
+
+
 # ---------------------------------------------------------------------------
 # Named full-size workloads, with an on-disk cache for the large ones.
 
@@ -358,4 +434,7 @@ def make(name: str, cache: bool = True):
         return _cached("cavity256_s3", b) if cache else b()
     if name == "batch256":
         return batch(256, 16, 64, seed=5, name=name)
+    if name == "momentum192":
+        b = lambda: momentum((192, 192, 192), seed=11, name=name)
+        return _cached("momentum192_s11", b) if cache else b()
     raise KeyError(name)

@@ -21,11 +21,11 @@ OK, NOT_CONVERGED, BREAKDOWN = 0, 1, -3
 PRECOND = {"none": 0, "jacobi": 1}
 
 
-SOURCES = ("oracle.c", "amg.c", "transient.c")
+SOURCES = ("oracle.c", "amg.c", "transient.c", "bicgstab.c")
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c and amg.c into liboracle.so (plain C99, gcc)."""
+    """Compile the oracle's C sources into liboracle.so (plain C99, gcc)."""
     srcs = [os.path.join(HERE, f) for f in SOURCES]
     newest = max(os.path.getmtime(f) for f in srcs + [os.path.join(HERE, "oracle.h")])
     if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= newest:
@@ -93,6 +93,8 @@ def lib():
         L.or_assemble_transient.restype = None
         L.or_transient_run.argtypes = [i32, i32, P, P, P, P, P, P, P, d, i32, P, d, i32, P]
         L.or_transient_run.restype = i32
+        L.or_bicgstab.argtypes = [i32, i32, P, P, P, P, P, P, P, d, i32, i32, P, P, P, P]
+        L.or_bicgstab.restype = i32
         L.or_adjoint_grads.argtypes = [i32, i32, P, P, P, P, P, P, P]
         L.or_adjoint_grads.restype = None
         _lib = L
@@ -165,6 +167,25 @@ def cg(A, b, x0=None, tol=1e-8, maxit=10000, precond="jacobi", history=False):
     if history:
         k = s["iters"]
         return x, s, {"alpha": ah[:k], "beta": bh[:k], "res": rh[: k + 1]}
+    return x, s
+
+
+def bicgstab(A, b, x0=None, tol=1e-8, maxit=10000, precond="jacobi", history=False):
+    """Preconditioned BiCGSTAB.  Returns (x, stats dict[, history dict])."""
+    A = _as_sys(A)
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    st = Stats()
+    m = max(int(maxit), 0) + 1
+    ah = np.zeros(m) if history else None
+    oh = np.zeros(m) if history else None
+    rh = np.zeros(m) if history else None
+    lib().or_bicgstab(*A.args(), _p(b), _p(x), float(tol), int(maxit), PRECOND[precond], ctypes.byref(st),
+                      _p(ah), _p(oh), _p(rh))
+    s = st.asdict()
+    if history:
+        k = s["iters"]
+        return x, s, {"alpha": ah[:k], "omega": oh[:k], "res": rh[: k + 1]}
     return x, s
 
 

@@ -113,6 +113,17 @@ int32_t or_transient_run(int32_t n, int32_t nf, const int32_t* owner, const int3
                          const double* bsrc, double dt, int32_t nsteps, double* T, double tol, int32_t maxit,
                          int32_t* total_iters);
 
+/* ---- BiCGSTAB (bicgstab.c), van der Vorst's form with M = I or Jacobi
+ * applied to the search directions, for matrices with lower != upper
+ * (Section 2: icoFoam's momentum solve).  x holds x0 on entry.  Optional
+ * histories (length >= maxit+1, may be NULL): alpha[k], omega[k] of
+ * iteration k (omega = 0 for a half-step exit) and ||r|| after k iterations
+ * (res_hist[0] = ||r0||). */
+int32_t or_bicgstab(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                    const double* diag, const double* upper, const double* lower,
+                    const double* b, double* x, double tol, int32_t maxit, int32_t precond,
+                    or_stats* st, double* alpha_hist, double* omega_hist, double* res_hist);
+
 /* Gradients of a scalar loss L(x) with A x = b on the LDU pattern, given x
  * and lambda = A^-T dL/dx:  dL/ddiag = -lambda*x, dL/dupper[f] =
  * -lambda[owner]*x[nb], dL/dlower[f] = -lambda[nb]*x[owner]. */
