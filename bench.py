@@ -120,8 +120,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=150)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time the other workloads")
-    ap.add_argument("--extras-select", default="mixed,batched,amg,transient,small",
-                    help="comma-separated groups of extras: mixed, batched, amg, transient, small")
+    ap.add_argument("--extras-select", default="mixed,batched,amg,transient,momentum,small",
+                    help="comma-separated groups of extras: mixed, batched, amg, transient, momentum, small")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU: the library solves on one device "
@@ -232,7 +232,7 @@ def main():
 
 
 def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None,
-           groups=("mixed", "batched", "amg", "transient", "small")):
+           groups=("mixed", "batched", "amg", "transient", "momentum", "small")):
     """Other workloads, for information (not the headline line)."""
     res = {}
     to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).to(dev)
@@ -391,6 +391,31 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None,
             log(f"extra {key}: {res[key]}")
         At.close()
         mt.close()
+    if "momentum" in groups:
+        # icoFoam's momentum predictor stand-in: BiCGSTAB with Jacobi on the
+        # 192^3 non-symmetric upwind system (permuted + RCM) to 1e-8, median of
+        # three solves after a warm-up, and a fixed run of 40 iterations (tol =
+        # 0) for the per-iteration rate against the 136 n + 48 F bytes its
+        # three kernels must move (int32-column accounting, as the headline)
+        c = fvcases.make("momentum192")
+        mm = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
+        Am = fv.Matrix(mm, to(c.diag, torch.float64), to(c.upper, torch.float64), to(c.lower, torch.float64))
+        bm = to(c.b, torch.float64)
+        fv.solve_bicgstab(Am, bm, tol=c.tol, maxit=5000)
+        runs = sorted((fv.solve_bicgstab(Am, bm, tol=c.tol, maxit=5000)[1] for _ in range(3)),
+                      key=lambda t: t["device_ms"])
+        st = runs[1]
+        _, fx = fv.solve_bicgstab(Am, bm, tol=0.0, maxit=40)
+        us_it = fx["iter_ms"] * 1e3 / max(fx["iters"], 1)
+        alg = 136 * c.n + 48 * c.F
+        res["momentum192/bicgstab_jacobi_to_1e-08"] = {
+            "status": st["status_name"], "iters": st["iters"], "ms": round(st["device_ms"], 2),
+            "true_rel_res": st["true_rel_res"], "us_per_iter_fixed40": round(us_it, 2),
+            "alg_bytes_per_iter": alg, "alg_gbs": round(alg / (us_it * 1e-6) / 1e9, 1),
+            "frac_of_8tbs": round(alg / (us_it * 1e-6) / 8e12, 4)}
+        log(f"extra momentum192: {res['momentum192/bicgstab_jacobi_to_1e-08']}")
+        Am.close()
+        mm.close()
     if "small" in groups:
         # small and graded cases: one warm-up solve, then repeated solves timed one
         # by one with HIP events on the solve stream (median reported), and

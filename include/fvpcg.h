@@ -140,6 +140,23 @@ FVPCG_API int fvpcg_spmv(const fvpcg_matrix* mat, const double* v, double* y, vo
 FVPCG_API int fvpcg_solve(const fvpcg_matrix* mat, const double* b, double* x, double tol, int32_t maxit,
                 int32_t method, int32_t precond, void* stream, fvpcg_stats* stats);
 
+/* ---- BiCGSTAB for non-symmetric matrices (lower != upper), the solver of
+ * icoFoam's momentum equation (Section 2; the paper does not print it):
+ * van der Vorst's Bi-CGSTAB with the preconditioner (precond:
+ * FVPCG_PRECOND_NONE / FVPCG_PRECOND_JACOBI) applied to the search
+ * directions, so r is the residual of A x = b, and shadow residual
+ * rhat = r0.  Stops when ||r|| <= tol ||b|| (OK; also when ||s|| does after
+ * the first half of an iteration, with x += alpha M^-1 p), after maxit
+ * iterations (NOT_CONVERGED), or when (rhat, r), (rhat, A M^-1 p) or omega
+ * is zero or not finite (BREAKDOWN).  Works on matrices created with or
+ * without lower.  x holds x0 on entry (FP64[n_cells], device); b likewise;
+ * they must not overlap.  The first call on a matrix allocates its
+ * workspace (5 vectors of n doubles), freed by fvpcg_matrix_destroy.
+ * Stats: iters = iterations that formed alpha, rel_res = ||r||/||b||,
+ * true_rel_res = ||b - A x||/||b||. */
+FVPCG_API int fvpcg_solve_bicgstab(const fvpcg_matrix* mat, const double* b, double* x, double tol, int32_t maxit,
+                                   int32_t precond, void* stream, fvpcg_stats* stats);
+
 /* ---- Mixed-precision iterative refinement (FP32 inner, FP64 outer).
  * Outer: r = b - A x in FP64 with the FP64 matrix, stop at
  * ||r|| <= outer_tol ||b|| or after max_outer corrections.  Inner: the

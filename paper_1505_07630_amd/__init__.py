@@ -220,6 +220,24 @@ def fvpcg_solve(A: Matrix, b, x=None, tol=1e-8, maxit=10000, method="pipecg", pr
 solve = fvpcg_solve
 
 
+def fvpcg_solve_bicgstab(A: Matrix, b, x=None, tol=1e-8, maxit=10000, precond="jacobi", stream=None):
+    """BiCGSTAB for A x = b (A may be non-symmetric); x (if given) holds x0
+    and is overwritten.  Returns (x, stats dict).  Raises FVPCGError on
+    negative status codes."""
+    import torch
+
+    if x is None:
+        x = torch.zeros_like(b)
+    st = Stats()
+    code = lib().fvpcg_solve_bicgstab(A.handle, _ptr(b, torch.float64, A.n, "b"), _ptr(x, torch.float64, A.n, "x"),
+                                      float(tol), int(maxit), PRECONDS[precond], _stream(stream), ctypes.byref(st))
+    _check(code, "fvpcg_solve_bicgstab")
+    return x, st.asdict()
+
+
+solve_bicgstab = fvpcg_solve_bicgstab
+
+
 def fvpcg_solve_mixed(A: Matrix, b, x=None, outer_tol=1e-10, inner_tol=1e-5, max_outer=30, max_inner=20000,
                       stream=None):
     import torch

@@ -7,7 +7,8 @@
 
 namespace fvpcg {
 
-// Implemented in setup.hip / solve.hip / batched.hip / calibrate.hip.
+// Implemented in setup.hip / solve.hip / batched.hip / calibrate.hip / amg.hip /
+// transient.hip / bicgstab.hip.
 int mesh_create(int32_t n, int32_t F, const int32_t* owner, const int32_t* nb, hipStream_t s, fvpcg_mesh** out);
 int mesh_destroy(fvpcg_mesh* m);
 int matrix_create(const fvpcg_mesh* m, const double* diag, const double* upper, const double* lower, uint32_t flags,
@@ -37,6 +38,9 @@ int solve_batched_backward(const fvpcg_batch* bt, const double* x, const double*
                            double* grad_diag, double* grad_upper, double* grad_lower, double tol, int maxit,
                            int method, int precond, hipStream_t s, fvpcg_stats* stats);
 int stream_calibrate(hipStream_t s, uint64_t bytes, double* copy_gbs, double* triad_gbs);
+int solve_bicgstab(const fvpcg_matrix* A, const double* b, double* x, double tol, int maxit, int precond,
+                   hipStream_t s, fvpcg_stats* stats);
+void bicgstab_free(fvpcg_matrix* A);
 int assemble_transient(const fvpcg_mesh* m, const double* k, const double* w, const double* vol, const double* bdiag,
                        const double* bsrc, double dt, const double* T_old, double* diag, double* upper, double* b,
                        hipStream_t s);
@@ -212,7 +216,11 @@ int fvpcg_matrix_update(fvpcg_matrix* mat, const double* diag, const double* upp
 }
 
 int fvpcg_matrix_destroy(fvpcg_matrix* mat) {
-    return guard([&]() -> int { return mat ? matrix_destroy(mat) : FVPCG_OK; });
+    return guard([&]() -> int {
+        if (!mat) return FVPCG_OK;
+        bicgstab_free(mat);
+        return matrix_destroy(mat);
+    });
 }
 
 int fvpcg_spmv(const fvpcg_matrix* mat, const double* v, double* y, void* stream) {
@@ -242,6 +250,26 @@ int fvpcg_solve(const fvpcg_matrix* mat, const double* b, double* x, double tol,
         }
         int rc = solve(mat, b, x, tol, maxit, method, precond, (hipStream_t)stream, stats);
         if (rc == FVPCG_BREAKDOWN) set_error(rc, "breakdown: p'Ap <= 0 or a non-finite scalar");
+        return rc;
+    });
+}
+
+int fvpcg_solve_bicgstab(const fvpcg_matrix* mat, const double* b, double* x, double tol, int32_t maxit,
+                         int32_t precond, void* stream, fvpcg_stats* stats) {
+    return guard([&]() -> int {
+        stats_status(stats, FVPCG_INVALID_ARG);
+        if (!mat) return set_error(FVPCG_INVALID_ARG, "mat is NULL");
+        size_t bytes = sizeof(double) * (size_t)mat->mesh->n;
+        FV_TRY(check_solver_args(tol, maxit, FVPCG_CG, precond));
+        FV_TRY(check_dev(b, bytes, "b"));
+        FV_TRY(check_dev(x, bytes, "x"));
+        if (overlap(b, bytes, x, bytes)) return set_error(FVPCG_INVALID_ARG, "b and x overlap");
+        if (precond == FVPCG_PRECOND_JACOBI && !mat->diag_ok) {
+            stats_status(stats, FVPCG_BREAKDOWN);
+            return set_error(FVPCG_BREAKDOWN, "Jacobi preconditioner needs a finite positive diagonal");
+        }
+        int rc = solve_bicgstab(mat, b, x, tol, maxit, precond, (hipStream_t)stream, stats);
+        if (rc == FVPCG_BREAKDOWN) set_error(rc, "breakdown: (rhat, r), (rhat, A p) or omega is zero or not finite");
         return rc;
     });
 }

@@ -44,6 +44,10 @@ int work_need_mixed(Work& w);
 
 }  // namespace fvpcg
 
+namespace fvpcg {
+struct BiWork;  // BiCGSTAB workspace (bicgstab.hip)
+}
+
 struct fvpcg_mesh {
     int device = 0;
     int n = 0;
@@ -72,6 +76,7 @@ struct fvpcg_matrix {
     float* val32 = nullptr;     // [W][n] FP32 A[c][col]
     float* val32_cs = nullptr;  // [W][n] FP32 A[c][col] / d[col]
     fvpcg::Work* work = nullptr;
+    mutable fvpcg::BiWork* bi = nullptr;  // allocated by the first BiCGSTAB solve
 };
 
 namespace fvpcg {
