@@ -395,7 +395,7 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None,
         # icoFoam's momentum predictor stand-in: BiCGSTAB with Jacobi on the
         # 192^3 non-symmetric upwind system (permuted + RCM) to 1e-8, median of
         # three solves after a warm-up, and a fixed run of 40 iterations (tol =
-        # 0) for the per-iteration rate against the 136 n + 48 F bytes its
+        # 0) for the per-iteration rate against the 128 n + 48 F bytes its
         # three kernels must move (int32-column accounting, as the headline)
         c = fvcases.make("momentum192")
         mm = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
@@ -407,7 +407,7 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None,
         st = runs[1]
         _, fx = fv.solve_bicgstab(Am, bm, tol=0.0, maxit=40)
         us_it = fx["iter_ms"] * 1e3 / max(fx["iters"], 1)
-        alg = 136 * c.n + 48 * c.F
+        alg = 128 * c.n + 48 * c.F
         res["momentum192/bicgstab_jacobi_to_1e-08"] = {
             "status": st["status_name"], "iters": st["iters"], "ms": round(st["device_ms"], 2),
             "true_rel_res": st["true_rel_res"], "us_per_iter_fixed40": round(us_it, 2),

@@ -4,22 +4,27 @@
 // preconditioning: r stays the residual of A x = b), shadow residual
 // rhat = r0.
 //
-// Each iteration needs three global reductions (alpha, omega, then rho and
-// the stopping test), so it runs as three row-parallel kernels, each ending
-// in the single-pass reduction whose last workgroup forms the next scalar.
-// With Jacobi the products use the column-scaled values A D^-1 (unit
-// diagonal), so neither phat = D^-1 p nor shat = D^-1 s is ever stored:
+// Each iteration needs three global reductions (alpha; omega; the stopping
+// test), so it runs as three row-parallel kernels, each ending in the
+// single-pass reduction whose last workgroup forms the next scalars.  With
+// Jacobi the products use the column-scaled values A D^-1 (unit diagonal), so
+// neither phat = D^-1 p nor shat = D^-1 s is ever stored:
 //
-//   k_bi_pv     p = r + beta q (q = p_prev - omega v_prev, formed on the fly
-//               for the gathered neighbours), v = A D^-1 p;  (rhat, v) -> alpha
-//   k_bi_st     s = r - alpha v (on the fly likewise), t = A D^-1 s;
-//               (t, s), (t, t), (s, s) -> omega, or the half-step exit
-//   k_bi_update x += D^-1 (alpha p + omega s), r = s - omega t,
-//               q = p - omega v;  (rhat, r), (r, r) -> stop or beta
+//   k_bi_pv     v = A D^-1 p;  (rhat, v) -> alpha
+//   k_bi_st     s = r - alpha v (formed on the fly, also for the gathered
+//               neighbours), t = A D^-1 s;  (t, s), (t, t), (s, s), (rhat, s),
+//               (rhat, t) -> omega (or the half-step exit) and
+//               rho' = (rhat, r') = (rhat, s) - omega (rhat, t), so
+//               beta = (rho'/rho)(alpha/omega) is known one kernel early
+//   k_bi_update x += D^-1 (alpha p + omega s), r' = s - omega t,
+//               p' = r' + beta (p - omega v);  (r', r') -> stop
 //
-// p and s are recomputed from r, q, v where needed instead of being stored:
-// per iteration the three kernels move 136 n + 48 F bytes (int32 columns)
-// against 2 x 24 F for the two products alone.
+// rho' is the inner product of rhat with r' = s - omega t split by linearity
+// (the vectors are the computed ones; only the rounding order differs from
+// forming r' first).  Knowing beta before the update lets that kernel store
+// p' itself, so the first product gathers one vector.  Per iteration the
+// kernels move 128 n + 48 F bytes (int32 columns) against 2 x 24 F for the
+// two products alone.
 #include "handles.hpp"
 #include "rows.hpp"
 
@@ -28,6 +33,7 @@ namespace fvpcg {
 // Scalars of the recurrences, written by the last workgroup of each kernel.
 struct alignas(128) BiState {
     double rho;      // (rhat, r) of the current iterate
+    double rho_next; // (rhat, r') of the iterate being formed
     double alpha;
     double omega;    // 0 after a half-step exit
     double beta;
@@ -50,10 +56,10 @@ struct BiWork {
     int n = 0;
     double* r = nullptr;
     double* rhat = nullptr;
-    double* q = nullptr;
+    double* p = nullptr;
     double* v = nullptr;
     double* t = nullptr;
-    double* partials = nullptr;  // [3][grid]
+    double* partials = nullptr;  // [5][kBiMaxGrid]
     BiState* st = nullptr;
     BiState* hst = nullptr;  // pinned [3]: two chunk slots and the reset image
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -65,19 +71,29 @@ namespace {
 #ifndef FVPCG_BS_BICG
 #define FVPCG_BS_BICG 512
 #endif
+#ifndef FVPCG_GRID_BICG
+#define FVPCG_GRID_BICG 256
+#endif
 constexpr int kBsBi = FVPCG_BS_BICG;
+constexpr int kBiMaxGrid = FVPCG_GRID_BICG;  // workgroups per launch at most
 
-// p = r + beta q and s = r - alpha v, one rounding each: the row that owns an
-// entry and every row that gathers it compute the same bits.
-__device__ __forceinline__ double bi_dir(double r, double q, double beta) { return fma(beta, q, r); }
+Geom bi_geom(int n) {
+    if (n < 1) n = 1;
+    int g = (n + kBsBi - 1) / kBsBi;
+    if (g > kBiMaxGrid) g = kBiMaxGrid;
+    return {g, kBsBi};
+}
+
+// s = r - alpha v with one rounding: the row that owns an entry and every
+// row that gathers it compute the same bits.
 __device__ __forceinline__ double bi_half(double r, double v, double alpha) { return fma(-alpha, v, r); }
 
-// acc + sum_k val[k][c] * f(a[j], b[j]) over the WT slots of row c, with
-// f(a, b) = a + k b (k = beta: p from r and q; k = -alpha: s from r and v).
+// acc + sum_k val[k][c] * s[j] over the WT slots of row c, with s = r - alpha v
+// formed from the gathered r[j] and v[j].
 template <int WT, typename CI>
-__device__ __forceinline__ double gather_combo(const CI* __restrict__ col, const double* __restrict__ val, int n,
-                                               int c, const double* __restrict__ a, const double* __restrict__ b,
-                                               double k, double acc) {
+__device__ __forceinline__ double gather_s(const CI* __restrict__ col, const double* __restrict__ val, int n, int c,
+                                           const double* __restrict__ r, const double* __restrict__ v, double alpha,
+                                           double acc) {
     int j[WT];
     double m[WT];
 #pragma unroll
@@ -87,25 +103,25 @@ __device__ __forceinline__ double gather_combo(const CI* __restrict__ col, const
         m[i] = ld_once(val + o);
     }
 #pragma unroll
-    for (int i = 0; i < WT; ++i) acc += m[i] * fma(k, b[j[i]], a[j[i]]);
+    for (int i = 0; i < WT; ++i) acc += m[i] * bi_half(r[j[i]], v[j[i]], alpha);
     return acc;
 }
 
-// r = b - A x, rhat = r, q = 0; (r, r) and (b, b) -> the tolerance and
+// r = b - A x, rhat = r, p = r; (r, r) and (b, b) -> the tolerance and
 // rho_1 = (rhat, r) = (r, r).
 template <int BS, int WT, typename CI>
 __global__ __launch_bounds__(BS) void k_bi_init(const CI* __restrict__ col, const double* __restrict__ val,
                                                 const double* __restrict__ d, int n, Geom g,
                                                 const double* __restrict__ b, const double* __restrict__ x,
                                                 double* __restrict__ r, double* __restrict__ rhat,
-                                                double* __restrict__ q, BiState* st, double* partials) {
+                                                double* __restrict__ p, BiState* st, double* partials) {
     double acc[2] = {0.0, 0.0};
     FV_ROWS(blk) {
         const double bc = b[c];
         const double rc = bc - row_gather<double, WT, CI>(col, val, n, c, x, d[c] * x[c]);
         r[c] = rc;
         st_once(rhat + c, rc);
-        q[c] = 0.0;
+        p[c] = rc;
         acc[0] += rc * rc;
         acc[1] += bc * bc;
     }
@@ -124,8 +140,6 @@ __global__ __launch_bounds__(BS) void k_bi_init(const CI* __restrict__ col, cons
         st->rr = t[0];
         st->rho = t[0];
         st->r0norm = sqrt(t[0]);
-        st->beta = 0.0;
-        st->omega = 1.0;
         if (st->r0norm <= st->tol_abs) {
             st->done = 1;
             st->status = FVPCG_OK;
@@ -136,19 +150,17 @@ __global__ __launch_bounds__(BS) void k_bi_init(const CI* __restrict__ col, cons
     }
 }
 
-// v = A M^-1 p with p = r + beta q; alpha = rho / (rhat, v).
+// v = A M^-1 p; alpha = rho / (rhat, v).
 template <int BS, int WT, typename CI, bool JAC>
 __global__ __launch_bounds__(BS) void k_bi_pv(const CI* __restrict__ col, const double* __restrict__ val,
                                               const double* __restrict__ d, int n, Geom g,
-                                              const double* __restrict__ r, const double* __restrict__ q,
-                                              const double* __restrict__ rhat, double* __restrict__ v, BiState* st,
-                                              double* partials) {
+                                              const double* __restrict__ p, const double* __restrict__ rhat,
+                                              double* __restrict__ v, BiState* st, double* partials) {
     if (st->done) return;
-    const double beta = st->beta;
     double acc[1] = {0.0};
     FV_ROWS(blk) {
-        const double pc = bi_dir(r[c], q[c], beta);
-        const double vc = gather_combo<WT, CI>(col, val, n, c, r, q, beta, JAC ? pc : ld_once(d + c) * pc);
+        const double pc = p[c];
+        const double vc = row_gather<double, WT, CI>(col, val, n, c, p, JAC ? pc : ld_once(d + c) * pc);
         v[c] = vc;
         acc[0] += ld_once(rhat + c) * vc;
     }
@@ -166,27 +178,32 @@ __global__ __launch_bounds__(BS) void k_bi_pv(const CI* __restrict__ col, const 
 }
 
 // t = A M^-1 s with s = r - alpha v; omega = (t, s) / (t, t), or omega = 0
-// and the half-step exit when ||s|| meets the tolerance.
+// and the half-step exit when ||s|| meets the tolerance; rho' and beta.
 template <int BS, int WT, typename CI, bool JAC>
 __global__ __launch_bounds__(BS) void k_bi_st(const CI* __restrict__ col, const double* __restrict__ val,
                                               const double* __restrict__ d, int n, Geom g,
                                               const double* __restrict__ r, const double* __restrict__ v,
-                                              double* __restrict__ t, BiState* st, double* partials) {
+                                              const double* __restrict__ rhat, double* __restrict__ t, BiState* st,
+                                              double* partials) {
     if (st->done) return;
     const double alpha = st->alpha;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     FV_ROWS(blk) {
         const double sc = bi_half(r[c], v[c], alpha);
-        const double tc = gather_combo<WT, CI>(col, val, n, c, r, v, -alpha, JAC ? sc : ld_once(d + c) * sc);
+        const double tc = gather_s<WT, CI>(col, val, n, c, r, v, alpha, JAC ? sc : ld_once(d + c) * sc);
+        const double hc = ld_once(rhat + c);
         st_once(t + c, tc);
         acc[0] += tc * sc;
         acc[1] += tc * tc;
         acc[2] += sc * sc;
+        acc[3] += hc * sc;
+        acc[4] += hc * tc;
     }
-    double tot[3];
-    if (device_reduce<BS, 3>(acc, partials, &st->ticket, blk, g.grid, tot) && threadIdx.x == 0) {
+    double tot[5];
+    if (device_reduce<BS, 5>(acc, partials, &st->ticket, blk, g.grid, tot) && threadIdx.x == 0) {
         if (sqrt(tot[2]) <= st->tol_abs) {
             st->omega = 0.0;
+            st->beta = 0.0;
             st->half = 1;
             return;
         }
@@ -197,39 +214,39 @@ __global__ __launch_bounds__(BS) void k_bi_st(const CI* __restrict__ col, const 
             st->status = FVPCG_BREAKDOWN;
             return;
         }
+        const double rho_next = tot[3] - omega * tot[4];
         st->omega = omega;
+        st->rho_next = rho_next;
+        st->beta = (rho_next / st->rho) * (alpha / omega);
     }
 }
 
-// x += M^-1 (alpha p + omega s), r = s - omega t, q = p - omega v;
-// rho' = (rhat, r), (r, r): stopping test, then beta = (rho'/rho)(alpha/omega).
+// x += M^-1 (alpha p + omega s), r' = s - omega t, p' = r' + beta (p - omega v);
+// (r', r'): stopping test; breakdown if rho' is zero or a scalar not finite.
 template <int BS, bool JAC>
 __global__ __launch_bounds__(BS) void k_bi_update(double* __restrict__ x, double* __restrict__ r,
-                                                  double* __restrict__ q, const double* __restrict__ v,
-                                                  const double* __restrict__ t, const double* __restrict__ rhat,
-                                                  const double* __restrict__ d, int n, Geom g, BiState* st,
-                                                  double* partials) {
+                                                  double* __restrict__ p, const double* __restrict__ v,
+                                                  const double* __restrict__ t, const double* __restrict__ d, int n,
+                                                  Geom g, BiState* st, double* partials) {
     if (st->done) return;
     const double alpha = st->alpha, omega = st->omega, beta = st->beta;
-    double acc[2] = {0.0, 0.0};
+    double acc[1] = {0.0};
     FV_ROWS(blk) {
-        const double rc = ld_once(r + c), vc = ld_once(v + c);
-        const double pc = bi_dir(rc, ld_once(q + c), beta);
+        const double rc = ld_once(r + c), vc = ld_once(v + c), pc = ld_once(p + c);
         const double sc = bi_half(rc, vc, alpha);
         const double dx = alpha * pc + omega * sc;
         st_once(x + c, ld_once(x + c) + (JAC ? dx / ld_once(d + c) : dx));
         const double rn = sc - omega * ld_once(t + c);
         r[c] = rn;
-        q[c] = pc - omega * vc;
-        acc[0] += ld_once(rhat + c) * rn;
-        acc[1] += rn * rn;
+        p[c] = rn + beta * (pc - omega * vc);
+        acc[0] += rn * rn;
     }
-    double tot[2];
-    if (device_reduce<BS, 2>(acc, partials, &st->ticket, blk, g.grid, tot) && threadIdx.x == 0) {
+    double tot[1];
+    if (device_reduce<BS, 1>(acc, partials, &st->ticket, blk, g.grid, tot) && threadIdx.x == 0) {
         const int it = st->iter + 1;
         st->iter = it;
-        st->rr = tot[1];
-        if (st->half || sqrt(tot[1]) <= st->tol_abs) {
+        st->rr = tot[0];
+        if (st->half || sqrt(tot[0]) <= st->tol_abs) {
             st->done = 1;
             st->status = FVPCG_OK;
             return;
@@ -239,13 +256,12 @@ __global__ __launch_bounds__(BS) void k_bi_update(double* __restrict__ x, double
             st->status = FVPCG_NOT_CONVERGED;
             return;
         }
-        const double rho = tot[0];
-        if (rho == 0.0 || !isfinite(rho)) {
+        const double rho = st->rho_next;
+        if (rho == 0.0 || !isfinite(rho) || !isfinite(beta)) {
             st->done = 1;
             st->status = FVPCG_BREAKDOWN;
             return;
         }
-        st->beta = (rho / st->rho) * (alpha / omega);
         st->rho = rho;
     }
 }
@@ -270,7 +286,7 @@ void bi_release(BiWork* w) {
     if (!w) return;
     dev_free(w->r);
     dev_free(w->rhat);
-    dev_free(w->q);
+    dev_free(w->p);
     dev_free(w->v);
     dev_free(w->t);
     dev_free(w->partials);
@@ -289,9 +305,9 @@ int bi_alloc(BiWork* w, int n) {
     int rc;
     const size_t m = (size_t)n;
     if ((rc = dev_alloc(&w->r, m, "BiCGSTAB r")) || (rc = dev_alloc(&w->rhat, m, "BiCGSTAB rhat")) ||
-        (rc = dev_alloc(&w->q, m, "BiCGSTAB q")) || (rc = dev_alloc(&w->v, m, "BiCGSTAB v")) ||
+        (rc = dev_alloc(&w->p, m, "BiCGSTAB p")) || (rc = dev_alloc(&w->v, m, "BiCGSTAB v")) ||
         (rc = dev_alloc(&w->t, m, "BiCGSTAB t")) ||
-        (rc = dev_alloc(&w->partials, (size_t)3 * kMaxGrid, "BiCGSTAB partials")) ||
+        (rc = dev_alloc(&w->partials, (size_t)5 * kBiMaxGrid, "BiCGSTAB partials")) ||
         (rc = dev_alloc(&w->st, 1, "BiCGSTAB state")))
         return rc;
     FV_HIP(hipMemset(w->st, 0, sizeof(BiState)));
@@ -352,7 +368,7 @@ int solve_bicgstab(const fvpcg_matrix* A, const double* b, double* x, double tol
     int rc;
     if ((rc = bi_work(A->bi, n))) return rc;
     BiWork& w = *A->bi;
-    const Geom g = geom_for(n, kBsBi);
+    const Geom g = bi_geom(n);
     BiState* st = w.st;
     double* part = w.partials;
     const double* val = jac ? A->val_cs : A->val;
@@ -365,7 +381,7 @@ int solve_bicgstab(const fvpcg_matrix* A, const double* b, double* x, double tol
     h0->status = FVPCG_NOT_CONVERGED;
     FV_HIP(hipMemcpyAsync(st, h0, sizeof(BiState), hipMemcpyHostToDevice, s));
     FV_LAYOUT(m, hipLaunchKernelGGL((k_bi_init<kBsBi, W_, CI_>), dim3(g.grid), dim3(kBsBi), 0, s, cols_, A->val, A->d,
-                                    n, g, b, x, w.r, w.rhat, w.q, st, part));
+                                    n, g, b, x, w.r, w.rhat, w.p, st, part));
     FV_LAUNCHED();
     BiState h;
     if ((rc = bi_state_read(w, 0, &h, s))) return rc;
@@ -384,21 +400,21 @@ int solve_bicgstab(const fvpcg_matrix* A, const double* b, double* x, double tol
                 FV_LAYOUT(m,
                           if (jac) {
                               hipLaunchKernelGGL((k_bi_pv<kBsBi, W_, CI_, true>), dim3(g.grid), dim3(kBsBi), 0, s,
-                                                 cols_, val, A->d, n, g, w.r, w.q, w.rhat, w.v, st, part);
+                                                 cols_, val, A->d, n, g, w.p, w.rhat, w.v, st, part);
                               hipLaunchKernelGGL((k_bi_st<kBsBi, W_, CI_, true>), dim3(g.grid), dim3(kBsBi), 0, s,
-                                                 cols_, val, A->d, n, g, w.r, w.v, w.t, st, part);
+                                                 cols_, val, A->d, n, g, w.r, w.v, w.rhat, w.t, st, part);
                           } else {
                               hipLaunchKernelGGL((k_bi_pv<kBsBi, W_, CI_, false>), dim3(g.grid), dim3(kBsBi), 0, s,
-                                                 cols_, val, A->d, n, g, w.r, w.q, w.rhat, w.v, st, part);
+                                                 cols_, val, A->d, n, g, w.p, w.rhat, w.v, st, part);
                               hipLaunchKernelGGL((k_bi_st<kBsBi, W_, CI_, false>), dim3(g.grid), dim3(kBsBi), 0, s,
-                                                 cols_, val, A->d, n, g, w.r, w.v, w.t, st, part);
+                                                 cols_, val, A->d, n, g, w.r, w.v, w.rhat, w.t, st, part);
                           });
                 if (jac)
-                    hipLaunchKernelGGL((k_bi_update<kBsBi, true>), dim3(g.grid), dim3(kBsBi), 0, s, x, w.r, w.q, w.v,
-                                       w.t, w.rhat, A->d, n, g, st, part);
+                    hipLaunchKernelGGL((k_bi_update<kBsBi, true>), dim3(g.grid), dim3(kBsBi), 0, s, x, w.r, w.p, w.v,
+                                       w.t, A->d, n, g, st, part);
                 else
-                    hipLaunchKernelGGL((k_bi_update<kBsBi, false>), dim3(g.grid), dim3(kBsBi), 0, s, x, w.r, w.q, w.v,
-                                       w.t, w.rhat, A->d, n, g, st, part);
+                    hipLaunchKernelGGL((k_bi_update<kBsBi, false>), dim3(g.grid), dim3(kBsBi), 0, s, x, w.r, w.p, w.v,
+                                       w.t, A->d, n, g, st, part);
             }
             FV_LAUNCHED();
             launched += cnt;
