@@ -414,6 +414,31 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None,
             "alg_bytes_per_iter": alg, "alg_gbs": round(alg / (us_it * 1e-6) / 1e9, 1),
             "frac_of_8tbs": round(alg / (us_it * 1e-6) / 8e12, 4)}
         log(f"extra momentum192: {res['momentum192/bicgstab_jacobi_to_1e-08']}")
+        # the three velocity components: one after another against all three
+        # solved together (the matrix read once per iteration for all)
+        B3 = torch.stack([bm, to(fvcases.momentum_rhs(c, 1), torch.float64),
+                          to(fvcases.momentum_rhs(c, 2), torch.float64)])
+        fv.solve_bicgstab_multi(Am, B3, tol=c.tol, maxit=5000)
+        seq, its = [], []
+        for _ in range(3):
+            tot = 0.0
+            for k in range(3):
+                _, sk = fv.solve_bicgstab(Am, B3[k].contiguous(), tol=c.tol, maxit=5000)
+                tot += sk["device_ms"]
+                its.append(sk["iters"])
+            seq.append(tot)
+        mult = sorted((fv.solve_bicgstab_multi(Am, B3, tol=c.tol, maxit=5000)[1] for _ in range(3)),
+                      key=lambda t: t[0]["device_ms"])[1]
+        _, fx3 = fv.solve_bicgstab_multi(Am, B3, tol=0.0, maxit=40)
+        us3 = fx3[0]["iter_ms"] * 1e3 / 40
+        alg3 = 3 * 128 * c.n + 48 * c.F
+        res["momentum192/bicgstab_3_components"] = {
+            "status": [t["status_name"] for t in mult], "iters": [t["iters"] for t in mult],
+            "ms_together": round(mult[0]["device_ms"], 2), "ms_one_after_another": round(sorted(seq)[1], 2),
+            "speedup": round(sorted(seq)[1] / mult[0]["device_ms"], 2),
+            "us_per_iter_fixed40": round(us3, 2), "alg_bytes_per_iter": alg3,
+            "alg_gbs": round(alg3 / (us3 * 1e-6) / 1e9, 1), "frac_of_8tbs": round(alg3 / (us3 * 1e-6) / 8e12, 4)}
+        log(f"extra momentum192 3 components: {res['momentum192/bicgstab_3_components']}")
         Am.close()
         mm.close()
     if "small" in groups:

@@ -4,5 +4,5 @@ HIP path's tests and benchmark and by the CPU oracle's tests.
 Pure NumPy/SciPy; holds none of the solver's arithmetic.
 """
 from .configs import (Batch, Case, Transient, batch, cavity, concat, graded_spacing, laplace, make,  # noqa: F401
-                      momentum, transient, varcoef)
+                      momentum, momentum_rhs, transient, varcoef)
 from . import mesh, rng  # noqa: F401

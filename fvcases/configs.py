@@ -385,6 +385,19 @@ def momentum(shape=(192, 192, 192), seed=11, nu=0.01, co=2.0, permute=True, tol=
     return _finish(name, shape, n, owner, nb, diag, upper, lower, b, tol, seed, meta)
 
 
+def momentum_rhs(case, component, seed=12):
+    """Right-hand side of another velocity component (1 = y, 2 = z) of a
+    momentum case: the recipe of its b without the lid term,
+    (h^3/dt) u_old + h^3 g with fresh u_old, g ~ U[-1,1] (streams vel and
+    src of seed + component).  Independent draws per cell, so the cell order
+    of the case does not matter."""
+    h, dt = case.meta["h"], case.meta["dt"]
+    vol = h ** 3
+    u_old = R.uniform(R.stream(seed + component, "vel"), case.n)
+    g = R.uniform(R.stream(seed + component, "src"), case.n)
+    return vol / dt * u_old + vol * g
+
+
 # ---------------------------------------------------------------------------
 # Named full-size workloads, with an on-disk cache for the large ones.
 

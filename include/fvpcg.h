@@ -157,6 +157,20 @@ FVPCG_API int fvpcg_solve(const fvpcg_matrix* mat, const double* b, double* x, d
 FVPCG_API int fvpcg_solve_bicgstab(const fvpcg_matrix* mat, const double* b, double* x, double tol, int32_t maxit,
                                    int32_t precond, void* stream, fvpcg_stats* stats);
 
+/* ---- BiCGSTAB for nrhs = 1..4 right-hand sides with the same matrix (the
+ * velocity components of a momentum predictor, Section 2), solved together:
+ * each iteration reads the matrix once for all of them.  b and x hold the
+ * components one after another (FP64[nrhs][n_cells], device; x = x0 on
+ * entry); stats, if not NULL, points to nrhs structs.  Each component has
+ * its own scalars and stopping test, as in fvpcg_solve_bicgstab; one that
+ * has stopped is left untouched while the others go on.  Returns FVPCG_OK if
+ * every component converged, else FVPCG_BREAKDOWN if any broke down, else
+ * FVPCG_NOT_CONVERGED; device_ms and iter_ms are those of the whole call.
+ * The workspace grows to 5 nrhs vectors of n doubles. */
+FVPCG_API int fvpcg_solve_bicgstab_multi(const fvpcg_matrix* mat, int32_t nrhs, const double* b, double* x,
+                                         double tol, int32_t maxit, int32_t precond, void* stream,
+                                         fvpcg_stats* stats);
+
 /* ---- Mixed-precision iterative refinement (FP32 inner, FP64 outer).
  * Outer: r = b - A x in FP64 with the FP64 matrix, stop at
  * ||r|| <= outer_tol ||b|| or after max_outer corrections.  Inner: the

@@ -238,6 +238,29 @@ def fvpcg_solve_bicgstab(A: Matrix, b, x=None, tol=1e-8, maxit=10000, precond="j
 solve_bicgstab = fvpcg_solve_bicgstab
 
 
+def fvpcg_solve_bicgstab_multi(A: Matrix, b, x=None, tol=1e-8, maxit=10000, precond="jacobi", stream=None):
+    """BiCGSTAB for nrhs = b.shape[0] (1..4) right-hand sides with the same
+    matrix, solved together; b and x are (nrhs, n) float64 CUDA tensors (x,
+    if given, holds x0 and is overwritten).  Returns (x, [stats per
+    component]).  Raises FVPCGError if a component broke down."""
+    import torch
+
+    if b.dim() != 2:
+        raise ValueError("b must have shape (nrhs, n)")
+    nr = int(b.shape[0])
+    if x is None:
+        x = torch.zeros_like(b)
+    st = (Stats * max(nr, 1))()
+    code = lib().fvpcg_solve_bicgstab_multi(A.handle, nr, _ptr(b, torch.float64, nr * A.n, "b"),
+                                            _ptr(x, torch.float64, nr * A.n, "x"), float(tol), int(maxit),
+                                            PRECONDS[precond], _stream(stream), st)
+    _check(code, "fvpcg_solve_bicgstab_multi")
+    return x, [st[k].asdict() for k in range(nr)]
+
+
+solve_bicgstab_multi = fvpcg_solve_bicgstab_multi
+
+
 def fvpcg_solve_mixed(A: Matrix, b, x=None, outer_tol=1e-10, inner_tol=1e-5, max_outer=30, max_inner=20000,
                       stream=None):
     import torch

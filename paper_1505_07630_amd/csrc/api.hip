@@ -40,6 +40,8 @@ int solve_batched_backward(const fvpcg_batch* bt, const double* x, const double*
 int stream_calibrate(hipStream_t s, uint64_t bytes, double* copy_gbs, double* triad_gbs);
 int solve_bicgstab(const fvpcg_matrix* A, const double* b, double* x, double tol, int maxit, int precond,
                    hipStream_t s, fvpcg_stats* stats);
+int solve_bicgstab_multi(const fvpcg_matrix* A, int nrhs, const double* b, double* x, double tol, int maxit,
+                         int precond, hipStream_t s, fvpcg_stats* stats);
 void bicgstab_free(fvpcg_matrix* A);
 int assemble_transient(const fvpcg_mesh* m, const double* k, const double* w, const double* vol, const double* bdiag,
                        const double* bsrc, double dt, const double* T_old, double* diag, double* upper, double* b,
@@ -270,6 +272,30 @@ int fvpcg_solve_bicgstab(const fvpcg_matrix* mat, const double* b, double* x, do
         }
         int rc = solve_bicgstab(mat, b, x, tol, maxit, precond, (hipStream_t)stream, stats);
         if (rc == FVPCG_BREAKDOWN) set_error(rc, "breakdown: (rhat, r), (rhat, A p) or omega is zero or not finite");
+        return rc;
+    });
+}
+
+int fvpcg_solve_bicgstab_multi(const fvpcg_matrix* mat, int32_t nrhs, const double* b, double* x, double tol,
+                               int32_t maxit, int32_t precond, void* stream, fvpcg_stats* stats) {
+    return guard([&]() -> int {
+        if (stats && nrhs >= 1 && nrhs <= 4)
+            for (int k = 0; k < nrhs; ++k) stats_status(&stats[k], FVPCG_INVALID_ARG);
+        if (!mat) return set_error(FVPCG_INVALID_ARG, "mat is NULL");
+        if (nrhs < 1 || nrhs > 4) return set_error(FVPCG_INVALID_ARG, "nrhs must be 1..4 (got %d)", nrhs);
+        size_t bytes = sizeof(double) * (size_t)mat->mesh->n * (size_t)nrhs;
+        FV_TRY(check_solver_args(tol, maxit, FVPCG_CG, precond));
+        FV_TRY(check_dev(b, bytes, "b"));
+        FV_TRY(check_dev(x, bytes, "x"));
+        if (overlap(b, bytes, x, bytes)) return set_error(FVPCG_INVALID_ARG, "b and x overlap");
+        if (precond == FVPCG_PRECOND_JACOBI && !mat->diag_ok) {
+            if (stats)
+                for (int k = 0; k < nrhs; ++k) stats_status(&stats[k], FVPCG_BREAKDOWN);
+            return set_error(FVPCG_BREAKDOWN, "Jacobi preconditioner needs a finite positive diagonal");
+        }
+        int rc = solve_bicgstab_multi(mat, nrhs, b, x, tol, maxit, precond, (hipStream_t)stream, stats);
+        if (rc == FVPCG_BREAKDOWN)
+            set_error(rc, "breakdown in a component: (rhat, r), (rhat, A p) or omega is zero or not finite");
         return rc;
     });
 }

@@ -25,16 +25,27 @@
 // p' itself, so the first product gathers one vector.  Per iteration the
 // kernels move 128 n + 48 F bytes (int32 columns) against 2 x 24 F for the
 // two products alone.
+//
+// Several right-hand sides with the same matrix (the three velocity
+// components of a momentum predictor) are solved together: the kernels are
+// templated on the count NR, every vector is stored component after
+// component (each component's streams stay unit-stride), each component
+// keeps its own scalars and stopping test, and the matrix slots of a row are
+// loaded once for all of them: 128 NR n + 48 F bytes per iteration.  A
+// component that has stopped is skipped (no loads, no stores) while the
+// others go on, so every component's iterates are those of its own single
+// solve.
 #include "handles.hpp"
 #include "rows.hpp"
 
 namespace fvpcg {
 
-// Scalars of the recurrences, written by the last workgroup of each kernel.
+// Scalars of one component's recurrences, written by the last workgroup of
+// each kernel.
 struct alignas(128) BiState {
     double rho;      // (rhat, r) of the current iterate
     double rho_next; // (rhat, r') of the iterate being formed
-    double alpha;
+    double alpha;    // alpha, omega, beta are 0 once the component has stopped
     double omega;    // 0 after a half-step exit
     double beta;
     double rr;       // (r, r)
@@ -48,20 +59,23 @@ struct alignas(128) BiState {
     int32_t status;
     int32_t zero_b;
     int32_t half;    // ||s|| met the tolerance: x += alpha phat ends the solve
-    uint32_t ticket;
+    uint32_t ticket; // reduction ticket (component 0's serves all)
     uint32_t pad;
 };
 
+constexpr int kBiMaxRhs = 4;
+
 struct BiWork {
     int n = 0;
-    double* r = nullptr;
+    int nr = 0;                  // components the vectors are sized for
+    double* r = nullptr;         // [nr][n] each
     double* rhat = nullptr;
     double* p = nullptr;
     double* v = nullptr;
     double* t = nullptr;
-    double* partials = nullptr;  // [5][kBiMaxGrid]
-    BiState* st = nullptr;
-    BiState* hst = nullptr;  // pinned [3]: two chunk slots and the reset image
+    double* partials = nullptr;  // [5 kBiMaxRhs][kBiMaxGrid]
+    BiState* st = nullptr;       // [kBiMaxRhs]
+    BiState* hst = nullptr;      // pinned [3][kBiMaxRhs]: two chunk slots and the reset image
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t t_begin = nullptr, t_end = nullptr, t_it0 = nullptr, t_it1 = nullptr;
 };
@@ -88,12 +102,35 @@ Geom bi_geom(int n) {
 // row that gathers it compute the same bits.
 __device__ __forceinline__ double bi_half(double r, double v, double alpha) { return fma(-alpha, v, r); }
 
-// acc + sum_k val[k][c] * s[j] over the WT slots of row c, with s = r - alpha v
-// formed from the gathered r[j] and v[j].
-template <int WT, typename CI>
-__device__ __forceinline__ double gather_s(const CI* __restrict__ col, const double* __restrict__ val, int n, int c,
-                                           const double* __restrict__ r, const double* __restrict__ v, double alpha,
-                                           double acc) {
+// True while any component still iterates; act[k] for each.
+template <int NR>
+__device__ __forceinline__ bool bi_active(const BiState* st, bool (&act)[NR]) {
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        act[k] = !st[k].done;
+        any |= act[k];
+    }
+    return any;
+}
+
+// The component's exit: status, and zero scalars so later launches leave it
+// untouched.
+__device__ __forceinline__ void bi_stop(BiState* st, int status) {
+    st->done = 1;
+    st->status = status;
+    st->alpha = 0.0;
+    st->omega = 0.0;
+    st->beta = 0.0;
+}
+
+// acc[k] += sum_i val[i][c] * v[k][j_i] over the WT slots of row c for the
+// components still iterating (v component-major).  Every component's values
+// are loaded before any is used, so all the row's gathers are in flight at
+// once; the loads of a stopped component are made and discarded.
+template <int WT, typename CI, int NR>
+__device__ __forceinline__ void gather_v(const CI* __restrict__ col, const double* __restrict__ val, int n, int c,
+                                         const double* __restrict__ v, const bool (&act)[NR], double (&acc)[NR]) {
     int j[WT];
     double m[WT];
 #pragma unroll
@@ -102,184 +139,305 @@ __device__ __forceinline__ double gather_s(const CI* __restrict__ col, const dou
         j[i] = slot_col(col, o, c);
         m[i] = ld_once(val + o);
     }
+    double g[NR][WT];
 #pragma unroll
-    for (int i = 0; i < WT; ++i) acc += m[i] * bi_half(r[j[i]], v[j[i]], alpha);
-    return acc;
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+        for (int i = 0; i < WT; ++i) g[k][i] = v[(size_t)k * n + j[i]];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        if (!act[k]) continue;
+#pragma unroll
+        for (int i = 0; i < WT; ++i) acc[k] += m[i] * g[k][i];
+    }
+}
+
+// Same with s = r - alpha v formed from the gathered r and v.
+template <int WT, typename CI, int NR>
+__device__ __forceinline__ void gather_s(const CI* __restrict__ col, const double* __restrict__ val, int n, int c,
+                                         const double* __restrict__ r, const double* __restrict__ v,
+                                         const double (&alpha)[NR], const bool (&act)[NR], double (&acc)[NR]) {
+    int j[WT];
+    double m[WT];
+#pragma unroll
+    for (int i = 0; i < WT; ++i) {
+        const size_t o = (size_t)i * n + c;
+        j[i] = slot_col(col, o, c);
+        m[i] = ld_once(val + o);
+    }
+    double gr[NR][WT], gv[NR][WT];
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+        for (int i = 0; i < WT; ++i) {
+            gr[k][i] = r[(size_t)k * n + j[i]];
+            gv[k][i] = v[(size_t)k * n + j[i]];
+        }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        if (!act[k]) continue;
+#pragma unroll
+        for (int i = 0; i < WT; ++i) acc[k] += m[i] * bi_half(gr[k][i], gv[k][i], alpha[k]);
+    }
 }
 
 // r = b - A x, rhat = r, p = r; (r, r) and (b, b) -> the tolerance and
-// rho_1 = (rhat, r) = (r, r).
-template <int BS, int WT, typename CI>
+// rho_1 = (rhat, r) = (r, r).  b and x are component-major ([NR][n]).
+template <int BS, int WT, typename CI, int NR>
 __global__ __launch_bounds__(BS) void k_bi_init(const CI* __restrict__ col, const double* __restrict__ val,
                                                 const double* __restrict__ d, int n, Geom g,
                                                 const double* __restrict__ b, const double* __restrict__ x,
                                                 double* __restrict__ r, double* __restrict__ rhat,
                                                 double* __restrict__ p, BiState* st, double* partials) {
-    double acc[2] = {0.0, 0.0};
+    double acc[2 * NR];
+#pragma unroll
+    for (int k = 0; k < 2 * NR; ++k) acc[k] = 0.0;
     FV_ROWS(blk) {
-        const double bc = b[c];
-        const double rc = bc - row_gather<double, WT, CI>(col, val, n, c, x, d[c] * x[c]);
-        r[c] = rc;
-        st_once(rhat + c, rc);
-        p[c] = rc;
-        acc[0] += rc * rc;
-        acc[1] += bc * bc;
-    }
-    double t[2];
-    if (device_reduce<BS, 2>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
-        st->iter = 0;
-        st->bnorm = sqrt(t[1]);
-        if (t[1] == 0.0) {
-            st->zero_b = 1;
-            st->done = 1;
-            st->status = FVPCG_OK;
-            st->rr = 0.0;
-            return;
+        const double dc = d[c];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const double* xk = x + (size_t)k * n;
+            const double bc = b[(size_t)k * n + c];
+            const double rc = bc - row_gather<double, WT, CI>(col, val, n, c, xk, dc * xk[c]);
+            const size_t e = (size_t)k * n + c;
+            r[e] = rc;
+            st_once(rhat + e, rc);
+            p[e] = rc;
+            acc[2 * k] += rc * rc;
+            acc[2 * k + 1] += bc * bc;
         }
-        st->tol_abs *= st->bnorm;
-        st->rr = t[0];
-        st->rho = t[0];
-        st->r0norm = sqrt(t[0]);
-        if (st->r0norm <= st->tol_abs) {
-            st->done = 1;
-            st->status = FVPCG_OK;
-        } else if (st->maxit <= 0) {
-            st->done = 1;
-            st->status = FVPCG_NOT_CONVERGED;
+    }
+    double t[2 * NR];
+    if (device_reduce<BS, 2 * NR>(acc, partials, &st[0].ticket, blk, g.grid, t) && threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            BiState* sk = &st[k];
+            const double rr = t[2 * k], bb = t[2 * k + 1];
+            sk->iter = 0;
+            sk->bnorm = sqrt(bb);
+            if (bb == 0.0) {
+                sk->zero_b = 1;
+                sk->rr = 0.0;
+                bi_stop(sk, FVPCG_OK);
+                continue;
+            }
+            sk->tol_abs *= sk->bnorm;
+            sk->rr = rr;
+            sk->rho = rr;
+            sk->r0norm = sqrt(rr);
+            if (sk->r0norm <= sk->tol_abs)
+                bi_stop(sk, FVPCG_OK);
+            else if (sk->maxit <= 0)
+                bi_stop(sk, FVPCG_NOT_CONVERGED);
         }
     }
 }
 
 // v = A M^-1 p; alpha = rho / (rhat, v).
-template <int BS, int WT, typename CI, bool JAC>
+template <int BS, int WT, typename CI, bool JAC, int NR>
 __global__ __launch_bounds__(BS) void k_bi_pv(const CI* __restrict__ col, const double* __restrict__ val,
                                               const double* __restrict__ d, int n, Geom g,
                                               const double* __restrict__ p, const double* __restrict__ rhat,
                                               double* __restrict__ v, BiState* st, double* partials) {
-    if (st->done) return;
-    double acc[1] = {0.0};
+    bool act[NR];
+    if (!bi_active<NR>(st, act)) return;
+    double acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
     FV_ROWS(blk) {
-        const double pc = p[c];
-        const double vc = row_gather<double, WT, CI>(col, val, n, c, p, JAC ? pc : ld_once(d + c) * pc);
-        v[c] = vc;
-        acc[0] += ld_once(rhat + c) * vc;
-    }
-    double t[1];
-    if (device_reduce<BS, 1>(acc, partials, &st->ticket, blk, g.grid, t) && threadIdx.x == 0) {
-        const double rv = t[0];
-        const double alpha = st->rho / rv;
-        if (rv == 0.0 || !isfinite(alpha)) {
-            st->done = 1;
-            st->status = FVPCG_BREAKDOWN;
-            return;
+        double vc[NR];
+        const double dc = JAC ? 1.0 : ld_once(d + c);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const double pc = p[(size_t)k * n + c];
+            vc[k] = JAC ? pc : dc * pc;
         }
-        st->alpha = alpha;
+        gather_v<WT, CI, NR>(col, val, n, c, p, act, vc);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            if (!act[k]) continue;
+            const size_t e = (size_t)k * n + c;
+            v[e] = vc[k];
+            acc[k] += ld_once(rhat + e) * vc[k];
+        }
+    }
+    double t[NR];
+    if (device_reduce<BS, NR>(acc, partials, &st[0].ticket, blk, g.grid, t) && threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            if (!act[k]) continue;
+            const double rv = t[k];
+            const double alpha = st[k].rho / rv;
+            if (rv == 0.0 || !isfinite(alpha)) {
+                bi_stop(&st[k], FVPCG_BREAKDOWN);
+                continue;
+            }
+            st[k].alpha = alpha;
+        }
     }
 }
 
 // t = A M^-1 s with s = r - alpha v; omega = (t, s) / (t, t), or omega = 0
 // and the half-step exit when ||s|| meets the tolerance; rho' and beta.
-template <int BS, int WT, typename CI, bool JAC>
+template <int BS, int WT, typename CI, bool JAC, int NR>
 __global__ __launch_bounds__(BS) void k_bi_st(const CI* __restrict__ col, const double* __restrict__ val,
                                               const double* __restrict__ d, int n, Geom g,
                                               const double* __restrict__ r, const double* __restrict__ v,
                                               const double* __restrict__ rhat, double* __restrict__ t, BiState* st,
                                               double* partials) {
-    if (st->done) return;
-    const double alpha = st->alpha;
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    bool act[NR];
+    if (!bi_active<NR>(st, act)) return;
+    double alpha[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) alpha[k] = st[k].alpha;
+    double acc[5 * NR];
+#pragma unroll
+    for (int k = 0; k < 5 * NR; ++k) acc[k] = 0.0;
     FV_ROWS(blk) {
-        const double sc = bi_half(r[c], v[c], alpha);
-        const double tc = gather_s<WT, CI>(col, val, n, c, r, v, alpha, JAC ? sc : ld_once(d + c) * sc);
-        const double hc = ld_once(rhat + c);
-        st_once(t + c, tc);
-        acc[0] += tc * sc;
-        acc[1] += tc * tc;
-        acc[2] += sc * sc;
-        acc[3] += hc * sc;
-        acc[4] += hc * tc;
+        double sc[NR], tc[NR];
+        const double dc = JAC ? 1.0 : ld_once(d + c);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const size_t e = (size_t)k * n + c;
+            sc[k] = bi_half(r[e], v[e], alpha[k]);
+            tc[k] = JAC ? sc[k] : dc * sc[k];
+        }
+        gather_s<WT, CI, NR>(col, val, n, c, r, v, alpha, act, tc);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            if (!act[k]) continue;
+            const size_t e = (size_t)k * n + c;
+            const double hc = ld_once(rhat + e);
+            st_once(t + e, tc[k]);
+            acc[5 * k] += tc[k] * sc[k];
+            acc[5 * k + 1] += tc[k] * tc[k];
+            acc[5 * k + 2] += sc[k] * sc[k];
+            acc[5 * k + 3] += hc * sc[k];
+            acc[5 * k + 4] += hc * tc[k];
+        }
     }
-    double tot[5];
-    if (device_reduce<BS, 5>(acc, partials, &st->ticket, blk, g.grid, tot) && threadIdx.x == 0) {
-        if (sqrt(tot[2]) <= st->tol_abs) {
-            st->omega = 0.0;
-            st->beta = 0.0;
-            st->half = 1;
-            return;
+    double tot[5 * NR];
+    if (device_reduce<BS, 5 * NR>(acc, partials, &st[0].ticket, blk, g.grid, tot) && threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            if (!act[k]) continue;
+            BiState* sk = &st[k];
+            const double* q = tot + 5 * k;
+            if (sqrt(q[2]) <= sk->tol_abs) {
+                sk->omega = 0.0;
+                sk->beta = 0.0;
+                sk->half = 1;
+                continue;
+            }
+            const double omega = q[0] / q[1];
+            if (q[1] == 0.0 || omega == 0.0 || !isfinite(omega)) {
+                sk->iter = sk->iter + 1;
+                bi_stop(sk, FVPCG_BREAKDOWN);
+                continue;
+            }
+            const double rho_next = q[3] - omega * q[4];
+            sk->omega = omega;
+            sk->rho_next = rho_next;
+            sk->beta = (rho_next / sk->rho) * (alpha[k] / omega);
         }
-        const double omega = tot[0] / tot[1];
-        if (tot[1] == 0.0 || omega == 0.0 || !isfinite(omega)) {
-            st->iter = st->iter + 1;
-            st->done = 1;
-            st->status = FVPCG_BREAKDOWN;
-            return;
-        }
-        const double rho_next = tot[3] - omega * tot[4];
-        st->omega = omega;
-        st->rho_next = rho_next;
-        st->beta = (rho_next / st->rho) * (alpha / omega);
     }
 }
 
-// x += M^-1 (alpha p + omega s), r' = s - omega t, p' = r' + beta (p - omega v);
-// (r', r'): stopping test; breakdown if rho' is zero or a scalar not finite.
-template <int BS, bool JAC>
+// x += M^-1 (alpha p + omega s), r' = s - omega t, p' = r' + beta (p - omega v)
+// for the components still iterating (x is component-major); (r', r'):
+// stopping test; breakdown if rho' is zero or a scalar not finite.
+template <int BS, bool JAC, int NR>
 __global__ __launch_bounds__(BS) void k_bi_update(double* __restrict__ x, double* __restrict__ r,
                                                   double* __restrict__ p, const double* __restrict__ v,
                                                   const double* __restrict__ t, const double* __restrict__ d, int n,
                                                   Geom g, BiState* st, double* partials) {
-    if (st->done) return;
-    const double alpha = st->alpha, omega = st->omega, beta = st->beta;
-    double acc[1] = {0.0};
-    FV_ROWS(blk) {
-        const double rc = ld_once(r + c), vc = ld_once(v + c), pc = ld_once(p + c);
-        const double sc = bi_half(rc, vc, alpha);
-        const double dx = alpha * pc + omega * sc;
-        st_once(x + c, ld_once(x + c) + (JAC ? dx / ld_once(d + c) : dx));
-        const double rn = sc - omega * ld_once(t + c);
-        r[c] = rn;
-        p[c] = rn + beta * (pc - omega * vc);
-        acc[0] += rn * rn;
+    bool act[NR];
+    if (!bi_active<NR>(st, act)) return;
+    double alpha[NR], omega[NR], beta[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        alpha[k] = st[k].alpha;
+        omega[k] = st[k].omega;
+        beta[k] = st[k].beta;
     }
-    double tot[1];
-    if (device_reduce<BS, 1>(acc, partials, &st->ticket, blk, g.grid, tot) && threadIdx.x == 0) {
-        const int it = st->iter + 1;
-        st->iter = it;
-        st->rr = tot[0];
-        if (st->half || sqrt(tot[0]) <= st->tol_abs) {
-            st->done = 1;
-            st->status = FVPCG_OK;
-            return;
+    double acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+    FV_ROWS(blk) {
+        const double dc = JAC ? ld_once(d + c) : 1.0;
+        double rc[NR], vc[NR], pc[NR], tc[NR], xc[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const size_t e = (size_t)k * n + c;
+            rc[k] = ld_once(r + e);
+            vc[k] = ld_once(v + e);
+            pc[k] = ld_once(p + e);
+            tc[k] = ld_once(t + e);
+            xc[k] = ld_once(x + e);
         }
-        if (it >= st->maxit) {
-            st->done = 1;
-            st->status = FVPCG_NOT_CONVERGED;
-            return;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            if (!act[k]) continue;
+            const size_t e = (size_t)k * n + c;
+            const double sc = bi_half(rc[k], vc[k], alpha[k]);
+            const double dx = alpha[k] * pc[k] + omega[k] * sc;
+            st_once(x + e, xc[k] + (JAC ? dx / dc : dx));
+            const double rn = sc - omega[k] * tc[k];
+            r[e] = rn;
+            p[e] = rn + beta[k] * (pc[k] - omega[k] * vc[k]);
+            acc[k] += rn * rn;
         }
-        const double rho = st->rho_next;
-        if (rho == 0.0 || !isfinite(rho) || !isfinite(beta)) {
-            st->done = 1;
-            st->status = FVPCG_BREAKDOWN;
-            return;
+    }
+    double tot[NR];
+    if (device_reduce<BS, NR>(acc, partials, &st[0].ticket, blk, g.grid, tot) && threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            if (!act[k]) continue;
+            BiState* sk = &st[k];
+            const int it = sk->iter + 1;
+            sk->iter = it;
+            sk->rr = tot[k];
+            if (sk->half || sqrt(tot[k]) <= sk->tol_abs) {
+                bi_stop(sk, FVPCG_OK);
+                continue;
+            }
+            if (it >= sk->maxit) {
+                bi_stop(sk, FVPCG_NOT_CONVERGED);
+                continue;
+            }
+            const double rho = sk->rho_next;
+            if (rho == 0.0 || !isfinite(rho) || !isfinite(beta[k])) {
+                bi_stop(sk, FVPCG_BREAKDOWN);
+                continue;
+            }
+            sk->rho = rho;
         }
-        st->rho = rho;
     }
 }
 
-// ||b - A x||^2 at exit.
-template <int BS, int WT, typename CI>
+// ||b_k - A x_k||^2 at exit (b and x component-major).
+template <int BS, int WT, typename CI, int NR>
 __global__ __launch_bounds__(BS) void k_bi_true(const CI* __restrict__ col, const double* __restrict__ val,
                                                 const double* __restrict__ d, int n, Geom g,
                                                 const double* __restrict__ b, const double* __restrict__ x,
                                                 BiState* st, double* partials) {
-    double acc[1] = {0.0};
+    double acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
     FV_ROWS(blk) {
-        const double rc = b[c] - row_gather<double, WT, CI>(col, val, n, c, x, d[c] * x[c]);
-        acc[0] += rc * rc;
+        const double dc = d[c];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const double* xk = x + (size_t)k * n;
+            const double rc = b[(size_t)k * n + c] - row_gather<double, WT, CI>(col, val, n, c, xk, dc * xk[c]);
+            acc[k] += rc * rc;
+        }
     }
-    double tot[1];
-    if (device_reduce<BS, 1>(acc, partials, &st->ticket, blk, g.grid, tot) && threadIdx.x == 0)
-        st->true_rr = tot[0];
+    double tot[NR];
+    if (device_reduce<BS, NR>(acc, partials, &st[0].ticket, blk, g.grid, tot) && threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) st[k].true_rr = tot[k];
+    }
 }
 
 void bi_release(BiWork* w) {
@@ -300,18 +458,19 @@ void bi_release(BiWork* w) {
     delete w;
 }
 
-int bi_alloc(BiWork* w, int n) {
+int bi_alloc(BiWork* w, int n, int nr) {
     w->n = n;
+    w->nr = nr;
     int rc;
-    const size_t m = (size_t)n;
+    const size_t m = (size_t)n * nr;
     if ((rc = dev_alloc(&w->r, m, "BiCGSTAB r")) || (rc = dev_alloc(&w->rhat, m, "BiCGSTAB rhat")) ||
         (rc = dev_alloc(&w->p, m, "BiCGSTAB p")) || (rc = dev_alloc(&w->v, m, "BiCGSTAB v")) ||
         (rc = dev_alloc(&w->t, m, "BiCGSTAB t")) ||
-        (rc = dev_alloc(&w->partials, (size_t)5 * kBiMaxGrid, "BiCGSTAB partials")) ||
-        (rc = dev_alloc(&w->st, 1, "BiCGSTAB state")))
+        (rc = dev_alloc(&w->partials, (size_t)5 * kBiMaxRhs * kBiMaxGrid, "BiCGSTAB partials")) ||
+        (rc = dev_alloc(&w->st, kBiMaxRhs, "BiCGSTAB state")))
         return rc;
-    FV_HIP(hipMemset(w->st, 0, sizeof(BiState)));
-    hipError_t e = hipHostMalloc((void**)&w->hst, 3 * sizeof(BiState), hipHostMallocDefault);
+    FV_HIP(hipMemset(w->st, 0, sizeof(BiState) * kBiMaxRhs));
+    hipError_t e = hipHostMalloc((void**)&w->hst, 3 * kBiMaxRhs * sizeof(BiState), hipHostMallocDefault);
     if (e != hipSuccess) {
         w->hst = nullptr;
         return set_error(FVPCG_OUT_OF_MEMORY, "pinned host allocation failed: %s", hipGetErrorString(e));
@@ -324,15 +483,17 @@ int bi_alloc(BiWork* w, int n) {
     return FVPCG_OK;
 }
 
-// The matrix's BiCGSTAB workspace, allocated on first use (all or nothing).
-int bi_work(BiWork*& w, int n) {
-    if (w) return FVPCG_OK;
+// The matrix's BiCGSTAB workspace for nr components, allocated on first use
+// and again when more components are asked for (all or nothing).
+int bi_work(BiWork*& w, int n, int nr) {
+    if (w && w->nr >= nr) return FVPCG_OK;
     BiWork* nw = new BiWork();
-    const int rc = bi_alloc(nw, n);
+    const int rc = bi_alloc(nw, n, nr);
     if (rc) {
         bi_release(nw);
         return rc;
     }
+    bi_release(w);
     w = nw;
     return FVPCG_OK;
 }
@@ -346,11 +507,117 @@ float bi_elapsed(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
-int bi_state_read(BiWork& w, int slot, BiState* out, hipStream_t s) {
-    FV_HIP(hipMemcpyAsync(&w.hst[slot], w.st, sizeof(BiState), hipMemcpyDeviceToHost, s));
+// The nr states into pinned slot `slot`, waited for.
+int bi_state_read(BiWork& w, int slot, int nr, hipStream_t s) {
+    FV_HIP(hipMemcpyAsync(&w.hst[slot * kBiMaxRhs], w.st, nr * sizeof(BiState), hipMemcpyDeviceToHost, s));
     FV_HIP(hipStreamSynchronize(s));
-    *out = w.hst[slot];
     return FVPCG_OK;
+}
+
+bool bi_all_done(const BiState* h, int nr) {
+    for (int k = 0; k < nr; ++k)
+        if (!h[k].done) return false;
+    return true;
+}
+
+template <int NR>
+int bi_solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int maxit, bool jac, hipStream_t s,
+             fvpcg_stats* stats) {
+    const fvpcg_mesh* m = A->mesh;
+    const int n = m->n;
+    BiWork& w = *A->bi;
+    const Geom g = bi_geom(n);
+    BiState* st = w.st;
+    double* part = w.partials;
+    const double* val = jac ? A->val_cs : A->val;
+
+    FV_HIP(hipEventRecord(w.t_begin, s));
+    BiState* h0 = &w.hst[2 * kBiMaxRhs];
+    for (int k = 0; k < NR; ++k) {
+        h0[k] = BiState();
+        h0[k].tol_abs = tol;
+        h0[k].maxit = maxit;
+        h0[k].status = FVPCG_NOT_CONVERGED;
+    }
+    FV_HIP(hipMemcpyAsync(st, h0, NR * sizeof(BiState), hipMemcpyHostToDevice, s));
+    FV_LAYOUT(m, hipLaunchKernelGGL((k_bi_init<kBsBi, W_, CI_, NR>), dim3(g.grid), dim3(kBsBi), 0, s, cols_, A->val,
+                                    A->d, n, g, b, x, w.r, w.rhat, w.p, st, part));
+    FV_LAUNCHED();
+    int rc;
+    if ((rc = bi_state_read(w, 0, NR, s))) return rc;
+    const BiState* h = &w.hst[0];
+    for (int k = 0; k < NR; ++k)
+        if (h[k].zero_b) FV_HIP(hipMemsetAsync(x + (size_t)k * n, 0, sizeof(double) * (size_t)n, s));
+    FV_HIP(hipEventRecord(w.t_it0, s));
+    if (!bi_all_done(h, NR)) {
+        // Iterations are enqueued in growing chunks; after each chunk the
+        // states are copied to pinned memory, and the previous chunk's copy
+        // is inspected while the current one runs.  Kernels enqueued after
+        // every component has stopped return at once.
+        int launched = 0, chunk = 2, pending = -1, slot = 0;
+        while (launched < maxit) {
+            const int cnt = chunk < maxit - launched ? chunk : maxit - launched;
+            for (int i = 0; i < cnt; ++i) {
+                FV_LAYOUT(m,
+                          if (jac) {
+                              hipLaunchKernelGGL((k_bi_pv<kBsBi, W_, CI_, true, NR>), dim3(g.grid), dim3(kBsBi), 0, s,
+                                                 cols_, val, A->d, n, g, w.p, w.rhat, w.v, st, part);
+                              hipLaunchKernelGGL((k_bi_st<kBsBi, W_, CI_, true, NR>), dim3(g.grid), dim3(kBsBi), 0, s,
+                                                 cols_, val, A->d, n, g, w.r, w.v, w.rhat, w.t, st, part);
+                          } else {
+                              hipLaunchKernelGGL((k_bi_pv<kBsBi, W_, CI_, false, NR>), dim3(g.grid), dim3(kBsBi), 0,
+                                                 s, cols_, val, A->d, n, g, w.p, w.rhat, w.v, st, part);
+                              hipLaunchKernelGGL((k_bi_st<kBsBi, W_, CI_, false, NR>), dim3(g.grid), dim3(kBsBi), 0,
+                                                 s, cols_, val, A->d, n, g, w.r, w.v, w.rhat, w.t, st, part);
+                          });
+                if (jac)
+                    hipLaunchKernelGGL((k_bi_update<kBsBi, true, NR>), dim3(g.grid), dim3(kBsBi), 0, s, x, w.r, w.p,
+                                       w.v, w.t, A->d, n, g, st, part);
+                else
+                    hipLaunchKernelGGL((k_bi_update<kBsBi, false, NR>), dim3(g.grid), dim3(kBsBi), 0, s, x, w.r, w.p,
+                                       w.v, w.t, A->d, n, g, st, part);
+            }
+            FV_LAUNCHED();
+            launched += cnt;
+            FV_HIP(hipMemcpyAsync(&w.hst[slot * kBiMaxRhs], st, NR * sizeof(BiState), hipMemcpyDeviceToHost, s));
+            FV_HIP(hipEventRecord(w.ev[slot], s));
+            if (pending >= 0) {
+                FV_HIP(hipEventSynchronize(w.ev[pending]));
+                if (bi_all_done(&w.hst[pending * kBiMaxRhs], NR)) break;
+            }
+            pending = slot;
+            slot ^= 1;
+            if (chunk < kMaxChunk) chunk *= 2;
+        }
+    }
+    FV_HIP(hipEventRecord(w.t_it1, s));
+    FV_LAYOUT(m, hipLaunchKernelGGL((k_bi_true<kBsBi, W_, CI_, NR>), dim3(g.grid), dim3(kBsBi), 0, s, cols_, A->val,
+                                    A->d, n, g, b, x, st, part));
+    FV_LAUNCHED();
+    FV_HIP(hipEventRecord(w.t_end, s));
+    if ((rc = bi_state_read(w, 0, NR, s))) return rc;
+    h = &w.hst[0];
+    const float dev_ms = bi_elapsed(w.t_begin, w.t_end), it_ms = bi_elapsed(w.t_it0, w.t_it1);
+    int worst = FVPCG_OK;
+    for (int k = 0; k < NR; ++k) {
+        if (stats) {
+            fvpcg_stats* sk = &stats[k];
+            sk->iters = h[k].iter;
+            sk->outer_iters = 0;
+            sk->status = h[k].status;
+            sk->b_norm = h[k].bnorm;
+            sk->r0_norm = h[k].r0norm;
+            sk->rel_res = h[k].bnorm > 0 ? sqrt(h[k].rr) / h[k].bnorm : 0.0;
+            sk->true_rel_res = h[k].bnorm > 0 ? sqrt(h[k].true_rr) / h[k].bnorm : 0.0;
+            sk->device_ms = dev_ms;
+            sk->iter_ms = it_ms;
+        }
+        if (h[k].status == FVPCG_BREAKDOWN)
+            worst = FVPCG_BREAKDOWN;
+        else if (h[k].status == FVPCG_NOT_CONVERGED && worst == FVPCG_OK)
+            worst = FVPCG_NOT_CONVERGED;
+    }
+    return worst;
 }
 
 }  // namespace
@@ -360,93 +627,22 @@ void bicgstab_free(fvpcg_matrix* A) {
     A->bi = nullptr;
 }
 
+int solve_bicgstab_multi(const fvpcg_matrix* A, int nrhs, const double* b, double* x, double tol, int maxit,
+                         int precond, hipStream_t s, fvpcg_stats* stats) {
+    int rc;
+    if ((rc = bi_work(A->bi, A->mesh->n, nrhs))) return rc;
+    const bool jac = precond == FVPCG_PRECOND_JACOBI;
+    switch (nrhs) {
+        case 1: return bi_solve<1>(A, b, x, tol, maxit, jac, s, stats);
+        case 2: return bi_solve<2>(A, b, x, tol, maxit, jac, s, stats);
+        case 3: return bi_solve<3>(A, b, x, tol, maxit, jac, s, stats);
+        default: return bi_solve<4>(A, b, x, tol, maxit, jac, s, stats);
+    }
+}
+
 int solve_bicgstab(const fvpcg_matrix* A, const double* b, double* x, double tol, int maxit, int precond,
                    hipStream_t s, fvpcg_stats* stats) {
-    const fvpcg_mesh* m = A->mesh;
-    const int n = m->n;
-    const bool jac = precond == FVPCG_PRECOND_JACOBI;
-    int rc;
-    if ((rc = bi_work(A->bi, n))) return rc;
-    BiWork& w = *A->bi;
-    const Geom g = bi_geom(n);
-    BiState* st = w.st;
-    double* part = w.partials;
-    const double* val = jac ? A->val_cs : A->val;
-
-    FV_HIP(hipEventRecord(w.t_begin, s));
-    BiState* h0 = &w.hst[2];
-    *h0 = BiState();
-    h0->tol_abs = tol;
-    h0->maxit = maxit;
-    h0->status = FVPCG_NOT_CONVERGED;
-    FV_HIP(hipMemcpyAsync(st, h0, sizeof(BiState), hipMemcpyHostToDevice, s));
-    FV_LAYOUT(m, hipLaunchKernelGGL((k_bi_init<kBsBi, W_, CI_>), dim3(g.grid), dim3(kBsBi), 0, s, cols_, A->val, A->d,
-                                    n, g, b, x, w.r, w.rhat, w.p, st, part));
-    FV_LAUNCHED();
-    BiState h;
-    if ((rc = bi_state_read(w, 0, &h, s))) return rc;
-    FV_HIP(hipEventRecord(w.t_it0, s));
-    if (h.zero_b) {
-        FV_HIP(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
-    } else if (!h.done) {
-        // Iterations are enqueued in growing chunks; after each chunk the
-        // state is copied to pinned memory, and the previous chunk's copy is
-        // inspected while the current one runs.  Kernels enqueued after the
-        // exit return at once.
-        int launched = 0, chunk = 2, pending = -1, slot = 0;
-        while (launched < maxit) {
-            const int cnt = chunk < maxit - launched ? chunk : maxit - launched;
-            for (int i = 0; i < cnt; ++i) {
-                FV_LAYOUT(m,
-                          if (jac) {
-                              hipLaunchKernelGGL((k_bi_pv<kBsBi, W_, CI_, true>), dim3(g.grid), dim3(kBsBi), 0, s,
-                                                 cols_, val, A->d, n, g, w.p, w.rhat, w.v, st, part);
-                              hipLaunchKernelGGL((k_bi_st<kBsBi, W_, CI_, true>), dim3(g.grid), dim3(kBsBi), 0, s,
-                                                 cols_, val, A->d, n, g, w.r, w.v, w.rhat, w.t, st, part);
-                          } else {
-                              hipLaunchKernelGGL((k_bi_pv<kBsBi, W_, CI_, false>), dim3(g.grid), dim3(kBsBi), 0, s,
-                                                 cols_, val, A->d, n, g, w.p, w.rhat, w.v, st, part);
-                              hipLaunchKernelGGL((k_bi_st<kBsBi, W_, CI_, false>), dim3(g.grid), dim3(kBsBi), 0, s,
-                                                 cols_, val, A->d, n, g, w.r, w.v, w.rhat, w.t, st, part);
-                          });
-                if (jac)
-                    hipLaunchKernelGGL((k_bi_update<kBsBi, true>), dim3(g.grid), dim3(kBsBi), 0, s, x, w.r, w.p, w.v,
-                                       w.t, A->d, n, g, st, part);
-                else
-                    hipLaunchKernelGGL((k_bi_update<kBsBi, false>), dim3(g.grid), dim3(kBsBi), 0, s, x, w.r, w.p, w.v,
-                                       w.t, A->d, n, g, st, part);
-            }
-            FV_LAUNCHED();
-            launched += cnt;
-            FV_HIP(hipMemcpyAsync(&w.hst[slot], st, sizeof(BiState), hipMemcpyDeviceToHost, s));
-            FV_HIP(hipEventRecord(w.ev[slot], s));
-            if (pending >= 0) {
-                FV_HIP(hipEventSynchronize(w.ev[pending]));
-                if (w.hst[pending].done) break;
-            }
-            pending = slot;
-            slot ^= 1;
-            if (chunk < kMaxChunk) chunk *= 2;
-        }
-    }
-    FV_HIP(hipEventRecord(w.t_it1, s));
-    FV_LAYOUT(m, hipLaunchKernelGGL((k_bi_true<kBsBi, W_, CI_>), dim3(g.grid), dim3(kBsBi), 0, s, cols_, A->val, A->d,
-                                    n, g, b, x, st, part));
-    FV_LAUNCHED();
-    FV_HIP(hipEventRecord(w.t_end, s));
-    if ((rc = bi_state_read(w, 0, &h, s))) return rc;
-    if (stats) {
-        stats->iters = h.iter;
-        stats->outer_iters = 0;
-        stats->status = h.status;
-        stats->b_norm = h.bnorm;
-        stats->r0_norm = h.r0norm;
-        stats->rel_res = h.bnorm > 0 ? sqrt(h.rr) / h.bnorm : 0.0;
-        stats->true_rel_res = h.bnorm > 0 ? sqrt(h.true_rr) / h.bnorm : 0.0;
-        stats->device_ms = bi_elapsed(w.t_begin, w.t_end);
-        stats->iter_ms = bi_elapsed(w.t_it0, w.t_it1);
-    }
-    return h.status;
+    return solve_bicgstab_multi(A, 1, b, x, tol, maxit, precond, s, stats);
 }
 
 }  // namespace fvpcg

@@ -35,9 +35,9 @@ def test_header_declares_the_boundary():
     for n in ["fvpcg_mesh_create", "fvpcg_matrix_create", "fvpcg_solve", "fvpcg_solve_mixed",
               "fvpcg_solve_mixed_reliable", "fvpcg_solve_batched",
               "fvpcg_solve_backward", "fvpcg_spmv", "fvpcg_stream_calibrate", "fvpcg_last_error",
-              "fvpcg_solve_bicgstab"]:
+              "fvpcg_solve_bicgstab", "fvpcg_solve_bicgstab_multi"]:
         assert n in names
-    assert len(names) == 27
+    assert len(names) == 28
 
 
 def test_library_exports_every_declared_symbol(lib_path):

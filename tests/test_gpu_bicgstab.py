@@ -1,7 +1,8 @@
-"""BiCGSTAB on the GPU (fvpcg_solve_bicgstab) against the oracle's
-(oracle/bicgstab.c) on the non-symmetric momentum systems: the iterate after
-a fixed number of iterations, solves to tolerance, the hand-worked 2x2 case,
-the half-step exit, determinism, edge cases and the 192^3 workload."""
+"""BiCGSTAB on the GPU (fvpcg_solve_bicgstab, fvpcg_solve_bicgstab_multi)
+against the oracle's (oracle/bicgstab.c) on the non-symmetric momentum
+systems: the iterate after a fixed number of iterations, solves to
+tolerance, the hand-worked 2x2 case, the half-step exit, determinism, edge
+cases, several right-hand sides solved together, and the 192^3 workload."""
 import json
 import os
 from fractions import Fraction
@@ -176,6 +177,80 @@ def test_edges(fv, orc):
     mesh.close()
 
 
+def _rhs3(case):
+    return np.stack([case.b, fc.momentum_rhs(case, 1), fc.momentum_rhs(case, 2)])
+
+
+def test_multi_matches_single_and_oracle(fv, orc):
+    """Three components solved together to 1e-12: each with the iteration
+    count of its own single solve and within 1e-12 of it, and within 1e-9 of
+    the oracle's solution."""
+    say("bicgstab multi vs single")
+    case = fc.momentum((24, 20, 18), permute=True)
+    dc = DevCase(case, symmetric=False)
+    B = _rhs3(case)
+    X, sts = fv.solve_bicgstab_multi(dc.A, to_dev(B), tol=1e-12, maxit=2000)
+    for k in range(3):
+        xs, ss = fv.solve_bicgstab(dc.A, to_dev(B[k]), tol=1e-12, maxit=2000)
+        xo, so = orc.bicgstab(case, B[k], tol=1e-12, maxit=2000)
+        assert sts[k]["status_name"] == "OK"
+        assert sts[k]["iters"] == ss["iters"]
+        assert rel(X[k].cpu().numpy(), xs.cpu().numpy()) <= 1e-12
+        assert rel(X[k].cpu().numpy(), xo) <= 1e-9
+        assert abs(sts[k]["iters"] - so["iters"]) <= 2
+    dc.close()
+
+
+def test_multi_fixed_iterations_vs_oracle(fv, orc):
+    say("bicgstab multi fixed iterations")
+    case = fc.momentum((17, 13, 11), permute=True)
+    dc = DevCase(case, symmetric=False)
+    B = _rhs3(case)[:2]
+    for precond in ("jacobi", "none"):
+        X, sts = fv.solve_bicgstab_multi(dc.A, to_dev(B), tol=0.0, maxit=3, precond=precond)
+        for k in range(2):
+            xo, so = orc.bicgstab(case, B[k], tol=0.0, maxit=3, precond=precond)
+            assert sts[k]["iters"] == 3 and sts[k]["status_name"] == "NOT_CONVERGED"
+            assert rel(X[k].cpu().numpy(), xo) <= 1e-12
+    dc.close()
+
+
+def test_multi_components_stop_independently(fv, orc):
+    """Four components: a zero right-hand side (x = 0 at once), an exact
+    initial guess (no iteration, x untouched) and two that iterate; then a
+    maxit that stops every component."""
+    import torch
+
+    say("bicgstab multi independent stops")
+    case = fc.momentum((14, 12, 10), permute=True)
+    dc = DevCase(case, symmetric=False)
+    R3 = _rhs3(case)
+    xs, _ = orc.bicgstab(case, R3[1], tol=1e-15, maxit=1000)
+    B = np.stack([R3[0], np.zeros(case.n), R3[1], R3[2]])
+    X0 = np.stack([np.zeros(case.n), np.ones(case.n), xs, np.zeros(case.n)])
+    X = to_dev(X0)
+    X, sts = fv.solve_bicgstab_multi(dc.A, to_dev(B), x=X, tol=1e-10, maxit=1000)
+    assert [s["status_name"] for s in sts] == ["OK"] * 4
+    assert sts[1]["iters"] == 0 and not X[1].any()
+    assert sts[2]["iters"] == 0 and torch.equal(X[2], to_dev(xs))
+    for k in (0, 3):
+        x1, s1 = fv.solve_bicgstab(dc.A, to_dev(B[k]), tol=1e-10, maxit=1000)
+        assert sts[k]["iters"] == s1["iters"] > 0
+        assert rel(X[k].cpu().numpy(), x1.cpu().numpy()) <= 1e-12
+    X, sts = fv.solve_bicgstab_multi(dc.A, to_dev(R3), tol=1e-14, maxit=4)
+    assert [s["iters"] for s in sts] == [4, 4, 4]
+    assert all(s["status_name"] == "NOT_CONVERGED" for s in sts)
+    # nrhs outside 1..4 is refused at the C boundary
+    import ctypes
+
+    xx = torch.zeros(5 * case.n, dtype=torch.float64, device="cuda")
+    bb = torch.ones(5 * case.n, dtype=torch.float64, device="cuda")
+    code = fv.lib().fvpcg_solve_bicgstab_multi(dc.A.handle, 5, ctypes.c_void_p(bb.data_ptr()),
+                                               ctypes.c_void_p(xx.data_ptr()), 1e-8, 100, 1, None, None)
+    assert code == -1 and b"nrhs" in fv.lib().fvpcg_last_error()
+    dc.close()
+
+
 @pytest.fixture(scope="module")
 def momentum192():
     say("generating momentum192")
@@ -198,4 +273,13 @@ def test_momentum192(fv, orc, momentum192):
     assert st["status_name"] == "OK"
     r = case.b - orc.spmv(case, x.cpu().numpy())
     assert np.linalg.norm(r) / np.linalg.norm(case.b) <= case.tol * 1.01
+    say("momentum192 three components")
+    B = _rhs3(case)
+    X, sts = fv.solve_bicgstab_multi(dc.A, to_dev(B), tol=case.tol, maxit=5000)
+    assert sts[0]["iters"] == st["iters"]
+    assert rel(X[0].cpu().numpy(), x.cpu().numpy()) <= 1e-12
+    for k in range(3):
+        assert sts[k]["status_name"] == "OK"
+        r = B[k] - orc.spmv(case, X[k].cpu().numpy())
+        assert np.linalg.norm(r) / np.linalg.norm(B[k]) <= case.tol * 1.01
     dc.close()
