@@ -431,7 +431,7 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None,
                       key=lambda t: t[0]["device_ms"])[1]
         _, fx3 = fv.solve_bicgstab_multi(Am, B3, tol=0.0, maxit=40)
         us3 = fx3[0]["iter_ms"] * 1e3 / 40
-        alg3 = 3 * 128 * c.n + 48 * c.F
+        alg3 = (120 * 3 + 8) * c.n + 48 * c.F  # d and the matrix read once for the three
         res["momentum192/bicgstab_3_components"] = {
             "status": [t["status_name"] for t in mult], "iters": [t["iters"] for t in mult],
             "ms_together": round(mult[0]["device_ms"], 2), "ms_one_after_another": round(sorted(seq)[1], 2),

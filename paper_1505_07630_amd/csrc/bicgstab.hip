@@ -31,7 +31,7 @@
 // templated on the count NR, every vector is stored component after
 // component (each component's streams stay unit-stride), each component
 // keeps its own scalars and stopping test, and the matrix slots of a row are
-// loaded once for all of them: 128 NR n + 48 F bytes per iteration.  A
+// loaded once for all of them: (120 NR + 8) n + 48 F bytes per iteration.  A
 // component that has stopped is skipped (no loads, no stores) while the
 // others go on, so every component's iterates are those of its own single
 // solve.
