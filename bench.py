@@ -120,8 +120,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=150)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time the other workloads")
-    ap.add_argument("--extras-select", default="mixed,batched,amg,transient,momentum,small",
-                    help="comma-separated groups of extras: mixed, batched, amg, transient, momentum, small")
+    ap.add_argument("--extras-select", default="mixed,batched,amg,transient,momentum,share,small",
+                    help="comma-separated groups of extras: mixed, batched, amg, transient, momentum, share, small")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU: the library solves on one device "
@@ -232,7 +232,7 @@ def main():
 
 
 def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None,
-           groups=("mixed", "batched", "amg", "transient", "momentum", "small")):
+           groups=("mixed", "batched", "amg", "transient", "momentum", "share", "small")):
     """Other workloads, for information (not the headline line)."""
     res = {}
     to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).to(dev)
@@ -441,6 +441,24 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None,
         log(f"extra momentum192 3 components: {res['momentum192/bicgstab_3_components']}")
         Am.close()
         mm.close()
+    if "share" in groups:
+        # one GPU's share of the 192^3 lognormal system cut into 8 slabs
+        # (192 x 192 x 24, same recipe, permuted + RCM): the per-iteration time
+        # of the fused pipelined kernel at the size each GPU would iterate on
+        c = fvcases.varcoef((192, 192, 24), permute=True, name="varcoef192_share8")
+        ms_ = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
+        As = fv.Matrix(ms_, to(c.diag, torch.float64), to(c.upper, torch.float64))
+        bs = to(c.b, torch.float64)
+        fv.solve(As, bs, tol=0.0, maxit=200, method="pipecg")
+        us = sorted(fv.solve(As, bs, tol=0.0, maxit=200, method="pipecg")[1]["iter_ms"] * 1e3 / 200
+                    for _ in range(5))[2]
+        alg = 96 * c.n + 24 * c.F
+        res["varcoef192_share8/pipecg_per_iteration"] = {
+            "n_cells": c.n, "us_per_iter": round(us, 2), "alg_bytes_per_iter": alg,
+            "alg_gbs": round(alg / (us * 1e-6) / 1e9, 1)}
+        log(f"extra share8: {res['varcoef192_share8/pipecg_per_iteration']}")
+        As.close()
+        ms_.close()
     if "small" in groups:
         # small and graded cases: one warm-up solve, then repeated solves timed one
         # by one with HIP events on the solve stream (median reported), and

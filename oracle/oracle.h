@@ -39,7 +39,8 @@ void or_spmv(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
              const double* diag, const double* upper, const double* lower,
              const double* v, double* y);
 
-/* Plain sequential sum of a[i]*b[i]. */
+/* Sum of a[i]*b[i], pairwise (halves summed recursively, blocks of <= 8
+ * sequentially). */
 double or_dot(int32_t n, const double* a, const double* b);
 
 /* Preconditioned CG, standard form (three inner products per iteration,
