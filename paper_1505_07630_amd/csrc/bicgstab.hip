@@ -32,9 +32,10 @@
 // component (each component's streams stay unit-stride), each component
 // keeps its own scalars and stopping test, and the matrix slots of a row are
 // loaded once for all of them: (120 NR + 8) n + 48 F bytes per iteration.  A
-// component that has stopped is skipped (no loads, no stores) while the
-// others go on, so every component's iterates are those of its own single
-// solve.
+// component that has stopped is left untouched while the others go on: its
+// values are still loaded (every load of a row is issued before the
+// arithmetic), but nothing is computed into its sums or stored for it.  So
+// every component's iterates are those of its own single solve.
 #include "handles.hpp"
 #include "rows.hpp"
 

@@ -46,8 +46,10 @@ def _small(fv, n, owner, nb, diag, upper, lower):
     return mesh, A
 
 
+# (200, 200, 2) in natural order has bandwidth 40,000 > 32,767: the int32
+# column layout instead of int16 offsets.
 @pytest.mark.parametrize("shape,permute,precond", [((17, 13, 11), False, "jacobi"), ((24, 20, 18), True, "jacobi"),
-                                                   ((24, 20, 18), True, "none")])
+                                                   ((24, 20, 18), True, "none"), ((200, 200, 2), False, "jacobi")])
 def test_fixed_iterations_match_oracle(fv, orc, shape, permute, precond):
     """Three iterations (tol = 0): the iterate within 1e-12 of the oracle's
     (only the summation order of the inner products differs)."""
@@ -63,7 +65,8 @@ def test_fixed_iterations_match_oracle(fv, orc, shape, permute, precond):
 
 
 @pytest.mark.parametrize("shape,permute,precond", [((17, 13, 11), False, "jacobi"), ((40, 36, 30), True, "jacobi"),
-                                                   ((40, 36, 30), True, "none"), ((9, 70, 5), True, "jacobi")])
+                                                   ((40, 36, 30), True, "none"), ((9, 70, 5), True, "jacobi"),
+                                                   ((200, 200, 2), False, "jacobi")])
 def test_solve_matches_oracle(fv, orc, shape, permute, precond):
     """To 1e-12: status OK, iterations within 2 of the oracle's, the solution
     within 1e-9 of the oracle's (both are within tol * cond(A D^-1) ~ 1e-10
@@ -201,9 +204,10 @@ def test_multi_matches_single_and_oracle(fv, orc):
     dc.close()
 
 
-def test_multi_fixed_iterations_vs_oracle(fv, orc):
-    say("bicgstab multi fixed iterations")
-    case = fc.momentum((17, 13, 11), permute=True)
+@pytest.mark.parametrize("shape,permute", [((17, 13, 11), True), ((200, 200, 2), False)])
+def test_multi_fixed_iterations_vs_oracle(fv, orc, shape, permute):
+    say("bicgstab multi fixed iterations", shape)
+    case = fc.momentum(shape, permute=permute)
     dc = DevCase(case, symmetric=False)
     B = _rhs3(case)[:2]
     for precond in ("jacobi", "none"):
