@@ -25,8 +25,10 @@
 // the column-scaled values), coarser levels CSR, one row per thread.  The
 // cycle is symmetric positive definite, so standard CG can use it as M^-1.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "handles.hpp"
@@ -106,36 +108,88 @@ Csr transpose(const Csr& A) {
     return T;
 }
 
+// f(t, begin, end) on T contiguous parts of [0, n), one host thread each
+// (up to 16).  Each output element is still computed by one thread in its
+// sequential order, so results do not depend on T.  False if a part failed
+// (an allocation inside it), which the caller reports.
+template <typename F>
+bool parallel_parts(int n, int min_part, F&& f) {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int T = std::max(1, std::min({(int)std::min(hw, 16u), n / std::max(min_part, 1), n}));
+    std::atomic<bool> ok{true};
+    auto run = [&](int t) {
+        const int b = (int)((long long)n * t / T), e = (int)((long long)n * (t + 1) / T);
+        try {
+            f(t, b, e);
+        } catch (...) {
+            ok = false;
+        }
+    };
+    if (T == 1) {
+        run(0);
+        return ok;
+    }
+    std::vector<std::thread> th;
+    th.reserve((size_t)T - 1);
+    try {
+        for (int t = 1; t < T; ++t) th.emplace_back(run, t);
+    } catch (...) {
+        ok = false;
+    }
+    run(0);
+    for (auto& x : th) x.join();
+    return ok;
+}
+
 // C = X Y, row by row: products summed in the order of X's columns and then
-// Y's columns into a dense accumulator; columns sorted.
+// Y's columns into a dense accumulator; columns sorted.  Rows are split over
+// host threads (each with its own accumulator) and concatenated in order.
+// Throws std::bad_alloc if a part runs out of memory.
 Csr multiply(const Csr& X, const Csr& Y) {
     Csr C;
     C.n = X.n;
     C.m = Y.m;
     C.ptr.assign((size_t)C.n + 1, 0);
-    std::vector<double> acc((size_t)std::max(Y.m, 1), 0.0);
-    std::vector<int> mark((size_t)std::max(Y.m, 1), -1), touched;
-    for (int i = 0; i < X.n; ++i) {
-        touched.clear();
-        for (int a = X.ptr[i]; a < X.ptr[(size_t)i + 1]; ++a) {
-            const int j = X.col[a];
-            const double xv = X.val[a];
-            for (int b = Y.ptr[j]; b < Y.ptr[(size_t)j + 1]; ++b) {
-                const int k = Y.col[b];
-                if (mark[k] != i) {
-                    mark[k] = i;
-                    acc[k] = 0.0;
-                    touched.push_back(k);
+    struct Part {
+        std::vector<int> col;
+        std::vector<double> val;
+    };
+    std::vector<Part> parts(16);
+    std::vector<int> len((size_t)std::max(X.n, 1), 0);
+    const bool ok = parallel_parts(X.n, 4096, [&](int t, int r0, int r1) {
+        Part& out = parts[(size_t)t];
+        std::vector<double> acc((size_t)std::max(Y.m, 1), 0.0);
+        std::vector<int> mark((size_t)std::max(Y.m, 1), -1), touched;
+        for (int i = r0; i < r1; ++i) {
+            touched.clear();
+            for (int a = X.ptr[i]; a < X.ptr[(size_t)i + 1]; ++a) {
+                const int j = X.col[a];
+                const double xv = X.val[a];
+                for (int b = Y.ptr[j]; b < Y.ptr[(size_t)j + 1]; ++b) {
+                    const int k = Y.col[b];
+                    if (mark[k] != i) {
+                        mark[k] = i;
+                        acc[k] = 0.0;
+                        touched.push_back(k);
+                    }
+                    acc[k] += xv * Y.val[b];
                 }
-                acc[k] += xv * Y.val[b];
             }
+            std::sort(touched.begin(), touched.end());
+            for (int k : touched) {
+                out.col.push_back(k);
+                out.val.push_back(acc[k]);
+            }
+            len[(size_t)i] = (int)touched.size();
         }
-        std::sort(touched.begin(), touched.end());
-        for (int k : touched) {
-            C.col.push_back(k);
-            C.val.push_back(acc[k]);
-        }
-        C.ptr[(size_t)i + 1] = (int)C.col.size();
+    });
+    if (!ok) throw std::bad_alloc();
+    for (int i = 0; i < X.n; ++i) C.ptr[(size_t)i + 1] = C.ptr[i] + len[(size_t)i];
+    C.col.reserve((size_t)C.ptr[C.n]);
+    C.val.reserve((size_t)C.ptr[C.n]);
+    for (const Part& q : parts) {
+        C.col.insert(C.col.end(), q.col.begin(), q.col.end());
+        C.val.insert(C.val.end(), q.val.begin(), q.val.end());
     }
     return C;
 }
@@ -234,20 +288,24 @@ bool spd_inverse(const Csr& A, std::vector<double>& inv) {
         }
     }
     inv.assign((size_t)n * n, 0.0);
-    std::vector<double> e((size_t)n);
-    for (int c = 0; c < n; ++c) {  // column c of A^-1: L L^T v = e_c
-        for (int i = 0; i < n; ++i) {
-            double s = i == c ? 1.0 : 0.0;
-            for (int k = 0; k < i; ++k) s -= L[(size_t)i * n + k] * e[k];
-            e[i] = s / L[(size_t)i * n + i];
+    // column c of A^-1: L L^T v = e_c; the columns are independent
+    const bool ok = parallel_parts(n, 32, [&](int, int c0, int c1) {
+        std::vector<double> e((size_t)n);
+        for (int c = c0; c < c1; ++c) {
+            for (int i = 0; i < n; ++i) {
+                double s = i == c ? 1.0 : 0.0;
+                for (int k = 0; k < i; ++k) s -= L[(size_t)i * n + k] * e[k];
+                e[i] = s / L[(size_t)i * n + i];
+            }
+            for (int i = n - 1; i >= 0; --i) {
+                double s = e[i];
+                for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * e[k];
+                e[i] = s / L[(size_t)i * n + i];
+            }
+            for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = e[i];
         }
-        for (int i = n - 1; i >= 0; --i) {
-            double s = e[i];
-            for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * e[k];
-            e[i] = s / L[(size_t)i * n + i];
-        }
-        for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = e[i];
-    }
+    });
+    if (!ok) throw std::bad_alloc();
     return true;
 }
 
@@ -860,15 +918,30 @@ void amg_free(fvpcg_amg* h) {
     delete h;
 }
 
+int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, hipStream_t s);
+
 int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, hipStream_t s,
                fvpcg_amg** out) {
     fvpcg_amg* h = new (std::nothrow) fvpcg_amg();
     if (!h) return set_error(FVPCG_OUT_OF_MEMORY, "host allocation failed");
     h->mat = A;
-    auto fail = [&](int rc) {
+    int rc;
+    try {
+        rc = amg_build(h, A, theta, max_levels, coarse_size, s);
+    } catch (const std::bad_alloc&) {
+        rc = set_error(FVPCG_OUT_OF_MEMORY, "host allocation failed during the AMG setup");
+    }
+    if (rc) {
         amg_free(h);
         return rc;
-    };
+    }
+    *out = h;
+    return FVPCG_OK;
+}
+
+// The hierarchy into h (freed by the caller on failure).
+int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, hipStream_t s) {
+    auto fail = [](int rc) { return rc; };
     int rc;
     Csr cur;
     if ((rc = level0_from_device(A, s, cur))) return fail(rc);
@@ -940,7 +1013,6 @@ int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_s
     hipEvent_t* evs[] = {&h->t_begin, &h->t_end, &h->t_it0, &h->t_it1};
     for (hipEvent_t* e : evs) FV_HIP(hipEventCreate(e));
     FV_HIP(hipStreamSynchronize(s));
-    *out = h;
     return FVPCG_OK;
 }
 
