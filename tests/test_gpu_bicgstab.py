@@ -255,6 +255,26 @@ def test_multi_components_stop_independently(fv, orc):
     dc.close()
 
 
+def test_multi_breakdown_is_confined(fv):
+    """[[0, 1, 0], [-1, 0, 0], [0, 0, 1]]: b = e1 breaks down at once
+    ((r, A r) = 0 on the skew block), b = e3 converges in one half step to
+    x = e3.  Solved together, the call reports the breakdown, the first
+    component's x stays at x0 and the second is exact."""
+    import torch
+
+    say("bicgstab multi breakdown")
+    mesh, A = _small(fv, 3, [0], [1], [0.0, 0.0, 1.0], [1.0], [-1.0])
+    B = to_dev(np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 1.0]]))
+    X = torch.zeros_like(B)
+    with pytest.raises(fv.FVPCGError) as e:
+        fv.solve_bicgstab_multi(A, B, x=X, tol=1e-12, precond="none")
+    assert e.value.code == -3
+    assert not X[0].any()
+    assert torch.equal(X[1], to_dev(np.array([0.0, 0.0, 1.0])))
+    A.close()
+    mesh.close()
+
+
 @pytest.fixture(scope="module")
 def momentum192():
     say("generating momentum192")
