@@ -87,6 +87,31 @@ def test_solve_matches_oracle(fv, orc, shape, permute, precond):
     dc.close()
 
 
+def test_warm_start_matches_oracle(fv, orc):
+    """From a non-zero x0 (the solution perturbed), single and two-component
+    solves: three fixed iterations within 1e-12 of the oracle's from the same
+    x0, and solves to 1e-12 within 1e-9."""
+    import torch
+
+    say("bicgstab warm start")
+    case = fc.momentum((19, 17, 13), permute=True)
+    dc = DevCase(case, symmetric=False)
+    B = _rhs3(case)[:2]
+    g = np.random.default_rng(21)
+    X0 = np.stack([orc.bicgstab(case, B[k], tol=1e-12, maxit=2000)[0] * (1 + 0.1 * g.standard_normal(case.n))
+                   for k in range(2)])
+    x, st = fv.solve_bicgstab(dc.A, to_dev(B[0]), x=to_dev(X0[0]), tol=0.0, maxit=3)
+    xo, _ = orc.bicgstab(case, B[0], x0=X0[0], tol=0.0, maxit=3)
+    assert st["iters"] == 3 and rel(x.cpu().numpy(), xo) <= 1e-12
+    X, sts = fv.solve_bicgstab_multi(dc.A, to_dev(B), x=to_dev(X0), tol=1e-12, maxit=2000)
+    for k in range(2):
+        xo, so = orc.bicgstab(case, B[k], x0=X0[k], tol=1e-12, maxit=2000)
+        assert sts[k]["status_name"] == "OK" and abs(sts[k]["iters"] - so["iters"]) <= 2
+        assert rel(X[k].cpu().numpy(), xo) <= 1e-9
+        assert 0 < sts[k]["r0_norm"] < np.linalg.norm(B[k])  # the warm start is closer than x = 0
+    dc.close()
+
+
 def test_two_by_two_by_hand(fv):
     """The hand-worked 2x2 system (tests/golden): the first iterate, then the
     exact solution after two iterations."""
