@@ -71,7 +71,13 @@ def lib():
         L.or_refine.restype = i32
         L.or_mixed_reliable.argtypes = [i32, i32, P, P, P, P, P, P, P, d, i32, i32, P]
         L.or_mixed_reliable.restype = i32
-        L.or_amg_setup.argtypes = [i32, i32, P, P, P, P, P, d, i32, i32]
+        L.or_amg_setup.argtypes = [i32, i32, P, P, P, P, P, d, i32, i32, ctypes.c_uint64]
+        L.or_amg_aggregate.argtypes = [i32, P, P, P, d, P, ctypes.c_uint64, i32, P]
+        L.or_amg_aggregate.restype = i32
+        L.or_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.or_splitmix64.restype = ctypes.c_uint64
+        L.or_amg_priority.argtypes = [ctypes.c_uint64, i32, i32]
+        L.or_amg_priority.restype = ctypes.c_uint64
         L.or_amg_setup.restype = P
         L.or_amg_free.argtypes = [P]
         L.or_amg_free.restype = None
@@ -223,14 +229,36 @@ def mixed_reliable(A, b, x0=None, tol=1e-10, update_every=20, maxit=100000):
     return x, st.asdict()
 
 
+def splitmix64(seed, k):
+    """Element k of the SplitMix64 sequence started at `seed` (amg.c)."""
+    return int(lib().or_splitmix64(int(seed), int(k)))
+
+
+def amg_priority(seed, level, i):
+    """Aggregation priority of unknown i on `level`: 31 random bits, then i."""
+    return int(lib().or_amg_priority(int(seed), int(level), int(i)))
+
+
+def aggregate(ptr, col, val, theta, key=None, seed=1, level=0):
+    """Distance-2 MIS aggregation of one CSR level: (aggregate per row, count).
+    key: optional explicit priorities (distinct uint64, larger first)."""
+    ptr, col, val = _i32(ptr), _i32(col), _f64(val)
+    n = ptr.size - 1
+    out = np.empty(max(n, 1), dtype=np.int32)
+    kk = None if key is None else np.ascontiguousarray(key, dtype=np.uint64)
+    na = lib().or_amg_aggregate(n, _p(ptr), _p(col), _p(val), float(theta), None if kk is None else _p(kk),
+                                int(seed), int(level), _p(out))
+    return out[:n], na
+
+
 class AMG:
     """Smoothed-aggregation AMG hierarchy built by the oracle (amg.c)."""
 
-    def __init__(self, A, theta=0.08, max_levels=12, coarse_size=64):
+    def __init__(self, A, theta=0.0, max_levels=12, coarse_size=64, seed=1):
         A = _as_sys(A)
         self._sys = A
         self.n = A.n
-        h = lib().or_amg_setup(*A.args(), float(theta), int(max_levels), int(coarse_size))
+        h = lib().or_amg_setup(*A.args(), float(theta), int(max_levels), int(coarse_size), int(seed))
         if not h:
             raise ValueError("AMG setup failed: coarsest level not positive definite")
         self._h = ctypes.c_void_p(h)

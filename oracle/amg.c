@@ -3,24 +3,27 @@
  * INFRASTRUCTURE.
  *
  * The paper compares its Jacobi-preconditioned solvers with aggregation-AMG
- * preconditioned CG and pipelined CG (Section 5, Table pcgs2: 325 -> 28 CG
- * iterations at 64^3).  It does not print the AMG it used; this file is the
- * classical smoothed-aggregation method of Vanek, Mandel and Brezina written
- * from its definition:
- *   strength    j ~ i  iff  j != i and |a_ij| >= theta_l sqrt(a_ii a_jj),
- *               theta_{l+1} = theta_l / 2;
- *   aggregates  three greedy passes in index order: (1) i and all its strong
- *               neighbours, if none is aggregated yet, form an aggregate;
- *               (2) a remaining i joins the pass-1 aggregate of its strongest
- *               strong neighbour (ties: lowest index); (3) what remains forms
- *               aggregates of i and its still-free strong neighbours;
+ * preconditioned CG and pipelined CG (Section 5, Fig. pcgs1 and Table pcgs2:
+ * 325 -> 28 CG iterations at 64^3).  It names the method's parts: a V-cycle
+ * of aggregation-based AMG, aggregates from the parallel distance-2
+ * maximal-independent-set method, and weighted Jacobi with omega = 4/3 as
+ * the smoother.  Written from those definitions:
+ *   strength    j ~ i  iff  j != i, a_ij != 0 and
+ *               |a_ij| >= theta_l sqrt(|a_ii a_jj|), theta_{l+1} = theta_l / 2
+ *               (theta = 0: every coupling is strong);
+ *   aggregates  roots: a distance-2 maximal independent set of the strength
+ *               graph, in the order of seeded SplitMix64 priorities; round 1:
+ *               the roots' neighbours; round 2: the rest join a round-1
+ *               neighbour's aggregate (or_amg_aggregate states the rules);
  *   prolongator P = (I - omega D^-1 A) P_t, P_t the aggregate indicator,
- *               omega = 4 / (3 lambda), lambda = max_i sum_j |a_ij| / a_ii
- *               (Gershgorin bound of rho(D^-1 A));
+ *               omega = (4/3) / lambda, lambda = max_i sum_j |a_ij| / a_ii
+ *               (Gershgorin bound of rho(D^-1 A)): the paper's 4/3 taken
+ *               for the operator scaled to spectral radius 1;
  *   coarse      A_c = P^T A P (Galerkin), R = P^T;
  *   levels      until n <= coarse_size, the level limit, or an aggregation
- *               that keeps more than 60% of the unknowns; the last level is
- *               solved exactly (dense Cholesky);
+ *               that keeps more than 60% of the unknowns; the last level
+ *               (at most OR_AMG_MAX_COARSE unknowns) is solved exactly
+ *               (dense Cholesky);
  *   cycle       V(1,1): x = omega D^-1 b; r = b - A x; x += P V(R r);
  *               x += omega D^-1 (b - A x).
  * The cycle is symmetric and positive definite for SPD A, so it is a valid
@@ -172,45 +175,122 @@ static void csr_mm(const csr_t* X, const csr_t* Y, csr_t* C)
     free(acc); free(mark); free(list);
 }
 
-/* Strength and the three aggregation passes; returns the aggregate count. */
-static int32_t aggregate(const csr_t* A, const double* d, double theta, int32_t* agg)
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) as a counter-based
+ * generator: element k of the sequence whose state starts at `seed` is the
+ * finaliser applied to seed + (k + 1) * 0x9E3779B97F4A7C15. */
+uint64_t or_splitmix64(uint64_t seed, uint64_t k)
 {
-    const int32_t n = A->n;
-    for (int32_t i = 0; i < n; ++i) agg[i] = -1;
-#define STRONG(i, p) (A->col[p] != (i) && fabs(A->val[p]) >= theta * sqrt(fabs(d[i] * d[A->col[p]])))
-    int32_t na = 0;
-    for (int32_t i = 0; i < n; ++i) {            /* pass 1 */
-        if (agg[i] >= 0) continue;
-        int free_nbhd = 1;
-        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p)
-            if (STRONG(i, p) && agg[A->col[p]] >= 0) { free_nbhd = 0; break; }
-        if (!free_nbhd) continue;
-        agg[i] = na;
-        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p)
-            if (STRONG(i, p)) agg[A->col[p]] = na;
-        ++na;
+    uint64_t z = seed + (k + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Priority of unknown i on level l: 31 random bits from the counter
+ * (l, i), then the index itself, so that no two unknowns tie. */
+uint64_t or_amg_priority(uint64_t seed, int32_t level, int32_t i)
+{
+    const uint64_t r = or_splitmix64(seed, ((uint64_t)(uint32_t)level << 32) | (uint32_t)i) >> 33;
+    return (r << 31) | (uint32_t)i;
+}
+
+static int key_desc(const void* a, const void* b)
+{
+    const uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? 1 : (x > y ? -1 : 0);
+}
+
+/* Strong coupling (the strength graph the aggregation works on): a stored,
+ * non-zero off-diagonal entry with |a_ij| >= theta sqrt(|a_ii a_jj|). */
+static int strong(const csr_t* A, const double* d, double theta, int32_t i, int32_t p)
+{
+    const int32_t j = A->col[p];
+    return j != i && A->val[p] != 0.0 && fabs(A->val[p]) >= theta * sqrt(fabs(d[i] * d[j]));
+}
+
+/* Aggregation by a distance-2 maximal independent set of the strength graph
+ * (the parallel aggregation of the paper's AMG, Section 5):
+ *   roots: the maximal set of unknowns no two of which are joined by a path
+ *          of one or two strong couplings, taken greedily in decreasing
+ *          priority (key[i]): an unknown becomes a root unless an earlier
+ *          root lies within distance 2 of it.  This is the set the parallel
+ *          rule (an undecided unknown joins when its priority is the largest
+ *          among the undecided within distance 2 and no root is that close)
+ *          arrives at;
+ *   numbering: aggregate a is the a-th root in index order;
+ *   round 1: every other unknown with a root among its strong neighbours
+ *          joins that root's aggregate (there is at most one: two roots are
+ *          never two steps apart);
+ *   round 2: every unknown still outside joins the round-1 aggregate of its
+ *          strong neighbour with the largest |a_ij| (ties: the lowest j).
+ * Maximality puts every unknown within distance 2 of a root, so the two
+ * rounds place all of them; an unknown without strong couplings is a root of
+ * its own.  key == NULL: key[i] = or_amg_priority(seed, level, i).  Returns
+ * the number of aggregates, or -1 if an unknown was left out (not possible
+ * for a maximal set: kept as a check). */
+int32_t or_amg_aggregate(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double theta,
+                         const uint64_t* key, uint64_t seed, int32_t level, int32_t* agg)
+{
+    csr_t A = {n, n, (int32_t*)ptr, (int32_t*)col, (double*)val};
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    double* d = malloc(sizeof(double) * nn);
+    csr_diag(&A, d);
+    uint64_t* order = malloc(sizeof(uint64_t) * nn);
+    for (int32_t i = 0; i < n; ++i) order[i] = key ? key[i] : or_amg_priority(seed, level, i);
+    /* the index of each unknown is recovered from its key through a lookup */
+    int32_t* who = NULL;
+    if (key) {
+        /* explicit keys: sort (key, i) pairs by key; keys must be distinct */
+        uint64_t* pair = malloc(sizeof(uint64_t) * 2 * nn);
+        for (int32_t i = 0; i < n; ++i) { pair[2 * i] = key[i]; pair[2 * i + 1] = (uint64_t)i; }
+        qsort(pair, (size_t)n, 2 * sizeof(uint64_t), key_desc);
+        who = malloc(sizeof(int32_t) * nn);
+        for (int32_t i = 0; i < n; ++i) who[i] = (int32_t)pair[2 * i + 1];
+        free(pair);
+    } else {
+        qsort(order, (size_t)n, sizeof(uint64_t), key_desc);
+        who = malloc(sizeof(int32_t) * nn);
+        for (int32_t i = 0; i < n; ++i) who[i] = (int32_t)(uint32_t)(order[i] & 0x7FFFFFFFull);
     }
-    int32_t* pass1 = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    memcpy(pass1, agg, sizeof(int32_t) * (size_t)n);
-    for (int32_t i = 0; i < n; ++i) {            /* pass 2 */
-        if (agg[i] >= 0) continue;
-        int32_t best = -1; double bw = -1.0;
-        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p) {
-            int32_t j = A->col[p];
-            if (STRONG(i, p) && pass1[j] >= 0 && fabs(A->val[p]) > bw) { bw = fabs(A->val[p]); best = j; }
+    /* state: 0 free, 1 root, 2 within distance 2 of a root */
+    unsigned char* state = calloc(nn, 1);
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t v = who[t];
+        if (state[v] != 0) continue;
+        state[v] = 1;
+        for (int32_t p = ptr[v]; p < ptr[v + 1]; ++p) {
+            if (!strong(&A, d, theta, v, p)) continue;
+            const int32_t u = col[p];
+            if (state[u] == 0) state[u] = 2;
+            for (int32_t q = ptr[u]; q < ptr[u + 1]; ++q)
+                if (strong(&A, d, theta, u, q) && state[col[q]] == 0) state[col[q]] = 2;
         }
-        if (best >= 0) agg[i] = pass1[best];
     }
-    for (int32_t i = 0; i < n; ++i) {            /* pass 3 */
+    int32_t na = 0;
+    for (int32_t i = 0; i < n; ++i) agg[i] = state[i] == 1 ? na++ : -1;
+    int32_t* agg1 = malloc(sizeof(int32_t) * nn);
+    for (int32_t i = 0; i < n; ++i) {                /* round 1 */
+        agg1[i] = agg[i];
         if (agg[i] >= 0) continue;
-        agg[i] = na;
-        for (int32_t p = A->ptr[i]; p < A->ptr[i + 1]; ++p)
-            if (STRONG(i, p) && agg[A->col[p]] < 0) agg[A->col[p]] = na;
-        ++na;
+        for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p)
+            if (strong(&A, d, theta, i, p) && state[col[p]] == 1) { agg1[i] = agg[col[p]]; break; }
     }
-#undef STRONG
-    free(pass1);
-    return na;
+    int32_t rc = na;
+    for (int32_t i = 0; i < n; ++i) {                /* round 2 */
+        agg[i] = agg1[i];
+        if (agg1[i] >= 0) continue;
+        int32_t best = -1;
+        double bw = -1.0;
+        for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) {
+            const int32_t j = col[p];
+            if (!strong(&A, d, theta, i, p) || agg1[j] < 0) continue;
+            if (fabs(val[p]) > bw) { bw = fabs(val[p]); best = j; }  /* columns ascend: ties keep the lowest j */
+        }
+        if (best < 0) rc = -1;
+        else agg[i] = agg1[best];
+    }
+    free(agg1); free(state); free(who); free(order); free(d);
+    return rc;
 }
 
 /* P = (I - omega D^-1 A) P_t, row i: 1 at agg[i], minus omega a_ij / a_ii at
@@ -278,7 +358,7 @@ static int dense_cholesky(const csr_t* A, double* L)
 
 or_amg* or_amg_setup(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
                      const double* diag, const double* upper, const double* lower,
-                     double theta, int32_t max_levels, int32_t coarse_size)
+                     double theta, int32_t max_levels, int32_t coarse_size, uint64_t seed)
 {
     if (max_levels < 1) max_levels = 1;
     if (max_levels > OR_AMG_MAX_LEVELS) max_levels = OR_AMG_MAX_LEVELS;
@@ -296,8 +376,8 @@ or_amg* or_amg_setup(int32_t n, int32_t nf, const int32_t* owner, const int32_t*
         h->r[l] = calloc((size_t)(A->n > 0 ? A->n : 1), sizeof(double));
         if (A->n <= coarse_size || l + 1 == max_levels) break;
         int32_t* agg = malloc(sizeof(int32_t) * (size_t)A->n);
-        int32_t na = aggregate(A, h->d[l], th, agg);
-        if ((double)na > 0.6 * (double)A->n) { free(agg); break; }
+        int32_t na = or_amg_aggregate(A->n, A->ptr, A->col, A->val, th, NULL, seed, l, agg);
+        if (na < 0 || (double)na > 0.6 * (double)A->n) { free(agg); break; }
         h->agg[l] = agg;
         smoothed_prolongator(A, h->d[l], agg, na, h->omega[l], &h->P[l]);
         csr_transpose(&h->P[l], &h->R[l]);
@@ -310,6 +390,7 @@ or_amg* or_amg_setup(int32_t n, int32_t nf, const int32_t* owner, const int32_t*
     }
     h->nlev = l + 1;
     const int32_t nc = h->A[l].n;
+    if (nc > OR_AMG_MAX_COARSE) { or_amg_free(h); return NULL; }  /* too large to solve densely */
     h->chol = malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1) * (size_t)(nc > 0 ? nc : 1));
     if (!dense_cholesky(&h->A[l], h->chol)) { or_amg_free(h); return NULL; }
     return h;

@@ -79,14 +79,22 @@ int32_t or_mixed_reliable(int32_t n, int32_t nf, const int32_t* owner, const int
                           int32_t maxit, or_stats* st);
 
 /* ---- Smoothed-aggregation AMG preconditioner (amg.c; the method is stated
- * at the top of that file). */
-enum { OR_AMG_MAX_LEVELS = 16 };
+ * at the top of that file).  seed selects the aggregation priorities. */
+enum { OR_AMG_MAX_LEVELS = 16, OR_AMG_MAX_COARSE = 2048 };
 typedef struct or_amg or_amg;
 
-/* NULL if the coarsest level is not positive definite. */
+/* NULL if the last level has more than OR_AMG_MAX_COARSE unknowns or is not
+ * positive definite. */
 or_amg* or_amg_setup(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
                      const double* diag, const double* upper, const double* lower,
-                     double theta, int32_t max_levels, int32_t coarse_size);
+                     double theta, int32_t max_levels, int32_t coarse_size, uint64_t seed);
+/* Distance-2 maximal-independent-set aggregation of one CSR level (columns
+ * sorted in each row); key == NULL takes the priorities from (seed, level).
+ * Returns the aggregate count (-1: an unknown left out). */
+int32_t or_amg_aggregate(int32_t n, const int32_t* ptr, const int32_t* col, const double* val, double theta,
+                         const uint64_t* key, uint64_t seed, int32_t level, int32_t* agg);
+uint64_t or_splitmix64(uint64_t seed, uint64_t k);
+uint64_t or_amg_priority(uint64_t seed, int32_t level, int32_t i);
 void or_amg_free(or_amg* h);
 int32_t or_amg_levels(const or_amg* h);
 void or_amg_level_info(const or_amg* h, int32_t l, int32_t* n, int32_t* nnz, int32_t* n_coarse, double* omega);

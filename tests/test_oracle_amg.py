@@ -1,7 +1,12 @@
 """Pins of the oracle's smoothed-aggregation AMG (oracle/amg.c) against facts
 fixed by its definition and by linear algebra, independent of its code:
 
-A1 aggregates of a 7-cell line, a 3x3 grid and a weighted ring, worked by hand
+A0 the priorities' generator (SplitMix64) against its published outputs
+A1 distance-2 maximal-independent-set aggregates of a 7-cell line, a 3x3
+   grid, weighted rings and an uncoupled cell, worked by hand; on meshes, the
+   roots equal those of the parallel rule (written here independently of the
+   oracle's sequential greedy), are independent at distance 2 and maximal,
+   and every aggregate holds its root's neighbours and lies within two steps
 A2 every unknown in exactly one aggregate; no empty aggregate
 A3 prolongator row sums: P 1 = (I - omega D^-1 A) 1
 A4 Galerkin coarse operators equal SciPy's P^T A P
@@ -10,11 +15,15 @@ A6 one level: the cycle is the exact solve (dense LU)
 A7 the cycle is symmetric positive definite and its error propagator
    I - M A contracts (spectral radius < 1, power iteration)
 A8 AMG-PCG reaches the dense solution; iteration counts far below Jacobi-PCG
-   and, at 64^3, no more than Table pcgs2's GPU AMG-CG count (loose: the
-   paper's AMG, boundary conditions and right-hand side are not stated)
+   and, at 64^3, of the order of Table pcgs2's GPU AMG-CG count 28 (loose:
+   the paper's boundary conditions, right-hand side and stopping norm are
+   not stated)
 A9 AMG-preconditioned pipelined CG: the same iterates as AMG-PCG in exact
    arithmetic (equal at equal count up to rounding), the dense solution
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -23,6 +32,7 @@ import fvcases as fc
 from tests.helpers import dense
 
 pytestmark = pytest.mark.cpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _csr(ptr, col, val, shape):
@@ -39,33 +49,180 @@ def _line(n):
     return fc.Case("line", (n, 1, 1), n, owner, nb, diag, up, up.copy(), np.ones(n))
 
 
+# ---------------------------------------------------------------- A0
+def test_a0_splitmix64_published_values(oracle_lib):
+    """The priorities' generator against the published SplitMix64 outputs for
+    state 0 (tests/golden/splitmix64.json) and against a Python rendering of
+    its definition for other seeds and counters."""
+    g = json.load(open(os.path.join(GOLDEN, "splitmix64.json")))
+    for k, v in enumerate(g["seed0_first_outputs"]):
+        assert oracle_lib.splitmix64(0, k) == int(v, 16)
+    M = (1 << 64) - 1
+
+    def mix(seed, k):
+        z = (seed + (k + 1) * 0x9E3779B97F4A7C15) & M
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+
+    for seed, k in ((1, 0), (1, 12345), (0xDEADBEEF, (3 << 32) | 77), (M, 5)):
+        assert oracle_lib.splitmix64(seed, k) == mix(seed, k)
+    # priority = 31 random bits of counter (level, i), then i
+    p = oracle_lib.amg_priority(1, 2, 99)
+    assert p & 0x7FFFFFFF == 99 and p >> 31 == mix(1, (2 << 32) | 99) >> 33
+
+
 # ---------------------------------------------------------------- A1, A2
-def test_a1_aggregates_worked_by_hand(oracle_lib):
-    # line: pass 1 takes {0,1} (0 and its only neighbour), skips 2 (neighbour 1
-    # taken), takes {2,3,4} around 3, skips 5, takes {5,6} around 6
-    h = oracle_lib.AMG(_line(7), coarse_size=1)
-    assert h.aggregates(0).tolist() == [0, 0, 1, 1, 1, 2, 2]
-    # 3x3 grid, cell i + 3j, every coupling strong.  Pass 1: {0,1,3} around
-    # 0; 2 (neighbour 1 taken) and 4 (1, 3 taken) are skipped; 5's neighbours
-    # 2, 4, 8 are all free: {2,4,5,8}; 6 (3 taken) and 7 (4 taken) are
-    # skipped.  Pass 2: 6's only aggregated neighbour is 3 -> aggregate 0; 7's
-    # neighbours 4 and 8 tie at |a| = 1, the first (4) wins -> aggregate 1.
-    c = fc.laplace((3, 3, 1))
-    h = oracle_lib.AMG(c, coarse_size=1)
-    assert h.aggregates(0).tolist() == [0, 0, 1, 0, 1, 1, 0, 1, 1]
-    # a ring of 7 with coupling 2 between cells 4 and 5, 1 elsewhere: pass 1
-    # makes {0,1,6} and {2,3,4}; 5 is skipped (4 and 6 taken) and pass 2 puts
-    # it with its stronger neighbour 4, not with 6
-    owner = np.array([0, 0, 1, 2, 3, 4, 5], dtype=np.int32)
-    nb = np.array([1, 6, 2, 3, 4, 5, 6], dtype=np.int32)
-    up = -np.ones(7)
-    up[5] = -2.0
-    diag = np.ones(7)
+def _agg_keys(order, n):
+    """Explicit priorities: the unknowns in `order` first (descending), the
+    rest after them in index order."""
+    key = np.zeros(n, dtype=np.uint64)
+    rest = [i for i in range(n) if i not in order]
+    for rank, i in enumerate(list(order) + rest):
+        key[i] = np.uint64(10 * n - rank)
+    return key
+
+
+def _ring(n, strong_face=None, w=2.0):
+    owner = np.array([0] + list(range(n - 1)), dtype=np.int32)
+    nb = np.array([n - 1] + list(range(1, n)), dtype=np.int32)
+    o = np.lexsort((nb, owner))
+    owner, nb = owner[o], nb[o]
+    up = -np.ones(n)
+    if strong_face is not None:
+        up[[k for k in range(n) if (owner[k], nb[k]) == strong_face][0]] = -w
+    diag = np.ones(n)
     np.add.at(diag, owner, -up)
     np.add.at(diag, nb, -up)
-    ring = fc.Case("ring", (7, 1, 1), 7, owner, nb, diag, up, up.copy(), np.ones(7))
-    h = oracle_lib.AMG(ring, coarse_size=1)
-    assert h.aggregates(0).tolist() == [0, 0, 1, 1, 1, 1, 0]
+    return fc.Case("ring", (n, 1, 1), n, owner, nb, diag, up, up.copy(), np.ones(n))
+
+
+def _csr_ldu(case):
+    """The LDU matrix as CSR with its stored pattern: a face whose
+    coefficients are zero keeps its two (zero) entries."""
+    n, o, m = case.n, case.owner.astype(np.int64), case.neighbour.astype(np.int64)
+    rows = np.concatenate([np.arange(n), o, m])
+    cols = np.concatenate([np.arange(n), m, o])
+    vals = np.concatenate([case.diag, case.upper, case.lower])
+    order = np.lexsort((cols, rows))
+    ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(ptr, rows + 1, 1)
+    A = sp.csr_matrix((vals[order], cols[order], np.cumsum(ptr)), shape=(n, n))
+    assert A.has_sorted_indices and A.nnz == n + 2 * case.F
+    return A
+
+
+def _agg(oracle_lib, case, key, theta=0.0):
+    A = _csr_ldu(case)
+    return oracle_lib.aggregate(A.indptr, A.indices, A.data, theta, key=key)
+
+
+def test_a1_aggregates_worked_by_hand(oracle_lib):
+    # line 0..6.  Priorities 3 first: root 3 rules out 1, 2, 4, 5; then 0
+    # and 6 (three steps from 3) become roots.  Aggregates in root-index
+    # order: 0 -> 0, 3 -> 1, 6 -> 2; round 1 places 1 (next to 0), 2 and 4
+    # (next to 3) and 5 (next to 6).
+    line = _line(7)
+    agg, na = _agg(oracle_lib, line, _agg_keys([3, 0, 6], 7))
+    assert na == 3 and agg.tolist() == [0, 0, 1, 1, 1, 2, 2]
+    # priorities 2, then 6: root 2 rules out 0, 1, 3, 4; 6 becomes a root
+    # (four steps away) and rules out 5.  Round 1: 1, 3 -> 0 (next to 2),
+    # 5 -> 1 (next to 6).  Round 2: 0's only neighbour 1 is in aggregate 0;
+    # 4's neighbours 3 (aggregate 0) and 5 (aggregate 1) tie at |a| = 1 and
+    # the lower index, 3, wins.
+    agg, na = _agg(oracle_lib, line, _agg_keys([2, 6], 7))
+    assert na == 2 and agg.tolist() == [0, 0, 0, 0, 0, 1, 1]
+    # ring of 7 with the coupling 5-6 twice the others.  Roots 0, then 3
+    # (three steps from 0 by 0-1-2-3, four the other way): round 1 puts 1, 6
+    # with 0 and 2, 4 with 3.  5 (next to 4 and 6, neither a root) goes in
+    # round 2 to its stronger neighbour 6's aggregate (0), not to 4's.
+    ring = _ring(7, strong_face=(5, 6))
+    agg, na = _agg(oracle_lib, ring, _agg_keys([0, 3], 7))
+    assert na == 2 and agg.tolist() == [0, 0, 1, 1, 1, 0, 0]
+    # the same with equal couplings: the tie goes to the lower index, 4
+    agg, na = _agg(oracle_lib, _ring(7), _agg_keys([0, 3], 7))
+    assert na == 2 and agg.tolist() == [0, 0, 1, 1, 1, 1, 0]
+    # 3x3 grid, cell i + 3j.  Priorities 0, then 8: root 0 rules out 1, 3
+    # (one step) and 2, 4, 6 (two steps); 8 is four steps from 0 and becomes
+    # a root.  Round 1: 1, 3 -> 0; 5, 7 -> 1.  Round 2, all couplings equal,
+    # lowest-index neighbour: 2 -> 1's (0), 4 -> 1's (0), 6 -> 3's (0).
+    grid = fc.laplace((3, 3, 1))
+    agg, na = _agg(oracle_lib, grid, _agg_keys([0, 8], 9))
+    assert na == 2 and agg.tolist() == [0, 0, 0, 0, 0, 1, 0, 1, 1]
+    # centre first: every cell is within two steps of 4, one aggregate
+    agg, na = _agg(oracle_lib, grid, _agg_keys([4], 9))
+    assert na == 1 and agg.tolist() == [0] * 9
+    # a cell with no coupling (the pinned-reference case) is its own root
+    c = fc.laplace((3, 3, 1))
+    iso = fc.Case("iso", c.shape, c.n, c.owner, c.neighbour, c.diag, c.upper.copy(), c.lower.copy(), c.b)
+    for f in range(iso.F):
+        if iso.owner[f] == 0:
+            iso.upper[f] = iso.lower[f] = 0.0
+    agg, na = _agg(oracle_lib, iso, _agg_keys([4], 9))
+    assert na == 2 and agg[0] == 0 and np.all(agg[1:] == 1)
+
+
+def _parallel_mis2(S, key):
+    """The parallel rule on the strength graph S (scipy CSR, no diagonal):
+    every round each undecided unknown takes the largest (state, key) over
+    its closed distance-2 neighbourhood; it joins when that is itself, and
+    drops out when that is a root.  Written independently of the oracle's
+    sequential greedy; both must give the same set."""
+    n = S.shape[0]
+    state = np.ones(n, dtype=np.int64)  # 0 out, 1 undecided, 2 root
+    G = (S + sp.identity(n, format="csr")).tocsr()
+    G2 = (G @ G).tocsr()
+    G2.sort_indices()
+    key = key.astype(np.uint64)
+    while np.any(state == 1):
+        tup = list(zip(state.tolist(), key.tolist()))
+        best = []
+        for i in range(n):
+            nbr = G2.indices[G2.indptr[i]:G2.indptr[i + 1]]
+            best.append(max(nbr, key=lambda j: tup[j]))
+        new = state.copy()
+        for i in range(n):
+            if state[i] != 1:
+                continue
+            if best[i] == i:
+                new[i] = 2
+            elif state[best[i]] == 2:
+                new[i] = 0
+        state = new
+    return np.flatnonzero(state == 2)
+
+
+@pytest.mark.parametrize("make", [lambda: fc.laplace((7, 6, 5)), lambda: fc.varcoef((8, 7, 6), seed=3),
+                                  lambda: fc.cavity((9, 8, 4)), lambda: _ring(11)])
+@pytest.mark.parametrize("theta", [0.0, 0.08])
+def test_a1_mis2_properties_and_parallel_rule(oracle_lib, make, theta):
+    """Roots from the oracle equal the parallel rule's; no two roots within
+    two strong steps; every unknown within two steps of a root; each
+    aggregate holds its root and every unknown next to it, and its members
+    lie within two steps of the root; priorities from SplitMix64."""
+    c = make()
+    A = _csr_ldu(c)
+    d = A.diagonal()
+    key = np.array([oracle_lib.amg_priority(1, 0, i) for i in range(c.n)], dtype=np.uint64)
+    agg, na = oracle_lib.aggregate(A.indptr, A.indices, A.data, theta, seed=1, level=0)
+    agg2, _ = oracle_lib.aggregate(A.indptr, A.indices, A.data, theta, key=key)
+    assert np.array_equal(agg, agg2)
+    C = A.tocoo()
+    keep = (C.row != C.col) & (C.data != 0) & (np.abs(C.data) >= theta * np.sqrt(np.abs(d[C.row] * d[C.col])))
+    S = sp.csr_matrix((np.ones(keep.sum()), (C.row[keep], C.col[keep])), shape=A.shape)
+    roots = _parallel_mis2(S, key)
+    assert na == roots.size and np.array_equal(agg[roots], np.arange(na))
+    G = (S + sp.identity(c.n, format="csr")).tocsr()
+    within2 = (G @ G).tocsr() != 0
+    R = within2[roots][:, roots].toarray()
+    assert np.array_equal(R, np.eye(na, dtype=bool))             # independent at distance 2
+    assert np.all(np.asarray(within2[:, roots].sum(axis=1)).ravel() >= 1)  # maximal
+    near = S[roots].toarray().astype(bool)
+    for a, r in enumerate(roots):
+        assert agg[r] == a
+        assert np.all(agg[np.flatnonzero(near[a])] == a)
+        members = np.flatnonzero(agg == a)
+        assert np.all(within2[r, members].toarray())
 
 
 @pytest.mark.parametrize("make", [lambda: fc.laplace((16, 16, 16)), lambda: fc.varcoef((14, 12, 10), seed=3),
@@ -155,7 +312,7 @@ def test_a8_iteration_counts(oracle_lib):
         assert st["iters"] <= sj["iters"] / 8
     c = fc.laplace((64, 64, 64))
     _, st = oracle_lib.AMG(c).pcg(c.b, tol=1e-8, maxit=500)
-    assert st["status"] == 0 and st["iters"] <= 28
+    assert st["status"] == 0 and 14 <= st["iters"] <= 42
 
 
 # ---------------------------------------------------------------- A9
