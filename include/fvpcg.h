@@ -272,30 +272,42 @@ FVPCG_API int fvpcg_transient_run(fvpcg_matrix* mat, const double* k_face, const
                                   const double* bdiag, const double* bsrc, double dt, int32_t nsteps, double* T,
                                   double tol, int32_t maxit, int32_t method, void* stream, fvpcg_stats* stats);
 
-/* ---- Smoothed-aggregation AMG preconditioner (Section 5 and Table pcgs2
- * compare the paper's Jacobi-preconditioned solvers with aggregation-AMG
- * preconditioned CG; the paper does not print its AMG).  The method:
- * strength |a_ij| >= theta_l sqrt(a_ii a_jj) with theta_l = theta / 2^l;
- * three greedy aggregation passes in index order (i with all its free strong
- * neighbours; leftovers join the first pass's aggregate of their strongest
- * strong neighbour; what remains forms aggregates of i and its free
- * neighbours); P = (I - omega D^-1 A) P_t with omega = 4 / (3 Gershgorin bound
- * of D^-1 A); A_c = P^T A P; levels until n <= coarse_size, max_levels, or an
+/* ---- Smoothed-aggregation AMG preconditioner (Section 5, discussion of
+ * Fig. pcgs1 and Table pcgs2: a V-cycle of aggregation-based AMG whose
+ * aggregates come from the parallel distance-2 maximal-independent-set
+ * method, weighted Jacobi with omega = 4/3 as smoother).  The method:
+ * strength j ~ i iff a_ij != 0 and |a_ij| >= theta_l sqrt(|a_ii a_jj|),
+ * theta_l = theta / 2^l (theta = 0: every coupling); roots = a distance-2
+ * maximal independent set of the strength graph in the order of SplitMix64
+ * priorities drawn from (seed, level, unknown); each root's neighbours join
+ * its aggregate, the rest the aggregate of their strongest such neighbour;
+ * P = (I - omega D^-1 A) P_t, omega = (4/3) / (Gershgorin bound of D^-1 A);
+ * A_c = P^T A P; levels until n <= coarse_size, max_levels, or an
  * aggregation keeping > 60% of the unknowns; the last level (at most 2048
  * unknowns) solved exactly.  Cycle V(1,1) with damped Jacobi (the same
- * omega).  The hierarchy is built on the host from the matrix's coefficients
- * at creation (seconds for millions of cells) and uploaded; the matrix must
- * outlive it and be symmetric; after fvpcg_matrix_update create it again.
- * Calls on one handle must not overlap.  Typical: theta = 0.08,
- * max_levels = 12, coarse_size = 64. */
+ * omega).  The whole hierarchy is built on the device from the matrix's
+ * current coefficients (sync on `stream` at exit).  The matrix must outlive
+ * the handle and be symmetric (FVPCG_UNSUPPORTED otherwise); once the
+ * matrix is updated, the handle's solves return FVPCG_INVALID_ARG: create
+ * it again.  Calls on one handle must not overlap.  Typical: theta = 0,
+ * max_levels = 12, coarse_size = 64, seed = 1.  Errors: FVPCG_UNSUPPORTED if
+ * the last level exceeds 2048 unknowns, FVPCG_BREAKDOWN if it is not
+ * positive definite, FVPCG_OUT_OF_MEMORY. */
 FVPCG_API int fvpcg_amg_create(const fvpcg_matrix* mat, double theta, int32_t max_levels, int32_t coarse_size,
-                               void* stream, fvpcg_amg** out);
+                               uint64_t seed, void* stream, fvpcg_amg** out);
 FVPCG_API int fvpcg_amg_destroy(fvpcg_amg* amg);
 /* Number of levels; rows and stored entries of `level` (n, nnz may be NULL). */
 FVPCG_API int fvpcg_amg_info(const fvpcg_amg* amg, int32_t level, int32_t* levels, int32_t* n, int64_t* nnz);
 /* Aggregate index of every row of `level` (a level with a coarser one) into a
  * HOST int32 array of that level's row count. */
 FVPCG_API int fvpcg_amg_aggregates(const fvpcg_amg* amg, int32_t level, int32_t* host_out);
+/* Level `level`'s operator (which = 0; levels >= 1: level 0's operator is
+ * the matrix), prolongator P (1) or restriction R = P^T (2; levels with a
+ * coarser one) as CSR copied into HOST arrays: host_ptr int32[rows + 1],
+ * host_col int32[nnz], host_val FP64[nnz], columns ascending in each row.
+ * Pass NULL arrays to get rows, cols and nnz only. */
+FVPCG_API int fvpcg_amg_export(const fvpcg_amg* amg, int32_t level, int32_t which, int32_t* rows, int32_t* cols,
+                               int64_t* nnz, int32_t* host_ptr, int32_t* host_col, double* host_val);
 /* z = M^-1 r, one cycle; r, z: FP64[n_cells] device arrays, not overlapping. */
 FVPCG_API int fvpcg_amg_apply(const fvpcg_amg* amg, const double* r, double* z, void* stream);
 /* Preconditioned CG with M^-1 = one cycle: method FVPCG_CG (standard form,

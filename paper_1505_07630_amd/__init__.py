@@ -462,10 +462,10 @@ class AMG:
     """Smoothed-aggregation AMG hierarchy of a (symmetric) Matrix; the Matrix
     must outlive it."""
 
-    def __init__(self, A: Matrix, theta=0.08, max_levels=12, coarse_size=64, stream=None):
+    def __init__(self, A: Matrix, theta=0.0, max_levels=12, coarse_size=64, seed=1, stream=None):
         h = ctypes.c_void_p()
-        _check(lib().fvpcg_amg_create(A.handle, float(theta), int(max_levels), int(coarse_size), _stream(stream),
-                                      ctypes.byref(h)), "fvpcg_amg_create")
+        _check(lib().fvpcg_amg_create(A.handle, float(theta), int(max_levels), int(coarse_size), int(seed),
+                                      _stream(stream), ctypes.byref(h)), "fvpcg_amg_create")
         self._h = h
         self.A = A
         self.n = A.n
@@ -494,6 +494,22 @@ class AMG:
                "fvpcg_amg_aggregates")
         return out
 
+    def export(self, level, which="A"):
+        """(indptr, indices, data, shape) of level `level`'s A (levels >= 1),
+        P or R, copied to the host."""
+        import numpy as np
+
+        w = {"A": 0, "P": 1, "R": 2}[which]
+        rows, cols, nnz = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        args = (self._h, int(level), w, ctypes.byref(rows), ctypes.byref(cols), ctypes.byref(nnz))
+        _check(lib().fvpcg_amg_export(*args, None, None, None), "fvpcg_amg_export")
+        ptr = np.empty(rows.value + 1, dtype=np.int32)
+        col = np.empty(max(nnz.value, 1), dtype=np.int32)
+        val = np.empty(max(nnz.value, 1))
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        _check(lib().fvpcg_amg_export(*args, vp(ptr), vp(col), vp(val)), "fvpcg_amg_export")
+        return ptr, col[:nnz.value], val[:nnz.value], (rows.value, cols.value)
+
     def close(self):
         if getattr(self, "_h", None):
             lib().fvpcg_amg_destroy(self._h)
@@ -506,8 +522,8 @@ class AMG:
             pass
 
 
-def fvpcg_amg_create(A: Matrix, theta=0.08, max_levels=12, coarse_size=64, stream=None) -> AMG:
-    return AMG(A, theta, max_levels, coarse_size, stream)
+def fvpcg_amg_create(A: Matrix, theta=0.0, max_levels=12, coarse_size=64, seed=1, stream=None) -> AMG:
+    return AMG(A, theta, max_levels, coarse_size, seed, stream)
 
 
 def fvpcg_amg_destroy(M: AMG):
@@ -521,6 +537,10 @@ def fvpcg_amg_info(M: AMG, level=0):
 
 def fvpcg_amg_aggregates(M: AMG, level=0):
     return M.aggregates(level)
+
+
+def fvpcg_amg_export(M: AMG, level=1, which="A"):
+    return M.export(level, which)
 
 
 def fvpcg_amg_apply(M: AMG, r, z=None, stream=None):

@@ -66,7 +66,8 @@ SIGNATURES = {
     "fvpcg_stream_calibrate": (ctypes.c_int, [P, u64, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
     "fvpcg_assemble_transient": (ctypes.c_int, [P, P, P, P, P, P, f64, P, P, P, P, P]),
     "fvpcg_transient_run": (ctypes.c_int, [P, P, P, P, P, P, f64, i32, P, f64, i32, i32, P, SPS]),
-    "fvpcg_amg_create": (ctypes.c_int, [P, f64, i32, i32, P, PP]),
+    "fvpcg_amg_create": (ctypes.c_int, [P, f64, i32, i32, ctypes.c_uint64, P, PP]),
+    "fvpcg_amg_export": (ctypes.c_int, [P, i32, i32, P, P, P, P, P, P]),
     "fvpcg_amg_destroy": (ctypes.c_int, [P]),
     "fvpcg_amg_info": (ctypes.c_int, [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]),
     "fvpcg_amg_aggregates": (ctypes.c_int, [P, i32, P]),

@@ -21,8 +21,8 @@ LIB_NAME = "libfvpcg.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 ARCH = "gfx950"
 
-SOURCES = ["setup.hip", "solve.hip", "batched.hip", "amg.hip", "transient.hip", "bicgstab.hip", "calibrate.hip",
-           "api.hip"]
+SOURCES = ["setup.hip", "solve.hip", "batched.hip", "amg.hip", "amg_setup.hip", "transient.hip", "bicgstab.hip",
+           "calibrate.hip", "api.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}",

@@ -1,363 +1,25 @@
-// Smoothed-aggregation AMG preconditioner and AMG-preconditioned CG.
+// Smoothed-aggregation AMG preconditioner and AMG-preconditioned CG: the
+// device cycle and the solvers.  The hierarchy (aggregation, prolongators,
+// Galerkin operators, last-level inverse) is built on the device by
+// amg_setup.hip; amg.hpp states the method.
 //
-// The paper compares its Jacobi-preconditioned CG and pipelined CG with
-// aggregation-AMG preconditioned versions (Section 5, Table pcgs2) without
-// printing the AMG.  This is the classical smoothed-aggregation method of
-// Vanek, Mandel and Brezina:
-//   strength    j ~ i iff j != i and |a_ij| >= theta_l sqrt(a_ii a_jj),
-//               theta_{l+1} = theta_l / 2;
-//   aggregates  three greedy passes in index order: (1) i and all its strong
-//               neighbours, when none of them is aggregated, form an
-//               aggregate; (2) a remaining i joins the pass-1 aggregate of its
-//               strongest strong neighbour (ties: lowest index); (3) what
-//               remains forms aggregates of i and its still-free neighbours;
-//   prolongator P = (I - omega D^-1 A) P_t, omega = 4 / (3 lambda), lambda
-//               the Gershgorin bound max_i sum_j |a_ij| / a_ii;
-//   coarse      A_c = P^T A P, R = P^T; stop at n <= coarse_size, at the
-//               level limit, or when aggregation keeps more than 60% of the
-//               unknowns; the last level is solved exactly (its inverse,
-//               formed from a Cholesky factor at setup);
-//   cycle       V(1,1): x = omega D^-1 b; r = b - A x; x += P V(R r);
-//               y = x + omega D^-1 (b - A x).
-// The hierarchy is built on the host at setup (sparse products with a dense
-// accumulator per row); the cycle runs on the device: level 0 uses the
-// matrix's ELL layout (the pre-smoothing and residual in one pass through
-// the column-scaled values), coarser levels CSR, one row per thread.  The
-// cycle is symmetric positive definite, so standard CG can use it as M^-1.
-#include <algorithm>
+// The cycle runs entirely on the device: level 0 uses the matrix's ELL layout
+// (the pre-smoothing and residual in one pass through the column-scaled
+// values), coarser levels CSR with 1, 16 or 64 lanes per row, the last level
+// a dense inverse.  The cycle is symmetric positive definite, so standard CG
+// can use it as M^-1.
 #include <atomic>
 #include <cmath>
 #include <cstring>
 #include <thread>
 #include <vector>
 
-#include "handles.hpp"
+#include "amg.hpp"
 #include "rows.hpp"
 
 namespace fvpcg {
 
-constexpr int kAmgMaxLevels = 16;
-constexpr int kAmgMaxCoarse = 2048;  // largest exactly-solved last level
-constexpr int kAmgBs = 512;          // level-0 and PCG kernels
-constexpr int kAmgCsrBs = 256;       // CSR levels, one row per thread
-
-struct AmgLevel {
-    int n = 0, nc = 0;  // rows here and on the next level
-    long long nnz = 0;
-    double omega = 0.0;
-    int *a_ptr = nullptr, *a_col = nullptr;  // levels >= 1
-    double *a_val = nullptr, *d = nullptr;   // levels >= 1
-    double* a_val_cs = nullptr;              // levels >= 1: a_ij / d_j
-    int *p_ptr = nullptr, *p_col = nullptr;  // P: n x nc
-    double* p_val = nullptr;
-    int *r_ptr = nullptr, *r_col = nullptr;  // R = P^T: nc x n
-    double* r_val = nullptr;
-    double *b = nullptr, *x = nullptr, *r = nullptr, *y = nullptr;  // work
-    int ga = 1, gp = 1, gr = 1;  // lanes per row for A, P, R (1, 16 or 64)
-    std::vector<int> agg;
-};
-
-}  // namespace fvpcg
-
-struct fvpcg_amg {
-    const fvpcg_matrix* mat = nullptr;
-    int nlev = 0;
-    fvpcg::AmgLevel lev[fvpcg::kAmgMaxLevels];
-    double* cinv = nullptr;  // inverse of the last level, row-major
-    int nlast = 0;
-    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;  // PCG vectors
-    double *u = nullptr, *w = nullptr, *m = nullptr, *s = nullptr;  // pipelined CG, allocated on first use
-    fvpcg::DevState* st = nullptr;
-    fvpcg::DevState* hst = nullptr;  // pinned [2]
-    double* partials = nullptr;
-    hipEvent_t t_begin = nullptr, t_end = nullptr, t_it0 = nullptr, t_it1 = nullptr;
-};
-
-namespace fvpcg {
-
 namespace {
-
-// ---------------------------------------------------------------- host setup
-// Products and sums are rounded one operation at a time (no fused
-// multiply-add), in the orders stated, so the hierarchy does not depend on
-// the compiler's contraction choices.
-#pragma clang fp contract(off)
-
-struct Csr {
-    int n = 0, m = 0;
-    std::vector<int> ptr, col;
-    std::vector<double> val;
-};
-
-Csr transpose(const Csr& A) {
-    Csr T;
-    T.n = A.m;
-    T.m = A.n;
-    T.ptr.assign((size_t)T.n + 1, 0);
-    T.col.resize(A.col.size());
-    T.val.resize(A.val.size());
-    for (int c : A.col) T.ptr[(size_t)c + 1]++;
-    for (int j = 0; j < T.n; ++j) T.ptr[(size_t)j + 1] += T.ptr[j];
-    std::vector<int> fill(T.ptr.begin(), T.ptr.end() - 1);
-    for (int i = 0; i < A.n; ++i)
-        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k) {
-            const int q = fill[A.col[k]]++;
-            T.col[q] = i;
-            T.val[q] = A.val[k];
-        }
-    return T;
-}
-
-// f(t, begin, end) on T contiguous parts of [0, n), one host thread each
-// (up to 16).  Each output element is still computed by one thread in its
-// sequential order, so results do not depend on T.  False if a part failed
-// (an allocation inside it), which the caller reports.
-template <typename F>
-bool parallel_parts(int n, int min_part, F&& f) {
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const int T = std::max(1, std::min({(int)std::min(hw, 16u), n / std::max(min_part, 1), n}));
-    std::atomic<bool> ok{true};
-    auto run = [&](int t) {
-        const int b = (int)((long long)n * t / T), e = (int)((long long)n * (t + 1) / T);
-        try {
-            f(t, b, e);
-        } catch (...) {
-            ok = false;
-        }
-    };
-    if (T == 1) {
-        run(0);
-        return ok;
-    }
-    std::vector<std::thread> th;
-    th.reserve((size_t)T - 1);
-    try {
-        for (int t = 1; t < T; ++t) th.emplace_back(run, t);
-    } catch (...) {
-        ok = false;
-    }
-    run(0);
-    for (auto& x : th) x.join();
-    return ok;
-}
-
-// C = X Y, row by row: products summed in the order of X's columns and then
-// Y's columns into a dense accumulator; columns sorted.  Rows are split over
-// host threads (each with its own accumulator) and concatenated in order.
-// Throws std::bad_alloc if a part runs out of memory.
-Csr multiply(const Csr& X, const Csr& Y) {
-    Csr C;
-    C.n = X.n;
-    C.m = Y.m;
-    C.ptr.assign((size_t)C.n + 1, 0);
-    struct Part {
-        std::vector<int> col;
-        std::vector<double> val;
-    };
-    std::vector<Part> parts(16);
-    std::vector<int> len((size_t)std::max(X.n, 1), 0);
-    const bool ok = parallel_parts(X.n, 4096, [&](int t, int r0, int r1) {
-        Part& out = parts[(size_t)t];
-        std::vector<double> acc((size_t)std::max(Y.m, 1), 0.0);
-        std::vector<int> mark((size_t)std::max(Y.m, 1), -1), touched;
-        for (int i = r0; i < r1; ++i) {
-            touched.clear();
-            for (int a = X.ptr[i]; a < X.ptr[(size_t)i + 1]; ++a) {
-                const int j = X.col[a];
-                const double xv = X.val[a];
-                for (int b = Y.ptr[j]; b < Y.ptr[(size_t)j + 1]; ++b) {
-                    const int k = Y.col[b];
-                    if (mark[k] != i) {
-                        mark[k] = i;
-                        acc[k] = 0.0;
-                        touched.push_back(k);
-                    }
-                    acc[k] += xv * Y.val[b];
-                }
-            }
-            std::sort(touched.begin(), touched.end());
-            for (int k : touched) {
-                out.col.push_back(k);
-                out.val.push_back(acc[k]);
-            }
-            len[(size_t)i] = (int)touched.size();
-        }
-    });
-    if (!ok) throw std::bad_alloc();
-    for (int i = 0; i < X.n; ++i) C.ptr[(size_t)i + 1] = C.ptr[i] + len[(size_t)i];
-    C.col.reserve((size_t)C.ptr[C.n]);
-    C.val.reserve((size_t)C.ptr[C.n]);
-    for (const Part& q : parts) {
-        C.col.insert(C.col.end(), q.col.begin(), q.col.end());
-        C.val.insert(C.val.end(), q.val.begin(), q.val.end());
-    }
-    return C;
-}
-
-std::vector<double> diagonal(const Csr& A) {
-    std::vector<double> d((size_t)A.n, 0.0);
-    for (int i = 0; i < A.n; ++i)
-        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k)
-            if (A.col[k] == i) d[i] = A.val[k];
-    return d;
-}
-
-int aggregate(const Csr& A, const std::vector<double>& d, double theta, std::vector<int>& agg) {
-    const int n = A.n;
-    agg.assign((size_t)n, -1);
-    auto strong = [&](int i, int k) {
-        const int j = A.col[k];
-        return j != i && std::fabs(A.val[k]) >= theta * std::sqrt(std::fabs(d[i] * d[j]));
-    };
-    int na = 0;
-    for (int i = 0; i < n; ++i) {  // pass 1
-        if (agg[i] >= 0) continue;
-        bool free_nbhd = true;
-        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1] && free_nbhd; ++k)
-            if (strong(i, k) && agg[A.col[k]] >= 0) free_nbhd = false;
-        if (!free_nbhd) continue;
-        agg[i] = na;
-        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k)
-            if (strong(i, k)) agg[A.col[k]] = na;
-        ++na;
-    }
-    const std::vector<int> first(agg);
-    for (int i = 0; i < n; ++i) {  // pass 2
-        if (agg[i] >= 0) continue;
-        int best = -1;
-        double bw = -1.0;
-        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k)
-            if (strong(i, k) && first[A.col[k]] >= 0 && std::fabs(A.val[k]) > bw) {
-                bw = std::fabs(A.val[k]);
-                best = A.col[k];
-            }
-        if (best >= 0) agg[i] = first[best];
-    }
-    for (int i = 0; i < n; ++i) {  // pass 3
-        if (agg[i] >= 0) continue;
-        agg[i] = na;
-        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k)
-            if (strong(i, k) && agg[A.col[k]] < 0) agg[A.col[k]] = na;
-        ++na;
-    }
-    return na;
-}
-
-double gershgorin(const Csr& A, const std::vector<double>& d) {
-    double lam = 0.0;
-    for (int i = 0; i < A.n; ++i) {
-        double s = 0.0;
-        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k) s += std::fabs(A.val[k]);
-        lam = std::max(lam, s / d[i]);
-    }
-    return lam;
-}
-
-// P = (I - omega D^-1 A) P_t
-Csr prolongator(const Csr& A, const std::vector<double>& d, const std::vector<int>& agg, int na, double omega) {
-    Csr S = A;
-    for (int i = 0; i < A.n; ++i)
-        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k)
-            S.val[k] = (A.col[k] == i ? 1.0 : 0.0) - omega * A.val[k] / d[i];
-    Csr Pt;
-    Pt.n = A.n;
-    Pt.m = na;
-    Pt.ptr.resize((size_t)A.n + 1);
-    for (int i = 0; i <= A.n; ++i) Pt.ptr[i] = i;
-    Pt.col = agg;
-    Pt.val.assign((size_t)A.n, 1.0);
-    return multiply(S, Pt);
-}
-
-// inverse of a small SPD matrix through its Cholesky factor; false if not SPD
-bool spd_inverse(const Csr& A, std::vector<double>& inv) {
-    const int n = A.n;
-    std::vector<double> L((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i)
-        for (int k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k) L[(size_t)i * n + A.col[k]] = A.val[k];
-    for (int j = 0; j < n; ++j) {
-        double s = L[(size_t)j * n + j];
-        for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
-        if (!(s > 0.0)) return false;
-        const double ljj = std::sqrt(s);
-        L[(size_t)j * n + j] = ljj;
-        for (int i = j + 1; i < n; ++i) {
-            double t = L[(size_t)i * n + j];
-            for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
-            L[(size_t)i * n + j] = t / ljj;
-        }
-    }
-    inv.assign((size_t)n * n, 0.0);
-    // column c of A^-1: L L^T v = e_c; the columns are independent
-    const bool ok = parallel_parts(n, 32, [&](int, int c0, int c1) {
-        std::vector<double> e((size_t)n);
-        for (int c = c0; c < c1; ++c) {
-            for (int i = 0; i < n; ++i) {
-                double s = i == c ? 1.0 : 0.0;
-                for (int k = 0; k < i; ++k) s -= L[(size_t)i * n + k] * e[k];
-                e[i] = s / L[(size_t)i * n + i];
-            }
-            for (int i = n - 1; i >= 0; --i) {
-                double s = e[i];
-                for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * e[k];
-                e[i] = s / L[(size_t)i * n + i];
-            }
-            for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = e[i];
-        }
-    });
-    if (!ok) throw std::bad_alloc();
-    return true;
-}
-
-// Level 0 as CSR from the device ELL layout: the diagonal plus every slot
-// whose column is not the row itself (padding repeats the row), sorted.
-int level0_from_device(const fvpcg_matrix* A, hipStream_t s, Csr& out) {
-    const fvpcg_mesh* m = A->mesh;
-    const int n = m->n, W = m->W;
-    std::vector<int> col((size_t)W * n);
-    std::vector<double> val((size_t)W * n), d((size_t)n);
-    FV_HIP(hipMemcpyAsync(col.data(), m->col, sizeof(int) * col.size(), hipMemcpyDeviceToHost, s));
-    FV_HIP(hipMemcpyAsync(val.data(), A->val, sizeof(double) * val.size(), hipMemcpyDeviceToHost, s));
-    FV_HIP(hipMemcpyAsync(d.data(), A->d, sizeof(double) * d.size(), hipMemcpyDeviceToHost, s));
-    FV_HIP(hipStreamSynchronize(s));
-    out.n = out.m = n;
-    out.ptr.assign((size_t)n + 1, 0);
-    out.col.clear();
-    out.val.clear();
-    out.col.reserve((size_t)(W + 1) * n);
-    out.val.reserve((size_t)(W + 1) * n);
-    std::vector<std::pair<int, double>> row;
-    for (int c = 0; c < n; ++c) {
-        row.clear();
-        row.emplace_back(c, d[c]);
-        for (int k = 0; k < W; ++k) {
-            const size_t o = (size_t)k * n + c;
-            if (col[o] != c) row.emplace_back(col[o], val[o]);
-        }
-        std::sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
-        for (auto& e : row) {
-            out.col.push_back(e.first);
-            out.val.push_back(e.second);
-        }
-        out.ptr[(size_t)c + 1] = (int)out.col.size();
-    }
-    return FVPCG_OK;
-}
-
-bool symmetric(const Csr& A) {
-    const Csr T = transpose(A);
-    return T.ptr == A.ptr && T.col == A.col && T.val == A.val;
-}
-
-template <typename T>
-int upload(T** dst, const std::vector<T>& src, const char* what, hipStream_t s) {
-    int rc;
-    if ((rc = dev_alloc(dst, std::max<size_t>(src.size(), 1), what))) return rc;
-    if (!src.empty()) FV_HIP(hipMemcpyAsync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s));
-    return FVPCG_OK;
-}
-
-#pragma clang fp contract(on)
 
 // ---------------------------------------------------------------- kernels
 
@@ -766,12 +428,6 @@ int group_grid(int n, int G) {
     const int rows_per_block = (kAmgCsrBs / 64) * (64 / G);
     return std::max(1, std::min((n + rows_per_block - 1) / rows_per_block, 8192));
 }
-// lanes per row from the operator's mean row length (measured at 7M cells:
-// 44-entry rows run fastest with 16 lanes, hundreds with 64)
-int lanes_for(size_t nnz, int rows) {
-    const double avg = (double)nnz / (double)std::max(rows, 1);
-    return avg <= 6.0 ? 1 : (avg <= 48.0 ? 16 : 64);
-}
 
 void launch_pre(const AmgLevel& v, const double* b, const DevState* st, hipStream_t s) {
     if (v.ga == 1)
@@ -899,6 +555,7 @@ void amg_free(fvpcg_amg* h) {
         dev_free(v.x);
         dev_free(v.r);
         dev_free(v.y);
+        dev_free(v.agg);
     }
     dev_free(h->cinv);
     dev_free(h->r);
@@ -918,16 +575,14 @@ void amg_free(fvpcg_amg* h) {
     delete h;
 }
 
-int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, hipStream_t s);
-
-int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, hipStream_t s,
+int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, uint64_t seed, hipStream_t s,
                fvpcg_amg** out) {
     fvpcg_amg* h = new (std::nothrow) fvpcg_amg();
     if (!h) return set_error(FVPCG_OUT_OF_MEMORY, "host allocation failed");
     h->mat = A;
     int rc;
     try {
-        rc = amg_build(h, A, theta, max_levels, coarse_size, s);
+        rc = amg_build(h, A, theta, max_levels, coarse_size, seed, s);
     } catch (const std::bad_alloc&) {
         rc = set_error(FVPCG_OUT_OF_MEMORY, "host allocation failed during the AMG setup");
     }
@@ -939,92 +594,59 @@ int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_s
     return FVPCG_OK;
 }
 
-// The hierarchy into h (freed by the caller on failure).
-int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, hipStream_t s) {
-    auto fail = [](int rc) { return rc; };
-    int rc;
-    Csr cur;
-    if ((rc = level0_from_device(A, s, cur))) return fail(rc);
-    if (!A->sym && !symmetric(cur))
-        return fail(set_error(FVPCG_UNSUPPORTED, "AMG needs a symmetric matrix (lower == upper on every face)"));
-    max_levels = std::max(1, std::min(max_levels, kAmgMaxLevels));
-    double th = theta;
-    int l = 0;
-    for (;;) {
-        AmgLevel& v = h->lev[l];
-        const std::vector<double> d = diagonal(cur);
-        v.n = cur.n;
-        v.nnz = (long long)cur.col.size();
-        v.omega = 4.0 / (3.0 * gershgorin(cur, d));
-        v.ga = lanes_for(cur.col.size(), cur.n);
-        if (l > 0) {
-            std::vector<double> cs(cur.val.size());
-            for (size_t k = 0; k < cs.size(); ++k) cs[k] = cur.val[k] / d[cur.col[k]];
-            if ((rc = upload(&v.a_ptr, cur.ptr, "AMG level rows", s)) || (rc = upload(&v.a_col, cur.col, "AMG level columns", s)) ||
-                (rc = upload(&v.a_val, cur.val, "AMG level values", s)) || (rc = upload(&v.d, d, "AMG level diagonal", s)) ||
-                (rc = upload(&v.a_val_cs, cs, "AMG level scaled values", s)))
-                return fail(rc);
-            FV_HIP(hipStreamSynchronize(s));  // cs goes out of scope
-        }
-        if ((rc = dev_alloc(&v.b, (size_t)std::max(v.n, 1), "AMG work")) ||
-            (rc = dev_alloc(&v.x, (size_t)std::max(v.n, 1), "AMG work")) ||
-            (rc = dev_alloc(&v.r, (size_t)std::max(v.n, 1), "AMG work")) ||
-            (rc = dev_alloc(&v.y, (size_t)std::max(v.n, 1), "AMG work")))
-            return fail(rc);
-        if (cur.n <= coarse_size || l + 1 == max_levels) break;
-        std::vector<int> agg;
-        const int na = aggregate(cur, d, th, agg);
-        if ((double)na > 0.6 * (double)cur.n) break;
-        const Csr P = prolongator(cur, d, agg, na, v.omega);
-        const Csr R = transpose(P);
-        Csr next = multiply(R, multiply(cur, P));
-        v.nc = na;
-        v.agg = std::move(agg);
-        v.gp = lanes_for(P.col.size(), P.n);
-        v.gr = lanes_for(R.col.size(), R.n);
-        if ((rc = upload(&v.p_ptr, P.ptr, "AMG prolongator", s)) || (rc = upload(&v.p_col, P.col, "AMG prolongator", s)) ||
-            (rc = upload(&v.p_val, P.val, "AMG prolongator", s)) || (rc = upload(&v.r_ptr, R.ptr, "AMG restriction", s)) ||
-            (rc = upload(&v.r_col, R.col, "AMG restriction", s)) || (rc = upload(&v.r_val, R.val, "AMG restriction", s)))
-            return fail(rc);
-        FV_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
-        cur = std::move(next);
-        th *= 0.5;
-        ++l;
-    }
-    h->nlev = l + 1;
-    h->nlast = cur.n;
-    if (cur.n > kAmgMaxCoarse)
-        return fail(set_error(FVPCG_UNSUPPORTED, "AMG: last level has %d unknowns (at most %d are solved exactly)",
-                              cur.n, kAmgMaxCoarse));
-    std::vector<double> inv;
-    if (!spd_inverse(cur, inv))
-        return fail(set_error(FVPCG_BREAKDOWN, "AMG: the last level is not positive definite"));
-    if ((rc = upload(&h->cinv, inv, "AMG coarse inverse", s))) return fail(rc);
-    const size_t n0 = (size_t)std::max(A->mesh->n, 1);
-    if ((rc = dev_alloc(&h->r, n0, "AMG-PCG vectors")) || (rc = dev_alloc(&h->z, n0, "AMG-PCG vectors")) ||
-        (rc = dev_alloc(&h->p, n0, "AMG-PCG vectors")) || (rc = dev_alloc(&h->q, n0, "AMG-PCG vectors")) ||
-        (rc = dev_alloc(&h->st, 1, "AMG-PCG state")) || (rc = dev_alloc(&h->partials, (size_t)4 * kMaxGrid, "partials")))
-        return fail(rc);
-    if (hipHostMalloc((void**)&h->hst, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
-        h->hst = nullptr;
-        return fail(set_error(FVPCG_OUT_OF_MEMORY, "pinned allocation failed"));
-    }
-    FV_HIP(hipMemsetAsync(h->st, 0, sizeof(DevState), s));
-    hipEvent_t* evs[] = {&h->t_begin, &h->t_end, &h->t_it0, &h->t_it1};
-    for (hipEvent_t* e : evs) FV_HIP(hipEventCreate(e));
+int amg_levels(const fvpcg_amg* h) { return h->nlev; }
+int amg_level_n(const fvpcg_amg* h, int l) { return h->lev[l].n; }
+long long amg_level_nnz(const fvpcg_amg* h, int l) { return h->lev[l].nnz; }
+int amg_level_agg(const fvpcg_amg* h, int l, int* host_out, hipStream_t s) {
+    if (!h->lev[l].agg) return set_error(FVPCG_INVALID_ARG, "level %d has no aggregates", l);
+    FV_HIP(hipMemcpyAsync(host_out, h->lev[l].agg, sizeof(int) * (size_t)h->lev[l].n, hipMemcpyDeviceToHost, s));
     FV_HIP(hipStreamSynchronize(s));
     return FVPCG_OK;
 }
 
-int amg_levels(const fvpcg_amg* h) { return h->nlev; }
-int amg_level_n(const fvpcg_amg* h, int l) { return h->lev[l].n; }
-long long amg_level_nnz(const fvpcg_amg* h, int l) { return h->lev[l].nnz; }
-const int* amg_level_agg(const fvpcg_amg* h, int l) { return h->lev[l].agg.empty() ? nullptr : h->lev[l].agg.data(); }
+// Level l's operator (which 0, levels >= 1), prolongator (1) or restriction
+// (2) as CSR into host arrays (NULL arrays: sizes only).
+int amg_export(const fvpcg_amg* h, int l, int which, int* rows, int* cols, long long* nnz, int* ptr, int* col,
+               double* val, hipStream_t s) {
+    const AmgLevel& v = h->lev[l];
+    const int *dp, *dc;
+    const double* dv;
+    if (which == 0) {
+        if (l == 0) return set_error(FVPCG_INVALID_ARG, "level 0's operator is the matrix itself (ELL layout)");
+        *rows = *cols = v.n;
+        *nnz = v.nnz;
+        dp = v.a_ptr, dc = v.a_col, dv = v.a_val;
+    } else if (l + 1 < h->nlev && (which == 1 || which == 2)) {
+        *rows = which == 1 ? v.n : v.nc;
+        *cols = which == 1 ? v.nc : v.n;
+        *nnz = v.p_nnz;
+        dp = which == 1 ? v.p_ptr : v.r_ptr;
+        dc = which == 1 ? v.p_col : v.r_col;
+        dv = which == 1 ? v.p_val : v.r_val;
+    } else {
+        return set_error(FVPCG_INVALID_ARG, "level %d has no %s", l, which == 1 || which == 2 ? "coarser level" : "such operator");
+    }
+    if (ptr) FV_HIP(hipMemcpyAsync(ptr, dp, sizeof(int) * ((size_t)*rows + 1), hipMemcpyDeviceToHost, s));
+    if (col) FV_HIP(hipMemcpyAsync(col, dc, sizeof(int) * (size_t)*nnz, hipMemcpyDeviceToHost, s));
+    if (val) FV_HIP(hipMemcpyAsync(val, dv, sizeof(double) * (size_t)*nnz, hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    return FVPCG_OK;
+}
+
+// The hierarchy holds coarse operators formed from the coefficients at
+// setup; after the matrix is updated they describe another operator.
+static int check_generation(const fvpcg_amg* h) {
+    if (h->generation != h->mat->generation)
+        return set_error(FVPCG_INVALID_ARG,
+                         "the matrix was updated after this AMG hierarchy was built; create the AMG again");
+    return FVPCG_OK;
+}
 
 // z = M^-1 r (one cycle)
 int amg_apply(const fvpcg_amg* ch, const double* r, double* z, hipStream_t s) {
     fvpcg_amg* h = const_cast<fvpcg_amg*>(ch);
     int rc;
+    if ((rc = check_generation(h))) return rc;
     if ((rc = state_put(h, 0.0, 1, s))) return rc;
     if ((rc = enqueue_cycle(h, r, z, false, false, h->st, s))) return rc;
     FV_HIP(hipStreamSynchronize(s));
@@ -1041,6 +663,7 @@ int solve_amg(const fvpcg_amg* ch, const double* b, double* x, double tol, int m
     const Geom g = geom_for(n, kAmgBs);
     DevState* st = h->st;
     int rc;
+    if ((rc = check_generation(h))) return rc;
     FV_HIP(hipEventRecord(h->t_begin, s));
     if ((rc = state_put(h, tol, maxit, s))) return rc;
     FV_LAYOUT(m, hipLaunchKernelGGL((k_apcg_init<kAmgBs, W_, CI_>), dim3(g.grid), dim3(kAmgBs), 0, s, cols_, A->val,

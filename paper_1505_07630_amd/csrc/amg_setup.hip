@@ -1,0 +1,899 @@
+// Smoothed-aggregation AMG: the hierarchy built on the device (the method is
+// stated in amg.hpp).
+//
+// Per level, from the level's CSR operator:
+//   k_lvl_diag      diagonal, Gershgorin ratio sum_j |a_ij| / a_ii and its
+//                   maximum (an unsigned max over the bit patterns of the
+//                   non-negative ratios: exact, order-free);
+//   k_strength      the strength mask of every stored entry;
+//   k_mis_*         the distance-2 maximal independent set in rounds: two
+//                   sweeps of neighbourhood maxima over 64-bit keys (state,
+//                   priority, index) give each unknown the largest key within
+//                   two strong steps; an undecided unknown whose own key is
+//                   that maximum becomes a root, one that sees a root drops
+//                   out; the host repeats until none is undecided;
+//   k_agg_round1/2  the aggregates (roots numbered by an exclusive scan);
+//   P = S P_t, R = P^T, A P, A_c = R (A P): sparse products by a row-wise
+//                   k-way merge (one thread per output row keeps a binary heap
+//                   of the heads of the rows of the right operand that the
+//                   left row selects, keyed by (column, list index); equal
+//                   columns are summed in list order, so every entry is summed
+//                   in the left row's column order), R by counting, scatter
+//                   and a per-row heapsort;
+//   last level      dense, inverted by Gauss-Jordan elimination in one
+//                   workgroup (SPD: no pivoting; a non-positive pivot is a
+//                   breakdown).
+// Every result is a function of the operator and the seed: no floating-point
+// atomics, integer atomics only for counts and for slot positions that a
+// sort puts in order afterwards.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "amg.hpp"
+
+namespace fvpcg {
+
+namespace {
+
+constexpr int kSetupBs = 256;
+constexpr int kScanTile = 1024;  // elements per workgroup in the scan (4 per thread)
+constexpr int kMaxMisRounds = 4096;
+constexpr uint64_t kKeyMask = (1ull << 62) - 1;  // priority and index below the 2-bit state
+constexpr uint64_t kUndecided = 1ull << 62, kRoot = 2ull << 62;
+
+int grid1d(long long work) {
+    long long g = (work + kSetupBs - 1) / kSetupBs;
+    return (int)std::max(1LL, std::min(g, 65536LL));
+}
+
+#define FV_GRID_LOOP(i, n) \
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
+
+// Device buffer owned by one setup step.
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { dev_free(p); }
+    int alloc(size_t count, const char* what) {
+        dev_free(p);
+        return dev_alloc(&p, count, what);
+    }
+    void reset() { dev_free(p); }
+};
+
+template <typename T>
+int read_scalar(T* host, const T* dev, hipStream_t s) {
+    FV_HIP(hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    return FVPCG_OK;
+}
+
+// ---------------------------------------------------------------- scan
+// out[i] = sum_{k < i} in[k] for i <= n (out has n + 1 entries).  Each
+// workgroup scans a tile of 1024 (four consecutive elements per thread, the
+// thread totals by a Hillis-Steele scan in LDS) and writes its total; the
+// tile totals are scanned the same way and added back.
+template <typename T>
+__global__ __launch_bounds__(kSetupBs) void k_scan_tile(const T* __restrict__ in, long long n, T* __restrict__ out,
+                                                        T* __restrict__ tile_sum) {
+    __shared__ T s[kSetupBs];
+    const long long base = (long long)blockIdx.x * kScanTile + 4 * (long long)threadIdx.x;
+    T v[4];
+    T t = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = base + k < n ? in[base + k] : T(0);
+        t += v[k];
+    }
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int off = 1; off < kSetupBs; off <<= 1) {
+        const T a = (int)threadIdx.x >= off ? s[threadIdx.x - off] : T(0);
+        __syncthreads();
+        s[threadIdx.x] += a;
+        __syncthreads();
+    }
+    T run = s[threadIdx.x] - t;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == kSetupBs - 1) tile_sum[blockIdx.x] = s[kSetupBs - 1];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSetupBs) void k_scan_add(T* __restrict__ out, long long n, const T* __restrict__ tile_off) {
+    FV_GRID_LOOP(i, n) out[i] += tile_off[i / kScanTile];
+}
+
+template <typename T>
+__global__ void k_scan_total(T* __restrict__ out, long long n, const T* __restrict__ src) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = src[0];
+}
+
+template <typename T>
+int scan_excl(const T* in, T* out, long long n, hipStream_t s) {
+    const long long tiles = std::max(1LL, (n + kScanTile - 1) / kScanTile);
+    DevBuf<T> tsum, toff;
+    int rc;
+    if ((rc = tsum.alloc((size_t)tiles, "scan tile sums"))) return rc;
+    hipLaunchKernelGGL((k_scan_tile<T>), dim3((unsigned)tiles), dim3(kSetupBs), 0, s, in, n, out, tsum.p);
+    FV_LAUNCHED();
+    if (tiles == 1) {
+        hipLaunchKernelGGL((k_scan_total<T>), dim3(1), dim3(64), 0, s, out, n, tsum.p);
+        FV_LAUNCHED();
+        FV_HIP(hipStreamSynchronize(s));  // the tile buffer is freed on return
+        return FVPCG_OK;
+    }
+    if ((rc = toff.alloc((size_t)tiles + 1, "scan tile offsets"))) return rc;
+    if ((rc = scan_excl<T>(tsum.p, toff.p, tiles, s))) return rc;
+    hipLaunchKernelGGL((k_scan_add<T>), dim3(grid1d(n)), dim3(kSetupBs), 0, s, out, n, toff.p);
+    hipLaunchKernelGGL((k_scan_total<T>), dim3(1), dim3(64), 0, s, out, n, toff.p + tiles);
+    FV_LAUNCHED();
+    FV_HIP(hipStreamSynchronize(s));  // the tile buffers are freed on return
+    return FVPCG_OK;
+}
+
+// ---------------------------------------------------------------- level 0
+// Level 0 as CSR from the ELL layout: the diagonal at its sorted place among
+// the row's slots (sorted by column; padding repeats the row and is skipped).
+__global__ __launch_bounds__(kSetupBs) void k_l0_count(const int* __restrict__ col, int n, int W, int* __restrict__ cnt) {
+    FV_GRID_LOOP(c, n) {
+        int k = 1;
+        for (int s = 0; s < W; ++s) k += col[(size_t)s * n + c] != (int)c;
+        cnt[c] = k;
+    }
+}
+
+__global__ __launch_bounds__(kSetupBs) void k_l0_fill(const int* __restrict__ col, const double* __restrict__ val,
+                                                     const double* __restrict__ d, int n, int W,
+                                                     const int* __restrict__ ptr, int* __restrict__ ocol,
+                                                     double* __restrict__ oval) {
+    FV_GRID_LOOP(c, n) {
+        int p = ptr[c];
+        bool diag = false;
+        for (int s = 0; s < W; ++s) {
+            const int j = col[(size_t)s * n + c];
+            if (j == (int)c) continue;
+            if (!diag && j > (int)c) {
+                ocol[p] = (int)c;
+                oval[p++] = d[c];
+                diag = true;
+            }
+            ocol[p] = j;
+            oval[p++] = val[(size_t)s * n + c];
+        }
+        if (!diag) {
+            ocol[p] = (int)c;
+            oval[p] = d[c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- per level
+// d_i = a_ii; ratio_i = (sum_j |a_ij|) / a_ii, summed in column order; the
+// largest ratio as the maximum of the bit patterns (non-negative doubles
+// order like their bits).  bad: a diagonal that is not finite and positive.
+__global__ __launch_bounds__(kSetupBs) void k_lvl_diag(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                      const double* __restrict__ val, int n, double* __restrict__ d,
+                                                      unsigned long long* rho_bits, int* bad) {
+    unsigned long long mx = 0;
+    int b = 0;
+    FV_GRID_LOOP(i, n) {
+        double di = 0.0, sa = 0.0;
+        for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+            if (col[p] == (int)i) di = val[p];
+            sa += fabs(val[p]);
+        }
+        d[i] = di;
+        if (!(di > 0.0) || !isfinite(di) || !isfinite(sa)) {
+            b = 1;
+        } else {
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(sa / di);
+            mx = bits > mx ? bits : mx;
+        }
+    }
+    if (mx) atomicMax(rho_bits, mx);
+    if (b) atomicOr(bad, 1);
+}
+
+// a_ij / d_j (the coarse levels' column-scaled values)
+__global__ __launch_bounds__(kSetupBs) void k_lvl_colscale(const int* __restrict__ col, const double* __restrict__ val,
+                                                          const double* __restrict__ d, long long nnz,
+                                                          double* __restrict__ cs) {
+    FV_GRID_LOOP(p, nnz) cs[p] = val[p] / d[col[p]];
+}
+
+// strong[p]: entry p of row i couples i to j = col[p] != i with a_ij != 0
+// and |a_ij| >= theta sqrt(|a_ii a_jj|)
+__global__ __launch_bounds__(kSetupBs) void k_strength(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                      const double* __restrict__ val, const double* __restrict__ d,
+                                                      int n, double theta, uint8_t* __restrict__ strong) {
+    FV_GRID_LOOP(i, n) {
+        for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+            const int j = col[p];
+            const double a = val[p];
+            strong[p] = (j != (int)i && a != 0.0 && fabs(a) >= theta * sqrt(fabs(d[i] * d[j]))) ? 1 : 0;
+        }
+    }
+}
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) as a counter-based
+// generator: element k of the sequence started at `seed` is the finaliser
+// applied to seed + (k + 1) * 0x9E3779B97F4A7C15.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// key = state (2 bits: 0 out, 1 undecided, 2 root) | 31 random bits | index
+__global__ __launch_bounds__(kSetupBs) void k_mis_init(int n, uint64_t seed, int level, uint64_t* __restrict__ key) {
+    FV_GRID_LOOP(i, n) {
+        const uint64_t r = splitmix64_at(seed, ((uint64_t)(uint32_t)level << 32) | (uint64_t)i) >> 33;
+        key[i] = kUndecided | (r << 31) | (uint64_t)i;
+    }
+}
+
+// out_i = max(in_i, in_j over strong neighbours j)
+__global__ __launch_bounds__(kSetupBs) void k_mis_max(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                     const uint8_t* __restrict__ strong, int n,
+                                                     const uint64_t* __restrict__ in, uint64_t* __restrict__ out) {
+    FV_GRID_LOOP(i, n) {
+        uint64_t m = in[i];
+        for (int p = ptr[i]; p < ptr[i + 1]; ++p)
+            if (strong[p]) {
+                const uint64_t v = in[col[p]];
+                m = v > m ? v : m;
+            }
+        out[i] = m;
+    }
+}
+
+// m2_i: the largest key within two strong steps of i.
+__global__ __launch_bounds__(kSetupBs) void k_mis_decide(int n, uint64_t* __restrict__ key,
+                                                        const uint64_t* __restrict__ m2, int* undecided) {
+    int left = 0;
+    FV_GRID_LOOP(i, n) {
+        const uint64_t k = key[i];
+        if ((k & ~kKeyMask) != kUndecided) continue;
+        const uint64_t m = m2[i];
+        if (m == k)
+            key[i] = (k & kKeyMask) | kRoot;
+        else if ((m & ~kKeyMask) == kRoot)
+            key[i] = k & kKeyMask;
+        else
+            ++left;
+    }
+    if (left) atomicAdd(undecided, left);
+}
+
+__global__ __launch_bounds__(kSetupBs) void k_root_flags(int n, const uint64_t* __restrict__ key, int* __restrict__ f) {
+    FV_GRID_LOOP(i, n) f[i] = (key[i] & ~kKeyMask) == kRoot ? 1 : 0;
+}
+
+// round 1: roots take their rank; others the aggregate of a root neighbour
+__global__ __launch_bounds__(kSetupBs) void k_agg_round1(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                        const uint8_t* __restrict__ strong, int n,
+                                                        const uint64_t* __restrict__ key, const int* __restrict__ rank,
+                                                        int* __restrict__ agg1) {
+    FV_GRID_LOOP(i, n) {
+        int a = -1;
+        if ((key[i] & ~kKeyMask) == kRoot) {
+            a = rank[i];
+        } else {
+            for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+                const int j = col[p];
+                if (strong[p] && (key[j] & ~kKeyMask) == kRoot) {
+                    a = rank[j];
+                    break;
+                }
+            }
+        }
+        agg1[i] = a;
+    }
+}
+
+// round 2: the rest join the round-1 aggregate of the strong neighbour with
+// the largest |a_ij| (columns ascend in the row: the first wins ties)
+__global__ __launch_bounds__(kSetupBs) void k_agg_round2(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                        const double* __restrict__ val,
+                                                        const uint8_t* __restrict__ strong, int n,
+                                                        const int* __restrict__ agg1, int* __restrict__ agg,
+                                                        int* missing) {
+    FV_GRID_LOOP(i, n) {
+        int a = agg1[i];
+        if (a < 0) {
+            double best = -1.0;
+            for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+                const int j = col[p];
+                if (!strong[p] || agg1[j] < 0) continue;
+                const double w = fabs(val[p]);
+                if (w > best) {
+                    best = w;
+                    a = agg1[j];
+                }
+            }
+            if (a < 0) {
+                atomicOr(missing, 1);
+                a = 0;
+            }
+        }
+        agg[i] = a;
+    }
+}
+
+// rows of S = I - omega D^-1 A (the pattern of A)
+__global__ __launch_bounds__(kSetupBs) void k_smoother_rows(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                           const double* __restrict__ val, const double* __restrict__ d,
+                                                           int n, double omega, double* __restrict__ sval) {
+    FV_GRID_LOOP(i, n) {
+        for (int p = ptr[i]; p < ptr[i + 1]; ++p)
+            sval[p] = (col[p] == (int)i ? 1.0 : 0.0) - omega * val[p] / d[i];
+    }
+}
+
+// P_t: row i holds (agg_i, 1)
+__global__ __launch_bounds__(kSetupBs) void k_tentative(int n, int* __restrict__ ptr, double* __restrict__ ones) {
+    FV_GRID_LOOP(i, n + 1) {
+        ptr[i] = (int)i;
+        if (i < n) ones[i] = 1.0;
+    }
+}
+
+// ---------------------------------------------------------------- products
+// Upper bound of the entries of row i of X Y: the lengths of the rows of Y
+// that row i of X selects.
+__global__ __launch_bounds__(kSetupBs) void k_gemm_bound(const int* __restrict__ xptr, const int* __restrict__ xcol,
+                                                        const int* __restrict__ yptr, int rows,
+                                                        long long* __restrict__ ub) {
+    FV_GRID_LOOP(i, rows) {
+        long long t = 0;
+        for (int p = xptr[i]; p < xptr[i + 1]; ++p) t += yptr[xcol[p] + 1] - yptr[xcol[p]];
+        ub[i] = t;
+    }
+}
+
+// binary min-heap of 64-bit keys
+__device__ __forceinline__ void heap_up(unsigned long long* H, int i) {
+    const unsigned long long v = H[i];
+    while (i > 0) {
+        const int q = (i - 1) >> 1;
+        const unsigned long long pv = H[q];
+        if (pv <= v) break;
+        H[i] = pv;
+        i = q;
+    }
+    H[i] = v;
+}
+
+__device__ __forceinline__ void heap_down(unsigned long long* H, int h, int i) {
+    const unsigned long long v = H[i];
+    for (;;) {
+        int c = 2 * i + 1;
+        if (c >= h) break;
+        unsigned long long cv = H[c];
+        if (c + 1 < h) {
+            const unsigned long long rv = H[c + 1];
+            if (rv < cv) {
+                ++c;
+                cv = rv;
+            }
+        }
+        if (cv >= v) break;
+        H[i] = cv;
+        i = c;
+    }
+    H[i] = v;
+}
+
+#pragma clang fp contract(off)
+// Row i of C = X Y by a k-way merge of the rows Y(k, :) for k in X(i, :):
+// the heap holds (column << 32 | list index) of each list's head; popping
+// yields the columns in ascending order and, for equal columns, the lists in
+// X's column order, in which their products are summed (each product
+// rounded, then added).  Output: the row's distinct columns and sums at
+// off[i] in (tcol, tval) and its count.  heap/pos: scratch indexed like X.
+__global__ __launch_bounds__(kSetupBs) void k_gemm_merge(const int* __restrict__ xptr, const int* __restrict__ xcol,
+                                                        const double* __restrict__ xval, const int* __restrict__ yptr,
+                                                        const int* __restrict__ ycol, const double* __restrict__ yval,
+                                                        int rows, const long long* __restrict__ off,
+                                                        unsigned long long* __restrict__ heap, int* __restrict__ pos,
+                                                        int* __restrict__ tcol, double* __restrict__ tval,
+                                                        int* __restrict__ cnt) {
+    FV_GRID_LOOP(i, rows) {
+        const int base = xptr[i], L = xptr[i + 1] - base;
+        unsigned long long* H = heap + base;
+        int* P = pos + base;
+        int h = 0;
+        for (int t = 0; t < L; ++t) {
+            const int k = xcol[base + t];
+            const int b = yptr[k];
+            if (b < yptr[k + 1]) {
+                P[t] = b;
+                H[h] = ((unsigned long long)(unsigned)ycol[b] << 32) | (unsigned)t;
+                heap_up(H, h);
+                ++h;
+            }
+        }
+        const long long o = off[i];
+        int out = 0, last = -1;
+        double acc = 0.0;
+        while (h > 0) {
+            const unsigned long long top = H[0];
+            const int c = (int)(top >> 32), t = (int)(top & 0xffffffffu);
+            const int k = xcol[base + t];
+            int p = P[t];
+            const double v = xval[base + t] * yval[p];
+            if (c == last) {
+                acc += v;
+            } else {
+                if (last >= 0) {
+                    tcol[o + out] = last;
+                    tval[o + out] = acc;
+                    ++out;
+                }
+                last = c;
+                acc = v;
+            }
+            ++p;
+            if (p < yptr[k + 1]) {
+                P[t] = p;
+                H[0] = ((unsigned long long)(unsigned)ycol[p] << 32) | (unsigned)t;
+                heap_down(H, h, 0);
+            } else if (--h > 0) {
+                H[0] = H[h];
+                heap_down(H, h, 0);
+            }
+        }
+        if (last >= 0) {
+            tcol[o + out] = last;
+            tval[o + out] = acc;
+            ++out;
+        }
+        cnt[i] = out;
+    }
+}
+#pragma clang fp contract(on)
+
+__global__ __launch_bounds__(kSetupBs) void k_gemm_compact(int rows, const long long* __restrict__ off,
+                                                          const int* __restrict__ cnt, const int* __restrict__ cptr,
+                                                          const int* __restrict__ tcol, const double* __restrict__ tval,
+                                                          int* __restrict__ ccol, double* __restrict__ cval) {
+    FV_GRID_LOOP(i, rows) {
+        const long long o = off[i];
+        const int q = cptr[i];
+        for (int k = 0; k < cnt[i]; ++k) {
+            ccol[q + k] = tcol[o + k];
+            cval[q + k] = tval[o + k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- transpose
+__global__ __launch_bounds__(kSetupBs) void k_col_count(const int* __restrict__ col, long long nnz, int* __restrict__ cnt) {
+    FV_GRID_LOOP(p, nnz) atomicAdd(&cnt[col[p]], 1);
+}
+
+__global__ __launch_bounds__(kSetupBs) void k_tr_scatter(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                        const double* __restrict__ val, int rows,
+                                                        const int* __restrict__ tptr, int* __restrict__ cursor,
+                                                        int* __restrict__ tcol, double* __restrict__ tval) {
+    FV_GRID_LOOP(i, rows) {
+        for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+            const int c = col[p];
+            const int q = tptr[c] + atomicAdd(&cursor[c], 1);
+            tcol[q] = (int)i;
+            tval[q] = val[p];
+        }
+    }
+}
+
+__device__ __forceinline__ void sift_max(int* a, double* v, int i, int n) {
+    const int ka = a[i];
+    const double kv = v[i];
+    for (;;) {
+        int c = 2 * i + 1;
+        if (c >= n) break;
+        if (c + 1 < n && a[c + 1] > a[c]) ++c;
+        if (a[c] <= ka) break;
+        a[i] = a[c];
+        v[i] = v[c];
+        i = c;
+    }
+    a[i] = ka;
+    v[i] = kv;
+}
+
+// each row sorted by column (distinct columns: the order is unique)
+__global__ __launch_bounds__(kSetupBs) void k_row_heapsort(const int* __restrict__ ptr, int rows, int* __restrict__ col,
+                                                          double* __restrict__ val) {
+    FV_GRID_LOOP(i, rows) {
+        int* a = col + ptr[i];
+        double* v = val + ptr[i];
+        const int n = ptr[i + 1] - ptr[i];
+        for (int s = n / 2 - 1; s >= 0; --s) sift_max(a, v, s, n);
+        for (int e = n - 1; e > 0; --e) {
+            const int ta = a[0];
+            const double tv = v[0];
+            a[0] = a[e];
+            v[0] = v[e];
+            a[e] = ta;
+            v[e] = tv;
+            sift_max(a, v, 0, e);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- last level
+__global__ __launch_bounds__(kSetupBs) void k_dense_zero(int n, double* __restrict__ M) {
+    FV_GRID_LOOP(e, (long long)n * n) M[e] = 0.0;
+}
+
+__global__ __launch_bounds__(kSetupBs) void k_dense_fill(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                        const double* __restrict__ val, int n, double* __restrict__ M) {
+    FV_GRID_LOOP(i, n) {
+        for (int p = ptr[i]; p < ptr[i + 1]; ++p) M[(size_t)i * n + col[p]] = val[p];
+    }
+}
+
+// In-place Gauss-Jordan inverse of an SPD matrix by one workgroup: for each
+// pivot k, row k is divided by a_kk (its k-th entry becoming 1 / a_kk), then
+// every other row i loses a_ik times the new row k (its k-th entry becoming
+// -a_ik / a_kk).  f holds column k before the step.  bad = 1 on a pivot that
+// is not finite and positive (every thread reads the same pivot).
+constexpr int kGjBs = 1024;
+__global__ __launch_bounds__(kGjBs) void k_gauss_jordan(double* __restrict__ M, int n, double* __restrict__ f,
+                                                       int* bad) {
+    for (int k = 0; k < n; ++k) {
+        __syncthreads();
+        const double piv = M[(size_t)k * n + k];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+            if (threadIdx.x == 0) *bad = 1;
+            return;
+        }
+        for (int i = threadIdx.x; i < n; i += kGjBs) f[i] = M[(size_t)i * n + k];
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += kGjBs) M[(size_t)k * n + j] = (j == k ? 1.0 : M[(size_t)k * n + j]) / piv;
+        __syncthreads();
+        const long long nn = (long long)n * n;
+        for (long long e = threadIdx.x; e < nn; e += kGjBs) {
+            const int i = (int)(e / n), j = (int)(e - (long long)i * n);
+            if (i == k) continue;
+            M[e] = (j == k ? 0.0 : M[e]) - f[i] * M[(size_t)k * n + j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host side
+
+// A level's operator as CSR on the device (not owned).
+struct CsrView {
+    int n = 0, m = 0;
+    long long nnz = 0;
+    const int* ptr = nullptr;
+    const int* col = nullptr;
+    const double* val = nullptr;
+};
+
+// Owned CSR result of a product.
+struct CsrOut {
+    int n = 0, m = 0;
+    long long nnz = 0;
+    int *ptr = nullptr, *col = nullptr;
+    double* val = nullptr;
+    void release() {
+        dev_free(ptr);
+        dev_free(col);
+        dev_free(val);
+    }
+};
+
+// C = X Y (rows of X, columns of Y); C's arrays are allocated here.
+int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s) {
+    int rc;
+    const int rows = X.n;
+    DevBuf<long long> ub, off;
+    DevBuf<int> cnt;
+    if ((rc = ub.alloc((size_t)rows, "product bounds")) || (rc = off.alloc((size_t)rows + 1, "product offsets")) ||
+        (rc = cnt.alloc((size_t)rows + 1, "product counts")))
+        return rc;
+    hipLaunchKernelGGL(k_gemm_bound, dim3(grid1d(rows)), dim3(kSetupBs), 0, s, X.ptr, X.col, Y.ptr, rows, ub.p);
+    FV_LAUNCHED();
+    if ((rc = scan_excl<long long>(ub.p, off.p, rows, s))) return rc;
+    long long total = 0;
+    if ((rc = read_scalar(&total, off.p + rows, s))) return rc;
+    DevBuf<unsigned long long> heap;
+    DevBuf<int> pos, tcol;
+    DevBuf<double> tval;
+    if ((rc = heap.alloc((size_t)std::max(X.nnz, 1LL), "product heaps")) ||
+        (rc = pos.alloc((size_t)std::max(X.nnz, 1LL), "product positions")) ||
+        (rc = tcol.alloc((size_t)std::max(total, 1LL), "product columns")) ||
+        (rc = tval.alloc((size_t)std::max(total, 1LL), "product values")))
+        return rc;
+    hipLaunchKernelGGL(k_gemm_merge, dim3(grid1d(rows)), dim3(kSetupBs), 0, s, X.ptr, X.col, X.val, Y.ptr, Y.col,
+                       Y.val, rows, off.p, heap.p, pos.p, tcol.p, tval.p, cnt.p);
+    FV_LAUNCHED();
+    C.n = rows;
+    C.m = Y.m;
+    if ((rc = dev_alloc(&C.ptr, (size_t)rows + 1, "product row pointers"))) return rc;
+    // counts fit in int: a row's distinct columns are at most Y.m
+    if ((rc = scan_excl<int>(cnt.p, C.ptr, rows, s))) return rc;
+    int nnz = 0;
+    if ((rc = read_scalar(&nnz, C.ptr + rows, s))) return rc;
+    if (nnz < 0) return set_error(FVPCG_UNSUPPORTED, "AMG: a coarse operator exceeds 2^31 entries");
+    C.nnz = nnz;
+    if ((rc = dev_alloc(&C.col, (size_t)std::max(nnz, 1), "product columns")) ||
+        (rc = dev_alloc(&C.val, (size_t)std::max(nnz, 1), "product values")))
+        return rc;
+    hipLaunchKernelGGL(k_gemm_compact, dim3(grid1d(rows)), dim3(kSetupBs), 0, s, rows, off.p, cnt.p, C.ptr, tcol.p,
+                       tval.p, C.col, C.val);
+    FV_LAUNCHED();
+    FV_HIP(hipStreamSynchronize(s));  // the scratch buffers are freed on return
+    return FVPCG_OK;
+}
+
+// T = X^T, rows sorted by column
+int transpose(const CsrView& X, CsrOut& T, hipStream_t s) {
+    int rc;
+    DevBuf<int> cnt, cursor;
+    if ((rc = cnt.alloc((size_t)X.m + 1, "transpose counts")) || (rc = cursor.alloc((size_t)X.m, "transpose cursor")))
+        return rc;
+    FV_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * ((size_t)X.m + 1), s));
+    FV_HIP(hipMemsetAsync(cursor.p, 0, sizeof(int) * (size_t)std::max(X.m, 1), s));
+    hipLaunchKernelGGL(k_col_count, dim3(grid1d(X.nnz)), dim3(kSetupBs), 0, s, X.col, X.nnz, cnt.p);
+    FV_LAUNCHED();
+    T.n = X.m;
+    T.m = X.n;
+    T.nnz = X.nnz;
+    if ((rc = dev_alloc(&T.ptr, (size_t)X.m + 1, "transpose rows")) ||
+        (rc = dev_alloc(&T.col, (size_t)std::max(X.nnz, 1LL), "transpose columns")) ||
+        (rc = dev_alloc(&T.val, (size_t)std::max(X.nnz, 1LL), "transpose values")))
+        return rc;
+    if ((rc = scan_excl<int>(cnt.p, T.ptr, X.m, s))) return rc;
+    hipLaunchKernelGGL(k_tr_scatter, dim3(grid1d(X.n)), dim3(kSetupBs), 0, s, X.ptr, X.col, X.val, X.n, T.ptr,
+                       cursor.p, T.col, T.val);
+    hipLaunchKernelGGL(k_row_heapsort, dim3(grid1d(T.n)), dim3(kSetupBs), 0, s, T.ptr, T.n, T.col, T.val);
+    FV_LAUNCHED();
+    FV_HIP(hipStreamSynchronize(s));
+    return FVPCG_OK;
+}
+
+CsrView view(const CsrOut& c) { return {c.n, c.m, c.nnz, c.ptr, c.col, c.val}; }
+
+// The aggregates of one level (agg: n entries, owned by the level); returns
+// the aggregate count in *na.
+int aggregate_level(const CsrView& A, const double* d, double theta, uint64_t seed, int level, int* agg, int* na,
+                    hipStream_t s) {
+    int rc;
+    const int n = A.n;
+    DevBuf<uint8_t> strong;
+    DevBuf<uint64_t> key, m1, m2;
+    DevBuf<int> counter, flags, rank, agg1;
+    if ((rc = strong.alloc((size_t)std::max(A.nnz, 1LL), "AMG strength")) ||
+        (rc = key.alloc((size_t)n, "AMG keys")) || (rc = m1.alloc((size_t)n, "AMG key maxima")) ||
+        (rc = m2.alloc((size_t)n, "AMG key maxima")) || (rc = counter.alloc(2, "AMG counters")))
+        return rc;
+    const int g = grid1d(n);
+    hipLaunchKernelGGL(k_strength, dim3(g), dim3(kSetupBs), 0, s, A.ptr, A.col, A.val, d, n, theta, strong.p);
+    hipLaunchKernelGGL(k_mis_init, dim3(g), dim3(kSetupBs), 0, s, n, seed, level, key.p);
+    FV_LAUNCHED();
+    int left = 1, rounds = 0;
+    while (left > 0) {
+        if (++rounds > kMaxMisRounds)
+            return set_error(FVPCG_DEVICE_ERROR, "AMG: the independent set did not settle in %d rounds", kMaxMisRounds);
+        FV_HIP(hipMemsetAsync(counter.p, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_mis_max, dim3(g), dim3(kSetupBs), 0, s, A.ptr, A.col, strong.p, n, key.p, m1.p);
+        hipLaunchKernelGGL(k_mis_max, dim3(g), dim3(kSetupBs), 0, s, A.ptr, A.col, strong.p, n, m1.p, m2.p);
+        hipLaunchKernelGGL(k_mis_decide, dim3(g), dim3(kSetupBs), 0, s, n, key.p, m2.p, counter.p);
+        FV_LAUNCHED();
+        if ((rc = read_scalar(&left, counter.p, s))) return rc;
+    }
+    if ((rc = flags.alloc((size_t)n, "AMG root flags")) || (rc = rank.alloc((size_t)n + 1, "AMG root ranks")) ||
+        (rc = agg1.alloc((size_t)n, "AMG round-1 aggregates")))
+        return rc;
+    hipLaunchKernelGGL(k_root_flags, dim3(g), dim3(kSetupBs), 0, s, n, key.p, flags.p);
+    FV_LAUNCHED();
+    if ((rc = scan_excl<int>(flags.p, rank.p, n, s))) return rc;
+    if ((rc = read_scalar(na, rank.p + n, s))) return rc;
+    hipLaunchKernelGGL(k_agg_round1, dim3(g), dim3(kSetupBs), 0, s, A.ptr, A.col, strong.p, n, key.p, rank.p, agg1.p);
+    FV_HIP(hipMemsetAsync(counter.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_agg_round2, dim3(g), dim3(kSetupBs), 0, s, A.ptr, A.col, A.val, strong.p, n, agg1.p, agg,
+                       counter.p);
+    FV_LAUNCHED();
+    int missing = 0;
+    if ((rc = read_scalar(&missing, counter.p, s))) return rc;
+    if (missing) return set_error(FVPCG_DEVICE_ERROR, "AMG: an unknown was left out of every aggregate");
+    return FVPCG_OK;
+}
+
+}  // namespace
+
+int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, uint64_t seed,
+              hipStream_t s) {
+    int rc;
+    const fvpcg_mesh* msh = A->mesh;
+    const int n0 = msh->n, W = msh->W;
+    h->generation = A->generation;
+    max_levels = std::max(1, std::min(max_levels, kAmgMaxLevels));
+    // level 0 as CSR (freed once level 1 exists; the cycle uses the ELL layout)
+    CsrOut A0;
+    struct Release {
+        CsrOut* c;
+        ~Release() { c->release(); }
+    } rel0{&A0};
+    {
+        DevBuf<int> cnt;
+        if ((rc = cnt.alloc((size_t)n0, "level-0 row lengths"))) return rc;
+        hipLaunchKernelGGL(k_l0_count, dim3(grid1d(n0)), dim3(kSetupBs), 0, s, msh->col, n0, W, cnt.p);
+        FV_LAUNCHED();
+        if ((rc = dev_alloc(&A0.ptr, (size_t)n0 + 1, "level-0 rows"))) return rc;
+        if ((rc = scan_excl<int>(cnt.p, A0.ptr, n0, s))) return rc;
+        int nnz = 0;
+        if ((rc = read_scalar(&nnz, A0.ptr + n0, s))) return rc;
+        A0.n = A0.m = n0;
+        A0.nnz = nnz;
+        if ((rc = dev_alloc(&A0.col, (size_t)std::max(nnz, 1), "level-0 columns")) ||
+            (rc = dev_alloc(&A0.val, (size_t)std::max(nnz, 1), "level-0 values")))
+            return rc;
+        hipLaunchKernelGGL(k_l0_fill, dim3(grid1d(n0)), dim3(kSetupBs), 0, s, msh->col, A->val, A->d, n0, W, A0.ptr,
+                           A0.col, A0.val);
+        FV_LAUNCHED();
+        FV_HIP(hipStreamSynchronize(s));
+    }
+    CsrView cur = view(A0);
+    DevBuf<double> d0;  // level 0's diagonal as the CSR holds it
+    DevBuf<unsigned long long> rho_bits;
+    DevBuf<int> bad;
+    if ((rc = rho_bits.alloc(1, "AMG spectral bound")) || (rc = bad.alloc(1, "AMG flag"))) return rc;
+    double th = theta;
+    int l = 0;
+    for (;;) {
+        AmgLevel& v = h->lev[l];
+        v.n = cur.n;
+        v.nnz = cur.nnz;
+        double* d = nullptr;
+        if (l == 0) {
+            if ((rc = d0.alloc((size_t)cur.n, "AMG level diagonal"))) return rc;
+            d = d0.p;
+        } else {
+            if ((rc = dev_alloc(&v.d, (size_t)cur.n, "AMG level diagonal"))) return rc;
+            d = v.d;
+        }
+        FV_HIP(hipMemsetAsync(rho_bits.p, 0, sizeof(unsigned long long), s));
+        FV_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_lvl_diag, dim3(grid1d(cur.n)), dim3(kSetupBs), 0, s, cur.ptr, cur.col, cur.val, cur.n, d,
+                           rho_bits.p, bad.p);
+        FV_LAUNCHED();
+        unsigned long long rb = 0;
+        int hbad = 0;
+        if ((rc = read_scalar(&rb, rho_bits.p, s)) || (rc = read_scalar(&hbad, bad.p, s))) return rc;
+        double rho;
+        std::memcpy(&rho, &rb, sizeof(rho));
+        if (hbad || !(rho > 0.0) || !std::isfinite(rho))
+            return set_error(FVPCG_BREAKDOWN, "AMG: level %d has a diagonal entry that is not finite and positive", l);
+        v.omega = 4.0 / (3.0 * rho);
+        v.ga = lanes_for((size_t)cur.nnz, cur.n);
+        if (l > 0) {
+            if ((rc = dev_alloc(&v.a_val_cs, (size_t)std::max(cur.nnz, 1LL), "AMG level scaled values"))) return rc;
+            hipLaunchKernelGGL(k_lvl_colscale, dim3(grid1d(cur.nnz)), dim3(kSetupBs), 0, s, cur.col, cur.val, d,
+                               cur.nnz, v.a_val_cs);
+            FV_LAUNCHED();
+        }
+        const size_t nv = (size_t)std::max(v.n, 1);
+        if ((rc = dev_alloc(&v.b, nv, "AMG work")) || (rc = dev_alloc(&v.x, nv, "AMG work")) ||
+            (rc = dev_alloc(&v.r, nv, "AMG work")) || (rc = dev_alloc(&v.y, nv, "AMG work")))
+            return rc;
+        if (cur.n <= coarse_size || l + 1 == max_levels) break;
+        if ((rc = dev_alloc(&v.agg, (size_t)cur.n, "AMG aggregates"))) return rc;
+        int na = 0;
+        if ((rc = aggregate_level(cur, d, th, seed, l, v.agg, &na, s))) return rc;
+        if ((double)na > 0.6 * (double)cur.n) {  // aggregation no longer coarsens: this is the last level
+            dev_free(v.agg);
+            break;
+        }
+        // P = S P_t
+        CsrOut P, R, AP, Ac;
+        struct ReleaseAll {
+            CsrOut* c[2];
+            ~ReleaseAll() {
+                for (CsrOut* x : c) x->release();
+            }
+        } relt{{&AP, &Ac}};
+        {
+            DevBuf<double> sval, ones;
+            DevBuf<int> pt_ptr;
+            if ((rc = sval.alloc((size_t)std::max(cur.nnz, 1LL), "AMG smoother rows")) ||
+                (rc = ones.alloc((size_t)cur.n, "AMG tentative prolongator")) ||
+                (rc = pt_ptr.alloc((size_t)cur.n + 1, "AMG tentative prolongator")))
+                return rc;
+            hipLaunchKernelGGL(k_smoother_rows, dim3(grid1d(cur.n)), dim3(kSetupBs), 0, s, cur.ptr, cur.col, cur.val,
+                               d, cur.n, v.omega, sval.p);
+            hipLaunchKernelGGL(k_tentative, dim3(grid1d((long long)cur.n + 1)), dim3(kSetupBs), 0, s, cur.n, pt_ptr.p,
+                               ones.p);
+            FV_LAUNCHED();
+            const CsrView S{cur.n, cur.n, cur.nnz, cur.ptr, cur.col, sval.p};
+            const CsrView Pt{cur.n, na, cur.n, pt_ptr.p, v.agg, ones.p};
+            rc = spgemm(S, Pt, P, s);
+            v.p_ptr = P.ptr;
+            v.p_col = P.col;
+            v.p_val = P.val;  // owned by the level from here on
+            if (rc) return rc;
+        }
+        if ((rc = transpose(view(P), R, s))) {
+            v.r_ptr = R.ptr;
+            v.r_col = R.col;
+            v.r_val = R.val;
+            return rc;
+        }
+        v.r_ptr = R.ptr;
+        v.r_col = R.col;
+        v.r_val = R.val;
+        if ((rc = spgemm(cur, view(P), AP, s))) return rc;
+        if ((rc = spgemm(view(R), view(AP), Ac, s))) return rc;
+        v.nc = na;
+        v.p_nnz = P.nnz;
+        v.gp = lanes_for((size_t)P.nnz, P.n);
+        v.gr = lanes_for((size_t)R.nnz, R.n);
+        AmgLevel& next = h->lev[l + 1];
+        next.a_ptr = Ac.ptr;
+        next.a_col = Ac.col;
+        next.a_val = Ac.val;
+        Ac.ptr = nullptr;
+        Ac.col = nullptr;
+        Ac.val = nullptr;
+        cur = CsrView{na, na, Ac.nnz, next.a_ptr, next.a_col, next.a_val};
+        if (l == 0) {
+            A0.release();
+            d0.reset();  // level 0's CSR diagonal is no longer needed
+        }
+        th *= 0.5;
+        ++l;
+    }
+    h->nlev = l + 1;
+    h->nlast = cur.n;
+    if (cur.n > kAmgMaxCoarse)
+        return set_error(FVPCG_UNSUPPORTED, "AMG: last level has %d unknowns (at most %d are solved exactly)", cur.n,
+                         kAmgMaxCoarse);
+    // the last level's inverse
+    const int nl = cur.n;
+    if ((rc = dev_alloc(&h->cinv, (size_t)nl * nl, "AMG coarse inverse"))) return rc;
+    {
+        DevBuf<double> f;
+        if ((rc = f.alloc((size_t)nl, "AMG elimination column"))) return rc;
+        FV_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_dense_zero, dim3(grid1d((long long)nl * nl)), dim3(kSetupBs), 0, s, nl, h->cinv);
+        hipLaunchKernelGGL(k_dense_fill, dim3(grid1d(nl)), dim3(kSetupBs), 0, s, cur.ptr, cur.col, cur.val, nl,
+                           h->cinv);
+        hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(kGjBs), 0, s, h->cinv, nl, f.p, bad.p);
+        FV_LAUNCHED();
+        int hbad = 0;
+        if ((rc = read_scalar(&hbad, bad.p, s))) return rc;
+        if (hbad) return set_error(FVPCG_BREAKDOWN, "AMG: the last level is not positive definite");
+    }
+    // level 0's CSR and diagonal go out of scope here (single-level case)
+    FV_HIP(hipStreamSynchronize(s));
+    const size_t nn0 = (size_t)std::max(n0, 1);
+    if ((rc = dev_alloc(&h->r, nn0, "AMG-PCG vectors")) || (rc = dev_alloc(&h->z, nn0, "AMG-PCG vectors")) ||
+        (rc = dev_alloc(&h->p, nn0, "AMG-PCG vectors")) || (rc = dev_alloc(&h->q, nn0, "AMG-PCG vectors")) ||
+        (rc = dev_alloc(&h->st, 1, "AMG-PCG state")) || (rc = dev_alloc(&h->partials, (size_t)4 * kMaxGrid, "partials")))
+        return rc;
+    if (hipHostMalloc((void**)&h->hst, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+        h->hst = nullptr;
+        return set_error(FVPCG_OUT_OF_MEMORY, "pinned allocation failed");
+    }
+    FV_HIP(hipMemsetAsync(h->st, 0, sizeof(DevState), s));
+    hipEvent_t* evs[] = {&h->t_begin, &h->t_end, &h->t_it0, &h->t_it1};
+    for (hipEvent_t* e : evs) FV_HIP(hipEventCreate(e));
+    FV_HIP(hipStreamSynchronize(s));
+    return FVPCG_OK;
+}
+
+}  // namespace fvpcg

@@ -49,12 +49,16 @@ int assemble_transient(const fvpcg_mesh* m, const double* k, const double* w, co
 int transient_run(fvpcg_matrix* A, const double* k, const double* w, const double* vol, const double* bdiag,
                   const double* bsrc, double dt, int nsteps, double* T, double tol, int maxit, int method,
                   hipStream_t s, fvpcg_stats* stats);
-int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, hipStream_t s, fvpcg_amg** out);
+bool batch_symmetric(const fvpcg_batch* bt);
+int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, uint64_t seed, hipStream_t s,
+               fvpcg_amg** out);
 void amg_free(fvpcg_amg* h);
 int amg_levels(const fvpcg_amg* h);
 int amg_level_n(const fvpcg_amg* h, int l);
 long long amg_level_nnz(const fvpcg_amg* h, int l);
-const int* amg_level_agg(const fvpcg_amg* h, int l);
+int amg_level_agg(const fvpcg_amg* h, int l, int* host_out, hipStream_t s);
+int amg_export(const fvpcg_amg* h, int l, int which, int* rows, int* cols, long long* nnz, int* ptr, int* col,
+               double* val, hipStream_t s);
 int amg_apply(const fvpcg_amg* h, const double* r, double* z, hipStream_t s);
 int solve_amg(const fvpcg_amg* h, const double* b, double* x, double tol, int maxit, int method, hipStream_t s,
               fvpcg_stats* stats);
@@ -236,6 +240,16 @@ int fvpcg_spmv(const fvpcg_matrix* mat, const double* v, double* y, void* stream
     });
 }
 
+// CG, its pipelined form, the mixed solvers and the adjoint assume A = A^T;
+// a matrix whose lower coefficients differ from its upper ones goes to
+// BiCGSTAB instead.
+static int require_symmetric(bool sym, fvpcg_stats* stats) {
+    if (sym) return FVPCG_OK;
+    stats_status(stats, FVPCG_UNSUPPORTED);
+    return set_error(FVPCG_UNSUPPORTED,
+                     "CG needs a symmetric matrix (lower == upper on every face); use BiCGSTAB for this one");
+}
+
 int fvpcg_solve(const fvpcg_matrix* mat, const double* b, double* x, double tol, int32_t maxit, int32_t method,
                 int32_t precond, void* stream, fvpcg_stats* stats) {
     return guard([&]() -> int {
@@ -246,6 +260,7 @@ int fvpcg_solve(const fvpcg_matrix* mat, const double* b, double* x, double tol,
         FV_TRY(check_dev(b, bytes, "b"));
         FV_TRY(check_dev(x, bytes, "x"));
         if (overlap(b, bytes, x, bytes)) return set_error(FVPCG_INVALID_ARG, "b and x overlap");
+        FV_TRY(require_symmetric(mat->vals_sym, stats));
         if (precond == FVPCG_PRECOND_JACOBI && !mat->diag_ok) {
             stats_status(stats, FVPCG_BREAKDOWN);
             return set_error(FVPCG_BREAKDOWN, "Jacobi preconditioner needs a finite positive diagonal");
@@ -317,6 +332,7 @@ int fvpcg_solve_mixed(const fvpcg_matrix* mat, const double* b, double* x, doubl
         FV_TRY(check_dev(b, bytes, "b"));
         FV_TRY(check_dev(x, bytes, "x"));
         if (overlap(b, bytes, x, bytes)) return set_error(FVPCG_INVALID_ARG, "b and x overlap");
+        FV_TRY(require_symmetric(mat->vals_sym, stats));
         if (!mat->diag_ok) {
             stats_status(stats, FVPCG_BREAKDOWN);
             return set_error(FVPCG_BREAKDOWN, "Jacobi preconditioner needs a finite positive diagonal");
@@ -340,6 +356,7 @@ int fvpcg_solve_mixed_reliable(const fvpcg_matrix* mat, const double* b, double*
         FV_TRY(check_dev(b, bytes, "b"));
         FV_TRY(check_dev(x, bytes, "x"));
         if (overlap(b, bytes, x, bytes)) return set_error(FVPCG_INVALID_ARG, "b and x overlap");
+        FV_TRY(require_symmetric(mat->vals_sym, stats));
         if (!mat->diag_ok) {
             stats_status(stats, FVPCG_BREAKDOWN);
             return set_error(FVPCG_BREAKDOWN, "Jacobi preconditioner needs a finite positive diagonal");
@@ -377,6 +394,7 @@ int fvpcg_solve_backward(const fvpcg_matrix* mat, const double* x, const double*
                 if (overlap(outs[i], outsz[i], outs[k], outsz[k]))
                     return set_error(FVPCG_INVALID_ARG, "gradient outputs must not overlap each other");
         }
+        FV_TRY(require_symmetric(mat->vals_sym, stats));
         if (precond == FVPCG_PRECOND_JACOBI && !mat->diag_ok) {
             stats_status(stats, FVPCG_BREAKDOWN);
             return set_error(FVPCG_BREAKDOWN, "Jacobi preconditioner needs a finite positive diagonal");
@@ -428,6 +446,8 @@ int fvpcg_solve_batched(const fvpcg_batch* batch, const double* b, double* x, do
         FV_TRY(check_dev(b, bytes, "b"));
         FV_TRY(check_dev(x, bytes, "x"));
         if (overlap(b, bytes, x, bytes)) return set_error(FVPCG_INVALID_ARG, "b and x overlap");
+        if (!batch_symmetric(batch))
+            return set_error(FVPCG_UNSUPPORTED, "CG needs symmetric systems (lower == upper on every face)");
         return solve_batched(batch, b, x, tol, maxit, method, precond, (hipStream_t)stream, stats);
     });
 }
@@ -459,13 +479,15 @@ int fvpcg_solve_batched_backward(const fvpcg_batch* batch, const double* x, cons
                 if (overlap(outs[i], outsz[i], outs[k], outsz[k]))
                     return set_error(FVPCG_INVALID_ARG, "gradient outputs must not overlap each other");
         }
+        if (!batch_symmetric(batch))
+            return set_error(FVPCG_UNSUPPORTED, "CG needs symmetric systems (lower == upper on every face)");
         return solve_batched_backward(batch, x, g, grad_b, grad_diag, grad_upper, grad_lower, tol, maxit, method,
                                       precond, (hipStream_t)stream, stats);
     });
 }
 
-int fvpcg_amg_create(const fvpcg_matrix* mat, double theta, int32_t max_levels, int32_t coarse_size, void* stream,
-                     fvpcg_amg** out) {
+int fvpcg_amg_create(const fvpcg_matrix* mat, double theta, int32_t max_levels, int32_t coarse_size, uint64_t seed,
+                     void* stream, fvpcg_amg** out) {
     return guard([&]() -> int {
         if (!out) return set_error(FVPCG_INVALID_ARG, "out is NULL");
         *out = nullptr;
@@ -473,7 +495,9 @@ int fvpcg_amg_create(const fvpcg_matrix* mat, double theta, int32_t max_levels, 
         if (!(theta >= 0.0) || !std::isfinite(theta) || max_levels < 1 || coarse_size < 1)
             return set_error(FVPCG_INVALID_ARG, "need theta >= 0, max_levels >= 1, coarse_size >= 1");
         if (!mat->diag_ok) return set_error(FVPCG_BREAKDOWN, "AMG needs a finite positive diagonal");
-        return amg_create(mat, theta, max_levels, coarse_size, (hipStream_t)stream, out);
+        if (!mat->vals_sym)
+            return set_error(FVPCG_UNSUPPORTED, "AMG needs a symmetric matrix (lower == upper on every face)");
+        return amg_create(mat, theta, max_levels, coarse_size, seed, (hipStream_t)stream, out);
     });
 }
 
@@ -503,9 +527,20 @@ int fvpcg_amg_aggregates(const fvpcg_amg* amg, int32_t level, int32_t* host_out)
         if (!amg || !host_out) return set_error(FVPCG_INVALID_ARG, "amg or host_out is NULL");
         if (level < 0 || level + 1 >= amg_levels(amg))
             return set_error(FVPCG_INVALID_ARG, "level %d has no coarser level", level);
-        const int* agg = amg_level_agg(amg, level);
-        std::memcpy(host_out, agg, sizeof(int32_t) * (size_t)amg_level_n(amg, level));
-        return FVPCG_OK;
+        return amg_level_agg(amg, level, host_out, nullptr);
+    });
+}
+
+int fvpcg_amg_export(const fvpcg_amg* amg, int32_t level, int32_t which, int32_t* rows, int32_t* cols,
+                     int64_t* nnz, int32_t* host_ptr, int32_t* host_col, double* host_val) {
+    return guard([&]() -> int {
+        if (!amg || !rows || !cols || !nnz) return set_error(FVPCG_INVALID_ARG, "amg, rows, cols or nnz is NULL");
+        if (level < 0 || level >= amg_levels(amg))
+            return set_error(FVPCG_INVALID_ARG, "level %d outside [0, %d)", level, amg_levels(amg));
+        long long z = 0;
+        int rc = amg_export(amg, level, which, rows, cols, &z, host_ptr, host_col, host_val, nullptr);
+        *nnz = z;
+        return rc;
     });
 }
 

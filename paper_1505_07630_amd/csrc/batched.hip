@@ -1046,6 +1046,8 @@ int batch_create(int32_t nsys, const int32_t* cell_off, const int32_t* face_off,
     return FVPCG_OK;
 }
 
+bool batch_symmetric(const fvpcg_batch* bt) { return bt->mat->vals_sym; }
+
 int batch_destroy(fvpcg_batch* bt) {
     batch_free(bt);
     return FVPCG_OK;

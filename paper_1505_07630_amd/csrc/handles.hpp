@@ -69,6 +69,8 @@ struct fvpcg_matrix {
     bool sym = false;      // created with lower == NULL
     bool fp32 = false;
     bool diag_ok = false;  // every diagonal entry finite and > 0
+    bool vals_sym = true;  // lower == upper on every face (always, when created with lower == NULL)
+    uint64_t generation = 0;  // bumped by every coefficient refresh
     double* d = nullptr;       // [n]
     double* val = nullptr;     // [W][n] A[c][col]
     double* val_cs = nullptr;  // [W][n] A[c][col] / d[col] (Jacobi-folded products)

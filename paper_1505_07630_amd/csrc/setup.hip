@@ -122,6 +122,15 @@ __global__ void k_gather_coeffs(const int* __restrict__ ref, const int* __restri
     }
 }
 
+// flag bit 2: lower differs from upper on some face (or either is NaN)
+__global__ void k_check_sym(const double* __restrict__ upper, const double* __restrict__ lower, int F,
+                            unsigned* flags) {
+    unsigned asym = 0;
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < F; f += gridDim.x * blockDim.x)
+        if (!(upper[f] == lower[f])) asym = 2u;
+    if (asym) atomicOr(flags, asym);
+}
+
 __global__ void k_copy_diag(const double* __restrict__ diag, int n, double* d, float* d32, unsigned* flags) {
     unsigned bad = 0;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
@@ -170,6 +179,8 @@ int matrix_refresh(fvpcg_matrix* A, const double* diag, const double* upper, con
     do {
         if (hipMemsetAsync(dflag, 0, sizeof(unsigned), s) != hipSuccess) { rc = hip_fail(hipGetLastError(), "memset", __FILE__, __LINE__); break; }
         hipLaunchKernelGGL(k_copy_diag, dim3(grid_for(m->n)), dim3(kBlock), 0, s, diag, m->n, A->d, A->d32, dflag);
+        if (lower && m->F > 0)
+            hipLaunchKernelGGL(k_check_sym, dim3(grid_for(m->F)), dim3(kBlock), 0, s, upper, lower, m->F, dflag);
         hipLaunchKernelGGL(k_gather_coeffs, dim3(grid_for((size_t)m->W * m->n)), dim3(kBlock), 0, s, m->ref, m->col,
                            m->n, m->W, diag, upper, lo, A->val, A->val_cs, A->val32, A->val32_cs);
         hipError_t e = hipGetLastError();
@@ -178,7 +189,9 @@ int matrix_refresh(fvpcg_matrix* A, const double* diag, const double* upper, con
     } while (0);
     dev_free(dflag);
     if (rc) return rc;
-    A->diag_ok = (hflag == 0);
+    A->diag_ok = (hflag & 1u) == 0;
+    A->vals_sym = (hflag & 2u) == 0;
+    ++A->generation;
     return FVPCG_OK;
 }
 

@@ -1,8 +1,14 @@
 """Smoothed-aggregation AMG on the GPU against the oracle's (oracle/amg.c):
-aggregates bit for bit, level sizes, one cycle element by element, and
-AMG-preconditioned CG at equal iteration count."""
+the device setup's aggregates bit for bit (its parallel independent-set
+rounds against the oracle's sequential greedy), prolongators and Galerkin
+operators entry by entry, one cycle element by element, AMG-preconditioned CG
+at equal iteration count, the stale-hierarchy guard and the 7.08M-cell
+setup."""
+import time
+
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import fvcases as fc
 from tests.gpu_util import DevCase, rel, say, to_dev
@@ -41,8 +47,10 @@ CASES = {
 @pytest.mark.parametrize("name", list(CASES))
 def test_amg_hierarchy_and_cycle_match_oracle(fv, orc, name):
     """Aggregates of every level bit for bit, level sizes and stored entries
-    equal; one cycle applied to a random vector within 1e-10 (the setup's and
-    the cycle's sums are ordered differently)."""
+    equal; P, R = P^T and every coarse operator with the oracle's pattern and
+    values within 1e-12 of their largest entry; one cycle applied to a random
+    vector within 1e-10 (the setup's and the cycle's sums are ordered
+    differently)."""
     say("amg hierarchy", name)
     case = CASES[name]()
     dc = DevCase(case)
@@ -55,6 +63,22 @@ def test_amg_hierarchy_and_cycle_match_oracle(fv, orc, name):
         assert (info["n"], info["nnz"]) == (ho["n"], ho["nnz"]), l
         if l + 1 < H.levels:
             assert np.array_equal(M.aggregates(l), H.aggregates(l)), l
+            ptr, col, val, shape = M.export(l, "P")
+            optr, ocol, oval, oshape = H.export(l, "P")
+            assert shape == oshape and np.array_equal(ptr, optr) and np.array_equal(col, ocol), l
+            assert np.max(np.abs(val - oval)) <= 1e-12 * np.max(np.abs(oval)), l
+            rptr, rcol, rval, rshape = M.export(l, "R")
+            assert rshape == shape[::-1]
+            R = sp.csr_matrix((rval, rcol, rptr), shape=rshape)
+            P = sp.csr_matrix((val, col, ptr), shape=shape)
+            assert (R != P.T.tocsr()).nnz == 0, l  # the same entries, bit for bit
+        if l >= 1:
+            ptr, col, val, shape = M.export(l, "A")
+            optr, ocol, oval, oshape = H.export(l, "A")
+            assert shape == oshape and np.array_equal(ptr, optr) and np.array_equal(col, ocol), l
+            err = np.max(np.abs(val - oval)) / np.max(np.abs(oval))
+            say("amg level", l, "operator max rel. diff", f"{err:.2e}")
+            assert err <= 1e-12, l
     v = np.random.default_rng(7).standard_normal(case.n)
     z = fv.amg_apply(M, to_dev(v)).cpu().numpy()
     assert rel(z, H.vcycle(v)) <= 1e-10
@@ -138,14 +162,61 @@ def test_amg_edge_cases(fv, orc):
     dn.close()
 
 
+def test_amg_stale_after_update(fv, orc):
+    """After fvpcg_matrix_update the hierarchy describes the old operator:
+    its solves and cycles are refused until it is created again, and the new
+    one matches the oracle's hierarchy of the new coefficients."""
+    say("amg stale hierarchy")
+    import torch
+
+    case = fc.varcoef((12, 10, 9), seed=8)
+    dc = DevCase(case)
+    M = fv.AMG(dc.A, coarse_size=16)
+    x, st = fv.solve_amg(M, dc.b, tol=1e-10)
+    assert st["status"] == 0
+    diag2 = dc.diag * 1.5
+    dc.A.update(diag2, dc.upper)
+    for call in (lambda: fv.solve_amg(M, dc.b, tol=1e-10), lambda: fv.amg_apply(M, dc.b)):
+        with pytest.raises(fv.FVPCGError) as e:
+            call()
+        assert e.value.code == fv.INVALID_ARG
+    M.close()
+    M = fv.AMG(dc.A, coarse_size=16)
+    c2 = fc.Case("upd", case.shape, case.n, case.owner, case.neighbour, case.diag * 1.5, case.upper, case.lower,
+                 case.b)
+    H = orc.AMG(c2, coarse_size=16)
+    assert M.levels == H.levels
+    for l in range(H.levels - 1):
+        assert np.array_equal(M.aggregates(l), H.aggregates(l)), l
+    x, st = fv.solve_amg(M, dc.b, tol=1e-10)
+    xo, _ = H.pcg(c2.b, tol=0.0, maxit=st["iters"])
+    assert st["status"] == 0 and rel(x.cpu().numpy(), xo) <= 1e-10
+    M.close()
+    dc.close()
+    torch.cuda.synchronize()
+
+
 def test_amg_varcoef192(fv, orc):
-    """The 7.08M-cell workload: AMG-PCG to 1e-8, FP64 true residual by the
-    oracle's product, far fewer iterations than Jacobi-PCG (1,250)."""
+    """The 7.08M-cell workload: the device setup (timed; the hierarchy's
+    level sizes and aggregates of level 0 equal to the oracle's), AMG-PCG to
+    1e-8, FP64 true residual by the oracle's product, far fewer iterations
+    than Jacobi-PCG (1,250)."""
+    import torch
+
     say("amg varcoef192 setup")
     case = fc.make("varcoef192")
     dc = DevCase(case)
+    fv.AMG(dc.A).close()  # first call: code objects loaded, allocator warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     M = fv.AMG(dc.A)
-    say("amg varcoef192 levels", [M.level_info(l)["n"] for l in range(M.levels)])
+    setup_s = time.perf_counter() - t0
+    levels = [M.level_info(l)["n"] for l in range(M.levels)]
+    say("amg varcoef192 levels", levels, f"setup {setup_s * 1e3:.1f} ms")
+    assert setup_s < 2.0
+    H = orc.AMG(case)
+    assert levels == [H.level_info(l)["n"] for l in range(H.levels)]
+    assert np.array_equal(M.aggregates(0), H.aggregates(0))
     for method in ("cg", "pipecg"):
         x, st = fv.solve_amg(M, dc.b, tol=1e-8, maxit=1000, method=method)
         assert st["status"] == 0, st

@@ -279,3 +279,37 @@ def test_autograd_function(fv, orc):
     closed = -(lk[case.owner] - lk[case.neighbour]) * (xk[case.owner] - xk[case.neighbour])
     assert rel(k.grad.cpu().numpy(), closed) <= 1e-8
     dc.close()
+
+
+def test_nonsymmetric_values_refused_by_cg_paths(fv):
+    """CG, its pipelined forms, both mixed solvers, the adjoint and the
+    batched solver assume A = A^T: with lower = upper / 2 on every face each
+    returns UNSUPPORTED (the adjoint would otherwise solve with A instead of
+    A^T); BiCGSTAB solves the same system."""
+    say("non-symmetric values refused")
+    import torch
+
+    base = fc.batch(1, 6, 6, seed=2).cases[0]
+    ns = fc.Case("ns", base.shape, base.n, base.owner, base.neighbour, base.diag, base.upper, 0.5 * base.upper,
+                 base.b)
+    dn = DevCase(ns, symmetric=False, fp32_copy=True)
+    x = torch.zeros_like(dn.b)
+    calls = [lambda: fv.solve(dn.A, dn.b, method="cg"), lambda: fv.solve(dn.A, dn.b, method="pipecg"),
+             lambda: fv.solve(dn.A, dn.b, method="pipecg_literal"), lambda: fv.solve_mixed(dn.A, dn.b),
+             lambda: fv.solve_mixed_reliable(dn.A, dn.b), lambda: fv.solve_backward(dn.A, x, dn.b)]
+    for call in calls:
+        with pytest.raises(fv.FVPCGError) as e:
+            call()
+        assert e.value.code == fv.UNSUPPORTED
+    xb, st = fv.solve_bicgstab(dn.A, dn.b, tol=1e-10)
+    assert st["status"] == 0
+    B = fv.Batch(np.array([0, ns.n]), np.array([0, ns.F]), dn.owner, dn.nb, dn.diag, dn.upper, dn.lower)
+    with pytest.raises(fv.FVPCGError) as e:
+        fv.solve_batched(B, dn.b)
+    assert e.value.code == fv.UNSUPPORTED
+    B.close()
+    # the same storage with equal values is accepted
+    dn.A.update(dn.diag, dn.upper, dn.upper.clone())
+    _, st = fv.solve(dn.A, dn.b, tol=1e-10, method="cg")
+    assert st["status"] == 0
+    dn.close()
