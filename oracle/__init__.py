@@ -16,6 +16,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+# the same sources with OpenMP: or_cg and or_pipecg over all host threads,
+# bitwise the single-thread results (timing and full-size references only)
+LIB_OMP_PATH = os.path.join(HERE, "liboracle_omp.so")
 
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, -3
 PRECOND = {"none": 0, "jacobi": 1}
@@ -25,16 +28,18 @@ SOURCES = ("oracle.c", "amg.c", "transient.c", "bicgstab.c")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle's C sources into liboracle.so (plain C99, gcc)."""
+    """Compile the oracle's C sources into liboracle.so (plain C99, gcc) and
+    the OpenMP timing build liboracle_omp.so."""
     srcs = [os.path.join(HERE, f) for f in SOURCES]
     newest = max(os.path.getmtime(f) for f in srcs + [os.path.join(HERE, "oracle.h")])
-    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= newest:
-        return LIB_PATH
-    tmp = LIB_PATH + ".tmp"
-    cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", tmp, *srcs, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB_PATH)
+    for path, extra in ((LIB_PATH, []), (LIB_OMP_PATH, ["-fopenmp"])):
+        if not force and os.path.exists(path) and os.path.getmtime(path) >= newest:
+            continue
+        tmp = path + ".tmp"
+        cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-Wall", "-Wextra", *extra, "-o", tmp, *srcs, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, path)
     return LIB_PATH
 
 
@@ -47,15 +52,16 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            build()
-        L = ctypes.CDLL(LIB_PATH)
+def lib(omp: bool = False):
+    """The single-thread oracle, or (omp=True) its OpenMP timing build."""
+    path = LIB_OMP_PATH if omp else LIB_PATH
+    if path not in _libs:
+        if not os.path.exists(path):
+            build(force=False)
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i32 = ctypes.c_int32
         d = ctypes.c_double
@@ -103,8 +109,21 @@ def lib():
         L.or_bicgstab.restype = i32
         L.or_adjoint_grads.argtypes = [i32, i32, P, P, P, P, P, P, P]
         L.or_adjoint_grads.restype = None
-        _lib = L
-    return _lib
+        L.or_threads.argtypes = []
+        L.or_threads.restype = i32
+        L.or_set_threads.argtypes = [i32]
+        L.or_set_threads.restype = None
+        _libs[path] = L
+    return _libs[path]
+
+
+def threads(omp: bool = True) -> int:
+    """Threads the (OpenMP) build runs or_cg / or_pipecg on."""
+    return int(lib(omp).or_threads())
+
+
+def set_threads(t: int) -> None:
+    lib(True).or_set_threads(int(t))
 
 
 def _i32(a):
@@ -157,8 +176,9 @@ def dot(a, b):
     return lib().or_dot(a.shape[0], _p(a), _p(b))
 
 
-def cg(A, b, x0=None, tol=1e-8, maxit=10000, precond="jacobi", history=False):
-    """Standard PCG.  Returns (x, stats dict[, history dict])."""
+def cg(A, b, x0=None, tol=1e-8, maxit=10000, precond="jacobi", history=False, omp=False):
+    """Standard PCG.  Returns (x, stats dict[, history dict]).  omp: the
+    OpenMP build (bitwise the same result)."""
     A = _as_sys(A)
     b = _f64(b)
     x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
@@ -167,8 +187,8 @@ def cg(A, b, x0=None, tol=1e-8, maxit=10000, precond="jacobi", history=False):
     ah = np.zeros(m) if history else None
     bh = np.zeros(m) if history else None
     rh = np.zeros(m) if history else None
-    lib().or_cg(*A.args(), _p(b), _p(x), float(tol), int(maxit), PRECOND[precond], ctypes.byref(st),
-                _p(ah), _p(bh), _p(rh))
+    lib(omp).or_cg(*A.args(), _p(b), _p(x), float(tol), int(maxit), PRECOND[precond], ctypes.byref(st),
+                   _p(ah), _p(bh), _p(rh))
     s = st.asdict()
     if history:
         k = s["iters"]
@@ -195,15 +215,16 @@ def bicgstab(A, b, x0=None, tol=1e-8, maxit=10000, precond="jacobi", history=Fal
     return x, s
 
 
-def pipecg(A, b, x0=None, tol=1e-8, maxit=10000, precond="jacobi", folded=True, history=False):
-    """Pipelined PCG (literal or Jacobi-folded).  Returns (x, stats[, res])."""
+def pipecg(A, b, x0=None, tol=1e-8, maxit=10000, precond="jacobi", folded=True, history=False, omp=False):
+    """Pipelined PCG (literal or Jacobi-folded).  Returns (x, stats[, res]).
+    omp: the OpenMP build (bitwise the same result)."""
     A = _as_sys(A)
     b = _f64(b)
     x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
     st = Stats()
     rh = np.zeros(max(int(maxit), 0) + 1) if history else None
-    lib().or_pipecg(*A.args(), _p(b), _p(x), float(tol), int(maxit), PRECOND[precond], int(bool(folded)),
-                    ctypes.byref(st), _p(rh))
+    lib(omp).or_pipecg(*A.args(), _p(b), _p(x), float(tol), int(maxit), PRECOND[precond], int(bool(folded)),
+                       ctypes.byref(st), _p(rh))
     s = st.asdict()
     if history:
         return x, s, rh[: s["iters"] + 1]

@@ -13,7 +13,9 @@
  *     products are summed pairwise (see or_dot).
  *
  * Plain FP64, single thread, built with -O2 -ffp-contract=off.  Used only by
- * tests, the smoke check and the benchmark's CPU-baseline leg.
+ * tests, the smoke check and the benchmark's CPU-baseline leg.  A second
+ * build with OpenMP (liboracle_omp.so) spreads or_cg's and or_pipecg's loops
+ * over threads without changing a single rounding: see ldu_mv and dotp.
  */
 #include "oracle.h"
 
@@ -21,6 +23,12 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#define OR_PARFOR _Pragma("omp parallel for schedule(static)")
+#else
+#define OR_PARFOR
+#endif
 
 /* ---- LDU matrix-vector product (Section 4.2: nnz = n + 2F; Section 5:
  * OpenFOAM lduMatrix).  The plain definition: diagonal term, then each face
@@ -54,6 +62,112 @@ double or_dot(int32_t n, const double* a, const double* b)
     return or_dot(h, a, b) + or_dot(n - h, a + h, b + h);
 }
 
+/* or_dot with the top six levels of its halving tree spread over threads
+ * (OpenMP build): the 64 ranges of depth 6 are summed in parallel, each by
+ * or_dot, and combined pairwise in the tree's own order, so the result is
+ * bitwise or_dot's for any thread count. */
+static double dotp(int32_t n, const double* a, const double* b)
+{
+#ifdef _OPENMP
+    enum { DEPTH = 6, LEAVES = 1 << DEPTH };
+    if (n >= 16 * LEAVES) {
+        int32_t off[LEAVES], len[LEAVES];
+        off[0] = 0;
+        len[0] = n;
+        for (int32_t d = 0, cnt = 1; d < DEPTH; ++d, cnt *= 2)
+            for (int32_t k = cnt - 1; k >= 0; --k) {
+                const int32_t o = off[k], l = len[k], h = l / 2;
+                off[2 * k] = o;
+                len[2 * k] = h;
+                off[2 * k + 1] = o + h;
+                len[2 * k + 1] = l - h;
+            }
+        double s[LEAVES];
+        OR_PARFOR
+        for (int32_t k = 0; k < LEAVES; ++k) s[k] = or_dot(len[k], a + off[k], b + off[k]);
+        for (int32_t w = LEAVES; w > 1; w /= 2)
+            for (int32_t k = 0; k < w / 2; ++k) s[k] = s[2 * k] + s[2 * k + 1];
+        return s[0];
+    }
+#endif
+    return or_dot(n, a, b);
+}
+
+int32_t or_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_threads(int32_t t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+/* The LDU product as or_cg and or_pipecg apply it: or_spmv's face loop.  In
+ * the OpenMP build each row is evaluated on its own over its faces in
+ * increasing face order (owner side: upper times the neighbour's value,
+ * neighbour side: lower times the owner's), which is the sequence of
+ * additions the face loop makes to that row: bitwise or_spmv's result. */
+typedef struct {
+    int32_t n, nf;
+    const int32_t *owner, *nb;
+    const double *diag, *upper, *lower;
+    int32_t *fptr, *flist;  /* OpenMP build: row c's faces, 2f + side, at fptr[c] .. fptr[c+1] */
+} ldu_t;
+
+static void ldu_init(ldu_t* A, int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                     const double* diag, const double* upper, const double* lower)
+{
+    A->n = n; A->nf = nf; A->owner = owner; A->nb = nb;
+    A->diag = diag; A->upper = upper; A->lower = lower;
+    A->fptr = NULL; A->flist = NULL;
+#ifdef _OPENMP
+    A->fptr = calloc((size_t)n + 1, sizeof(int32_t));
+    A->flist = malloc(sizeof(int32_t) * (size_t)(nf > 0 ? 2 * nf : 1));
+    for (int32_t f = 0; f < nf; ++f) { A->fptr[owner[f] + 1]++; A->fptr[nb[f] + 1]++; }
+    for (int32_t c = 0; c < n; ++c) A->fptr[c + 1] += A->fptr[c];
+    int32_t* fill = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    memcpy(fill, A->fptr, sizeof(int32_t) * (size_t)n);
+    for (int32_t f = 0; f < nf; ++f) {
+        A->flist[fill[owner[f]]++] = 2 * f;
+        A->flist[fill[nb[f]]++] = 2 * f + 1;
+    }
+    free(fill);
+#endif
+}
+
+static void ldu_free(ldu_t* A)
+{
+    free(A->fptr);
+    free(A->flist);
+}
+
+static void ldu_mv(const ldu_t* A, const double* v, double* y)
+{
+#ifdef _OPENMP
+    OR_PARFOR
+    for (int32_t c = 0; c < A->n; ++c) {
+        double s = A->diag[c] * v[c];
+        for (int32_t k = A->fptr[c]; k < A->fptr[c + 1]; ++k) {
+            const int32_t f = A->flist[k] >> 1;
+            if (A->flist[k] & 1) s += A->lower[f] * v[A->owner[f]];
+            else s += A->upper[f] * v[A->nb[f]];
+        }
+        y[c] = s;
+    }
+#else
+    or_spmv(A->n, A->nf, A->owner, A->nb, A->diag, A->upper, A->lower, v, y);
+#endif
+}
+
 /* The same pairwise sum for FP32 vectors, accumulated in FP64. */
 static double dot32(int32_t n, const float* a, const float* b)
 {
@@ -84,10 +198,13 @@ static void residual(int32_t n, int32_t nf, const int32_t* owner, const int32_t*
  * Section 2, taken as Jacobi). */
 static void precond_apply(int32_t n, int32_t precond, const double* diag, const double* r, double* z)
 {
-    if (precond == OR_PRECOND_JACOBI)
+    if (precond == OR_PRECOND_JACOBI) {
+        OR_PARFOR
         for (int32_t c = 0; c < n; ++c) z[c] = r[c] / diag[c];
-    else
+    } else {
+        OR_PARFOR
         for (int32_t c = 0; c < n; ++c) z[c] = r[c];
+    }
 }
 
 static int diag_positive(int32_t n, const double* diag)
@@ -97,15 +214,21 @@ static int diag_positive(int32_t n, const double* diag)
     return 1;
 }
 
-static void finish_stats(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
-                         const double* diag, const double* upper, const double* lower,
-                         const double* b, const double* x, double bnorm, double rnorm,
-                         or_stats* st)
+/* r = b - A x and the exit statistics through the context's product */
+static void residual_ldu(const ldu_t* A, const double* b, const double* x, double* r)
+{
+    ldu_mv(A, x, r);
+    OR_PARFOR
+    for (int32_t c = 0; c < A->n; ++c) r[c] = b[c] - r[c];
+}
+
+static void finish_stats_ldu(const ldu_t* A, const double* b, const double* x, double bnorm, double rnorm,
+                             or_stats* st)
 {
     if (!st) return;
-    double* r = alloc_vec(n);
-    residual(n, nf, owner, nb, diag, upper, lower, b, x, r);
-    double tr = sqrt(or_dot(n, r, r));
+    double* r = alloc_vec(A->n);
+    residual_ldu(A, b, x, r);
+    const double tr = sqrt(dotp(A->n, r, r));
     free(r);
     st->b_norm = bnorm;
     st->rel_res = bnorm > 0.0 ? rnorm / bnorm : 0.0;
@@ -122,8 +245,9 @@ int32_t or_cg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
               or_stats* st, double* alpha_hist, double* beta_hist, double* res_hist)
 {
     if (st) memset(st, 0, sizeof(*st));
-    double bnorm = sqrt(or_dot(n, b, b));
+    double bnorm = sqrt(dotp(n, b, b));
     if (bnorm == 0.0) {
+        OR_PARFOR
         for (int32_t c = 0; c < n; ++c) x[c] = 0.0;
         if (st) { st->status = OR_OK; st->b_norm = 0.0; }
         if (res_hist) res_hist[0] = 0.0;
@@ -137,12 +261,14 @@ int32_t or_cg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
     double* z = alloc_vec(n);
     double* p = alloc_vec(n);
     double* q = alloc_vec(n);
+    ldu_t A;
+    ldu_init(&A, n, nf, owner, nb, diag, upper, lower);
 
-    residual(n, nf, owner, nb, diag, upper, lower, b, x, r);
+    residual_ldu(&A, b, x, r);
     precond_apply(n, precond, diag, r, z);
     memcpy(p, z, sizeof(double) * (size_t)n);
-    double gamma = or_dot(n, r, z);
-    double rnorm = sqrt(or_dot(n, r, r));
+    double gamma = dotp(n, r, z);
+    double rnorm = sqrt(dotp(n, r, r));
     if (st) st->r0_norm = rnorm;
     if (res_hist) res_hist[0] = rnorm;
 
@@ -152,19 +278,21 @@ int32_t or_cg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
         status = OR_OK;
     } else {
         for (k = 1; k <= maxit; ++k) {
-            or_spmv(n, nf, owner, nb, diag, upper, lower, p, q);
-            double delta = or_dot(n, p, q);
+            ldu_mv(&A, p, q);
+            double delta = dotp(n, p, q);
             if (!(delta > 0.0) || !isfinite(delta) || !isfinite(gamma)) {
                 status = OR_BREAKDOWN;
                 k -= 1;
                 break;
             }
             double alpha = gamma / delta;
+            OR_PARFOR
             for (int32_t c = 0; c < n; ++c) x[c] += alpha * p[c];
+            OR_PARFOR
             for (int32_t c = 0; c < n; ++c) r[c] -= alpha * q[c];
             precond_apply(n, precond, diag, r, z);
-            double gamma_new = or_dot(n, r, z);
-            double rho = or_dot(n, r, r);
+            double gamma_new = dotp(n, r, z);
+            double rho = dotp(n, r, r);
             rnorm = sqrt(rho);
             if (alpha_hist) alpha_hist[k - 1] = alpha;
             if (res_hist) res_hist[k] = rnorm;
@@ -175,12 +303,14 @@ int32_t or_cg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
             double beta = gamma_new / gamma;
             if (beta_hist) beta_hist[k - 1] = beta;
             gamma = gamma_new;
+            OR_PARFOR
             for (int32_t c = 0; c < n; ++c) p[c] = z[c] + beta * p[c];
         }
         if (k > maxit) k = maxit;
     }
     if (st) { st->iters = k; st->status = status; }
-    finish_stats(n, nf, owner, nb, diag, upper, lower, b, x, bnorm, rnorm, st);
+    finish_stats_ldu(&A, b, x, bnorm, rnorm, st);
+    ldu_free(&A);
     free(r); free(z); free(p); free(q);
     return status;
 }
@@ -203,8 +333,9 @@ int32_t or_pipecg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb
 {
     if (st) memset(st, 0, sizeof(*st));
     if (folded && precond != OR_PRECOND_JACOBI) folded = 0;
-    double bnorm = sqrt(or_dot(n, b, b));
+    double bnorm = sqrt(dotp(n, b, b));
     if (bnorm == 0.0) {
+        OR_PARFOR
         for (int32_t c = 0; c < n; ++c) x[c] = 0.0;
         if (st) st->status = OR_OK;
         if (res_hist) res_hist[0] = 0.0;
@@ -217,20 +348,24 @@ int32_t or_pipecg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb
     double *r = alloc_vec(n), *u = alloc_vec(n), *w = alloc_vec(n), *m = alloc_vec(n);
     double *nv = alloc_vec(n), *z = alloc_vec(n), *q = alloc_vec(n), *s = alloc_vec(n);
     double *p = alloc_vec(n);
+    ldu_t A;
+    ldu_init(&A, n, nf, owner, nb, diag, upper, lower);
 
-    residual(n, nf, owner, nb, diag, upper, lower, b, x, r);
+    residual_ldu(&A, b, x, r);
     precond_apply(n, precond, diag, r, u);
-    or_spmv(n, nf, owner, nb, diag, upper, lower, u, w);
+    ldu_mv(&A, u, w);
 
     double gamma_prev = 0.0, alpha_prev = 0.0, rnorm = 0.0;
     int32_t status = OR_NOT_CONVERGED;
     int32_t i;
     for (i = 0;; ++i) {
-        if (folded)
+        if (folded) {
+            OR_PARFOR
             for (int32_t c = 0; c < n; ++c) u[c] = r[c] / diag[c];
-        double gamma = or_dot(n, r, u);
-        double delta = or_dot(n, w, u);
-        double rho = or_dot(n, r, r);
+        }
+        double gamma = dotp(n, r, u);
+        double delta = dotp(n, w, u);
+        double rho = dotp(n, r, r);
         rnorm = sqrt(rho);
         if (i == 0 && st) st->r0_norm = rnorm;
         if (res_hist) res_hist[i] = rnorm;
@@ -238,7 +373,7 @@ int32_t or_pipecg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb
         if (i == maxit) { status = OR_NOT_CONVERGED; break; }
 
         precond_apply(n, precond, diag, w, m);
-        or_spmv(n, nf, owner, nb, diag, upper, lower, m, nv);
+        ldu_mv(&A, m, nv);
 
         double alpha, beta, den;
         if (i == 0) {
@@ -253,12 +388,14 @@ int32_t or_pipecg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb
             status = OR_BREAKDOWN;
             break;
         }
+        OR_PARFOR
         for (int32_t c = 0; c < n; ++c) {
             z[c] = nv[c] + beta * z[c];
             s[c] = w[c] + beta * s[c];
             p[c] = u[c] + beta * p[c];
             if (!folded) q[c] = m[c] + beta * q[c];
         }
+        OR_PARFOR
         for (int32_t c = 0; c < n; ++c) {
             x[c] += alpha * p[c];
             r[c] -= alpha * s[c];
@@ -269,7 +406,8 @@ int32_t or_pipecg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb
         alpha_prev = alpha;
     }
     if (st) { st->iters = i; st->status = status; }
-    finish_stats(n, nf, owner, nb, diag, upper, lower, b, x, bnorm, rnorm, st);
+    finish_stats_ldu(&A, b, x, bnorm, rnorm, st);
+    ldu_free(&A);
     free(r); free(u); free(w); free(m); free(nv); free(z); free(q); free(s); free(p);
     return status;
 }
