@@ -9,10 +9,17 @@ solve: initial residual, every iteration, stopping test and the true residual
 at exit, with inputs resident in HBM.
 
 Prints ONE JSON line.  value = iterations/s over the timed solves.  roofline:
-the fused pipelined kernel, algorithmic bytes per launch (96n + 24F) divided
-by its average launch time from HIP events on the solve stream, against the
-8 TB/s HBM peak.  cpu_baseline: the plain-C oracle (single thread) on a
-bounded sample of the same workload.
+the fused pipelined kernel, algorithmic bytes per iteration (104n + 24F, every
+vector pass of the folded pipelined iteration counted once) divided by its
+average launch time from HIP events on the solve stream, against the 8 TB/s
+HBM peak; the 96n + 24F the kernel actually needs (x updated every second
+iteration) is a second field.  mixed: the reliable-update and restarted
+FP32/FP64 solvers on the same system against plain FP64, time and error
+against the oracle's FP64 solution.  batched: 256 systems of uneven size in
+one persistent launch against one solve per system.  cpu_baseline: the
+plain-C oracle on all host cores (its OpenMP build, bitwise the
+single-thread results) on a bounded sample of the same workload, with the
+single-thread rate beside it.
 """
 from __future__ import annotations
 
@@ -61,8 +68,9 @@ def alg_bytes_pipecg_folded(n, F, iters):
 
 
 def alg_bytes_per_iter(method, n, F, iters):
+    """Algorithmic bytes of one iteration: matrix 24F, every vector pass 8n."""
     if method == "pipecg":
-        return alg_bytes_pipecg_folded(n, F, iters)
+        return 104 * n + 24 * F  # 13 vector passes: reads w z s p r d x, writes z s p r w' x
     if method == "pipecg_literal":
         return 136 * n + 24 * F  # also carries u and q: 4 more vector passes
     # standard form: SpMV 24n + 24F, r update 32n, x/p update 48n
@@ -82,18 +90,27 @@ def measured_traffic(n_launch_bytes):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(case, iters):
+def cpu_baseline(case, iters, iters_single):
+    """The oracle's folded pipelined Jacobi-CG on the full workload for a
+    fixed number of iterations: its OpenMP build on every host thread (the
+    value), and the single-thread build beside it."""
     import oracle
 
     oracle.build(force=False)
     A = oracle.system(case)
     t0 = time.perf_counter()
-    _, st = oracle.pipecg(A, case.b, tol=0.0, maxit=iters, precond="jacobi", folded=True)
+    _, st = oracle.pipecg(A, case.b, tol=0.0, maxit=iters, precond="jacobi", folded=True, omp=True)
     dt = time.perf_counter() - t0
-    return {"value": st["iters"] / dt, "unit": "CG iters/s", "cores": 1, "kind": "oracle",
+    t1 = time.perf_counter()
+    _, s1 = oracle.pipecg(A, case.b, tol=0.0, maxit=iters_single, precond="jacobi", folded=True)
+    d1 = time.perf_counter() - t1
+    thr = oracle.threads(omp=True)
+    return {"value": st["iters"] / dt, "unit": "CG iters/s", "cores": thr, "kind": "oracle",
             "sample": f"{st['iters']} fixed iterations (plus setup and final residual) of the folded pipelined "
-                      f"Jacobi-CG on the full 192^3 workload, single thread, {dt:.1f} s",
-            "seconds": dt, "host": host_cpu()}
+                      f"Jacobi-CG on the full 192^3 workload, OpenMP build on {thr} threads, {dt:.1f} s",
+            "seconds": dt, "single_thread": {"value": s1["iters"] / d1, "cores": 1, "iters": s1["iters"],
+                                             "seconds": d1},
+            "host": host_cpu()}
 
 
 def host_cpu():
@@ -117,8 +134,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--method", default="pipecg", choices=["pipecg", "cg", "pipecg_literal"])
     ap.add_argument("--roofline-iters", type=int, default=500)
-    ap.add_argument("--cpu-iters", type=int, default=150)
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=300, help="oracle iterations on all host threads")
+    ap.add_argument("--cpu-iters-single", type=int, default=60, help="oracle iterations on one thread")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (baseline and mixed-precision errors)")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time the other workloads")
     ap.add_argument("--extras-select", default="mixed,batched,amg,transient,momentum,share,small",
                     help="comma-separated groups of extras: mixed, batched, amg, transient, momentum, share, small")
@@ -147,7 +167,6 @@ def main():
     mesh = fv.Mesh(case.n, owner, nb)
     A = fv.Matrix(mesh, diag, upper)
     x = torch.zeros_like(b)
-    stream = torch.cuda.current_stream()
     tol, maxit = 1e-8, 50000
 
     calib = fv.stream_calibrate(1 << 30)
@@ -173,7 +192,7 @@ def main():
     assert all(s["status"] == 0 for s in stats), stats
 
     n, F = case.n, case.F
-    bpi = sum(alg_bytes_per_iter(args.method, n, F, s_["iters"]) * s_["iters"] for s_ in stats) / total_iters
+    bpi = alg_bytes_per_iter(args.method, n, F, 1)
     its = total_iters / elapsed
     # dominant kernel: average duration of one fused iteration over the timed
     # solves (HIP events around the iteration launches on the solve stream)
@@ -187,10 +206,24 @@ def main():
     log(f"fused kernel: {kern_s * 1e6:.1f} us/launch in solves, {kern_fixed_s * 1e6:.1f} us/launch over "
         f"{stf['iters']} fixed iterations")
 
-    traffic = measured_traffic(bpi)
+    kernel_bytes = None
+    if args.method == "pipecg":
+        # what the kernel must move: x updated every second iteration
+        kernel_bytes = sum(alg_bytes_pipecg_folded(n, F, s_["iters"]) * s_["iters"] for s_ in stats) / total_iters
+    traffic = measured_traffic(kernel_bytes)
     kernel_name = {"pipecg": "k_pipe_iter<512, double, 6, int16_t, JAC=true, LIT=false>",
                    "pipecg_literal": "k_pipe_iter<512, double, 6, int16_t, JAC=true, LIT=true>",
                    "cg": "k_cg_spmv + k_cg_update_r + k_cg_update_xp"}[args.method]
+    roof = {
+        "bound": "hbm", "kernel": kernel_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "alg_bytes_per_launch": bpi, "avg_launch_us": round(kern_s * 1e6, 2),
+        "avg_launch_us_fixed_iters": round(kern_fixed_s * 1e6, 2),
+    }
+    if kernel_bytes is not None:
+        roof["kernel_bytes_per_launch"] = kernel_bytes
+        roof["kernel_bytes_gbs"] = round(kernel_bytes / kern_s / 1e9, 1)
+        roof["kernel_bytes_frac"] = round(kernel_bytes / kern_s / 1e9 / HBM_PEAK_GBS, 4)
     out = {
         "metric": METRIC,
         "value": round(its, 2),
@@ -211,24 +244,135 @@ def main():
             "iters_per_solve": stats[-1]["iters"], "true_rel_res": stats[-1]["true_rel_res"],
         },
         "hbm_gbs_algorithmic": round(bpi * its / 1e9, 1),
-        "roofline": {
-            "bound": "hbm", "kernel": kernel_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "alg_bytes_per_launch": bpi, "avg_launch_us": round(kern_s * 1e6, 2),
-            "avg_launch_us_fixed_iters": round(kern_fixed_s * 1e6, 2),
-        },
+        "roofline": roof,
         "stream_calibration_gbs": {"copy": round(calib["copy_gbs"], 1), "triad": round(calib["triad_gbs"], 1)},
         "frac_of_stream_copy": round(achieved / calib["copy_gbs"], 4) if calib["copy_gbs"] > 0 else None,
     }
+    pending = None
+    if not args.no_mixed:
+        out["mixed"], pending = mixed_block(fv, torch, np, case, mesh, b)
+    if not args.no_batched:
+        out["batched"] = batched_block(fv, torch, np, fvcases, dev)
     if args.extras:
         out["extras"] = extras(fv, torch, np, fvcases, dev, case, mesh, b,
                                groups=set(args.extras_select.split(",")))
     if not args.no_cpu:
-        log(f"oracle baseline: {args.cpu_iters} iterations on the CPU ...")
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_iters)
-        log(f"oracle: {out['cpu_baseline']['value']:.2f} it/s")
+        if pending is not None:
+            oracle_errors(case, out["mixed"], pending)
+        log(f"oracle baseline: {args.cpu_iters} iterations on all host threads, {args.cpu_iters_single} on one ...")
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_iters, args.cpu_iters_single)
+        log(f"oracle: {out['cpu_baseline']['value']:.2f} it/s on {out['cpu_baseline']['cores']} threads, "
+            f"{out['cpu_baseline']['single_thread']['value']:.2f} it/s on one")
     print(json.dumps(out), flush=True)
+
+
+def mixed_block(fv, torch, np, case, mesh, b):
+    """The two FP32/FP64 solvers on the headline system against plain FP64
+    pipelined CG, to 1e-8 and to 1e-10: device time of each solve (the median
+    of three after a warm-up), iterations, FP64 true residual.  Returns the
+    block and the solutions, whose error against the oracle's FP64 solution
+    is filled in later (oracle_errors)."""
+    to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).to(b.device)
+    A32 = fv.Matrix(mesh, to(case.diag, torch.float64), to(case.upper, torch.float64), fp32_copy=True)
+    res, sols = {"update_every": RELIABLE_PERIOD, "inner_tol_restarted": 1e-5}, {}
+
+    def med3(f):
+        f()
+        runs = []
+        for _ in range(3):
+            x_, st_ = f()
+            runs.append((st_["device_ms"], x_, st_))
+        runs.sort(key=lambda r: r[0])
+        return runs[1]
+
+    for tol in (1e-8, 1e-10):
+        t64, x64, s64 = med3(lambda: fv.solve(A32, b, tol=tol, maxit=50000, method="pipecg"))
+        tr, xr, sr = med3(lambda: fv.solve_mixed_reliable(A32, b, tol=tol, update_every=RELIABLE_PERIOD))
+        tm, xm, sm = med3(lambda: fv.solve_mixed(A32, b, outer_tol=tol, inner_tol=1e-5))
+        key = f"to_{tol:g}"
+        res[key] = {
+            "fp64_pipecg": {"ms": round(t64, 2), "iters": s64["iters"], "true_rel_res": s64["true_rel_res"]},
+            "reliable": {"ms": round(tr, 2), "status": sr["status_name"], "fp32_iters": sr["iters"],
+                         "fp64_updates": sr["outer_iters"], "true_rel_res": sr["true_rel_res"],
+                         "speedup_vs_fp64": round(t64 / tr, 3)},
+            "restarted": {"ms": round(tm, 2), "status": sm["status_name"], "fp32_iters": sm["iters"],
+                          "outer_iters": sm["outer_iters"], "true_rel_res": sm["true_rel_res"],
+                          "speedup_vs_fp64": round(t64 / tm, 3)},
+        }
+        sols[key] = {"fp64_pipecg": x64.cpu().numpy(), "reliable": xr.cpu().numpy(), "restarted": xm.cpu().numpy()}
+        log(f"mixed to {tol:g}: {res[key]}")
+    A32.close()
+    return res, sols
+
+
+def oracle_errors(case, block, sols):
+    """||x - x_oracle|| / ||x_oracle|| of every solution in `sols`, x_oracle
+    the oracle's FP64 standard Jacobi-CG to 1e-12 (OpenMP build)."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    xo, so = oracle.cg(oracle.system(case), case.b, tol=1e-12, maxit=100000, omp=True)
+    dt = time.perf_counter() - t0
+    block["oracle_reference"] = {"method": "cg-jacobi", "tol": 1e-12, "iters": so["iters"],
+                                 "true_rel_res": so["true_rel_res"], "threads": oracle.threads(omp=True),
+                                 "seconds": round(dt, 1)}
+    nrm = np.linalg.norm(xo)
+    for key, d in sols.items():
+        for name, xs in d.items():
+            block[key][name]["rel_err_vs_oracle"] = float(np.linalg.norm(xs - xo) / nrm)
+    log(f"oracle reference: {so['iters']} CG iterations in {dt:.1f} s; errors "
+        f"{ {k: {n: block[k][n]['rel_err_vs_oracle'] for n in d} for k, d in sols.items()} }")
+
+
+def batched_block(fv, torch, np, fvcases, dev):
+    """256 variable-coefficient systems (edges 16..64) solved to 1e-8 by the
+    persistent batched pipelined and standard CG (autotuned, graph replay;
+    the tuning run untimed) against the same systems solved one after another
+    by the single-system solver: system-iterations per second."""
+    to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).to(dev)
+    bt = fvcases.make("batch256")
+    B = fv.Batch(bt.cell_off, bt.face_off, to(bt.owner, torch.int32), to(bt.neighbour, torch.int32),
+                 to(bt.diag, torch.float64), to(bt.upper, torch.float64))
+    bb = to(bt.b, torch.float64)
+    res = {"systems": len(bt.cases), "total_cells": int(bt.cell_off[-1]), "tol": 1e-8}
+    for method in ("pipecg", "cg"):
+        fv.solve_batched(B, bb, tol=1e-8, method=method)  # tunes and captures
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xb, sts, code = fv.solve_batched(B, bb, tol=1e-8, method=method)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        its = int(sum(s_["iters"] for s_ in sts))
+        res[method] = {"status": code, "ms": round(tb * 1e3, 2), "system_iters": its,
+                       "system_iters_per_s": round(its / tb, 1), "max_iters": max(s_["iters"] for s_ in sts)}
+    B.close()
+    singles = []
+    for c in bt.cases:
+        m_ = fv.Mesh(c.n, to(c.owner, torch.int32), to(c.neighbour, torch.int32))
+        singles.append((m_, fv.Matrix(m_, to(c.diag, torch.float64), to(c.upper, torch.float64)),
+                        to(c.b, torch.float64)))
+    for method in ("pipecg", "cg"):
+        for m_, A_, b_ in singles[:4]:
+            fv.solve(A_, b_, tol=1e-8, method=method)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = 0
+        for m_, A_, b_ in singles:
+            _, st_ = fv.solve(A_, b_, tol=1e-8, maxit=100000, method=method)
+            its += st_["iters"]
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        res[method]["one_solve_per_system_ms"] = round(ts * 1e3, 1)
+        res[method]["one_solve_per_system_iters_per_s"] = round(its / ts, 1)
+        res[method]["speedup_vs_one_solve_per_system"] = round(ts * 1e3 / res[method]["ms"], 2)
+    for m_, A_, b_ in singles:
+        A_.close()
+        m_.close()
+    log(f"batched: {res}")
+    return res
 
 
 def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None,

@@ -3,8 +3,14 @@
 // (Section 1, Figure perf1); this is the same measurement on gfx950: copy
 // (c = a, 2 arrays moved) and triad (a = b + s*c, 3 arrays moved) over
 // FP64 arrays far larger than the 256 MB last-level cache, timed with HIP
-// events: the best over several passes, grid sizes and kernel shapes (plain,
-// 4-way unrolled, non-temporal) is reported as attainable.
+// events: the best over several passes, grid sizes and kernel shapes is
+// reported as attainable.  Shapes: grid-stride (consecutive workgroups touch
+// consecutive 4 KB pieces) with 1, 4 or 8 independent 16-byte accesses per
+// thread, plain or non-temporal; and contiguous chunks (each workgroup
+// streams one long run of each array, the layout the solver kernels use).
+// FVPCG_CALIBRATE_VERBOSE=1 prints every variant's rate to stderr.
+#include <cstdlib>
+
 #include "common.hpp"
 
 namespace fvpcg {
@@ -63,6 +69,47 @@ __global__ __launch_bounds__(kBlock) void k_triad(double2* __restrict__ a, const
     }
 }
 
+// Contiguous chunks: workgroup b copies / triads elements [b*len, (b+1)*len)
+// with U accesses of 16 bytes in flight per thread, non-temporal.
+template <int U>
+__global__ __launch_bounds__(kBlock) void k_copy_chunk(const double2* __restrict__ a, double2* __restrict__ c,
+                                                      size_t n2, size_t len) {
+    const size_t b0 = (size_t)blockIdx.x * len;
+    const size_t e = b0 + len < n2 ? b0 + len : n2;
+    size_t i = b0 + threadIdx.x;
+    for (; i + (U - 1) * kBlock < e; i += U * kBlock) {
+        double2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = ld2<true>(a + i + u * kBlock);
+#pragma unroll
+        for (int u = 0; u < U; ++u) st2<true>(c + i + u * kBlock, v[u]);
+    }
+    for (; i < e; i += kBlock) st2<true>(c + i, ld2<true>(a + i));
+}
+
+template <int U>
+__global__ __launch_bounds__(kBlock) void k_triad_chunk(double2* __restrict__ a, const double2* __restrict__ b,
+                                                       const double2* __restrict__ c, double s, size_t n2,
+                                                       size_t len) {
+    const size_t b0 = (size_t)blockIdx.x * len;
+    const size_t e = b0 + len < n2 ? b0 + len : n2;
+    size_t i = b0 + threadIdx.x;
+    for (; i + (U - 1) * kBlock < e; i += U * kBlock) {
+        double2 x[U], y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            x[u] = ld2<true>(b + i + u * kBlock);
+            y[u] = ld2<true>(c + i + u * kBlock);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) st2<true>(a + i + u * kBlock, make_double2(x[u].x + s * y[u].x, x[u].y + s * y[u].y));
+    }
+    for (; i < e; i += kBlock) {
+        double2 x = ld2<true>(b + i), y = ld2<true>(c + i);
+        st2<true>(a + i, make_double2(x.x + s * y.x, x.y + s * y.y));
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill(double2* __restrict__ a, size_t n2, double v) {
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n2; i += (size_t)gridDim.x * kBlock)
         a[i] = make_double2(v, v);
@@ -111,15 +158,32 @@ int stream_calibrate(hipStream_t s, uint64_t bytes, double* copy_gbs, double* tr
             return FVPCG_OK;
         };
         const double b2 = 2.0 * n2 * sizeof(double2), b3 = 3.0 * n2 * sizeof(double2);
+        const char* vb = getenv("FVPCG_CALIBRATE_VERBOSE");
+        const bool verbose = vb && vb[0] == '1';
         int rc2;
+        auto run = [&](const char* name, int gg, auto&& launch, double bytes, double& best) -> int {
+            double mine = 0.0;
+            int r = timed(launch, bytes, mine);
+            if (verbose) fprintf(stderr, "[calibrate] %-16s grid %5d: %7.1f GB/s\n", name, gg, mine);
+            best = std::fmax(best, mine);
+            return r;
+        };
         for (int gm : {4, 8, 16}) {
             const int gg = cus * gm;
-            if ((rc2 = timed([&] { hipLaunchKernelGGL((k_copy<1, false>), dim3(gg), dim3(kBlock), 0, s, a, c, n2); }, b2, best_copy))) return rc2;
-            if ((rc2 = timed([&] { hipLaunchKernelGGL((k_copy<4, false>), dim3(gg), dim3(kBlock), 0, s, a, c, n2); }, b2, best_copy))) return rc2;
-            if ((rc2 = timed([&] { hipLaunchKernelGGL((k_copy<4, true>), dim3(gg), dim3(kBlock), 0, s, a, c, n2); }, b2, best_copy))) return rc2;
-            if ((rc2 = timed([&] { hipLaunchKernelGGL((k_triad<1, false>), dim3(gg), dim3(kBlock), 0, s, a, b, c, 0.5, n2); }, b3, best_triad))) return rc2;
-            if ((rc2 = timed([&] { hipLaunchKernelGGL((k_triad<4, false>), dim3(gg), dim3(kBlock), 0, s, a, b, c, 0.5, n2); }, b3, best_triad))) return rc2;
-            if ((rc2 = timed([&] { hipLaunchKernelGGL((k_triad<4, true>), dim3(gg), dim3(kBlock), 0, s, a, b, c, 0.5, n2); }, b3, best_triad))) return rc2;
+            if ((rc2 = run("copy", gg, [&] { hipLaunchKernelGGL((k_copy<1, false>), dim3(gg), dim3(kBlock), 0, s, a, c, n2); }, b2, best_copy))) return rc2;
+            if ((rc2 = run("copy u4", gg, [&] { hipLaunchKernelGGL((k_copy<4, false>), dim3(gg), dim3(kBlock), 0, s, a, c, n2); }, b2, best_copy))) return rc2;
+            if ((rc2 = run("copy u4 nt", gg, [&] { hipLaunchKernelGGL((k_copy<4, true>), dim3(gg), dim3(kBlock), 0, s, a, c, n2); }, b2, best_copy))) return rc2;
+            if ((rc2 = run("copy u8 nt", gg, [&] { hipLaunchKernelGGL((k_copy<8, true>), dim3(gg), dim3(kBlock), 0, s, a, c, n2); }, b2, best_copy))) return rc2;
+            if ((rc2 = run("triad", gg, [&] { hipLaunchKernelGGL((k_triad<1, false>), dim3(gg), dim3(kBlock), 0, s, a, b, c, 0.5, n2); }, b3, best_triad))) return rc2;
+            if ((rc2 = run("triad u4", gg, [&] { hipLaunchKernelGGL((k_triad<4, false>), dim3(gg), dim3(kBlock), 0, s, a, b, c, 0.5, n2); }, b3, best_triad))) return rc2;
+            if ((rc2 = run("triad u4 nt", gg, [&] { hipLaunchKernelGGL((k_triad<4, true>), dim3(gg), dim3(kBlock), 0, s, a, b, c, 0.5, n2); }, b3, best_triad))) return rc2;
+        }
+        for (int gm : {1, 2, 4, 8}) {
+            const int gg = cus * gm;
+            const size_t len = (n2 + gg - 1) / gg;
+            if ((rc2 = run("copy chunk u4", gg, [&] { hipLaunchKernelGGL((k_copy_chunk<4>), dim3(gg), dim3(kBlock), 0, s, a, c, n2, len); }, b2, best_copy))) return rc2;
+            if ((rc2 = run("copy chunk u8", gg, [&] { hipLaunchKernelGGL((k_copy_chunk<8>), dim3(gg), dim3(kBlock), 0, s, a, c, n2, len); }, b2, best_copy))) return rc2;
+            if ((rc2 = run("triad chunk u4", gg, [&] { hipLaunchKernelGGL((k_triad_chunk<4>), dim3(gg), dim3(kBlock), 0, s, a, b, c, 0.5, n2, len); }, b3, best_triad))) return rc2;
         }
         FV_LAUNCHED();
         *copy_gbs = best_copy;
