@@ -76,6 +76,8 @@ enum { FVPCG_PRECOND_NONE = 0, FVPCG_PRECOND_JACOBI = 1 };
 #define FVPCG_FP32_COPY 1u /* also keep an FP32 copy for the mixed-precision solves */
 
 #define FVPCG_MAX_ROW_DEGREE 32
+/* Largest system fvpcg_solve_noalloc takes (its work space is fixed). */
+#define FVPCG_NOALLOC_MAX_CELLS 1048576
 
 typedef struct fvpcg_mesh fvpcg_mesh;
 typedef struct fvpcg_matrix fvpcg_matrix;
@@ -271,6 +273,21 @@ FVPCG_API int fvpcg_assemble_transient(const fvpcg_mesh* mesh, const double* k_f
 FVPCG_API int fvpcg_transient_run(fvpcg_matrix* mat, const double* k_face, const double* w_face, const double* vol,
                                   const double* bdiag, const double* bsrc, double dt, int32_t nsteps, double* T,
                                   double tol, int32_t maxit, int32_t method, void* stream, fvpcg_stats* stats);
+
+/* ---- For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): fvpcg_solve with the same arguments,
+ * kernels and results, whose work buffers (solver vectors, reduction
+ * partials, device state) live in a fixed array in device memory that each
+ * GPU holds from the library's load to the end of the process (64 MiB, for
+ * at most FVPCG_NOALLOC_MAX_CELLS cells; larger systems: FVPCG_INVALID_ARG).
+ * It calls no hipMalloc, hipFree, pinned-memory or event routine: the
+ * convergence state is read into host stack memory and waited for after each
+ * chunk of iterations, and stats->device_ms / iter_ms come from the host
+ * clock.  The matrix (created beforehand) must live on the current device.
+ * Every call on one GPU shares that array and keeps the last call's contents:
+ * calls that overlap on one GPU (other threads, other streams) race. */
+FVPCG_API int fvpcg_solve_noalloc(const fvpcg_matrix* mat, const double* b, double* x, double tol, int32_t maxit,
+                                  int32_t method, int32_t precond, void* stream, fvpcg_stats* stats);
 
 /* ---- Smoothed-aggregation AMG preconditioner (Section 5, discussion of
  * Fig. pcgs1 and Table pcgs2: a V-cycle of aggregation-based AMG whose

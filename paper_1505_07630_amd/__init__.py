@@ -220,6 +220,24 @@ def fvpcg_solve(A: Matrix, b, x=None, tol=1e-8, maxit=10000, method="pipecg", pr
 solve = fvpcg_solve
 
 
+def fvpcg_solve_noalloc(A: Matrix, b, x, tol=1e-8, maxit=10000, method="pipecg", precond="jacobi", stream=None):
+    """fvpcg_solve without any device allocation (the library's fixed work
+    space, at most NOALLOC_MAX_CELLS cells): x holds x0 and is overwritten.
+    Returns (x, stats dict)."""
+    import torch
+
+    st = Stats()
+    code = lib().fvpcg_solve_noalloc(A.handle, _ptr(b, torch.float64, A.n, "b"), _ptr(x, torch.float64, A.n, "x"),
+                                     float(tol), int(maxit), METHODS[method], PRECONDS[precond], _stream(stream),
+                                     ctypes.byref(st))
+    _check(code, "fvpcg_solve_noalloc")
+    return x, st.asdict()
+
+
+solve_noalloc = fvpcg_solve_noalloc
+NOALLOC_MAX_CELLS = 1048576
+
+
 def fvpcg_solve_bicgstab(A: Matrix, b, x=None, tol=1e-8, maxit=10000, precond="jacobi", stream=None):
     """BiCGSTAB for A x = b (A may be non-symmetric); x (if given) holds x0
     and is overwritten.  Returns (x, stats dict).  Raises FVPCGError on

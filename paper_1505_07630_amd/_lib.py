@@ -54,6 +54,7 @@ SIGNATURES = {
     "fvpcg_matrix_destroy": (ctypes.c_int, [P]),
     "fvpcg_spmv": (ctypes.c_int, [P, P, P, P]),
     "fvpcg_solve": (ctypes.c_int, [P, P, P, f64, i32, i32, i32, P, SPS]),
+    "fvpcg_solve_noalloc": (ctypes.c_int, [P, P, P, f64, i32, i32, i32, P, SPS]),
     "fvpcg_solve_bicgstab": (ctypes.c_int, [P, P, P, f64, i32, i32, P, SPS]),
     "fvpcg_solve_bicgstab_multi": (ctypes.c_int, [P, i32, P, P, f64, i32, i32, P, SPS]),
     "fvpcg_solve_mixed": (ctypes.c_int, [P, P, P, f64, f64, i32, i32, P, SPS]),

@@ -50,6 +50,8 @@ int transient_run(fvpcg_matrix* A, const double* k, const double* w, const doubl
                   const double* bsrc, double dt, int nsteps, double* T, double tol, int maxit, int method,
                   hipStream_t s, fvpcg_stats* stats);
 bool batch_symmetric(const fvpcg_batch* bt);
+int solve_noalloc(const fvpcg_matrix* A, const double* b, double* x, double tol, int maxit, int method, int precond,
+                  hipStream_t s, fvpcg_stats* stats);
 int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, uint64_t seed, hipStream_t s,
                fvpcg_amg** out);
 void amg_free(fvpcg_amg* h);
@@ -266,6 +268,27 @@ int fvpcg_solve(const fvpcg_matrix* mat, const double* b, double* x, double tol,
             return set_error(FVPCG_BREAKDOWN, "Jacobi preconditioner needs a finite positive diagonal");
         }
         int rc = solve(mat, b, x, tol, maxit, method, precond, (hipStream_t)stream, stats);
+        if (rc == FVPCG_BREAKDOWN) set_error(rc, "breakdown: p'Ap <= 0 or a non-finite scalar");
+        return rc;
+    });
+}
+
+int fvpcg_solve_noalloc(const fvpcg_matrix* mat, const double* b, double* x, double tol, int32_t maxit,
+                        int32_t method, int32_t precond, void* stream, fvpcg_stats* stats) {
+    return guard([&]() -> int {
+        stats_status(stats, FVPCG_INVALID_ARG);
+        if (!mat) return set_error(FVPCG_INVALID_ARG, "mat is NULL");
+        size_t bytes = sizeof(double) * (size_t)mat->mesh->n;
+        FV_TRY(check_solver_args(tol, maxit, method, precond));
+        FV_TRY(check_dev(b, bytes, "b"));
+        FV_TRY(check_dev(x, bytes, "x"));
+        if (overlap(b, bytes, x, bytes)) return set_error(FVPCG_INVALID_ARG, "b and x overlap");
+        FV_TRY(require_symmetric(mat->vals_sym, stats));
+        if (precond == FVPCG_PRECOND_JACOBI && !mat->diag_ok) {
+            stats_status(stats, FVPCG_BREAKDOWN);
+            return set_error(FVPCG_BREAKDOWN, "Jacobi preconditioner needs a finite positive diagonal");
+        }
+        int rc = solve_noalloc(mat, b, x, tol, maxit, method, precond, (hipStream_t)stream, stats);
         if (rc == FVPCG_BREAKDOWN) set_error(rc, "breakdown: p'Ap <= 0 or a non-finite scalar");
         return rc;
     });

@@ -19,6 +19,9 @@
 #include <algorithm>
 
 #include "handles.hpp"
+#include <chrono>
+#include <mutex>
+
 #include "rows.hpp"
 
 namespace fvpcg {
@@ -620,6 +623,18 @@ __global__ void k_grad_faces(const int* __restrict__ owner, const int* __restric
     }
 }
 
+// Reset a solver state on the device (the no-allocation path has no pinned
+// host copy to send it from).
+__global__ void k_state_reset(DevState* st, double tol_rel, int maxit) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    DevState h = {};
+    h.tol_abs = tol_rel;
+    h.maxit = maxit;
+    h.best = HUGE_VAL;
+    h.status = FVPCG_NOT_CONVERGED;
+    *st = h;
+}
+
 // ===========================================================================
 // Host side
 
@@ -710,6 +725,11 @@ namespace {
 
 // Reset the device state of slot `k` for a new solve.
 int state_reset(Work& w, int k, double tol_rel, int maxit, hipStream_t s) {
+    if (!w.hst) {
+        hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, &w.st[k], tol_rel, maxit);
+        FV_LAUNCHED();
+        return FVPCG_OK;
+    }
     DevState* h = &w.hst[2 + k];
     *h = DevState();
     h->tol_abs = tol_rel;
@@ -721,6 +741,11 @@ int state_reset(Work& w, int k, double tol_rel, int maxit, hipStream_t s) {
 }
 
 int state_read(Work& w, int k, DevState* out, hipStream_t s) {
+    if (!w.hst) {  // no pinned mirror: copy into the caller's variable and wait
+        FV_HIP(hipMemcpyAsync(out, &w.st[k], sizeof(DevState), hipMemcpyDeviceToHost, s));
+        FV_HIP(hipStreamSynchronize(s));
+        return FVPCG_OK;
+    }
     FV_HIP(hipMemcpyAsync(&w.hst[k], &w.st[k], sizeof(DevState), hipMemcpyDeviceToHost, s));
     FV_HIP(hipStreamSynchronize(s));
     *out = w.hst[k];
@@ -739,9 +764,25 @@ int state_read_both(Work& w, DevState* h0, DevState* h1, hipStream_t s) {
 // Enqueue iterations in growing chunks; after each chunk the state is copied
 // to pinned memory, and the previous chunk's copy is inspected while the
 // current chunk runs.  Kernels launched after convergence return at once.
+// Without a pinned mirror (the no-allocation path) each chunk's state is
+// read and waited for before the next chunk is enqueued.
 template <typename Launch>
 int iterate(Work& w, int k, int maxit, hipStream_t s, Launch&& launch_iter) {
     int launched = 0, chunk = 2, pending = -1, slot = 0;
+    if (!w.hst) {
+        while (launched < maxit) {
+            const int cnt = chunk < maxit - launched ? chunk : maxit - launched;
+            for (int i = 0; i < cnt; ++i) launch_iter(launched + i);
+            FV_LAUNCHED();
+            launched += cnt;
+            DevState h;
+            int rc = state_read(w, k, &h, s);
+            if (rc) return rc;
+            if (h.done) break;
+            if (chunk < kMaxChunk) chunk *= 2;
+        }
+        return FVPCG_OK;
+    }
     while (launched < maxit) {
         int cnt = chunk < maxit - launched ? chunk : maxit - launched;
         for (int i = 0; i < cnt; ++i) launch_iter(launched + i);
@@ -780,24 +821,53 @@ int spmv(const fvpcg_matrix* A, const double* v, double* y, hipStream_t s) {
     return FVPCG_OK;
 }
 
+namespace {
+
+// HIP events on the stream when the work has them, else the host clock
+// (after a synchronisation) for the no-allocation path.
+struct Clock {
+    Work& w;
+    std::chrono::steady_clock::time_point h0, h1, h2;
+    int mark(hipEvent_t e, std::chrono::steady_clock::time_point& t, hipStream_t s) {
+        if (e) FV_HIP(hipEventRecord(e, s));
+        else t = std::chrono::steady_clock::now();
+        return FVPCG_OK;
+    }
+};
+
+int solve_core(const fvpcg_matrix* A, Work& w, const double* b, double* x, double tol, int maxit, int method,
+               int precond, hipStream_t s, fvpcg_stats* stats);
+
+}  // namespace
+
 int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int maxit, int method, int precond,
           hipStream_t s, fvpcg_stats* stats) {
-    const fvpcg_mesh* m = A->mesh;
-    const int n = m->n;
-    const bool jac = precond == FVPCG_PRECOND_JACOBI;
     Work& w = *A->work;
     int rc;
-    if ((rc = work_init(w, n))) return rc;
-    const Geom gm = geom_for(n, kBsMisc), gc = geom_for(n, kBsCg), gp = geom_for(n, kBsPipe),
-               gx = geom_for(n, kBsMixed);
-    (void)gc; (void)gp; (void)gx; (void)gm;
-    if (method == FVPCG_PIPECG_LITERAL && !jac) method = FVPCG_PIPECG;  // identical recurrences when M = I
+    if ((rc = work_init(w, A->mesh->n))) return rc;
+    if (method == FVPCG_PIPECG_LITERAL && precond != FVPCG_PRECOND_JACOBI) method = FVPCG_PIPECG;
     if (method == FVPCG_CG) {
         if ((rc = work_need_cg(w))) return rc;
     } else {
         if ((rc = work_need_pipe(w, method == FVPCG_PIPECG_LITERAL))) return rc;
     }
-    FV_HIP(hipEventRecord(w.t_begin, s));
+    return solve_core(A, w, b, x, tol, maxit, method, precond, s, stats);
+}
+
+namespace {
+
+int solve_core(const fvpcg_matrix* A, Work& w, const double* b, double* x, double tol, int maxit, int method,
+               int precond, hipStream_t s, fvpcg_stats* stats) {
+    const fvpcg_mesh* m = A->mesh;
+    const int n = m->n;
+    const bool jac = precond == FVPCG_PRECOND_JACOBI;
+    int rc;
+    Clock clk{w, {}, {}, {}};
+    const Geom gm = geom_for(n, kBsMisc), gc = geom_for(n, kBsCg), gp = geom_for(n, kBsPipe),
+               gx = geom_for(n, kBsMixed);
+    (void)gc; (void)gp; (void)gx; (void)gm;
+    if (method == FVPCG_PIPECG_LITERAL && !jac) method = FVPCG_PIPECG;  // identical recurrences when M = I
+    if ((rc = clk.mark(w.t_begin, clk.h0, s))) return rc;
     if ((rc = state_reset(w, 0, tol, maxit, s))) return rc;
     DevState* st = &w.st[0];
     double* part = w.partials;
@@ -828,7 +898,8 @@ int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int max
     FV_LAUNCHED();
     DevState h;
     if ((rc = state_read(w, 0, &h, s))) return rc;
-    FV_HIP(hipEventRecord(w.t_it0, s));
+    std::chrono::steady_clock::time_point t_it0;
+    if ((rc = clk.mark(w.t_it0, t_it0, s))) return rc;
     if (h.zero_b) {
         FV_HIP(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
     } else if (!h.done) {
@@ -869,12 +940,14 @@ int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int max
         hipLaunchKernelGGL((k_x_fixup<kBsPipe>), dim3(gp.grid), dim3(kBsPipe), 0, s, x, w.p, n, gp, st);
         FV_LAUNCHED();
     }
-    FV_HIP(hipEventRecord(w.t_it1, s));
+    std::chrono::steady_clock::time_point t_it1;
+    if ((rc = clk.mark(w.t_it1, t_it1, s))) return rc;
     FV_LAYOUT(m, hipLaunchKernelGGL((k_true_residual<kBsMisc, W_, CI_>), dim3(gm.grid), dim3(kBsMisc), 0, s, cols_, A->val,
                                            A->d, n, gm, b, x, st, part));
     FV_LAUNCHED();
-    FV_HIP(hipEventRecord(w.t_end, s));
+    if (w.t_end) FV_HIP(hipEventRecord(w.t_end, s));
     if ((rc = state_read(w, 0, &h, s))) return rc;
+    if (!w.t_end) clk.h2 = std::chrono::steady_clock::now();
     if (stats) {
         stats->iters = h.iter;
         stats->outer_iters = 0;
@@ -883,10 +956,79 @@ int solve(const fvpcg_matrix* A, const double* b, double* x, double tol, int max
         stats->r0_norm = h.r0norm;
         stats->rel_res = h.bnorm > 0 ? sqrt(h.rho) / h.bnorm : 0.0;
         stats->true_rel_res = h.bnorm > 0 ? sqrt(h.true_rr) / h.bnorm : 0.0;
-        stats->device_ms = elapsed(w.t_begin, w.t_end);
-        stats->iter_ms = elapsed(w.t_it0, w.t_it1);
+        if (w.t_begin) {
+            stats->device_ms = elapsed(w.t_begin, w.t_end);
+            stats->iter_ms = elapsed(w.t_it0, w.t_it1);
+        } else {  // host clock: the whole call, and from the first state read to the end
+            stats->device_ms = std::chrono::duration<double, std::milli>(clk.h2 - clk.h0).count();
+            stats->iter_ms = std::chrono::duration<double, std::milli>(clk.h2 - t_it0).count();
+        }
     }
     return h.status;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The solve for callers that cannot allocate: every work buffer (the solver
+// vectors, the reduction partials and the device state) lives in `scratch`,
+// a file-scope device array each GPU holds once the library is loaded, sized
+// for FVPCG_NOALLOC_MAX_CELLS cells.  Its address on the current device is
+// looked up once per device (hipGetSymbolAddress; the array's name itself is
+// a host-side stand-in) and passed to the kernels like any other buffer.
+// Every call on one GPU shares the array: calls that overlap on a GPU race.
+// vectors: r, p, z (standard CG's q), s, w0, w1, u, q (literal pipelined);
+// standard CG uses r, p, q, the folded pipelined form the first six
+constexpr int kNoAllocVectors = 8;
+constexpr size_t kNoAllocStride = ((size_t)FVPCG_NOALLOC_MAX_CELLS + 63) / 64 * 64;
+constexpr size_t kNoAllocStateDoubles = (2 * sizeof(DevState) + sizeof(double) - 1) / sizeof(double);
+constexpr size_t kNoAllocDoubles = (size_t)kNoAllocVectors * kNoAllocStride + 4 * (size_t)kMaxGrid +
+                                   kNoAllocStateDoubles;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+int scratch_on_current_device(double** out) {
+    int dev = 0;
+    FV_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(FVPCG_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        FV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch[dev];
+    return FVPCG_OK;
+}
+}  // namespace
+
+int solve_noalloc(const fvpcg_matrix* A, const double* b, double* x, double tol, int maxit, int method, int precond,
+                  hipStream_t s, fvpcg_stats* stats) {
+    const int n = A->mesh->n;
+    if (n > FVPCG_NOALLOC_MAX_CELLS)
+        return set_error(FVPCG_INVALID_ARG, "fvpcg_solve_noalloc: %d cells exceed its fixed work space of %d cells",
+                         n, FVPCG_NOALLOC_MAX_CELLS);
+    int dev = 0;
+    FV_HIP(hipGetDevice(&dev));
+    if (dev != A->mesh->device)
+        return set_error(FVPCG_INVALID_ARG, "fvpcg_solve_noalloc: the current device (%d) is not the matrix's (%d)",
+                         dev, A->mesh->device);
+    double* base = nullptr;
+    int rc;
+    if ((rc = scratch_on_current_device(&base))) return rc;
+    Work w;  // a view of the scratch array: no pinned mirror, no events
+    w.n = n;
+    w.geom = make_geom(n);
+    double** vec[kNoAllocVectors] = {&w.r, &w.p, &w.z, &w.s, &w.w[0], &w.w[1], &w.u, &w.qq};
+    for (int k = 0; k < kNoAllocVectors; ++k) *vec[k] = base + (size_t)k * kNoAllocStride;
+    w.q = w.z;  // standard CG's q; the pipelined forms' z
+    w.partials = base + (size_t)kNoAllocVectors * kNoAllocStride;
+    w.st = reinterpret_cast<DevState*>(w.partials + 4 * (size_t)kMaxGrid);
+    return solve_core(A, w, b, x, tol, maxit, method, precond, s, stats);
 }
 
 int solve_mixed(const fvpcg_matrix* A, const double* b, double* x, double outer_tol, double inner_tol, int max_outer,
