@@ -385,6 +385,117 @@ def momentum(shape=(192, 192, 192), seed=11, nu=0.01, co=2.0, permute=True, tol=
     return _finish(name, shape, n, owner, nb, diag, upper, lower, b, tol, seed, meta)
 
 
+@dataclasses.dataclass
+class Piso:
+    """Inputs of an icoFoam-style PISO run (incompressible Navier-Stokes,
+    implicit Euler, upwind convection) in a lid-driven box of cubes of side h:
+    the LDU addressing, per internal face its axis (face_dir 0/1/2) and the
+    orientation of owner -> neighbour along that axis (face_sgn +1/-1), per
+    cell the no-slip wall coefficient bwall = 2 nu h per wall face (lid
+    included), the lid source blid = 2 nu h U_lid per lid face (x-velocity
+    only) and bgrad[d] = the sum of the outward unit normals (+-1) of its
+    boundary faces along axis d (zero-gradient pressure at the walls); the
+    initial fields U0[3][n], p0[n] and face fluxes phi0[F]."""
+    name: str
+    shape: tuple
+    n: int
+    owner: np.ndarray
+    neighbour: np.ndarray
+    face_dir: np.ndarray
+    face_sgn: np.ndarray
+    bwall: np.ndarray
+    blid: np.ndarray
+    bgrad: np.ndarray
+    U0: np.ndarray
+    p0: np.ndarray
+    phi0: np.ndarray
+    h: float
+    nu: float
+    dt: float
+    meta: dict = dataclasses.field(default_factory=dict)
+    new_index: Optional[np.ndarray] = None  # natural cell c -> its number here (None: natural order)
+
+    @property
+    def F(self) -> int:
+        return int(self.owner.shape[0])
+
+
+def piso(shape=(32, 32, 32), seed=13, nu=0.01, co=1.0, u_lid=1.0, permute=False, name="piso"):
+    """Lid-driven cavity for icoFoam's PISO loop (Section 2 names icoFoam;
+    the paper's cavity case is stood in for): cubes of side h = 1/nx in
+    [0,1] x [0, ny h] x [0, nz h], no-slip walls, the y-max lid moving at
+    u = u_lid in x, viscosity nu, dt = co h / u_lid.  The initial state is
+    the discretely divergence-free flow of the momentum workload's stream
+    function (face fluxes from psi differences, stream vel), cell velocities
+    the mean of the two face fluxes per axis over the face area, p0 = 0.
+    Optionally randomly permuted and RCM-renumbered (stream perm), which
+    flips face_sgn where owner and neighbour swap."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    h = 1.0 / nx
+    Ly, Lz = ny * h, nz * h
+    owner, nb, direction = M.structured_faces(nx, ny, nz)
+    gvel = R.stream(seed, "vel")
+    theta = 2.0 * np.pi * gvel.random()
+    a = 1.0 / (1.5 * np.pi * max(1.0, 1.0 / Ly))
+
+    def psi(x, y, z):
+        return a * np.sin(np.pi * x) * np.sin(np.pi * y / Ly) * (1.0 + 0.5 * np.sin(2.0 * np.pi * z / Lz + theta))
+
+    i, j, k = M.cell_ijk(shape, owner)
+    zc = (k + 0.5) * h
+    phi = np.zeros(owner.shape[0])
+    m = direction == 0
+    xf = (i[m] + 1) * h
+    phi[m] = (psi(xf, (j[m] + 1) * h, zc[m]) - psi(xf, j[m] * h, zc[m])) * h
+    m = direction == 1
+    yf = (j[m] + 1) * h
+    phi[m] = -(psi((i[m] + 1) * h, yf, zc[m]) - psi(i[m] * h, yf, zc[m])) * h
+    # cell velocities: per axis, the mean of the cell's two face fluxes along it over h^2
+    U0 = np.zeros((3, n))
+    for d in range(3):
+        md = direction == d
+        np.add.at(U0[d], owner[md], 0.5 * phi[md] / h ** 2)
+        np.add.at(U0[d], nb[md], 0.5 * phi[md] / h ** 2)
+    bwall = np.zeros(n)
+    blid = np.zeros(n)
+    bgrad = np.zeros((3, n))
+    for side, d, sgn in (("xmin", 0, -1.0), ("xmax", 0, 1.0), ("ymin", 1, -1.0), ("ymax", 1, 1.0),
+                         ("zmin", 2, -1.0), ("zmax", 2, 1.0)):
+        cells = M.boundary_cells(shape, side)
+        np.add.at(bwall, cells, 2.0 * nu * h)
+        np.add.at(bgrad[d], cells, sgn)
+        if side == "ymax":
+            np.add.at(blid, cells, 2.0 * nu * h * u_lid)
+    sgn = np.ones(owner.shape[0], dtype=np.int8)
+    meta = {"ordering": "natural", "u_lid": u_lid, "courant": co}
+    new_index = None
+    if permute:
+        p1 = R.stream(seed, "perm").permutation(n).astype(np.int64)
+        p2 = M.rcm_order(n, p1[owner], p1[nb])
+        new_index = p2[p1]
+        swapped = new_index[owner] > new_index[nb]
+        owner, nb, _, _, order = M.renumber(n, owner, nb, phi, phi, new_index)
+        direction = direction[order]
+        sgn = np.where(swapped, -1, 1).astype(np.int8)[order]
+        phi = (np.where(swapped, -phi, phi))[order]
+
+        def moved(v):
+            out = np.empty_like(v)
+            out[..., new_index] = v
+            return out
+
+        U0, bwall, blid, bgrad = moved(U0), moved(bwall), moved(blid), moved(bgrad)
+        meta["ordering"] = "random permutation, then reverse Cuthill-McKee"
+        meta["bandwidth"] = M.bandwidth(owner, nb)
+    return Piso(name=name, shape=tuple(shape), n=n, owner=np.ascontiguousarray(owner, dtype=np.int32),
+                neighbour=np.ascontiguousarray(nb, dtype=np.int32), face_dir=np.ascontiguousarray(direction,
+                dtype=np.int8), face_sgn=np.ascontiguousarray(sgn), bwall=bwall, blid=blid,
+                bgrad=np.ascontiguousarray(bgrad), U0=np.ascontiguousarray(U0), p0=np.zeros(n),
+                phi0=np.ascontiguousarray(phi), h=h, nu=nu, dt=co * h / max(u_lid, 1.0), meta=meta,
+                new_index=new_index)
+
+
 def momentum_rhs(case, component, seed=12):
     """Right-hand side of another velocity component (1 = y, 2 = z) of a
     momentum case: the recipe of its b without the lid term,

@@ -24,7 +24,7 @@ OK, NOT_CONVERGED, BREAKDOWN = 0, 1, -3
 PRECOND = {"none": 0, "jacobi": 1}
 
 
-SOURCES = ("oracle.c", "amg.c", "transient.c", "bicgstab.c")
+SOURCES = ("oracle.c", "amg.c", "transient.c", "bicgstab.c", "piso.c")
 
 
 def build(force: bool = True) -> str:
@@ -109,6 +109,16 @@ def lib(omp: bool = False):
         L.or_bicgstab.restype = i32
         L.or_adjoint_grads.argtypes = [i32, i32, P, P, P, P, P, P, P]
         L.or_adjoint_grads.restype = None
+        L.or_piso_momentum.argtypes = [i32, i32, P, P, P, P, P, d, d, d, P, P, P, P, P]
+        L.or_piso_momentum.restype = None
+        L.or_piso_gradp.argtypes = [i32, i32, P, P, P, P, P, d, P, P]
+        L.or_piso_gradp.restype = None
+        L.or_piso_div.argtypes = [i32, i32, P, P, P, P]
+        L.or_piso_div.restype = None
+        L.or_piso_pressure_system.argtypes = [i32, i32, P, P, P, P, d, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.or_piso_pressure_system.restype = None
+        L.or_piso_run.argtypes = [i32, i32, P, P, P, P, P, P, P, d, d, d, i32, i32, P, P, P, d, d, i32, P, P]
+        L.or_piso_run.restype = i32
         L.or_threads.argtypes = []
         L.or_threads.restype = i32
         L.or_set_threads.argtypes = [i32]
@@ -371,3 +381,69 @@ def dense(A):
     M[A.owner, A.nb] += A.upper
     M[A.nb, A.owner] += A.lower
     return M
+
+
+# ---------------------------------------------------------------- PISO (icoFoam)
+
+def _i8(a):
+    return np.ascontiguousarray(a, dtype=np.int8)
+
+
+def _piso_geom(pc):
+    return (_i32(pc.owner), _i32(pc.neighbour), _i8(pc.face_dir), _i8(pc.face_sgn))
+
+
+def piso_momentum(pc, phi, U_old, dt=None):
+    """(diag, upper, lower, bH[3][n]) of the momentum matrix of a fvcases.Piso."""
+    o, m, fd, fs = _piso_geom(pc)
+    phi, U_old = _f64(phi), _f64(U_old)
+    bw, bl = _f64(pc.bwall), _f64(pc.blid)
+    diag, bH = np.empty(pc.n), np.empty((3, pc.n))
+    upper, lower = np.empty(pc.F), np.empty(pc.F)
+    lib().or_piso_momentum(pc.n, pc.F, _p(o), _p(m), _p(phi), _p(bw), _p(bl), float(pc.h), float(pc.nu),
+                           float(pc.dt if dt is None else dt), _p(U_old), _p(diag), _p(upper), _p(lower), _p(bH))
+    return diag, upper, lower, bH
+
+
+def piso_gradp(pc, p):
+    o, m, fd, fs = _piso_geom(pc)
+    p, bg = _f64(p), _f64(pc.bgrad)
+    g = np.empty((3, pc.n))
+    lib().or_piso_gradp(pc.n, pc.F, _p(o), _p(m), _p(fd), _p(fs), _p(bg), float(pc.h), _p(p), _p(g))
+    return g
+
+
+def piso_div(pc, phi):
+    o, m, _, _ = _piso_geom(pc)
+    phi = _f64(phi)
+    out = np.empty(pc.n)
+    lib().or_piso_div(pc.n, pc.F, _p(o), _p(m), _p(phi), _p(out))
+    return out
+
+
+def piso_pressure_system(pc, diag, upper, lower, bH, U):
+    """One corrector's pieces: dict of HbyA, rAU, phiHbyA, cf, pdiag, pupper, prhs."""
+    o, m, fd, fs = _piso_geom(pc)
+    ins = [_f64(a) for a in (diag, upper, lower, bH, U)]
+    out = {"HbyA": np.empty((3, pc.n)), "rAU": np.empty(pc.n), "phiHbyA": np.empty(pc.F), "cf": np.empty(pc.F),
+           "pdiag": np.empty(pc.n), "pupper": np.empty(pc.F), "prhs": np.empty(pc.n)}
+    lib().or_piso_pressure_system(pc.n, pc.F, _p(o), _p(m), _p(fd), _p(fs), float(pc.h), *[_p(a) for a in ins],
+                                  *[_p(out[k]) for k in ("HbyA", "rAU", "phiHbyA", "cf", "pdiag", "pupper", "prhs")])
+    return out
+
+
+def piso_run(pc, nsteps, n_corr=2, U=None, p=None, phi=None, tol_u=1e-10, tol_p=1e-10, maxit=100000, dt=None):
+    """nsteps PISO steps from (U, p, phi) (default: the case's initial
+    state).  Returns (U, p, phi, status, momentum iterations, pressure
+    iterations)."""
+    o, m, fd, fs = _piso_geom(pc)
+    U = _f64(pc.U0 if U is None else U).copy()
+    p = _f64(pc.p0 if p is None else p).copy()
+    phi = _f64(pc.phi0 if phi is None else phi).copy()
+    bw, bl, bg = _f64(pc.bwall), _f64(pc.blid), _f64(pc.bgrad)
+    iu, ip = ctypes.c_int32(), ctypes.c_int32()
+    status = lib().or_piso_run(pc.n, pc.F, _p(o), _p(m), _p(fd), _p(fs), _p(bw), _p(bl), _p(bg), float(pc.h),
+                               float(pc.nu), float(pc.dt if dt is None else dt), int(nsteps), int(n_corr), _p(U),
+                               _p(p), _p(phi), float(tol_u), float(tol_p), int(maxit), ctypes.byref(iu),
+                               ctypes.byref(ip))
+    return U, p, phi, status, iu.value, ip.value

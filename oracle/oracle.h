@@ -110,6 +110,25 @@ int32_t or_amg_pcg(const or_amg* h, const double* b, double* x, double tol, int3
 /* Pipelined CG (literal recurrences) with the V-cycle; x holds x0 on entry. */
 int32_t or_amg_pipecg(const or_amg* h, const double* b, double* x, double tol, int32_t maxit, or_stats* st);
 
+/* ---- icoFoam's PISO step (piso.c; the method is stated at the top of that
+ * file).  Fields: U [3][n] (x, y, z components), p [n], phi [F]. */
+void or_piso_momentum(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb, const double* phi,
+                      const double* bwall, const double* blid, double h, double nu, double dt, const double* U_old,
+                      double* diag, double* upper, double* lower, double* bH);
+void or_piso_gradp(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb, const int8_t* face_dir,
+                   const int8_t* face_sgn, const double* bgrad, double h, const double* p, double* g);
+void or_piso_div(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb, const double* phi, double* div);
+void or_piso_pressure_system(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb, const int8_t* face_dir,
+                             const int8_t* face_sgn, double h, const double* diag, const double* upper,
+                             const double* lower, const double* bH, const double* U, double* HbyA, double* rAU,
+                             double* phiHbyA, double* cf, double* pdiag, double* pupper, double* prhs);
+/* nsteps PISO steps (momentum predictor by BiCGSTAB to tol_u, n_corr
+ * pressure correctors by CG to tol_p), U, p and phi updated in place. */
+int32_t or_piso_run(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb, const int8_t* face_dir,
+                    const int8_t* face_sgn, const double* bwall, const double* blid, const double* bgrad, double h,
+                    double nu, double dt, int32_t nsteps, int32_t n_corr, double* U, double* p, double* phi,
+                    double tol_u, double tol_p, int32_t maxit, int32_t* iters_u, int32_t* iters_p);
+
 /* ---- Transient diffusion (transient.c): implicit-Euler LDU assembly of
  * laplacianFoam's heat equation and a run of nsteps steps (each solved by
  * Jacobi-PCG from the previous field; T in/out). */
