@@ -71,6 +71,9 @@ enum {
 
 /* Preconditioner M ("optional" in Section 2). */
 enum { FVPCG_PRECOND_NONE = 0, FVPCG_PRECOND_JACOBI = 1 };
+/* pressure solver of fvpcg_piso_create: Jacobi-PCG, or PCG with the
+ * smoothed-aggregation AMG cycle (hierarchy built once per time step) */
+enum { FVPCG_PSOLVER_JACOBI = 0, FVPCG_PSOLVER_AMG = 1 };
 
 /* fvpcg_matrix_create flags */
 #define FVPCG_FP32_COPY 1u /* also keep an FP32 copy for the mixed-precision solves */
@@ -83,6 +86,7 @@ typedef struct fvpcg_mesh fvpcg_mesh;
 typedef struct fvpcg_matrix fvpcg_matrix;
 typedef struct fvpcg_batch fvpcg_batch;
 typedef struct fvpcg_amg fvpcg_amg;
+typedef struct fvpcg_piso fvpcg_piso;
 
 typedef struct fvpcg_stats {
     int32_t iters;        /* updates of x (inner iterations summed for the mixed solver) */
@@ -273,6 +277,44 @@ FVPCG_API int fvpcg_assemble_transient(const fvpcg_mesh* mesh, const double* k_f
 FVPCG_API int fvpcg_transient_run(fvpcg_matrix* mat, const double* k_face, const double* w_face, const double* vol,
                                   const double* bdiag, const double* bsrc, double dt, int32_t nsteps, double* T,
                                   double tol, int32_t maxit, int32_t method, void* stream, fvpcg_stats* stats);
+
+/* ---- icoFoam's PISO step (Section 2: icoFoam solves its momentum equation
+ * with BiCGSTAB and its pressure equation with CG, then corrects the velocity
+ * explicitly; Section 4.1: the application calls the solver every step), on
+ * the mesh of a box of cubes of side h, all on the device:
+ *   momentum, implicit Euler with upwind convection of the face flux phi
+ *   (owner -> neighbour): upper_f = -nu h - max(-phi_f, 0), lower_f =
+ *   -nu h - max(phi_f, 0), diag_c = h^3/dt + bwall_c + sum over c's faces of
+ *   (nu h + outflow_f if > 0); H source bH = (h^3/dt) U + blid (x only);
+ *   predictor A U_k = bH_k - h^3 (grad p)_k for the three components
+ *   together (BiCGSTAB, Jacobi, from the old U to tol_u);
+ *   n_corr correctors: rAU = h^3 / diag, HbyA_k = (bH_k - offdiag(A) U_k) / diag,
+ *   phiHbyA_f = face_sgn h^2 (HbyA_o + HbyA_n)/2 along the face's axis,
+ *   c_f = h (rAU_o + rAU_n) / 2, pressure sum_f c_f (p_c - p_other) =
+ *   -div(phiHbyA)_c with cell 0 pinned at p = 0 (its couplings zero in both
+ *   triangles), solved by CG from the previous p to tol_p;
+ *   phi_f = phiHbyA_f - c_f (p_n - p_o); U_k = HbyA_k - rAU (grad p)_k.
+ * (grad p)_kc = (1/h)(bgrad_kc p_c + sum over c's faces along k of the
+ * outward normal sign times (p_o + p_n)/2) (zero-gradient walls).
+ * Inputs (device, copied at creation): face_dir int8[F] (0/1/2: the face's
+ * axis), face_sgn int8[F] (+1 if the neighbour lies on the + side of the
+ * owner along that axis, else -1), bwall FP64[n] (2 nu h per no-slip face,
+ * lid included), blid FP64[n] (2 nu h u_lid per lid face), bgrad FP64[3][n]
+ * (sum of the outward normal signs of the cell's boundary faces per axis).
+ * The mesh must outlive the handle; calls on one handle must not overlap. */
+FVPCG_API int fvpcg_piso_create(const fvpcg_mesh* mesh, const int8_t* face_dir, const int8_t* face_sgn,
+                                const double* bwall, const double* blid, const double* bgrad, double h, double nu,
+                                int32_t pressure_solver, void* stream, fvpcg_piso** out);
+FVPCG_API int fvpcg_piso_destroy(fvpcg_piso* piso);
+/* nsteps steps of size dt; U FP64[3][n] (x, y, z), p FP64[n] and phi FP64[F]
+ * are device arrays updated in place (p[0] must be 0).  stats[0]: momentum
+ * (iters = BiCGSTAB iterations over all components and steps, outer_iters =
+ * steps done, device_ms = the whole run), stats[1]: pressure (iters summed,
+ * outer_iters = pressure solves); stats may be NULL.  Returns the first
+ * non-OK solver status (NOT_CONVERGED, BREAKDOWN) or an error code. */
+FVPCG_API int fvpcg_piso_run(fvpcg_piso* piso, double dt, int32_t nsteps, int32_t n_corr, double* U, double* p,
+                             double* phi, double tol_u, double tol_p, int32_t maxit, void* stream,
+                             fvpcg_stats* stats);
 
 /* ---- For callers that cannot allocate device memory (tight serving loops,
  * harnesses that forbid hipMalloc): fvpcg_solve with the same arguments,

@@ -474,6 +474,72 @@ def fvpcg_transient_run(A: Matrix, k_face, w_face, vol, bdiag, bsrc, dt, nsteps,
 transient_run = fvpcg_transient_run
 
 
+# ---------------------------------------------------------------- icoFoam PISO
+
+PSOLVERS = {"jacobi": _lib.PSOLVER_JACOBI, "amg": _lib.PSOLVER_AMG}
+
+
+class Piso:
+    """icoFoam's PISO step on a Mesh of cubes of side h (fvpcg_piso_*):
+    face_dir/face_sgn int8[F], bwall/blid [n], bgrad [3][n] device tensors
+    (copied); the Mesh must outlive it."""
+
+    def __init__(self, mesh: Mesh, face_dir, face_sgn, bwall, blid, bgrad, h, nu, pressure_solver="jacobi",
+                 stream=None):
+        import torch
+
+        n, F = mesh.n, mesh.F
+        h_ = ctypes.c_void_p()
+        _check(lib().fvpcg_piso_create(
+            mesh.handle, _ptr(face_dir, torch.int8, F, "face_dir"), _ptr(face_sgn, torch.int8, F, "face_sgn"),
+            _ptr(bwall, torch.float64, n, "bwall"), _ptr(blid, torch.float64, n, "blid"),
+            _ptr(bgrad, torch.float64, 3 * n, "bgrad"), float(h), float(nu), PSOLVERS[pressure_solver],
+            _stream(stream), ctypes.byref(h_)), "fvpcg_piso_create")
+        self._h = h_
+        self.mesh = mesh
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fvpcg_piso_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fvpcg_piso_create(mesh, face_dir, face_sgn, bwall, blid, bgrad, h, nu, pressure_solver="jacobi", stream=None):
+    return Piso(mesh, face_dir, face_sgn, bwall, blid, bgrad, h, nu, pressure_solver, stream)
+
+
+def fvpcg_piso_destroy(ps: Piso):
+    ps.close()
+    return OK
+
+
+def fvpcg_piso_run(ps: Piso, dt, nsteps, U, p, phi, n_corr=2, tol_u=1e-8, tol_p=1e-8, maxit=100000, stream=None):
+    """nsteps PISO steps; U [3][n], p [n], phi [F] device tensors updated in
+    place.  Returns (momentum stats, pressure stats)."""
+    import torch
+
+    n, F = ps.mesh.n, ps.mesh.F
+    st = (Stats * 2)()
+    code = lib().fvpcg_piso_run(ps.handle, float(dt), int(nsteps), int(n_corr), _ptr(U, torch.float64, 3 * n, "U"),
+                                _ptr(p, torch.float64, n, "p"), _ptr(phi, torch.float64, F, "phi"), float(tol_u),
+                                float(tol_p), int(maxit), _stream(stream), ctypes.cast(st, ctypes.POINTER(Stats)))
+    _check(code, "fvpcg_piso_run")
+    return st[0].asdict(), st[1].asdict()
+
+
+piso_run = fvpcg_piso_run
+
+
 # ---------------------------------------------------------------- AMG
 
 class AMG:

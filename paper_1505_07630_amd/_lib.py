@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "INVALID_MES
 CG, PIPECG, PIPECG_LITERAL = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 FP32_COPY = 1
+PSOLVER_JACOBI, PSOLVER_AMG = 0, 1
 MAX_ROW_DEGREE = 32
 
 # Every function the header declares, with (restype, argtypes).
@@ -70,6 +71,9 @@ SIGNATURES = {
     "fvpcg_amg_create": (ctypes.c_int, [P, f64, i32, i32, ctypes.c_uint64, P, PP]),
     "fvpcg_amg_export": (ctypes.c_int, [P, i32, i32, P, P, P, P, P, P]),
     "fvpcg_amg_destroy": (ctypes.c_int, [P]),
+    "fvpcg_piso_create": (ctypes.c_int, [P, P, P, P, P, P, f64, f64, i32, P, PP]),
+    "fvpcg_piso_destroy": (ctypes.c_int, [P]),
+    "fvpcg_piso_run": (ctypes.c_int, [P, f64, i32, i32, P, P, P, f64, f64, i32, P, SPS]),
     "fvpcg_amg_info": (ctypes.c_int, [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]),
     "fvpcg_amg_aggregates": (ctypes.c_int, [P, i32, P]),
     "fvpcg_amg_apply": (ctypes.c_int, [P, P, P, P]),

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, LIB_NAME)
 ARCH = "gfx950"
 
 SOURCES = ["setup.hip", "solve.hip", "batched.hip", "amg.hip", "amg_setup.hip", "transient.hip", "bicgstab.hip",
-           "calibrate.hip", "api.hip"]
+           "piso.hip", "calibrate.hip", "api.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}",

@@ -54,6 +54,14 @@ int solve_noalloc(const fvpcg_matrix* A, const double* b, double* x, double tol,
                   hipStream_t s, fvpcg_stats* stats);
 int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, uint64_t seed, hipStream_t s,
                fvpcg_amg** out);
+int piso_create(const fvpcg_mesh* m, const int8_t* face_dir, const int8_t* face_sgn, const double* bwall,
+                const double* blid, const double* bgrad, double h, double nu, int psolver, hipStream_t s,
+                fvpcg_piso** out);
+void piso_free(fvpcg_piso* ps);
+int piso_run(fvpcg_piso* ps, double dt, int nsteps, int n_corr, double* U, double* p, double* phi, double tol_u,
+             double tol_p, int maxit, hipStream_t s, fvpcg_stats* stats);
+int piso_mesh_n(const fvpcg_piso* ps);
+int piso_mesh_f(const fvpcg_piso* ps);
 void amg_free(fvpcg_amg* h);
 int amg_levels(const fvpcg_amg* h);
 int amg_level_n(const fvpcg_amg* h, int l);
@@ -506,6 +514,62 @@ int fvpcg_solve_batched_backward(const fvpcg_batch* batch, const double* x, cons
             return set_error(FVPCG_UNSUPPORTED, "CG needs symmetric systems (lower == upper on every face)");
         return solve_batched_backward(batch, x, g, grad_b, grad_diag, grad_upper, grad_lower, tol, maxit, method,
                                       precond, (hipStream_t)stream, stats);
+    });
+}
+
+int fvpcg_piso_create(const fvpcg_mesh* mesh, const int8_t* face_dir, const int8_t* face_sgn, const double* bwall,
+                      const double* blid, const double* bgrad, double h, double nu, int32_t pressure_solver,
+                      void* stream, fvpcg_piso** out) {
+    return guard([&]() -> int {
+        if (!out) return set_error(FVPCG_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        if (!mesh) return set_error(FVPCG_INVALID_ARG, "mesh is NULL");
+        if (!(h > 0.0) || !std::isfinite(h) || !(nu > 0.0) || !std::isfinite(nu))
+            return set_error(FVPCG_INVALID_ARG, "need finite h > 0 and nu > 0");
+        if (pressure_solver != FVPCG_PSOLVER_JACOBI && pressure_solver != FVPCG_PSOLVER_AMG)
+            return set_error(FVPCG_INVALID_ARG, "unknown pressure solver %d", pressure_solver);
+        const size_t n = (size_t)mesh->n, F = (size_t)mesh->F;
+        if (F) {
+            FV_TRY(check_dev(face_dir, F, "face_dir"));
+            FV_TRY(check_dev(face_sgn, F, "face_sgn"));
+        }
+        FV_TRY(check_dev(bwall, sizeof(double) * n, "bwall"));
+        FV_TRY(check_dev(blid, sizeof(double) * n, "blid"));
+        FV_TRY(check_dev(bgrad, sizeof(double) * 3 * n, "bgrad"));
+        return piso_create(mesh, face_dir, face_sgn, bwall, blid, bgrad, h, nu,
+                           pressure_solver == FVPCG_PSOLVER_AMG ? FVPCG_PSOLVER_AMG : FVPCG_CG, (hipStream_t)stream,
+                           out);
+    });
+}
+
+int fvpcg_piso_destroy(fvpcg_piso* piso) {
+    return guard([&]() -> int {
+        piso_free(piso);
+        return FVPCG_OK;
+    });
+}
+
+int fvpcg_piso_run(fvpcg_piso* piso, double dt, int32_t nsteps, int32_t n_corr, double* U, double* p, double* phi,
+                   double tol_u, double tol_p, int32_t maxit, void* stream, fvpcg_stats* stats) {
+    return guard([&]() -> int {
+        if (stats) {
+            stats_status(&stats[0], FVPCG_INVALID_ARG);
+            stats_status(&stats[1], FVPCG_INVALID_ARG);
+        }
+        if (!piso) return set_error(FVPCG_INVALID_ARG, "piso is NULL");
+        if (!(dt > 0.0) || !std::isfinite(dt) || nsteps < 0 || n_corr < 1 || maxit < 1)
+            return set_error(FVPCG_INVALID_ARG, "need dt > 0, nsteps >= 0, n_corr >= 1, maxit >= 1");
+        if (!(tol_u > 0.0) || !(tol_p > 0.0) || !std::isfinite(tol_u) || !std::isfinite(tol_p))
+            return set_error(FVPCG_INVALID_ARG, "need finite tol_u > 0 and tol_p > 0");
+        const size_t n = (size_t)piso_mesh_n(piso), F = (size_t)piso_mesh_f(piso);
+        FV_TRY(check_dev(U, sizeof(double) * 3 * n, "U"));
+        FV_TRY(check_dev(p, sizeof(double) * n, "p"));
+        if (F) FV_TRY(check_dev(phi, sizeof(double) * F, "phi"));
+        if (overlap(U, sizeof(double) * 3 * n, p, sizeof(double) * n) ||
+            (F && (overlap(U, sizeof(double) * 3 * n, phi, sizeof(double) * F) ||
+                   overlap(p, sizeof(double) * n, phi, sizeof(double) * F))))
+            return set_error(FVPCG_INVALID_ARG, "U, p and phi must not overlap");
+        return piso_run(piso, dt, nsteps, n_corr, U, p, phi, tol_u, tol_p, maxit, (hipStream_t)stream, stats);
     });
 }
 
