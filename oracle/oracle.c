@@ -413,17 +413,8 @@ int32_t or_pipecg(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb
 }
 
 /* ---- FP32 pieces for the refinement driver: the same LDU product and the
- * folded pipelined Jacobi-CG in single precision, inner products accumulated
- * in double.  In FP32 the recursively updated residual of the pipelined
- * recurrences drifts away from the true one within a few dozen iterations,
- * so every OR_REPLACE_EVERY iterations the recurrence vectors are replaced
- * by their definitions (residual replacement for pipelined CG):
- *   r = b - A x,  w = A D^-1 r,  s = A p,  z = A D^-1 s,
- * and the inner solve stops once OR_STAGNATION_CHECKS consecutive
- * replacements bring no new minimum of ||r||: FP32 has then reached the
- * accuracy it can attain for this system, and the FP64 outer loop takes
- * over. */
-enum { OR_REPLACE_EVERY = 20, OR_STAGNATION_CHECKS = 5 };
+ * folded pipelined Jacobi-CG (O-3) in single precision, inner products
+ * accumulated in double, stopped on its recursively updated residual. */
 
 static void spmv32(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
                    const float* diag, const float* upper, const float* lower,
@@ -456,8 +447,8 @@ static int32_t pipecg32_folded(int32_t n, int32_t nf, const int32_t* owner, cons
     spmv32(n, nf, owner, nb, diag, upper, lower, x, r);
     for (int32_t c = 0; c < n; ++c) r[c] = b[c] - r[c];
     spmv32_scaled(n, nf, owner, nb, diag, upper, lower, r, m, w);
-    double gamma_prev = 0.0, alpha_prev = 0.0, best = INFINITY;
-    int32_t status = OR_NOT_CONVERGED, i, no_min = 0;
+    double gamma_prev = 0.0, alpha_prev = 0.0;
+    int32_t status = OR_NOT_CONVERGED, i;
     for (i = 0;; ++i) {
         for (int32_t c = 0; c < n; ++c) u[c] = r[c] / diag[c];
         double gamma = dot32(n, r, u);
@@ -483,21 +474,6 @@ static int32_t pipecg32_folded(int32_t n, int32_t nf, const int32_t* owner, cons
         }
         gamma_prev = gamma;
         alpha_prev = alpha;
-        if ((i + 1) % OR_REPLACE_EVERY == 0) {
-            spmv32(n, nf, owner, nb, diag, upper, lower, x, r);
-            for (int32_t c = 0; c < n; ++c) r[c] = b[c] - r[c];
-            spmv32_scaled(n, nf, owner, nb, diag, upper, lower, r, m, w);
-            spmv32(n, nf, owner, nb, diag, upper, lower, p, s);
-            spmv32_scaled(n, nf, owner, nb, diag, upper, lower, s, m, z);
-            double t = dot32(n, r, r);
-            if (t < best) {
-                best = t;
-                no_min = 0;
-            } else if (++no_min >= OR_STAGNATION_CHECKS) {
-                i += 1;
-                break;
-            }
-        }
     }
     *iters = i;
     free(r); free(u); free(w); free(m); free(nv); free(z); free(s); free(p);
@@ -505,10 +481,12 @@ static int32_t pipecg32_folded(int32_t n, int32_t nf, const int32_t* owner, cons
 }
 
 /* ---- Mixed-precision iterative refinement (an extension beside the
- * paper's FP64 solver).  Outer loop in FP64 with the FP64 matrix:
- *   r = b - A x; stop when ||r|| <= outer_tol ||b||, or when ||r|| no longer
- *   decreases (NOT_CONVERGED, the last correction taken back);
- *   solve A32 c = fp32(r / ||r||) to inner_tol from c = 0;
+ * paper's FP64 solver, as the workload list states it).  Outer loop in FP64
+ * with the FP64 matrix:
+ *   r = b - A x; stop when ||r|| <= outer_tol ||b|| (OK), at max_outer
+ *   (NOT_CONVERGED) or on a non-finite ||r|| (BREAKDOWN);
+ *   solve A32 c = fp32(r / ||r||) by the FP32 folded pipelined Jacobi-CG to
+ *   inner_tol (its recursive residual) or max_inner, from c = 0;
  *   x += ||r|| * c. */
 int32_t or_refine(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
                   const double* diag, const double* upper, const double* lower,
@@ -535,21 +513,14 @@ int32_t or_refine(int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb
     for (int32_t f = 0; f < nf; ++f) { u32[f] = (float)upper[f]; l32[f] = (float)lower[f]; }
 
     int32_t status = OR_NOT_CONVERGED, j, total_inner = 0;
-    double rnorm = 0.0, prev = INFINITY;
+    double rnorm = 0.0;
     for (j = 0;; ++j) {
         residual(n, nf, owner, nb, diag, upper, lower, b, x, r);
         rnorm = sqrt(or_dot(n, r, r));
         if (j == 0 && st) st->r0_norm = rnorm;
         if (rnorm <= outer_tol * bnorm) { status = OR_OK; break; }
         if (!isfinite(rnorm)) { status = OR_BREAKDOWN; break; }
-        if (rnorm >= prev) {
-            /* the last correction did not help: take it back */
-            for (int32_t c = 0; c < n; ++c) x[c] -= prev * (double)cor[c];
-            rnorm = prev;
-            break;
-        }
         if (j == max_outer) break;
-        prev = rnorm;
         for (int32_t c = 0; c < n; ++c) { rhs[c] = (float)(r[c] / rnorm); cor[c] = 0.0f; }
         int32_t it = 0;
         int32_t s = pipecg32_folded(n, nf, owner, nb, d32, u32, l32, rhs, cor, inner_tol, max_inner, &it);
