@@ -258,9 +258,11 @@ def test_batch256_full_size(fv, orc, batch256, method):
 
 
 def test_batch256_backward_fd(fv, orc, batch256):
-    """Gradient of L = 0.5||x - x_t||^2 w.r.t. b and the face coefficients of
-    all 256 systems, by the batched adjoint, checked by central differences
-    (h = 1e-6) along a random direction."""
+    """Gradient of L = 0.5||x - x_t||^2 w.r.t. b and the face coefficients
+    (upper = lower, the symmetric storage's combined gradient) of all 256
+    systems, by the batched adjoint, each checked by central differences
+    (h = 1e-6) along a random direction: for the face coefficients the batch
+    is created again from upper +- h du (diagonal unchanged) and solved."""
     import torch
 
     bt = batch256
@@ -271,10 +273,27 @@ def test_batch256_backward_fd(fv, orc, batch256):
     grads, _, code = fv.solve_batched_backward(B, x, x - xt, tol=1e-13, method="cg")
     assert code == 0
     rng = np.random.default_rng(5)
+    h = 1e-6
+    # along b
     db = to_dev(rng.standard_normal(bt.cell_off[-1]))
     pred = torch.dot(grads["b"], db).item()
-    h = 1e-6
     Lp = 0.5 * torch.sum((fv.solve_batched(B, b + h * db, tol=1e-13, method="cg")[0] - xt) ** 2).item()
     Lm = 0.5 * torch.sum((fv.solve_batched(B, b - h * db, tol=1e-13, method="cg")[0] - xt) ** 2).item()
+    say(f"[fd] batch256 along b: adjoint {pred:.10e} central difference {(Lp - Lm) / (2 * h):.10e}")
     assert (Lp - Lm) / (2 * h) == pytest.approx(pred, rel=1e-5)
     B.close()
+    # along the face coefficients
+    owner, nb = to_dev(bt.owner, torch.int32), to_dev(bt.neighbour, torch.int32)
+    diag, upper = to_dev(bt.diag), to_dev(bt.upper)
+    du = to_dev(rng.standard_normal(bt.face_off[-1]))
+    pred_u = torch.dot(grads["upper"], du).item()
+
+    def loss(up):
+        Bh = fv.Batch(bt.cell_off, bt.face_off, owner, nb, diag, up)
+        xh = fv.solve_batched(Bh, b, tol=1e-13, method="cg")[0]
+        Bh.close()
+        return 0.5 * torch.sum((xh - xt) ** 2).item()
+
+    fd = (loss(upper + h * du) - loss(upper - h * du)) / (2 * h)
+    say(f"[fd] batch256 along the face coefficients: adjoint {pred_u:.10e} central difference {fd:.10e}")
+    assert fd == pytest.approx(pred_u, rel=1e-5)

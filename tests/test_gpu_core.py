@@ -4,7 +4,10 @@ SpMV: element by element against the oracle's face-loop product, within a
 rounding bound proportional to each row's absolute sum.
 Solves: the GPU solve runs to tolerance; the oracle is rerun with the same
 method for exactly the GPU's iteration count; relative solution difference
-<= 1e-10 (FP64), iteration counts within +-2 of the oracle's own count.
+<= 1e-10 (FP64), iteration counts within +-2 of the oracle's own count, for
+every Jacobi combination of the named workloads; the other combinations and
+the pipelined forms on the graded cavity are checked against the oracle's
+own sensitivity to the order of its sums (each bar is printed).
 """
 import ctypes
 
@@ -98,10 +101,19 @@ SOLVE_CASES = {
 }
 METHODS = [("cg", "jacobi"), ("pipecg", "jacobi"), ("pipecg_literal", "jacobi"), ("cg", "none"), ("pipecg", "none")]
 # (case, method, precond) combinations of the named workloads (uniform Dirichlet
-# cube: PCG and pipelined CG; lognormal permuted cube: pipelined PCG; graded
-# cavity: PCG), where the strict bars must hold as stated.
-STRICT = {("laplace32", "cg", "jacobi"), ("laplace32", "pipecg", "jacobi"), ("varcoef32_rcm", "pipecg", "jacobi"),
-          ("cavity64x64x16", "cg", "jacobi"), ("varcoef32_rcm", "cg", "jacobi")}
+# cube: PCG and both pipelined forms; lognormal permuted cube: the same three;
+# graded cavity: PCG), where the strict bars hold as stated: +-2 iterations and
+# 1e-10 at equal count.  On these the oracle's own solution moves by at most
+# 2.6e-11 when only the order of its sums changes.
+STRICT = {("laplace32", m, "jacobi") for m in ("cg", "pipecg", "pipecg_literal")} | \
+         {("varcoef32_rcm", m, "jacobi") for m in ("cg", "pipecg", "pipecg_literal")} | \
+         {("cavity64x64x16", "cg", "jacobi")}
+# The pipelined recurrences on the graded cavity amplify rounding: reordering
+# the oracle's own sums moves its solution at equal count by 2-4e-8 (standard
+# CG: 3e-14).  These get the check of check_amplifying instead of a bar.
+AMPLIFYING = {("cavity64x64x16", "pipecg", "jacobi"), ("cavity64x64x16", "pipecg_literal", "jacobi"),
+              ("cavity64x64x16", "pipecg", "none")}
+MEASURED_CAP = 1e-8
 
 
 def renumbered(case, seed=0):
@@ -119,20 +131,12 @@ def renumbered(case, seed=0):
     return fc.Case(case.name, case.shape, case.n, o.astype(np.int32), nb.astype(np.int32), d, up, lo, b), new_index
 
 
-def parity_bars(orc, case, method, precond, tol, k_or, k, xo, xs=None):
-    """(iteration-count bar, solution-difference bar, distance-to-solution
-    bar).  The oracle itself is run on randomly renumbered copies of the
-    system (three of them), which changes only the order of its
-    floating-point sums; its largest change of iteration count and of the
-    solution at equal count measure how much a reordering of the sums moves
-    this solve.  Bars: max(2, 2x that count change) and max(1e-10, 10x that
-    solution change).  For the pipelined recurrences and for unpreconditioned
-    solves of badly scaled systems the reordering alone moves the solution by
-    more than 1e-10.  With xs (the exact solution) also returns 4x the largest
-    distance of the oracle's iterates to it: where the pipelined iterate's
-    own rounding dominates (the graded cavity), its distance to the solution
-    varies by factors of 2 between orderings of the same sums; the true
-    residual (checked separately) stays within tolerance."""
+def oracle_spread(orc, case, method, precond, tol, k_or, k, xo, xs=None):
+    """How much reordering the oracle's floating-point sums moves this solve:
+    the oracle on three randomly renumbered copies of the system gives the
+    largest change of its iteration count (dk), of its solution at equal
+    count k (dx), and the largest distance of those iterates to the exact
+    solution xs (ex; 0 without xs)."""
     dk, dx, ex = 0, 0.0, (rel(xo, xs) if xs is not None else 0.0)
     for seed in range(3):
         pc, new_index = renumbered(case, seed)
@@ -142,38 +146,69 @@ def parity_bars(orc, case, method, precond, tol, k_or, k, xo, xs=None):
         dx = max(dx, rel(xp[new_index], xo))
         if xs is not None:
             ex = max(ex, rel(xp[new_index], xs))
-    return max(2, 2 * dk), max(PARITY, 10.0 * dx), 4.0 * ex + 1e-12
+    return dk, dx, ex
 
 
 @pytest.mark.parametrize("name", list(SOLVE_CASES))
 @pytest.mark.parametrize("method,precond", METHODS)
 def test_solve_parity_equal_iterations(fv, orc, name, method, precond):
-    say("solve", name, method, precond)
+    """Strict combinations: +-2 iterations and 1e-10 at equal count.  Others
+    (unpreconditioned solves of badly scaled systems): bars measured from the
+    oracle's own sensitivity to the order of its sums, max(2, 2 dk)
+    iterations and max(1e-10, 10 dx) capped at 1e-8.  The pipelined forms on
+    the graded cavity: check_amplifying."""
     mk, tol = SOLVE_CASES[name]
     case = mk()
     dc = DevCase(case)
+    say("solve", name, method, precond)
     x, st = fv.solve(dc.A, dc.b, tol=tol, maxit=20000, method=method, precond=precond)
     assert st["status"] == 0, st
     k = st["iters"]
     _, so = oracle_solve(orc, case, method, precond, tol, 20000)
     xo, _ = oracle_solve(orc, case, method, precond, 0.0, k)
     xg = x.cpu().numpy()
+    diff = rel(xg, xo)
+    key = (name, method, precond)
+    assert st["true_rel_res"] <= 10 * tol
+    assert st["b_norm"] == pytest.approx(np.linalg.norm(case.b), rel=1e-13)
     xs = None
     if method != "cg" and precond == "jacobi":
         xs, _ = orc.cg(case, case.b, tol=1e-13, maxit=50000, precond="jacobi")
-    if (name, method, precond) in STRICT:
-        count_bar, diff_bar = 2, PARITY
-        exact_bar = 2 * rel(xo, xs) + 1e-12 if xs is not None else None
+    if key in STRICT:
+        say(f"[bar] {key}: strict; iterations gpu {k} oracle {so['iters']}; difference {diff:.2e} <= 1e-10")
+        assert abs(so["iters"] - k) <= 2, (so["iters"], k)
+        assert diff <= PARITY
+        if xs is not None:  # as close to the exact solution as the oracle's own iterate
+            assert rel(xg, xs) <= 2 * rel(xo, xs) + 1e-12
+    elif key in AMPLIFYING:
+        check_amplifying(orc, case, method, precond, tol, so, k, st, xg, xo, xs)
     else:
-        count_bar, diff_bar, exact_bar = parity_bars(orc, case, method, precond, tol, so["iters"], k, xo, xs)
-    assert abs(so["iters"] - k) <= count_bar, (so["iters"], k)
-    assert rel(xg, xo) <= diff_bar
-    assert st["true_rel_res"] <= 10 * tol
-    assert st["b_norm"] == pytest.approx(np.linalg.norm(case.b), rel=1e-13)
+        dk, dx, _ = oracle_spread(orc, case, method, precond, tol, so["iters"], k, xo)
+        count_bar, diff_bar = max(2, 2 * dk), min(MEASURED_CAP, max(PARITY, 10.0 * dx))
+        say(f"[bar] {key}: measured; oracle spread dk={dk} dx={dx:.2e} -> bars +-{count_bar}, {diff_bar:.2e}; "
+            f"iterations gpu {k} oracle {so['iters']}; difference {diff:.2e}")
+        assert abs(so["iters"] - k) <= count_bar, (so["iters"], k)
+        assert diff <= diff_bar
+
+
+def check_amplifying(orc, case, method, precond, tol, so, k, st, xg, xo, xs):
+    """Where reordering the oracle's own sums moves its iterate by more than
+    the 1e-8 cap (the pipelined recurrences on the graded cavity), the GPU is
+    checked as one more ordering of the same sums: iteration count within
+    max(2, 2 dk) of the oracle's; difference from the oracle's iterate at
+    equal count within 2x the largest difference between the oracle and its
+    own renumbered runs; FP64 true residual within 2 tol; and, with Jacobi,
+    distance to the exact solution within 2x the oracle runs' largest."""
+    dk, dx, ex = oracle_spread(orc, case, method, precond, tol, so["iters"], k, xo, xs)
+    diff = rel(xg, xo)
+    say(f"[bar] {(case.name, method, precond)}: amplifying; oracle spread dk={dk} dx={dx:.2e} ex={ex:.2e}; "
+        f"iterations gpu {k} oracle {so['iters']}; difference {diff:.2e}; true residual {st['true_rel_res']:.2e}"
+        + (f"; distance to solution {rel(xg, xs):.2e}" if xs is not None else ""))
+    assert abs(so["iters"] - k) <= max(2, 2 * dk), (so["iters"], k)
+    assert diff <= 2.0 * dx
+    assert st["true_rel_res"] <= 2 * tol
     if xs is not None:
-        # as close to the exact solution as the oracle's own iterates
-        assert rel(xg, xs) <= exact_bar
-    dc.close()
+        assert rel(xg, xs) <= 2.0 * ex
 
 
 def test_fixed_iteration_mode(fv, orc):
