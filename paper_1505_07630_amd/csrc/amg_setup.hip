@@ -257,6 +257,38 @@ __global__ __launch_bounds__(kSetupBs) void k_mis_max(const int* __restrict__ pt
     }
 }
 
+// Level 0 in the matrix's slot layout (slot k of row c at k n + c, padding
+// repeating the row with a zero value): the same strength relation, stored
+// per slot, and the same maxima, read with coalesced slot loads.
+__global__ __launch_bounds__(kSetupBs) void k_strength_ell(const int* __restrict__ col, const double* __restrict__ val,
+                                                          const double* __restrict__ d, int n, int W, double theta,
+                                                          uint8_t* __restrict__ strong) {
+    FV_GRID_LOOP(c, n) {
+        for (int k = 0; k < W; ++k) {
+            const size_t o = (size_t)k * n + c;
+            const int j = col[o];
+            const double a = val[o];
+            strong[o] = (j != (int)c && a != 0.0 && fabs(a) >= theta * sqrt(fabs(d[c] * d[j]))) ? 1 : 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kSetupBs) void k_mis_max_ell(const int* __restrict__ col,
+                                                         const uint8_t* __restrict__ strong, int n, int W,
+                                                         const uint64_t* __restrict__ in, uint64_t* __restrict__ out) {
+    FV_GRID_LOOP(c, n) {
+        uint64_t m = in[c];
+        for (int k = 0; k < W; ++k) {
+            const size_t o = (size_t)k * n + c;
+            if (strong[o]) {
+                const uint64_t v = in[col[o]];
+                m = v > m ? v : m;
+            }
+        }
+        out[c] = m;
+    }
+}
+
 // m2_i: the largest key within two strong steps of i.
 __global__ __launch_bounds__(kSetupBs) void k_mis_decide(int n, uint64_t* __restrict__ key,
                                                         const uint64_t* __restrict__ m2, int* undecided) {
@@ -351,14 +383,18 @@ __global__ __launch_bounds__(kSetupBs) void k_tentative(int n, int* __restrict__
 // ---------------------------------------------------------------- products
 // Upper bound of the entries of row i of X Y: the lengths of the rows of Y
 // that row i of X selects.
+// Also the longest row of X into *maxlen.
 __global__ __launch_bounds__(kSetupBs) void k_gemm_bound(const int* __restrict__ xptr, const int* __restrict__ xcol,
                                                         const int* __restrict__ yptr, int rows,
-                                                        long long* __restrict__ ub) {
+                                                        long long* __restrict__ ub, int* maxlen) {
+    int m = 0;
     FV_GRID_LOOP(i, rows) {
         long long t = 0;
         for (int p = xptr[i]; p < xptr[i + 1]; ++p) t += yptr[xcol[p] + 1] - yptr[xcol[p]];
         ub[i] = t;
+        m = max(m, xptr[i + 1] - xptr[i]);
     }
+    if (m) atomicMax(maxlen, m);
 }
 
 // binary min-heap of 64-bit keys
@@ -396,11 +432,69 @@ __device__ __forceinline__ void heap_down(unsigned long long* H, int h, int i) {
 
 #pragma clang fp contract(off)
 // Row i of C = X Y by a k-way merge of the rows Y(k, :) for k in X(i, :):
-// the heap holds (column << 32 | list index) of each list's head; popping
-// yields the columns in ascending order and, for equal columns, the lists in
-// X's column order, in which their products are summed (each product
-// rounded, then added).  Output: the row's distinct columns and sums at
-// off[i] in (tcol, tval) and its count.  heap/pos: scratch indexed like X.
+// the heap H holds (column << 32 | list index) of each list's head, P each
+// list's current position; popping yields the columns in ascending order
+// and, for equal columns, the lists in X's column order, in which their
+// products are summed (each product rounded, then added).  Output: the
+// row's distinct columns and sums at off[i] in (tcol, tval), and its count.
+__device__ __forceinline__ void merge_row(long long i, const int* __restrict__ xptr, const int* __restrict__ xcol,
+                                          const double* __restrict__ xval, const int* __restrict__ yptr,
+                                          const int* __restrict__ ycol, const double* __restrict__ yval,
+                                          const long long* __restrict__ off, unsigned long long* H, int* P,
+                                          int* __restrict__ tcol, double* __restrict__ tval, int* __restrict__ cnt) {
+    const int base = xptr[i], L = xptr[i + 1] - base;
+    int h = 0;
+    for (int t = 0; t < L; ++t) {
+        const int k = xcol[base + t];
+        const int b = yptr[k];
+        if (b < yptr[k + 1]) {
+            P[t] = b;
+            H[h] = ((unsigned long long)(unsigned)ycol[b] << 32) | (unsigned)t;
+            heap_up(H, h);
+            ++h;
+        }
+    }
+    const long long o = off[i];
+    int out = 0, last = -1;
+    double acc = 0.0;
+    while (h > 0) {
+        const unsigned long long top = H[0];
+        const int c = (int)(top >> 32), t = (int)(top & 0xffffffffu);
+        const int k = xcol[base + t];
+        int p = P[t];
+        const double v = xval[base + t] * yval[p];
+        if (c == last) {
+            acc += v;
+        } else {
+            if (last >= 0) {
+                tcol[o + out] = last;
+                tval[o + out] = acc;
+                ++out;
+            }
+            last = c;
+            acc = v;
+        }
+        ++p;
+        if (p < yptr[k + 1]) {
+            P[t] = p;
+            H[0] = ((unsigned long long)(unsigned)ycol[p] << 32) | (unsigned)t;
+            heap_down(H, h, 0);
+        } else if (--h > 0) {
+            H[0] = H[h];
+            heap_down(H, h, 0);
+        }
+    }
+    if (last >= 0) {
+        tcol[o + out] = last;
+        tval[o + out] = acc;
+        ++out;
+    }
+    cnt[i] = out;
+}
+#pragma clang fp contract(on)
+
+// One row per thread, heap and positions in device memory indexed like X
+// (rows whose list count exceeds the LDS budget).
 __global__ __launch_bounds__(kSetupBs) void k_gemm_merge(const int* __restrict__ xptr, const int* __restrict__ xcol,
                                                         const double* __restrict__ xval, const int* __restrict__ yptr,
                                                         const int* __restrict__ ycol, const double* __restrict__ yval,
@@ -409,59 +503,103 @@ __global__ __launch_bounds__(kSetupBs) void k_gemm_merge(const int* __restrict__
                                                         int* __restrict__ tcol, double* __restrict__ tval,
                                                         int* __restrict__ cnt) {
     FV_GRID_LOOP(i, rows) {
+        const int base = xptr[i];
+        merge_row(i, xptr, xcol, xval, yptr, ycol, yval, off, heap + base, pos + base, tcol, tval, cnt);
+    }
+}
+
+// The same with each thread's heap and positions in LDS (lcap entries of 12
+// bytes per row, per_wg rows per workgroup of kLdsBs threads): the merge's
+// dependent heap accesses then cost LDS latency instead of device-memory
+// latency, which decides the coarse levels' long rows.
+constexpr int kLdsBs = 64;
+constexpr int kLdsBytes = 65536;
+constexpr long long kDenseEntries = 1LL << 27;  // rows x columns of a product accumulated densely (1.2 GB)
+__global__ __launch_bounds__(kLdsBs) void k_gemm_merge_lds(const int* __restrict__ xptr, const int* __restrict__ xcol,
+                                                          const double* __restrict__ xval,
+                                                          const int* __restrict__ yptr, const int* __restrict__ ycol,
+                                                          const double* __restrict__ yval, int rows, int per_wg,
+                                                          int lcap, const long long* __restrict__ off,
+                                                          int* __restrict__ tcol, double* __restrict__ tval,
+                                                          int* __restrict__ cnt) {
+    extern __shared__ unsigned long long lds_heap[];
+    const int t = (int)threadIdx.x;
+    const long long i = (long long)blockIdx.x * per_wg + t;
+    if (t >= per_wg || i >= rows) return;
+    unsigned long long* H = lds_heap + (size_t)t * lcap;
+    int* P = reinterpret_cast<int*>(lds_heap + (size_t)per_wg * lcap) + (size_t)t * lcap;
+    merge_row(i, xptr, xcol, xval, yptr, ycol, yval, off, H, P, tcol, tval, cnt);
+}
+
+// Row i of C = X Y with one wavefront per row and a dense accumulator of
+// the row in device memory (acc/touched: nc entries per row), for products
+// whose column count nc is small: lane k owns the columns [k w, (k+1) w)
+// and walks the rows Y(k_t, :) for t in X's column order, adding the
+// products that fall in its columns (found by binary search in each sorted
+// Y row).  Every column therefore receives its products in the merge's
+// order, so the sums are bitwise the merge's; the touched columns are
+// written in ascending order at off[i].
+#pragma clang fp contract(off)
+__global__ __launch_bounds__(64) void k_gemm_dense(const int* __restrict__ xptr, const int* __restrict__ xcol,
+                                                  const double* __restrict__ xval, const int* __restrict__ yptr,
+                                                  const int* __restrict__ ycol, const double* __restrict__ yval,
+                                                  int rows, int nc, const long long* __restrict__ off,
+                                                  double* __restrict__ acc_all, uint8_t* __restrict__ touched_all,
+                                                  int* __restrict__ tcol, double* __restrict__ tval,
+                                                  int* __restrict__ cnt) {
+    const int lane = (int)threadIdx.x;
+    const int w = (nc + 63) / 64;
+    const int c0 = min(lane * w, nc), c1 = min(c0 + w, nc);
+    for (long long i = blockIdx.x; i < rows; i += gridDim.x) {
+        double* acc = acc_all + (size_t)i * nc;
+        uint8_t* touched = touched_all + (size_t)i * nc;
+        for (int c = c0; c < c1; ++c) {
+            acc[c] = 0.0;
+            touched[c] = 0;
+        }
         const int base = xptr[i], L = xptr[i + 1] - base;
-        unsigned long long* H = heap + base;
-        int* P = pos + base;
-        int h = 0;
         for (int t = 0; t < L; ++t) {
             const int k = xcol[base + t];
-            const int b = yptr[k];
-            if (b < yptr[k + 1]) {
-                P[t] = b;
-                H[h] = ((unsigned long long)(unsigned)ycol[b] << 32) | (unsigned)t;
-                heap_up(H, h);
-                ++h;
+            const double xv = xval[base + t];
+            int lo = yptr[k], hi = yptr[k + 1];
+            while (lo < hi) {  // first entry with column >= c0
+                const int mid = (lo + hi) >> 1;
+                if (ycol[mid] < c0) lo = mid + 1;
+                else hi = mid;
+            }
+            for (int p = lo, e = yptr[k + 1]; p < e; ++p) {
+                const int c = ycol[p];
+                if (c >= c1) break;
+                acc[c] += xv * yval[p];
+                touched[c] = 1;
             }
         }
-        const long long o = off[i];
-        int out = 0, last = -1;
-        double acc = 0.0;
-        while (h > 0) {
-            const unsigned long long top = H[0];
-            const int c = (int)(top >> 32), t = (int)(top & 0xffffffffu);
-            const int k = xcol[base + t];
-            int p = P[t];
-            const double v = xval[base + t] * yval[p];
-            if (c == last) {
-                acc += v;
-            } else {
-                if (last >= 0) {
-                    tcol[o + out] = last;
-                    tval[o + out] = acc;
-                    ++out;
-                }
-                last = c;
-                acc = v;
-            }
-            ++p;
-            if (p < yptr[k + 1]) {
-                P[t] = p;
-                H[0] = ((unsigned long long)(unsigned)ycol[p] << 32) | (unsigned)t;
-                heap_down(H, h, 0);
-            } else if (--h > 0) {
-                H[0] = H[h];
-                heap_down(H, h, 0);
-            }
+        int mine = 0;
+        for (int c = c0; c < c1; ++c) mine += touched[c];
+        // exclusive prefix of the lanes' counts (lanes own ascending ranges)
+        int incl = mine;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += v;
         }
-        if (last >= 0) {
-            tcol[o + out] = last;
-            tval[o + out] = acc;
-            ++out;
-        }
-        cnt[i] = out;
+        long long o = off[i] + (incl - mine);
+        for (int c = c0; c < c1; ++c)
+            if (touched[c]) {
+                tcol[o] = c;
+                tval[o] = acc[c];
+                ++o;
+            }
+        if (lane == 63) cnt[i] = incl;
     }
 }
 #pragma clang fp contract(on)
+
+// the longest row of a CSR matrix
+__global__ __launch_bounds__(kSetupBs) void k_max_rowlen(const int* __restrict__ ptr, int rows, int* out) {
+    int m = 0;
+    FV_GRID_LOOP(i, rows) m = max(m, ptr[i + 1] - ptr[i]);
+    if (m) atomicMax(out, m);
+}
 
 __global__ __launch_bounds__(kSetupBs) void k_gemm_compact(int rows, const long long* __restrict__ off,
                                                           const int* __restrict__ cnt, const int* __restrict__ cptr,
@@ -512,23 +650,45 @@ __device__ __forceinline__ void sift_max(int* a, double* v, int i, int n) {
     v[i] = kv;
 }
 
+__device__ __forceinline__ void heapsort_row(int* a, double* v, int n) {
+    for (int s = n / 2 - 1; s >= 0; --s) sift_max(a, v, s, n);
+    for (int e = n - 1; e > 0; --e) {
+        const int ta = a[0];
+        const double tv = v[0];
+        a[0] = a[e];
+        v[0] = v[e];
+        a[e] = ta;
+        v[e] = tv;
+        sift_max(a, v, 0, e);
+    }
+}
+
 // each row sorted by column (distinct columns: the order is unique)
 __global__ __launch_bounds__(kSetupBs) void k_row_heapsort(const int* __restrict__ ptr, int rows, int* __restrict__ col,
                                                           double* __restrict__ val) {
-    FV_GRID_LOOP(i, rows) {
-        int* a = col + ptr[i];
-        double* v = val + ptr[i];
-        const int n = ptr[i + 1] - ptr[i];
-        for (int s = n / 2 - 1; s >= 0; --s) sift_max(a, v, s, n);
-        for (int e = n - 1; e > 0; --e) {
-            const int ta = a[0];
-            const double tv = v[0];
-            a[0] = a[e];
-            v[0] = v[e];
-            a[e] = ta;
-            v[e] = tv;
-            sift_max(a, v, 0, e);
-        }
+    FV_GRID_LOOP(i, rows) heapsort_row(col + ptr[i], val + ptr[i], ptr[i + 1] - ptr[i]);
+}
+
+// the same with the row copied into LDS first (lcap entries of 12 bytes per
+// row, per_wg rows per workgroup)
+__global__ __launch_bounds__(kLdsBs) void k_row_heapsort_lds(const int* __restrict__ ptr, int rows, int per_wg,
+                                                            int lcap, int* __restrict__ col,
+                                                            double* __restrict__ val) {
+    extern __shared__ double lds_row[];
+    const int t = (int)threadIdx.x;
+    const long long i = (long long)blockIdx.x * per_wg + t;
+    if (t >= per_wg || i >= rows) return;
+    double* v = lds_row + (size_t)t * lcap;
+    int* a = reinterpret_cast<int*>(lds_row + (size_t)per_wg * lcap) + (size_t)t * lcap;
+    const int b = ptr[i], n = ptr[i + 1] - b;
+    for (int k = 0; k < n; ++k) {
+        a[k] = col[b + k];
+        v[k] = val[b + k];
+    }
+    heapsort_row(a, v, n);
+    for (int k = 0; k < n; ++k) {
+        col[b + k] = a[k];
+        val[b + k] = v[k];
     }
 }
 
@@ -596,16 +756,39 @@ struct CsrOut {
     }
 };
 
+// Rows per LDS workgroup for rows of at most m entries of 12 bytes each (0:
+// the rows do not fit, use device memory).
+void lds_fit(int m, int* lcap, int* per_wg) {
+    *lcap = std::max(m, 1);
+    *per_wg = std::min(kLdsBs, kLdsBytes / (12 * *lcap));
+}
+
+// The longest row of a CSR matrix, and lds_fit for it.
+int lds_plan(const int* ptr, int rows, hipStream_t s, int* lcap, int* per_wg) {
+    DevBuf<int> mx;
+    int rc;
+    if ((rc = mx.alloc(1, "row length maximum"))) return rc;
+    FV_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_max_rowlen, dim3(grid1d(rows)), dim3(kSetupBs), 0, s, ptr, rows, mx.p);
+    FV_LAUNCHED();
+    int m = 0;
+    if ((rc = read_scalar(&m, mx.p, s))) return rc;
+    lds_fit(m, lcap, per_wg);
+    return FVPCG_OK;
+}
+
 // C = X Y (rows of X, columns of Y); C's arrays are allocated here.
 int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s) {
     int rc;
     const int rows = X.n;
     DevBuf<long long> ub, off;
-    DevBuf<int> cnt;
+    DevBuf<int> cnt, mx;
     if ((rc = ub.alloc((size_t)rows, "product bounds")) || (rc = off.alloc((size_t)rows + 1, "product offsets")) ||
-        (rc = cnt.alloc((size_t)rows + 1, "product counts")))
+        (rc = cnt.alloc((size_t)rows + 1, "product counts")) || (rc = mx.alloc(1, "row length maximum")))
         return rc;
-    hipLaunchKernelGGL(k_gemm_bound, dim3(grid1d(rows)), dim3(kSetupBs), 0, s, X.ptr, X.col, Y.ptr, rows, ub.p);
+    FV_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_gemm_bound, dim3(grid1d(rows)), dim3(kSetupBs), 0, s, X.ptr, X.col, Y.ptr, rows, ub.p,
+                       mx.p);
     FV_LAUNCHED();
     if ((rc = scan_excl<long long>(ub.p, off.p, rows, s))) return rc;
     long long total = 0;
@@ -613,13 +796,32 @@ int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s) {
     DevBuf<unsigned long long> heap;
     DevBuf<int> pos, tcol;
     DevBuf<double> tval;
-    if ((rc = heap.alloc((size_t)std::max(X.nnz, 1LL), "product heaps")) ||
-        (rc = pos.alloc((size_t)std::max(X.nnz, 1LL), "product positions")) ||
-        (rc = tcol.alloc((size_t)std::max(total, 1LL), "product columns")) ||
+    if ((rc = tcol.alloc((size_t)std::max(total, 1LL), "product columns")) ||
         (rc = tval.alloc((size_t)std::max(total, 1LL), "product values")))
         return rc;
-    hipLaunchKernelGGL(k_gemm_merge, dim3(grid1d(rows)), dim3(kSetupBs), 0, s, X.ptr, X.col, X.val, Y.ptr, Y.col,
-                       Y.val, rows, off.p, heap.p, pos.p, tcol.p, tval.p, cnt.p);
+    int lcap = 0, per_wg = 0, mlen = 0;
+    if ((rc = read_scalar(&mlen, mx.p, s))) return rc;
+    lds_fit(mlen, &lcap, &per_wg);
+    DevBuf<double> dacc;
+    DevBuf<uint8_t> dtouch;
+    if ((long long)rows * Y.m <= kDenseEntries) {  // narrow product: dense rows, a wavefront each
+        if ((rc = dacc.alloc((size_t)rows * std::max(Y.m, 1), "product accumulators")) ||
+            (rc = dtouch.alloc((size_t)rows * std::max(Y.m, 1), "product flags")))
+            return rc;
+        hipLaunchKernelGGL(k_gemm_dense, dim3((unsigned)std::min(rows, 65536)), dim3(64), 0, s, X.ptr, X.col, X.val,
+                           Y.ptr, Y.col, Y.val, rows, Y.m, off.p, dacc.p, dtouch.p, tcol.p, tval.p, cnt.p);
+    } else if (per_wg >= 1) {
+        const long long blocks = ((long long)rows + per_wg - 1) / per_wg;
+        hipLaunchKernelGGL(k_gemm_merge_lds, dim3((unsigned)std::max(blocks, 1LL)), dim3(kLdsBs),
+                           (size_t)per_wg * lcap * 12, s, X.ptr, X.col, X.val, Y.ptr, Y.col, Y.val, rows, per_wg,
+                           lcap, off.p, tcol.p, tval.p, cnt.p);
+    } else {
+        if ((rc = heap.alloc((size_t)std::max(X.nnz, 1LL), "product heaps")) ||
+            (rc = pos.alloc((size_t)std::max(X.nnz, 1LL), "product positions")))
+            return rc;
+        hipLaunchKernelGGL(k_gemm_merge, dim3(grid1d(rows)), dim3(kSetupBs), 0, s, X.ptr, X.col, X.val, Y.ptr,
+                           Y.col, Y.val, rows, off.p, heap.p, pos.p, tcol.p, tval.p, cnt.p);
+    }
     FV_LAUNCHED();
     C.n = rows;
     C.m = Y.m;
@@ -660,7 +862,16 @@ int transpose(const CsrView& X, CsrOut& T, hipStream_t s) {
     if ((rc = scan_excl<int>(cnt.p, T.ptr, X.m, s))) return rc;
     hipLaunchKernelGGL(k_tr_scatter, dim3(grid1d(X.n)), dim3(kSetupBs), 0, s, X.ptr, X.col, X.val, X.n, T.ptr,
                        cursor.p, T.col, T.val);
-    hipLaunchKernelGGL(k_row_heapsort, dim3(grid1d(T.n)), dim3(kSetupBs), 0, s, T.ptr, T.n, T.col, T.val);
+    FV_LAUNCHED();
+    int lcap = 0, per_wg = 0;
+    if ((rc = lds_plan(T.ptr, T.n, s, &lcap, &per_wg))) return rc;
+    if (per_wg >= 1) {
+        const long long blocks = ((long long)T.n + per_wg - 1) / per_wg;
+        hipLaunchKernelGGL(k_row_heapsort_lds, dim3((unsigned)std::max(blocks, 1LL)), dim3(kLdsBs),
+                           (size_t)per_wg * lcap * 12, s, T.ptr, T.n, per_wg, lcap, T.col, T.val);
+    } else {
+        hipLaunchKernelGGL(k_row_heapsort, dim3(grid1d(T.n)), dim3(kSetupBs), 0, s, T.ptr, T.n, T.col, T.val);
+    }
     FV_LAUNCHED();
     FV_HIP(hipStreamSynchronize(s));
     return FVPCG_OK;
@@ -670,8 +881,17 @@ CsrView view(const CsrOut& c) { return {c.n, c.m, c.nnz, c.ptr, c.col, c.val}; }
 
 // The aggregates of one level (agg: n entries, owned by the level); returns
 // the aggregate count in *na.
+// ell: level 0's slot layout (columns, values, W) for the rounds' maxima, or
+// nullptr.
+struct EllView {
+    const int* col;
+    const double* val;
+    const double* d;
+    int W;
+};
+
 int aggregate_level(const CsrView& A, const double* d, double theta, uint64_t seed, int level, int* agg, int* na,
-                    hipStream_t s) {
+                    const EllView* ell, hipStream_t s) {
     int rc;
     const int n = A.n;
     DevBuf<uint8_t> strong;
@@ -685,13 +905,27 @@ int aggregate_level(const CsrView& A, const double* d, double theta, uint64_t se
     hipLaunchKernelGGL(k_strength, dim3(g), dim3(kSetupBs), 0, s, A.ptr, A.col, A.val, d, n, theta, strong.p);
     hipLaunchKernelGGL(k_mis_init, dim3(g), dim3(kSetupBs), 0, s, n, seed, level, key.p);
     FV_LAUNCHED();
+    DevBuf<uint8_t> strong_ell;
+    if (ell) {
+        if ((rc = strong_ell.alloc((size_t)ell->W * n, "AMG slot strength"))) return rc;
+        hipLaunchKernelGGL(k_strength_ell, dim3(g), dim3(kSetupBs), 0, s, ell->col, ell->val, ell->d, n, ell->W,
+                           theta, strong_ell.p);
+        FV_LAUNCHED();
+    }
     int left = 1, rounds = 0;
     while (left > 0) {
         if (++rounds > kMaxMisRounds)
             return set_error(FVPCG_DEVICE_ERROR, "AMG: the independent set did not settle in %d rounds", kMaxMisRounds);
         FV_HIP(hipMemsetAsync(counter.p, 0, sizeof(int), s));
-        hipLaunchKernelGGL(k_mis_max, dim3(g), dim3(kSetupBs), 0, s, A.ptr, A.col, strong.p, n, key.p, m1.p);
-        hipLaunchKernelGGL(k_mis_max, dim3(g), dim3(kSetupBs), 0, s, A.ptr, A.col, strong.p, n, m1.p, m2.p);
+        if (ell) {
+            hipLaunchKernelGGL(k_mis_max_ell, dim3(g), dim3(kSetupBs), 0, s, ell->col, strong_ell.p, n, ell->W,
+                               key.p, m1.p);
+            hipLaunchKernelGGL(k_mis_max_ell, dim3(g), dim3(kSetupBs), 0, s, ell->col, strong_ell.p, n, ell->W,
+                               m1.p, m2.p);
+        } else {
+            hipLaunchKernelGGL(k_mis_max, dim3(g), dim3(kSetupBs), 0, s, A.ptr, A.col, strong.p, n, key.p, m1.p);
+            hipLaunchKernelGGL(k_mis_max, dim3(g), dim3(kSetupBs), 0, s, A.ptr, A.col, strong.p, n, m1.p, m2.p);
+        }
         hipLaunchKernelGGL(k_mis_decide, dim3(g), dim3(kSetupBs), 0, s, n, key.p, m2.p, counter.p);
         FV_LAUNCHED();
         if ((rc = read_scalar(&left, counter.p, s))) return rc;
@@ -794,7 +1028,8 @@ int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels,
         if (cur.n <= coarse_size || l + 1 == max_levels) break;
         if ((rc = dev_alloc(&v.agg, (size_t)cur.n, "AMG aggregates"))) return rc;
         int na = 0;
-        if ((rc = aggregate_level(cur, d, th, seed, l, v.agg, &na, s))) return rc;
+        const EllView ell0{msh->col, A->val, A->d, W};
+        if ((rc = aggregate_level(cur, d, th, seed, l, v.agg, &na, l == 0 ? &ell0 : nullptr, s))) return rc;
         if ((double)na > 0.6 * (double)cur.n) {  // aggregation no longer coarsens: this is the last level
             dev_free(v.agg);
             break;
