@@ -699,7 +699,7 @@ int solve_amg(const fvpcg_amg* ch, const double* b, double* x, double tol, int m
             launched += cnt;
             if ((rc = state_get(h, &hs, s))) return rc;
             if (hs.done) break;
-            chunk = std::min(chunk * 2, 16);
+            chunk = std::max(next_chunk(chunk, 16, std::sqrt(hs.rho), hs.r0norm, hs.tol_abs, hs.iter, 0), 1);
         }
     } else if (!hs.done) {
         // z = M^-1 r, gamma = (r, z), p = z
@@ -721,7 +721,7 @@ int solve_amg(const fvpcg_amg* ch, const double* b, double* x, double tol, int m
             launched += cnt;
             if ((rc = state_get(h, &hs, s))) return rc;
             if (hs.done) break;
-            chunk = std::min(chunk * 2, 16);
+            chunk = std::max(next_chunk(chunk, 16, std::sqrt(hs.rho), hs.r0norm, hs.tol_abs, hs.iter, 0), 1);
         }
     }
     FV_HIP(hipEventRecord(h->t_it1, s));

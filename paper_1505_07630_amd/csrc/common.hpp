@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -68,6 +69,24 @@ struct Geom {
     int grid;
     int rows;
 };
+
+// Iterations to enqueue before the host next looks at a solver state.  The
+// chunk doubles up to `cap`; once a state seen after `seen` iterations shows
+// the residual norm below its initial one, the chunk is also capped by the
+// iterations that the mean rate of decrease so far still needs to reach the
+// target (10% margin, one more), less the `in_flight` iterations already
+// enqueued after that state.  0: those in flight are expected to finish.
+// Kernels launched after a solve has stopped return at once, so this only
+// trades empty launches against host round trips; results do not depend on it.
+inline int next_chunk(int chunk, int cap, double rnorm, double r0norm, double target, int seen, int in_flight) {
+    const int grown = chunk * 2 < cap ? chunk * 2 : cap;
+    if (!(seen >= 2 && target > 0.0 && rnorm > target && rnorm < r0norm)) return grown;
+    const double rate = std::log(rnorm / r0norm) / (double)seen;  // < 0
+    const double need = std::ceil(1.1 * std::log(target / rnorm) / rate) + 1.0;
+    const double left = need - (double)in_flight;
+    if (left <= 0.0) return 0;
+    return left < (double)grown ? (int)left : grown;
+}
 
 inline Geom make_geom(int n, int max_grid = kMaxGrid) {
     if (n < 1) n = 1;

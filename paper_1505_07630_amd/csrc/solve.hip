@@ -761,14 +761,20 @@ int state_read_both(Work& w, DevState* h0, DevState* h1, hipStream_t s) {
     return FVPCG_OK;
 }
 
-// Enqueue iterations in growing chunks; after each chunk the state is copied
-// to pinned memory, and the previous chunk's copy is inspected while the
-// current chunk runs.  Kernels launched after convergence return at once.
-// Without a pinned mirror (the no-allocation path) each chunk's state is
-// read and waited for before the next chunk is enqueued.
+// Enqueue iterations in chunks; after each chunk the state is copied to
+// pinned memory, and the previous chunk's copy is inspected while the current
+// chunk runs.  Chunks grow geometrically and are capped by the iterations the
+// residual's rate so far still needs (next_chunk); when the chunk in flight is
+// expected to finish the solve, its state is waited for before anything more
+// is enqueued.  Kernels launched after convergence return at once.  Without a
+// pinned mirror (the no-allocation path) each chunk's state is read and
+// waited for before the next chunk is enqueued.
 template <typename Launch>
 int iterate(Work& w, int k, int maxit, hipStream_t s, Launch&& launch_iter) {
     int launched = 0, chunk = 2, pending = -1, slot = 0;
+    auto next = [&](const DevState& h, int in_flight) {
+        return next_chunk(chunk, kMaxChunk, std::sqrt(h.rho), h.r0norm, h.tol_abs, h.iter, in_flight);
+    };
     if (!w.hst) {
         while (launched < maxit) {
             const int cnt = chunk < maxit - launched ? chunk : maxit - launched;
@@ -779,24 +785,39 @@ int iterate(Work& w, int k, int maxit, hipStream_t s, Launch&& launch_iter) {
             int rc = state_read(w, k, &h, s);
             if (rc) return rc;
             if (h.done) break;
-            if (chunk < kMaxChunk) chunk *= 2;
+            chunk = std::max(next(h, 0), 1);
         }
         return FVPCG_OK;
     }
     while (launched < maxit) {
-        int cnt = chunk < maxit - launched ? chunk : maxit - launched;
+        const int cnt = chunk < maxit - launched ? chunk : maxit - launched;
         for (int i = 0; i < cnt; ++i) launch_iter(launched + i);
         FV_LAUNCHED();
         launched += cnt;
         FV_HIP(hipMemcpyAsync(&w.hst[slot], &w.st[k], sizeof(DevState), hipMemcpyDeviceToHost, s));
         FV_HIP(hipEventRecord(w.ev[slot], s));
-        if (pending >= 0) {
-            FV_HIP(hipEventSynchronize(w.ev[pending]));
-            if (w.hst[pending].done) break;
+        if (pending < 0) {  // nothing to inspect yet
+            if (launched == cnt) chunk = chunk * 2 < kMaxChunk ? chunk * 2 : kMaxChunk;
+            pending = slot;
+            slot ^= 1;
+            continue;
         }
-        pending = slot;
-        slot ^= 1;
-        if (chunk < kMaxChunk) chunk *= 2;
+        FV_HIP(hipEventSynchronize(w.ev[pending]));
+        const DevState& h = w.hst[pending];
+        if (h.done) break;
+        const int c = next(h, launched - h.iter);
+        if (c > 0) {
+            chunk = c;
+            pending = slot;
+            slot ^= 1;
+            continue;
+        }
+        // the chunk in flight should end the solve: wait for it
+        FV_HIP(hipEventSynchronize(w.ev[slot]));
+        const DevState& g = w.hst[slot];
+        if (g.done) break;
+        chunk = std::max(next(g, 0), 1);
+        pending = -1;
     }
     return FVPCG_OK;
 }
