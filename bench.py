@@ -170,7 +170,11 @@ def main():
     tol, maxit = 1e-8, 50000
 
     calib = fv.stream_calibrate(1 << 30)
-    log(f"STREAM copy {calib['copy_gbs']:.0f} GB/s, triad {calib['triad_gbs']:.0f} GB/s")
+    # the attainable line for the fused kernel's own mix (it reads about 2.5
+    # bytes per byte written, from 12 to 20 streams), and a read-only kernel
+    mix = {"read_2_write_0": fv.stream_mix(2, 0, 256 << 20), "read_12_write_5": fv.stream_mix(12, 5, 256 << 20)}
+    log(f"STREAM copy {calib['copy_gbs']:.0f} GB/s, triad {calib['triad_gbs']:.0f} GB/s, "
+        f"read-only {mix['read_2_write_0']:.0f} GB/s, 12 in 5 out {mix['read_12_write_5']:.0f} GB/s")
 
     for i in range(args.warmup):
         x.zero_()
@@ -245,8 +249,12 @@ def main():
         },
         "hbm_gbs_algorithmic": round(bpi * its / 1e9, 1),
         "roofline": roof,
-        "stream_calibration_gbs": {"copy": round(calib["copy_gbs"], 1), "triad": round(calib["triad_gbs"], 1)},
+        "stream_calibration_gbs": {"copy": round(calib["copy_gbs"], 1), "triad": round(calib["triad_gbs"], 1),
+                                   **{k: round(v, 1) for k, v in mix.items()}},
         "frac_of_stream_copy": round(achieved / calib["copy_gbs"], 4) if calib["copy_gbs"] > 0 else None,
+        # the kernel's HBM traffic (counters when current, else the bytes it
+        # must move) per launch time, against the line for its own mix
+        "real_gbs_vs_stream_mix": round((traffic or kernel_bytes or bpi) / kern_s / 1e9 / mix["read_12_write_5"], 4),
     }
     pending = None
     if not args.no_mixed:

@@ -667,4 +667,15 @@ def fvpcg_stream_calibrate(bytes_per_array=0, stream=None):
 
 stream_calibrate = fvpcg_stream_calibrate
 
+
+def fvpcg_stream_mix(n_read, n_write, bytes_per_array=0, stream=None):
+    """Attainable GB/s of a kernel streaming n_read arrays in and n_write out."""
+    g = ctypes.c_double()
+    _check(lib().fvpcg_stream_mix(_stream(stream), int(bytes_per_array), int(n_read), int(n_write), ctypes.byref(g)),
+           "fvpcg_stream_mix")
+    return g.value
+
+
+stream_mix = fvpcg_stream_mix
+
 from .autograd import FVSolve, fv_solve  # noqa: E402,F401

@@ -66,6 +66,7 @@ SIGNATURES = {
     "fvpcg_solve_batched": (ctypes.c_int, [P, P, P, f64, i32, i32, i32, P, SPS]),
     "fvpcg_solve_batched_backward": (ctypes.c_int, [P, P, P, P, P, P, P, f64, i32, i32, i32, P, SPS]),
     "fvpcg_stream_calibrate": (ctypes.c_int, [P, u64, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
+    "fvpcg_stream_mix": (ctypes.c_int, [P, u64, i32, i32, ctypes.POINTER(f64)]),
     "fvpcg_assemble_transient": (ctypes.c_int, [P, P, P, P, P, P, f64, P, P, P, P, P]),
     "fvpcg_transient_run": (ctypes.c_int, [P, P, P, P, P, P, f64, i32, P, f64, i32, i32, P, SPS]),
     "fvpcg_amg_create": (ctypes.c_int, [P, f64, i32, i32, ctypes.c_uint64, P, PP]),

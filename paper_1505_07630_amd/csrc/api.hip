@@ -38,6 +38,7 @@ int solve_batched_backward(const fvpcg_batch* bt, const double* x, const double*
                            double* grad_diag, double* grad_upper, double* grad_lower, double tol, int maxit,
                            int method, int precond, hipStream_t s, fvpcg_stats* stats);
 int stream_calibrate(hipStream_t s, uint64_t bytes, double* copy_gbs, double* triad_gbs);
+int stream_mix(hipStream_t s, uint64_t bytes, int nr, int nw, double* gbs);
 int solve_bicgstab(const fvpcg_matrix* A, const double* b, double* x, double tol, int maxit, int precond,
                    hipStream_t s, fvpcg_stats* stats);
 int solve_bicgstab_multi(const fvpcg_matrix* A, int nrhs, const double* b, double* x, double tol, int maxit,
@@ -726,6 +727,13 @@ int fvpcg_stream_calibrate(void* stream, uint64_t bytes_per_array, double* copy_
     return guard([&]() -> int {
         if (!copy_gbs || !triad_gbs) return set_error(FVPCG_INVALID_ARG, "result pointers are NULL");
         return stream_calibrate((hipStream_t)stream, bytes_per_array, copy_gbs, triad_gbs);
+    });
+}
+
+int fvpcg_stream_mix(void* stream, uint64_t bytes_per_array, int32_t n_read, int32_t n_write, double* gbs) {
+    return guard([&]() -> int {
+        if (!gbs) return set_error(FVPCG_INVALID_ARG, "result pointer is NULL");
+        return stream_mix((hipStream_t)stream, bytes_per_array, n_read, n_write, gbs);
     });
 }
 

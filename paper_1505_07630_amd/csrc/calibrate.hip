@@ -110,6 +110,42 @@ __global__ __launch_bounds__(kBlock) void k_triad_chunk(double2* __restrict__ a,
     }
 }
 
+// Mixed streams: nr arrays read and nw written, every workgroup over one
+// contiguous chunk of each (the solver kernels' layout), 16-byte
+// non-temporal accesses.  out_j = sum of the inputs; with nw = 0 the sum is
+// kept alive by a store that never happens (inputs are filled with 1.0).
+constexpr int kMixMaxIn = 16, kMixMaxOut = 8;
+struct MixArgs {
+    const double2* in[kMixMaxIn];
+    double2* out[kMixMaxOut];
+    double* sink;
+    int nr, nw;
+};
+
+__global__ __launch_bounds__(kBlock) void k_mix_chunk(MixArgs m, size_t n2, size_t len) {
+    const size_t b0 = (size_t)blockIdx.x * len;
+    const size_t e = b0 + len < n2 ? b0 + len : n2;
+    double keep = 0.0;
+    for (size_t i = b0 + threadIdx.x; i < e; i += kBlock) {
+        double2 v[kMixMaxIn];
+#pragma unroll
+        for (int k = 0; k < kMixMaxIn; ++k)
+            if (k < m.nr) v[k] = ld2<true>(m.in[k] + i);
+        double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < kMixMaxIn; ++k)
+            if (k < m.nr) {
+                sum.x += v[k].x;
+                sum.y += v[k].y;
+            }
+#pragma unroll
+        for (int k = 0; k < kMixMaxOut; ++k)
+            if (k < m.nw) st2<true>(m.out[k] + i, sum);
+        keep += sum.x + sum.y;
+    }
+    if (m.nw == 0 && keep == -1.0) m.sink[0] = keep;
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill(double2* __restrict__ a, size_t n2, double v) {
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n2; i += (size_t)gridDim.x * kBlock)
         a[i] = make_double2(v, v);
@@ -197,6 +233,68 @@ int stream_calibrate(hipStream_t s, uint64_t bytes, double* copy_gbs, double* tr
     dev_free(a);
     dev_free(b);
     dev_free(c);
+    return rc;
+}
+
+int stream_mix(hipStream_t s, uint64_t bytes, int nr, int nw, double* gbs) {
+    if (nr < 1 || nr > kMixMaxIn || nw < 0 || nw > kMixMaxOut)
+        return set_error(FVPCG_INVALID_ARG, "stream mix: %d arrays read (1..%d) and %d written (0..%d)", nr,
+                         kMixMaxIn, nw, kMixMaxOut);
+    if (bytes == 0) bytes = (uint64_t)1 << 28;
+    const size_t n2 = (size_t)(bytes / sizeof(double2));
+    if (n2 < 1024) return set_error(FVPCG_INVALID_ARG, "calibration arrays too small");
+    double2* arr[kMixMaxIn + kMixMaxOut] = {};
+    double* sink = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto body = [&]() -> int {
+        int rc;
+        for (int k = 0; k < nr + nw; ++k)
+            if ((rc = dev_alloc(&arr[k], n2, "stream mix array"))) return rc;
+        if ((rc = dev_alloc(&sink, 1, "stream mix sink"))) return rc;
+        FV_HIP(hipEventCreate(&e0));
+        FV_HIP(hipEventCreate(&e1));
+        int dev = 0, cus = 0;
+        FV_HIP(hipGetDevice(&dev));
+        FV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        for (int k = 0; k < nr + nw; ++k)
+            hipLaunchKernelGGL(k_fill, dim3(cus * 16), dim3(kBlock), 0, s, arr[k], n2, 1.0);
+        FV_LAUNCHED();
+        MixArgs m{};
+        for (int k = 0; k < nr; ++k) m.in[k] = arr[k];
+        for (int k = 0; k < nw; ++k) m.out[k] = arr[nr + k];
+        m.sink = sink;
+        m.nr = nr;
+        m.nw = nw;
+        const double moved = (double)(nr + nw) * (double)n2 * sizeof(double2);
+        const char* vb = getenv("FVPCG_CALIBRATE_VERBOSE");
+        const bool verbose = vb && vb[0] == '1';
+        double best = 0.0;
+        for (int gm : {1, 2, 4, 8, 16}) {
+            const int gg = cus * gm;
+            const size_t len = (n2 + gg - 1) / gg;
+            double mine = 0.0;
+            for (int rep = 0; rep < 4; ++rep) {
+                FV_HIP(hipEventRecord(e0, s));
+                hipLaunchKernelGGL(k_mix_chunk, dim3(gg), dim3(kBlock), 0, s, m, n2, len);
+                FV_LAUNCHED();
+                FV_HIP(hipEventRecord(e1, s));
+                FV_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                FV_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0 && ms > 0) mine = std::fmax(mine, moved / (ms * 1e6));
+            }
+            if (verbose) fprintf(stderr, "[calibrate] mix %2d in %d out grid %5d: %7.1f GB/s\n", nr, nw, gg, mine);
+            best = std::fmax(best, mine);
+        }
+        *gbs = best;
+        return FVPCG_OK;
+    };
+    const int rc = body();
+    (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (double2*& a : arr) dev_free(a);
+    dev_free(sink);
     return rc;
 }
 

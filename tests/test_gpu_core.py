@@ -394,6 +394,17 @@ def test_stream_calibrate(fv):
     assert r["copy_gbs"] > 500 and r["triad_gbs"] > 500
 
 
+def test_stream_mix(fv):
+    """Mixed-stream calibration: plausible rates for a read-only and a
+    12-in/5-out kernel; counts out of range are refused."""
+    say("stream mix")
+    assert 500 < fv.stream_mix(2, 0, 64 << 20) < 20000
+    assert 500 < fv.stream_mix(12, 5, 64 << 20) < 20000
+    for nr, nw in ((0, 1), (17, 0), (2, 9), (1, -1)):
+        with pytest.raises(fv.FVPCGError):
+            fv.stream_mix(nr, nw, 64 << 20)
+
+
 def test_int16_and_int32_columns_agree_bitwise(fv, monkeypatch):
     """The 16-bit column-offset layout (used when the bandwidth fits) and the
     32-bit layout encode the same columns: identical results, bit for bit."""
