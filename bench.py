@@ -384,7 +384,7 @@ def batched_block(fv, torch, np, fvcases, dev):
 
 
 def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None,
-           groups=("mixed", "batched", "amg", "transient", "piso", "momentum", "share", "small")):
+           groups=("mixed", "batched", "amg", "amg_setup", "transient", "piso", "momentum", "share", "small")):
     """Other workloads, for information (not the headline line)."""
     res = {}
     to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).to(dev)
@@ -520,6 +520,22 @@ def extras(fv, torch, np, fvcases, dev, case=None, mesh=None, b=None,
             A_.close()
             if m_ is not mesh:
                 m_.close()
+    if "amg_setup" in groups and case is not None:
+        # the AMG hierarchy of the 192^3 lognormal system built four times
+        # (the first loads the setup kernels), for setup profiles
+        A_ = fv.Matrix(mesh, to(case.diag, torch.float64), to(case.upper, torch.float64))
+        times = []
+        for _ in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            M = fv.AMG(A_)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+            levels = [M.level_info(l)["n"] for l in range(M.levels)]
+            M.close()
+        res["varcoef192/amg_setup"] = {"setup_ms": [round(t, 1) for t in times], "levels": levels}
+        log(f"extra varcoef192 amg setup: {res['varcoef192/amg_setup']}")
+        A_.close()
     if "transient" in groups:
         # laplacianFoam's repeated solve: 20 implicit-Euler steps at 192^3
         # (lognormal conductivities, permuted + RCM), each step assembled on

@@ -285,7 +285,7 @@ def aggregate(ptr, col, val, theta, key=None, seed=1, level=0):
 class AMG:
     """Smoothed-aggregation AMG hierarchy built by the oracle (amg.c)."""
 
-    def __init__(self, A, theta=0.0, max_levels=12, coarse_size=64, seed=1):
+    def __init__(self, A, theta=0.02, max_levels=12, coarse_size=64, seed=1):
         A = _as_sys(A)
         self._sys = A
         self.n = A.n

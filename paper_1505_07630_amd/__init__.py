@@ -546,7 +546,7 @@ class AMG:
     """Smoothed-aggregation AMG hierarchy of a (symmetric) Matrix; the Matrix
     must outlive it."""
 
-    def __init__(self, A: Matrix, theta=0.0, max_levels=12, coarse_size=64, seed=1, stream=None):
+    def __init__(self, A: Matrix, theta=0.02, max_levels=12, coarse_size=64, seed=1, stream=None):
         h = ctypes.c_void_p()
         _check(lib().fvpcg_amg_create(A.handle, float(theta), int(max_levels), int(coarse_size), int(seed),
                                       _stream(stream), ctypes.byref(h)), "fvpcg_amg_create")

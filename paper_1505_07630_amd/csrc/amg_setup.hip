@@ -29,9 +29,15 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 
 #include "amg.hpp"
+
+#ifndef FVPCG_AMG_THETA_DECAY
+#define FVPCG_AMG_THETA_DECAY 0.5
+#endif
 
 namespace fvpcg {
 
@@ -594,6 +600,139 @@ __global__ __launch_bounds__(64) void k_gemm_dense(const int* __restrict__ xptr,
 }
 #pragma clang fp contract(on)
 
+// Row i of C = X Y by one wavefront per row over tiles of kTileCols output
+// columns accumulated in LDS, for products whose rows gather many long rows
+// of Y (the coarse Galerkin products).  Each list (the row Y(k_t, :) for
+// the t-th entry of X's row) keeps a cursor in LDS.  A tile starts at the
+// smallest pending column; the lists are visited in X's column order, eight
+// at a time with their next 64 entries loaded together, and each list's
+// entries inside the tile are added lane by entry (a row's columns are
+// distinct, so one pass has no conflicts): the first product of a column is
+// stored, later ones added.  Every column therefore receives its products in
+// the merge's order and its sum is bitwise the merge's.  The touched columns
+// of the tile (a bitmap) are written in ascending order and cleared.
+constexpr int kTileCols = 4096;
+constexpr int kTileGroup = 8;
+constexpr int kTileMaxLists = 4096;
+constexpr long long kTileMinWork = 2048;  // mean product entries per row from which the tiles pay
+
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+#pragma clang fp contract(off)
+__global__ __launch_bounds__(64) void k_gemm_tiled(const int* __restrict__ xptr, const int* __restrict__ xcol,
+                                                  const double* __restrict__ xval, const int* __restrict__ yptr,
+                                                  const int* __restrict__ ycol, const double* __restrict__ yval,
+                                                  int rows, const long long* __restrict__ off,
+                                                  int* __restrict__ tcol, double* __restrict__ tval,
+                                                  int* __restrict__ cnt) {
+    __shared__ double acc[kTileCols];
+    __shared__ unsigned int bits[kTileCols / 32];
+    __shared__ int cur[kTileMaxLists];
+    const int lane = (int)threadIdx.x;
+    for (int q = lane; q < kTileCols / 32; q += 64) bits[q] = 0u;
+    for (long long i = blockIdx.x; i < rows; i += gridDim.x) {
+        const int base = xptr[i], L = xptr[i + 1] - base;
+        for (int t = lane; t < L; t += 64) cur[t] = yptr[xcol[base + t]];
+        __syncthreads();
+        long long o = off[i];
+        for (;;) {
+            int lo = INT_MAX;
+            for (int t = lane; t < L; t += 64) {
+                const int p = cur[t];
+                if (p < yptr[xcol[base + t] + 1]) lo = min(lo, ycol[p]);
+            }
+            lo = wave_min_int(lo);
+            if (lo == INT_MAX) break;
+            const int hi = lo > INT_MAX - kTileCols ? INT_MAX : lo + kTileCols;
+            for (int t0 = 0; t0 < L; t0 += kTileGroup) {
+                int cc[kTileGroup];
+                double vv[kTileGroup];
+#pragma unroll
+                for (int g = 0; g < kTileGroup; ++g) {
+                    cc[g] = INT_MAX;
+                    vv[g] = 0.0;
+                    const int t = t0 + g;
+                    if (t < L) {
+                        const int k = xcol[base + t];
+                        const int p = cur[t] + lane;
+                        if (p < yptr[k + 1]) {
+                            cc[g] = ycol[p];
+                            vv[g] = xval[base + t] * yval[p];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < kTileGroup; ++g) {
+                    const int t = t0 + g;
+                    if (t >= L) break;
+                    int c = cc[g];
+                    double v = vv[g];
+                    int p0 = cur[t];
+                    for (;;) {
+                        const bool in = c < hi;
+                        if (in) {
+                            const int idx = c - lo;
+                            const unsigned int m = 1u << (idx & 31);
+                            const unsigned int old = atomicOr(&bits[idx >> 5], m);
+                            if (old & m)
+                                acc[idx] += v;
+                            else
+                                acc[idx] = v;
+                        }
+                        const int n_in = __popcll(__ballot(in));
+                        p0 += n_in;
+                        if (n_in < 64) break;
+                        // a full chunk inside the tile: the list's next entries
+                        // come before the next list's
+                        const int k = xcol[base + t];
+                        const int p = p0 + lane;
+                        c = INT_MAX;
+                        v = 0.0;
+                        if (p < yptr[k + 1]) {
+                            c = ycol[p];
+                            v = xval[base + t] * yval[p];
+                        }
+                    }
+                    if (lane == 0) cur[t] = p0;
+                    __syncthreads();
+                }
+            }
+            // the tile's columns in ascending order: lane l owns bitmap words 2l, 2l+1
+            const unsigned int w0 = bits[2 * lane], w1 = bits[2 * lane + 1];
+            const int mine = __popc(w0) + __popc(w1);
+            int incl = mine;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int u = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += u;
+            }
+            long long q = o + (incl - mine);
+            for (int h = 0; h < 2; ++h) {
+                unsigned int w = h ? w1 : w0;
+                while (w) {
+                    const int b = __ffs(w) - 1;
+                    w &= w - 1;
+                    const int idx = (2 * lane + h) * 32 + b;
+                    tcol[q] = lo + idx;
+                    tval[q] = acc[idx];
+                    ++q;
+                }
+            }
+            bits[2 * lane] = 0u;
+            bits[2 * lane + 1] = 0u;
+            o += __shfl(incl, 63, 64);
+            __syncthreads();
+        }
+        if (lane == 0) cnt[i] = (int)(o - off[i]);
+        __syncthreads();
+    }
+}
+#pragma clang fp contract(on)
+
 // the longest row of a CSR matrix
 __global__ __launch_bounds__(kSetupBs) void k_max_rowlen(const int* __restrict__ ptr, int rows, int* out) {
     int m = 0;
@@ -732,6 +871,38 @@ __global__ __launch_bounds__(kGjBs) void k_gauss_jordan(double* __restrict__ M, 
     }
 }
 
+// The same elimination for larger last levels, one pivot per pair of
+// launches over the whole grid (one workgroup would stream the matrix
+// through a single CU at every step): k_gj_pivot saves column k in f and the
+// scaled row k in g (g_k = 1 / a_kk), or flags a bad pivot; k_gj_update
+// writes every entry, row k from g and row i != k as (j == k ? 0 : a_ij) -
+// f_i g_j, the expressions of k_gauss_jordan.  Both return at once once the
+// flag is set.
+__global__ __launch_bounds__(kSetupBs) void k_gj_pivot(const double* __restrict__ M, int n, int k,
+                                                      double* __restrict__ f, double* __restrict__ g, int* bad) {
+    if (*bad) return;
+    const double piv = M[(size_t)k * n + k];
+    if (!(piv > 0.0) || !isfinite(piv)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *bad = 1;
+        return;
+    }
+    FV_GRID_LOOP(i, n) {
+        f[i] = M[(size_t)i * n + k];
+        g[i] = (i == k ? 1.0 : M[(size_t)k * n + i]) / piv;
+    }
+}
+
+__global__ __launch_bounds__(kSetupBs) void k_gj_update(double* __restrict__ M, int n, int k,
+                                                       const double* __restrict__ f, const double* __restrict__ g,
+                                                       const int* bad) {
+    if (*bad) return;
+    FV_GRID_LOOP(e, (long long)n * n) {
+        const int i = (int)(e / n), j = (int)(e - (long long)i * n);
+        M[e] = i == k ? g[j] : (j == k ? 0.0 : M[e]) - f[i] * g[j];
+    }
+}
+constexpr int kGjGridMin = 256;  // last levels from this size use the grid-wide elimination
+
 // ---------------------------------------------------------------- host side
 
 // A level's operator as CSR on the device (not owned).
@@ -804,12 +975,24 @@ int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s) {
     lds_fit(mlen, &lcap, &per_wg);
     DevBuf<double> dacc;
     DevBuf<uint8_t> dtouch;
-    if ((long long)rows * Y.m <= kDenseEntries) {  // narrow product: dense rows, a wavefront each
+    // Kernel choice: dense rows for narrow products, LDS column tiles for
+    // long rows, else the heap merge.  FVPCG_AMG_PRODUCT = merge | tiled |
+    // dense forces one where it applies (all give the same sums); tests use it.
+    const char* force = getenv("FVPCG_AMG_PRODUCT");
+    const std::string fk = force ? force : "";
+    const bool dense_ok = (long long)rows * Y.m <= kDenseEntries, tiled_ok = mlen <= kTileMaxLists;
+    const bool use_dense = dense_ok && (fk.empty() || fk == "dense");
+    const bool use_tiled = !use_dense && tiled_ok &&
+                           (fk == "tiled" || (fk.empty() && (total >= kTileMinWork * (long long)rows || per_wg < 1)));
+    if (use_dense) {  // narrow product: dense rows, a wavefront each
         if ((rc = dacc.alloc((size_t)rows * std::max(Y.m, 1), "product accumulators")) ||
             (rc = dtouch.alloc((size_t)rows * std::max(Y.m, 1), "product flags")))
             return rc;
         hipLaunchKernelGGL(k_gemm_dense, dim3((unsigned)std::min(rows, 65536)), dim3(64), 0, s, X.ptr, X.col, X.val,
                            Y.ptr, Y.col, Y.val, rows, Y.m, off.p, dacc.p, dtouch.p, tcol.p, tval.p, cnt.p);
+    } else if (use_tiled) {  // long rows: LDS column tiles
+        hipLaunchKernelGGL(k_gemm_tiled, dim3((unsigned)std::min(rows, 65536)), dim3(64), 0, s, X.ptr, X.col, X.val,
+                           Y.ptr, Y.col, Y.val, rows, off.p, tcol.p, tval.p, cnt.p);
     } else if (per_wg >= 1) {
         const long long blocks = ((long long)rows + per_wg - 1) / per_wg;
         hipLaunchKernelGGL(k_gemm_merge_lds, dim3((unsigned)std::max(blocks, 1LL)), dim3(kLdsBs),
@@ -1089,7 +1272,7 @@ int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels,
             A0.release();
             d0.reset();  // level 0's CSR diagonal is no longer needed
         }
-        th *= 0.5;
+        th *= FVPCG_AMG_THETA_DECAY;
         ++l;
     }
     h->nlev = l + 1;
@@ -1101,13 +1284,23 @@ int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels,
     const int nl = cur.n;
     if ((rc = dev_alloc(&h->cinv, (size_t)nl * nl, "AMG coarse inverse"))) return rc;
     {
-        DevBuf<double> f;
-        if ((rc = f.alloc((size_t)nl, "AMG elimination column"))) return rc;
+        DevBuf<double> f, g;
+        if ((rc = f.alloc((size_t)nl, "AMG elimination column")) || (rc = g.alloc((size_t)nl, "AMG elimination row")))
+            return rc;
         FV_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
         hipLaunchKernelGGL(k_dense_zero, dim3(grid1d((long long)nl * nl)), dim3(kSetupBs), 0, s, nl, h->cinv);
         hipLaunchKernelGGL(k_dense_fill, dim3(grid1d(nl)), dim3(kSetupBs), 0, s, cur.ptr, cur.col, cur.val, nl,
                            h->cinv);
-        hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(kGjBs), 0, s, h->cinv, nl, f.p, bad.p);
+        if (nl < kGjGridMin) {
+            hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(kGjBs), 0, s, h->cinv, nl, f.p, bad.p);
+        } else {
+            for (int k = 0; k < nl; ++k) {
+                hipLaunchKernelGGL(k_gj_pivot, dim3(grid1d(nl)), dim3(kSetupBs), 0, s, h->cinv, nl, k, f.p, g.p,
+                                   bad.p);
+                hipLaunchKernelGGL(k_gj_update, dim3(grid1d((long long)nl * nl)), dim3(kSetupBs), 0, s, h->cinv,
+                                   nl, k, f.p, g.p, bad.p);
+            }
+        }
         FV_LAUNCHED();
         int hbad = 0;
         if ((rc = read_scalar(&hbad, bad.p, s))) return rc;

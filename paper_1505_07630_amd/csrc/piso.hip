@@ -64,6 +64,9 @@ int solve_amg(const fvpcg_amg* h, const double* b, double* x, double tol, int ma
 namespace {
 
 constexpr int kPisoBs = 256;
+// AMG for the pressure correctors: the library's default strength threshold,
+// the other parameters the typical ones of fvpcg_amg_create
+constexpr double kPisoAmgTheta = 0.02;
 
 int pgrid(size_t n) { return (int)std::max<size_t>(1, std::min<size_t>((n + kPisoBs - 1) / kPisoBs, 65536)); }
 
@@ -348,7 +351,7 @@ int piso_run(fvpcg_piso* ps, double dt, int nsteps, int n_corr, double* U, doubl
             if (corr == 0) {  // rAU, and so the pressure matrix, is fixed within a step
                 if ((rc = matrix_update(ps->pres, ps->pdiag, ps->pupper, nullptr, s))) break;
                 if (ps->psolver == FVPCG_PSOLVER_AMG &&
-                    (rc = amg_create(ps->pres, 0.0, 12, 64, 1, s, &amg)))
+                    (rc = amg_create(ps->pres, kPisoAmgTheta, 12, 64, 1, s, &amg)))
                     break;
             }
             if (amg)

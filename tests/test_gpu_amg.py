@@ -44,6 +44,83 @@ CASES = {
 }
 
 
+def _hierarchy(M, levels):
+    out = []
+    for l in range(levels):
+        lv = {"info": M.level_info(l)}
+        if l + 1 < levels:
+            lv["agg"] = M.aggregates(l)
+            lv["P"] = M.export(l, "P")
+            lv["R"] = M.export(l, "R")
+        if l >= 1:
+            lv["A"] = M.export(l, "A")
+        out.append(lv)
+    return out
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.02])
+@pytest.mark.parametrize("name", ["varcoef32_rcm", "cavity_24x24x8"])
+def test_amg_product_kernels_agree(fv, orc, name, theta, monkeypatch):
+    """The three sparse-product kernels of the setup (heap merge, LDS column
+    tiles, dense rows; FVPCG_AMG_PRODUCT forces one) sum every entry in the
+    same order: the hierarchies are equal entry for entry, and equal the
+    oracle's within 1e-12 (theta > 0 included)."""
+    say("amg product kernels", name, theta)
+    case = CASES[name]()
+    dc = DevCase(case)
+    hs = {}
+    for mode in ("merge", "tiled", "dense"):
+        monkeypatch.setenv("FVPCG_AMG_PRODUCT", mode)
+        M = fv.AMG(dc.A, theta=theta, coarse_size=16)
+        hs[mode] = (M.levels, _hierarchy(M, M.levels))
+        M.close()
+    monkeypatch.delenv("FVPCG_AMG_PRODUCT")
+    H = orc.AMG(case, theta=theta, coarse_size=16)
+    levels, ref = hs["merge"]
+    assert levels == H.levels
+    for mode in ("tiled", "dense"):
+        assert hs[mode][0] == levels
+        for l, (a, b) in enumerate(zip(ref, hs[mode][1])):
+            assert a["info"] == b["info"], (mode, l)
+            for key in ("agg", "P", "R", "A"):
+                if key in a:
+                    xa, xb = a[key], b[key]
+                    if key == "agg":
+                        assert np.array_equal(xa, xb), (mode, l)
+                    else:
+                        for u, w in zip(xa[:3], xb[:3]):
+                            assert np.array_equal(u, w), (mode, l, key)
+    for l in range(1, levels):
+        ptr, col, val, shape = ref[l]["A"]
+        optr, ocol, oval, oshape = H.export(l, "A")
+        assert shape == oshape and np.array_equal(ptr, optr) and np.array_equal(col, ocol), l
+        assert np.max(np.abs(val - oval)) <= 1e-12 * np.max(np.abs(oval)), l
+    for l in range(levels - 1):
+        assert np.array_equal(ref[l]["agg"], H.aggregates(l)), l
+    dc.close()
+
+
+def test_amg_large_last_level(fv, orc):
+    """A last level of several hundred unknowns (two levels on 16^3) is
+    inverted by the grid-wide elimination: the cycle within 1e-10 of the
+    oracle's (dense Cholesky there) and AMG-PCG at the oracle's count."""
+    say("amg large last level")
+    case = CASES["laplace16"]()
+    dc = DevCase(case)
+    M = fv.AMG(dc.A, max_levels=2, coarse_size=2048)
+    H = orc.AMG(case, max_levels=2, coarse_size=2048)
+    assert M.levels == H.levels == 2
+    assert M.level_info(1)["n"] == H.level_info(1)["n"] >= 256
+    v = np.random.default_rng(8).standard_normal(case.n)
+    z = fv.amg_apply(M, to_dev(v)).cpu().numpy()
+    assert rel(z, H.vcycle(v)) <= 1e-10
+    x, st = fv.solve_amg(M, dc.b, tol=1e-10, maxit=200)
+    _, so = H.pcg(case.b, tol=1e-10, maxit=200)
+    assert st["status"] == 0 and abs(st["iters"] - so["iters"]) <= 1
+    M.close()
+    dc.close()
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_amg_hierarchy_and_cycle_match_oracle(fv, orc, name):
     """Aggregates of every level bit for bit, level sizes and stored entries
