@@ -87,6 +87,8 @@ def lib(omp: bool = False):
         L.or_amg_setup.restype = P
         L.or_amg_free.argtypes = [P]
         L.or_amg_free.restype = None
+        L.or_amg_refresh.argtypes = [P, i32, i32, P, P, P, P, P]
+        L.or_amg_refresh.restype = i32
         L.or_amg_levels.argtypes = [P]
         L.or_amg_levels.restype = i32
         L.or_amg_level_info.argtypes = [P, i32, P, P, P, P]
@@ -293,6 +295,13 @@ class AMG:
         if not h:
             raise ValueError("AMG setup failed: coarsest level not positive definite")
         self._h = ctypes.c_void_p(h)
+
+    def refresh(self, A):
+        """New coefficients of the same mesh, the aggregates kept."""
+        A = _as_sys(A)
+        if A.n != self.n or lib().or_amg_refresh(self._h, *A.args()) != 0:
+            raise ValueError("AMG refresh failed: another size, or coarsest level not positive definite")
+        self._sys = A
 
     def __del__(self):
         if getattr(self, "_h", None):

@@ -396,6 +396,38 @@ or_amg* or_amg_setup(int32_t n, int32_t nf, const int32_t* owner, const int32_t*
     return h;
 }
 
+/* The hierarchy for new coefficients of the same mesh with the aggregates
+ * kept: level 0 from the LDU arrays, then on every level the diagonal, omega
+ * from the Gershgorin bound, P = (I - omega D^-1 A) P_t from the stored
+ * aggregates, R = P^T and A_c = R (A P), and the last level's factor, all as
+ * or_amg_setup computes them.  Returns 0, or -1 if the last level is not
+ * positive definite (the handle is then unusable) or n differs. */
+int32_t or_amg_refresh(or_amg* h, int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                       const double* diag, const double* upper, const double* lower)
+{
+    if (!h || n != h->A[0].n) return -1;
+    csr_free(&h->A[0]);
+    csr_from_ldu(n, nf, owner, nb, diag, upper, lower, &h->A[0]);
+    const int32_t last = h->nlev - 1;
+    for (int32_t l = 0; l <= last; ++l) {
+        const csr_t* A = &h->A[l];
+        csr_diag(A, h->d[l]);
+        h->omega[l] = 4.0 / (3.0 * gershgorin(A, h->d[l]));
+        if (l == last) break;
+        const int32_t na = h->A[l + 1].n;  /* the aggregate count */
+        csr_free(&h->P[l]);
+        csr_free(&h->R[l]);
+        csr_free(&h->A[l + 1]);
+        smoothed_prolongator(A, h->d[l], h->agg[l], na, h->omega[l], &h->P[l]);
+        csr_transpose(&h->P[l], &h->R[l]);
+        csr_t AP;
+        csr_mm(A, &h->P[l], &AP);
+        csr_mm(&h->R[l], &AP, &h->A[l + 1]);
+        csr_free(&AP);
+    }
+    return dense_cholesky(&h->A[last], h->chol) ? 0 : -1;
+}
+
 void or_amg_free(or_amg* h)
 {
     if (!h) return;

@@ -95,6 +95,9 @@ int32_t or_amg_aggregate(int32_t n, const int32_t* ptr, const int32_t* col, cons
                          const uint64_t* key, uint64_t seed, int32_t level, int32_t* agg);
 uint64_t or_splitmix64(uint64_t seed, uint64_t k);
 uint64_t or_amg_priority(uint64_t seed, int32_t level, int32_t i);
+/* New coefficients of the same mesh, the aggregates kept (0, or -1). */
+int32_t or_amg_refresh(or_amg* h, int32_t n, int32_t nf, const int32_t* owner, const int32_t* nb,
+                       const double* diag, const double* upper, const double* lower);
 void or_amg_free(or_amg* h);
 int32_t or_amg_levels(const or_amg* h);
 void or_amg_level_info(const or_amg* h, int32_t l, int32_t* n, int32_t* nnz, int32_t* n_coarse, double* omega);

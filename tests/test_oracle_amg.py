@@ -20,6 +20,12 @@ A8 AMG-PCG reaches the dense solution; iteration counts far below Jacobi-PCG
    not stated)
 A9 AMG-preconditioned pipelined CG: the same iterates as AMG-PCG in exact
    arithmetic (equal at equal count up to rounding), the dense solution
+R  refresh with new coefficients of the same mesh, the aggregates kept:
+   R1 the same coefficients give the same hierarchy bit for bit; R2 twice
+   the coefficients give the same P and every coarse operator doubled,
+   exactly; R3 other coefficients give P = (I - w D^-1 A) P_t from the kept
+   aggregates with w from NumPy's Gershgorin bound, Galerkin operators equal
+   to SciPy's P^T A P, and a cycle that is SPD and contracting
 """
 import json
 import os
@@ -331,3 +337,84 @@ def test_a9_pipelined_equals_standard(oracle_lib, make):
     assert st["status"] == 0 and abs(st["iters"] - s2["iters"]) <= 1
     xd = np.linalg.solve(dense(c), c.b)
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 1e-9
+
+
+# ---------------------------------------------------------------- R
+def _levels(h):
+    out = []
+    for l in range(h.levels):
+        lv = {"A": h.export(l, "A"), "info": h.level_info(l)}
+        if l + 1 < h.levels:
+            lv["P"] = h.export(l, "P")
+            lv["agg"] = h.aggregates(l)
+        out.append(lv)
+    return out
+
+
+def _scaled(case, f):
+    return fc.Case(case.name, case.shape, case.n, case.owner, case.neighbour, f * case.diag, f * case.upper,
+                   f * case.lower, case.b)
+
+
+@pytest.mark.parametrize("make", [lambda: fc.varcoef((14, 12, 10), seed=3), lambda: fc.cavity((16, 16, 6))])
+def test_r1_r2_refresh_same_and_scaled(oracle_lib, make):
+    c = make()
+    h = oracle_lib.AMG(c, coarse_size=16)
+    before = _levels(h)
+    h.refresh(c)
+    same = _levels(h)
+    for a, b in zip(before, same):
+        assert a["info"] == b["info"]
+        for key in ("A", "P"):
+            if key in a:
+                for u, v in zip(a[key][:3], b[key][:3]):
+                    assert np.array_equal(u, v)
+        if "agg" in a:
+            assert np.array_equal(a["agg"], b["agg"])
+    h.refresh(_scaled(c, 2.0))
+    for l, (a, b) in enumerate(zip(before, _levels(h))):
+        assert a["info"]["omega"] == b["info"]["omega"]
+        assert np.array_equal(a["A"][2] * 2.0, b["A"][2]), l
+        if "P" in a:
+            assert np.array_equal(a["P"][2], b["P"][2]), l
+            assert np.array_equal(a["agg"], b["agg"]), l
+
+
+@pytest.mark.parametrize("pair", [(lambda: fc.varcoef((14, 12, 10), seed=3, permute=False),
+                                   lambda: fc.varcoef((14, 12, 10), seed=9, permute=False)),
+                                  (lambda: fc.laplace((12, 12, 12)), lambda: fc.varcoef((12, 12, 12), seed=5,
+                                                                                      permute=False))])
+def test_r3_refresh_other_coefficients(oracle_lib, pair):
+    c1, c2 = pair[0](), pair[1]()
+    assert np.array_equal(c1.owner, c2.owner) and np.array_equal(c1.neighbour, c2.neighbour)
+    h = oracle_lib.AMG(c1, coarse_size=16)
+    aggs = [h.aggregates(l) for l in range(h.levels - 1)]
+    sizes = [h.level_info(l)["n"] for l in range(h.levels)]
+    h.refresh(c2)
+    assert [h.level_info(l)["n"] for l in range(h.levels)] == sizes
+    A = _csr_ldu(c2)
+    for l in range(h.levels - 1):
+        assert np.array_equal(h.aggregates(l), aggs[l])
+        Al = _csr(*h.export(l, "A"))
+        assert np.allclose(Al.toarray(), A.toarray(), rtol=0, atol=1e-12 * abs(A).max())
+        d = A.diagonal()
+        lam = np.max(np.asarray(abs(A).sum(axis=1)).ravel() / d)
+        w = h.level_info(l)["omega"]
+        assert w == pytest.approx(4.0 / (3.0 * lam), rel=1e-14)
+        n, nc = A.shape[0], sizes[l + 1]
+        Pt = sp.csr_matrix((np.ones(n), aggs[l], np.arange(n + 1)), shape=(n, nc))
+        S = sp.identity(n) - w * sp.diags(1.0 / d) @ A
+        P_ref = (S @ Pt).toarray()
+        P = _csr(*h.export(l, "P")).toarray()
+        assert np.allclose(P, P_ref, rtol=0, atol=1e-13)
+        Ac_ref = sp.csr_matrix(P_ref).T @ A @ sp.csr_matrix(P_ref)
+        Ac = _csr(*h.export(l + 1, "A"))
+        assert np.allclose(Ac.toarray(), Ac_ref.toarray(), rtol=0, atol=1e-12 * abs(Ac_ref).max())
+        A = Ac
+    # the refreshed cycle: symmetric positive definite, error propagator contracting
+    n = c2.n
+    M = np.column_stack([h.vcycle(e) for e in np.eye(n)])
+    assert np.allclose(M, M.T, atol=1e-10 * np.abs(M).max())
+    assert np.linalg.eigvalsh((M + M.T) / 2).min() > 0
+    E = np.eye(n) - M @ dense(c2)
+    assert np.max(np.abs(np.linalg.eigvals(E))) < 1.0
