@@ -347,14 +347,28 @@ FVPCG_API int fvpcg_solve_noalloc(const fvpcg_matrix* mat, const double* b, doub
  * omega).  The whole hierarchy is built on the device from the matrix's
  * current coefficients (sync on `stream` at exit).  The matrix must outlive
  * the handle and be symmetric (FVPCG_UNSUPPORTED otherwise); once the
- * matrix is updated, the handle's solves return FVPCG_INVALID_ARG: create
- * it again.  Calls on one handle must not overlap.  Typical: theta = 0.02
+ * matrix is updated, the handle's solves return FVPCG_INVALID_ARG until
+ * fvpcg_amg_refresh (or a new handle).  Calls on one handle must not overlap.  Typical: theta = 0.02
  * (measured best on the lognormal cube and the graded cavity; 0 takes 1.4x
  * and 3.2x their iterations), max_levels = 12, coarse_size = 64, seed = 1.  Errors: FVPCG_UNSUPPORTED if
  * the last level exceeds 2048 unknowns, FVPCG_BREAKDOWN if it is not
  * positive definite, FVPCG_OUT_OF_MEMORY. */
 FVPCG_API int fvpcg_amg_create(const fvpcg_matrix* mat, double theta, int32_t max_levels, int32_t coarse_size,
                                uint64_t seed, void* stream, fvpcg_amg** out);
+/* Repeated solves (Section 4.1: the application calls the solver every time
+ * step with new coefficients on the same mesh): the hierarchy for the
+ * matrix's current coefficients after fvpcg_matrix_update, keeping the
+ * aggregates, the level count and every sparsity pattern of the setup and
+ * recomputing the rest as fvpcg_amg_create does (diagonals, omega, P, R,
+ * the coarse operators, the last level's inverse), with the product kernels
+ * the setup chose and no independent-set rounds.  The result equals a fresh
+ * setup whenever the aggregates would not change (for instance all
+ * coefficients scaled by one factor); otherwise it is the same method on the
+ * kept aggregates.  Sync on `stream` at exit.  The matrix must still be
+ * symmetric (FVPCG_UNSUPPORTED); FVPCG_BREAKDOWN if a diagonal is not
+ * positive or the last level is not positive definite, after which the
+ * handle's solves return FVPCG_INVALID_ARG until a refresh succeeds. */
+FVPCG_API int fvpcg_amg_refresh(fvpcg_amg* amg, void* stream);
 FVPCG_API int fvpcg_amg_destroy(fvpcg_amg* amg);
 /* Number of levels; rows and stored entries of `level` (n, nnz may be NULL). */
 FVPCG_API int fvpcg_amg_info(const fvpcg_amg* amg, int32_t level, int32_t* levels, int32_t* n, int64_t* nnz);

@@ -564,6 +564,11 @@ class AMG:
         _check(lib().fvpcg_amg_info(self._h, -1, ctypes.byref(lv), None, None), "fvpcg_amg_info")
         return lv.value
 
+    def refresh(self, stream=None):
+        """The hierarchy for the matrix's current coefficients (after an
+        update), aggregates and patterns kept."""
+        _check(lib().fvpcg_amg_refresh(self._h, _stream(stream)), "fvpcg_amg_refresh")
+
     def level_info(self, level):
         lv, n, nnz = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
         _check(lib().fvpcg_amg_info(self._h, int(level), ctypes.byref(lv), ctypes.byref(n), ctypes.byref(nnz)),
@@ -625,6 +630,14 @@ def fvpcg_amg_aggregates(M: AMG, level=0):
 
 def fvpcg_amg_export(M: AMG, level=1, which="A"):
     return M.export(level, which)
+
+
+def fvpcg_amg_refresh(amg, stream=None):
+    """The hierarchy for the matrix's current coefficients (AMG.refresh)."""
+    amg.refresh(stream)
+
+
+amg_refresh = fvpcg_amg_refresh
 
 
 def fvpcg_amg_apply(M: AMG, r, z=None, stream=None):

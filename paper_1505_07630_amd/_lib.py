@@ -71,6 +71,7 @@ SIGNATURES = {
     "fvpcg_transient_run": (ctypes.c_int, [P, P, P, P, P, P, f64, i32, P, f64, i32, i32, P, SPS]),
     "fvpcg_amg_create": (ctypes.c_int, [P, f64, i32, i32, ctypes.c_uint64, P, PP]),
     "fvpcg_amg_export": (ctypes.c_int, [P, i32, i32, P, P, P, P, P, P]),
+    "fvpcg_amg_refresh": (ctypes.c_int, [P, P]),
     "fvpcg_amg_destroy": (ctypes.c_int, [P]),
     "fvpcg_piso_create": (ctypes.c_int, [P, P, P, P, P, P, f64, f64, i32, P, PP]),
     "fvpcg_piso_destroy": (ctypes.c_int, [P]),

@@ -556,8 +556,17 @@ void amg_free(fvpcg_amg* h) {
         dev_free(v.r);
         dev_free(v.y);
         dev_free(v.agg);
+        dev_free(v.ap_ptr);
+        dev_free(v.ap_col);
+        dev_free(v.ap_val);
+        dev_free(v.p_off);
+        dev_free(v.ap_off);
+        dev_free(v.c_off);
     }
     dev_free(h->cinv);
+    dev_free(h->a0_ptr);
+    dev_free(h->a0_col);
+    dev_free(h->a0_val);
     dev_free(h->r);
     dev_free(h->z);
     dev_free(h->p);
@@ -592,6 +601,21 @@ int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_s
     }
     *out = h;
     return FVPCG_OK;
+}
+
+// fvpcg_amg_refresh: the matrix's checks of fvpcg_amg_create, then the
+// numeric refresh
+int amg_update(fvpcg_amg* h, hipStream_t s) {
+    const fvpcg_matrix* mat = h->mat;
+    if (!mat->diag_ok) return set_error(FVPCG_BREAKDOWN, "AMG needs a finite positive diagonal");
+    if (!mat->vals_sym)
+        return set_error(FVPCG_UNSUPPORTED, "AMG needs a symmetric matrix (lower == upper on every face)");
+    try {
+        return amg_refresh(h, s);
+    } catch (const std::bad_alloc&) {
+        h->generation = kStaleGeneration;
+        return set_error(FVPCG_OUT_OF_MEMORY, "host allocation failed during the AMG refresh");
+    }
 }
 
 int amg_levels(const fvpcg_amg* h) { return h->nlev; }
@@ -638,7 +662,7 @@ int amg_export(const fvpcg_amg* h, int l, int which, int* rows, int* cols, long 
 static int check_generation(const fvpcg_amg* h) {
     if (h->generation != h->mat->generation)
         return set_error(FVPCG_INVALID_ARG,
-                         "the matrix was updated after this AMG hierarchy was built; create the AMG again");
+                         "the matrix was updated after this AMG hierarchy was built (or its refresh failed); refresh or create it");
     return FVPCG_OK;
 }
 

@@ -39,6 +39,15 @@ constexpr int kAmgMaxLevels = 16;
 constexpr int kAmgMaxCoarse = 2048;  // largest exactly-solved last level
 constexpr int kAmgBs = 512;          // level-0 and PCG kernels
 constexpr int kAmgCsrBs = 256;       // CSR levels
+constexpr uint64_t kStaleGeneration = ~0ull;  // a hierarchy no matrix generation matches (failed refresh)
+
+// The sparse-product kernel chosen for one Galerkin product at setup, kept
+// so that a numeric refresh runs the same kernel without sizing it again.
+enum ProdMode { kProdDense = 0, kProdTiled = 1, kProdMergeLds = 2, kProdMerge = 3 };
+struct ProdPlan {
+    int mode = kProdMerge;
+    int lcap = 0, per_wg = 0;  // heap entries per row and rows per workgroup of the LDS merge
+};
 
 struct AmgLevel {
     int n = 0, nc = 0;  // rows here and on the next level
@@ -55,6 +64,12 @@ struct AmgLevel {
     double *b = nullptr, *x = nullptr, *r = nullptr, *y = nullptr;  // work
     int ga = 1, gp = 1, gr = 1;  // lanes per row for A, P, R (1, 16 or 64)
     int* agg = nullptr;          // device: aggregate of every row (levels with a coarser one)
+    // kept for the numeric refresh (levels with a coarser one)
+    int *ap_ptr = nullptr, *ap_col = nullptr;  // A P
+    double* ap_val = nullptr;
+    long long ap_nnz = 0;
+    long long *p_off = nullptr, *ap_off = nullptr, *c_off = nullptr;  // row offsets of P, A P, A_c (64-bit)
+    ProdPlan plan_p, plan_ap, plan_c;  // kernels of P = S P_t, A P and A_c = R (A P)
 };
 
 // lanes per row from the operator's mean row length (measured at 7M cells:
@@ -67,6 +82,9 @@ inline int lanes_for(size_t nnz, int rows) {
 // The hierarchy into h (freed by the caller on failure).
 int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, uint64_t seed,
               hipStream_t s);
+// The same hierarchy for the matrix's current coefficients with the
+// aggregates, levels and sparsity patterns kept (see fvpcg_amg_refresh).
+int amg_refresh(fvpcg_amg* h, hipStream_t s);
 
 }  // namespace fvpcg
 
@@ -76,6 +94,9 @@ struct fvpcg_amg {
     int nlev = 0;
     fvpcg::AmgLevel lev[fvpcg::kAmgMaxLevels];
     double* cinv = nullptr;  // inverse of the last level, row-major
+    int *a0_ptr = nullptr, *a0_col = nullptr;  // level 0 as CSR, kept for the numeric refresh
+    double* a0_val = nullptr;
+    long long a0_nnz = 0;
     int nlast = 0;
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;  // PCG vectors
     double *u = nullptr, *w = nullptr, *m = nullptr, *s = nullptr;  // pipelined CG, allocated on first use

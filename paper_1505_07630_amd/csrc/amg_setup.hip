@@ -740,6 +740,11 @@ __global__ __launch_bounds__(kSetupBs) void k_max_rowlen(const int* __restrict__
     if (m) atomicMax(out, m);
 }
 
+// 64-bit copy of a row-pointer array
+__global__ __launch_bounds__(kSetupBs) void k_widen(const int* __restrict__ ptr, int n, long long* __restrict__ out) {
+    FV_GRID_LOOP(i, n) out[i] = ptr[i];
+}
+
 __global__ __launch_bounds__(kSetupBs) void k_gemm_compact(int rows, const long long* __restrict__ off,
                                                           const int* __restrict__ cnt, const int* __restrict__ cptr,
                                                           const int* __restrict__ tcol, const double* __restrict__ tval,
@@ -948,8 +953,53 @@ int lds_plan(const int* ptr, int rows, hipStream_t s, int* lcap, int* per_wg) {
     return FVPCG_OK;
 }
 
-// C = X Y (rows of X, columns of Y); C's arrays are allocated here.
-int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s) {
+// Launch the product kernel a plan names: every output row i's distinct
+// columns and sums at off[i] in (tcol, tval), and its count in cnt[i].
+// Scratch (dense accumulators, device-memory heaps) is allocated here and
+// freed after a synchronisation.
+int spgemm_launch(const CsrView& X, const CsrView& Y, const ProdPlan& plan, const long long* off, int* tcol,
+                  double* tval, int* cnt, hipStream_t s) {
+    int rc;
+    const int rows = X.n;
+    DevBuf<double> dacc;
+    DevBuf<uint8_t> dtouch;
+    DevBuf<unsigned long long> heap;
+    DevBuf<int> pos;
+    switch (plan.mode) {
+        case kProdDense:  // narrow product: dense rows, a wavefront each
+            if ((rc = dacc.alloc((size_t)rows * std::max(Y.m, 1), "product accumulators")) ||
+                (rc = dtouch.alloc((size_t)rows * std::max(Y.m, 1), "product flags")))
+                return rc;
+            hipLaunchKernelGGL(k_gemm_dense, dim3((unsigned)std::min(rows, 65536)), dim3(64), 0, s, X.ptr, X.col,
+                               X.val, Y.ptr, Y.col, Y.val, rows, Y.m, off, dacc.p, dtouch.p, tcol, tval, cnt);
+            break;
+        case kProdTiled:  // long rows: LDS column tiles
+            hipLaunchKernelGGL(k_gemm_tiled, dim3((unsigned)std::min(rows, 65536)), dim3(64), 0, s, X.ptr, X.col,
+                               X.val, Y.ptr, Y.col, Y.val, rows, off, tcol, tval, cnt);
+            break;
+        case kProdMergeLds: {
+            const long long blocks = ((long long)rows + plan.per_wg - 1) / plan.per_wg;
+            hipLaunchKernelGGL(k_gemm_merge_lds, dim3((unsigned)std::max(blocks, 1LL)), dim3(kLdsBs),
+                               (size_t)plan.per_wg * plan.lcap * 12, s, X.ptr, X.col, X.val, Y.ptr, Y.col, Y.val,
+                               rows, plan.per_wg, plan.lcap, off, tcol, tval, cnt);
+            break;
+        }
+        default:
+            if ((rc = heap.alloc((size_t)std::max(X.nnz, 1LL), "product heaps")) ||
+                (rc = pos.alloc((size_t)std::max(X.nnz, 1LL), "product positions")))
+                return rc;
+            hipLaunchKernelGGL(k_gemm_merge, dim3(grid1d(rows)), dim3(kSetupBs), 0, s, X.ptr, X.col, X.val, Y.ptr,
+                               Y.col, Y.val, rows, off, heap.p, pos.p, tcol, tval, cnt);
+            break;
+    }
+    FV_LAUNCHED();
+    if (dacc.p || heap.p) FV_HIP(hipStreamSynchronize(s));  // their scratch is freed on return
+    return FVPCG_OK;
+}
+
+// C = X Y (rows of X, columns of Y); C's arrays are allocated here, and the
+// kernel chosen is recorded in *plan.
+int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s, ProdPlan* plan) {
     int rc;
     const int rows = X.n;
     DevBuf<long long> ub, off;
@@ -964,8 +1014,7 @@ int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s) {
     if ((rc = scan_excl<long long>(ub.p, off.p, rows, s))) return rc;
     long long total = 0;
     if ((rc = read_scalar(&total, off.p + rows, s))) return rc;
-    DevBuf<unsigned long long> heap;
-    DevBuf<int> pos, tcol;
+    DevBuf<int> tcol;
     DevBuf<double> tval;
     if ((rc = tcol.alloc((size_t)std::max(total, 1LL), "product columns")) ||
         (rc = tval.alloc((size_t)std::max(total, 1LL), "product values")))
@@ -973,8 +1022,6 @@ int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s) {
     int lcap = 0, per_wg = 0, mlen = 0;
     if ((rc = read_scalar(&mlen, mx.p, s))) return rc;
     lds_fit(mlen, &lcap, &per_wg);
-    DevBuf<double> dacc;
-    DevBuf<uint8_t> dtouch;
     // Kernel choice: dense rows for narrow products, LDS column tiles for
     // long rows, else the heap merge.  FVPCG_AMG_PRODUCT = merge | tiled |
     // dense forces one where it applies (all give the same sums); tests use it.
@@ -984,28 +1031,10 @@ int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s) {
     const bool use_dense = dense_ok && (fk.empty() || fk == "dense");
     const bool use_tiled = !use_dense && tiled_ok &&
                            (fk == "tiled" || (fk.empty() && (total >= kTileMinWork * (long long)rows || per_wg < 1)));
-    if (use_dense) {  // narrow product: dense rows, a wavefront each
-        if ((rc = dacc.alloc((size_t)rows * std::max(Y.m, 1), "product accumulators")) ||
-            (rc = dtouch.alloc((size_t)rows * std::max(Y.m, 1), "product flags")))
-            return rc;
-        hipLaunchKernelGGL(k_gemm_dense, dim3((unsigned)std::min(rows, 65536)), dim3(64), 0, s, X.ptr, X.col, X.val,
-                           Y.ptr, Y.col, Y.val, rows, Y.m, off.p, dacc.p, dtouch.p, tcol.p, tval.p, cnt.p);
-    } else if (use_tiled) {  // long rows: LDS column tiles
-        hipLaunchKernelGGL(k_gemm_tiled, dim3((unsigned)std::min(rows, 65536)), dim3(64), 0, s, X.ptr, X.col, X.val,
-                           Y.ptr, Y.col, Y.val, rows, off.p, tcol.p, tval.p, cnt.p);
-    } else if (per_wg >= 1) {
-        const long long blocks = ((long long)rows + per_wg - 1) / per_wg;
-        hipLaunchKernelGGL(k_gemm_merge_lds, dim3((unsigned)std::max(blocks, 1LL)), dim3(kLdsBs),
-                           (size_t)per_wg * lcap * 12, s, X.ptr, X.col, X.val, Y.ptr, Y.col, Y.val, rows, per_wg,
-                           lcap, off.p, tcol.p, tval.p, cnt.p);
-    } else {
-        if ((rc = heap.alloc((size_t)std::max(X.nnz, 1LL), "product heaps")) ||
-            (rc = pos.alloc((size_t)std::max(X.nnz, 1LL), "product positions")))
-            return rc;
-        hipLaunchKernelGGL(k_gemm_merge, dim3(grid1d(rows)), dim3(kSetupBs), 0, s, X.ptr, X.col, X.val, Y.ptr,
-                           Y.col, Y.val, rows, off.p, heap.p, pos.p, tcol.p, tval.p, cnt.p);
-    }
-    FV_LAUNCHED();
+    plan->mode = use_dense ? kProdDense : use_tiled ? kProdTiled : per_wg >= 1 ? kProdMergeLds : kProdMerge;
+    plan->lcap = lcap;
+    plan->per_wg = per_wg;
+    if ((rc = spgemm_launch(X, Y, *plan, off.p, tcol.p, tval.p, cnt.p, s))) return rc;
     C.n = rows;
     C.m = Y.m;
     if ((rc = dev_alloc(&C.ptr, (size_t)rows + 1, "product row pointers"))) return rc;
@@ -1022,6 +1051,21 @@ int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s) {
                        tval.p, C.col, C.val);
     FV_LAUNCHED();
     FV_HIP(hipStreamSynchronize(s));  // the scratch buffers are freed on return
+    return FVPCG_OK;
+}
+
+// C's values for new values of X and Y with the patterns unchanged: C's
+// pattern is then unchanged too (every product's column set depends on the
+// patterns only), so the planned kernel writes each row straight into C at
+// its row offsets (off64: C's row pointers widened); the columns it writes
+// are the ones C already holds.
+int spgemm_numeric(const CsrView& X, const CsrView& Y, int* ccol, double* cval, const long long* off64,
+                   const ProdPlan& plan, hipStream_t s) {
+    DevBuf<int> cnt;
+    int rc;
+    if ((rc = cnt.alloc((size_t)X.n + 1, "product counts"))) return rc;
+    if ((rc = spgemm_launch(X, Y, plan, off64, ccol, cval, cnt.p, s))) return rc;
+    FV_HIP(hipStreamSynchronize(s));
     return FVPCG_OK;
 }
 
@@ -1061,6 +1105,54 @@ int transpose(const CsrView& X, CsrOut& T, hipStream_t s) {
 }
 
 CsrView view(const CsrOut& c) { return {c.n, c.m, c.nnz, c.ptr, c.col, c.val}; }
+
+// The inverse of the last level (n at most kAmgMaxCoarse) into cinv (n x n,
+// row-major) by Gauss-Jordan: one workgroup below kGjGridMin unknowns, one
+// pair of grid-wide launches per pivot from there.
+int invert_last(const CsrView& cur, double* cinv, int* bad, hipStream_t s) {
+    int rc;
+    const int nl = cur.n;
+    DevBuf<double> f, g;
+    if ((rc = f.alloc((size_t)nl, "AMG elimination column")) || (rc = g.alloc((size_t)nl, "AMG elimination row")))
+        return rc;
+    FV_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_dense_zero, dim3(grid1d((long long)nl * nl)), dim3(kSetupBs), 0, s, nl, cinv);
+    hipLaunchKernelGGL(k_dense_fill, dim3(grid1d(nl)), dim3(kSetupBs), 0, s, cur.ptr, cur.col, cur.val, nl, cinv);
+    if (nl < kGjGridMin) {
+        hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(kGjBs), 0, s, cinv, nl, f.p, bad);
+    } else {
+        for (int k = 0; k < nl; ++k) {
+            hipLaunchKernelGGL(k_gj_pivot, dim3(grid1d(nl)), dim3(kSetupBs), 0, s, cinv, nl, k, f.p, g.p, bad);
+            hipLaunchKernelGGL(k_gj_update, dim3(grid1d((long long)nl * nl)), dim3(kSetupBs), 0, s, cinv, nl, k, f.p,
+                               g.p, bad);
+        }
+    }
+    FV_LAUNCHED();
+    int hbad = 0;
+    if ((rc = read_scalar(&hbad, bad, s))) return rc;
+    if (hbad) return set_error(FVPCG_BREAKDOWN, "AMG: the last level is not positive definite");
+    return FVPCG_OK;
+}
+
+// R = P^T's values for new values of P (the patterns kept): the entry
+// (c, i) of R takes P's entry (i, c), found by a binary search in R's row c.
+__global__ __launch_bounds__(kSetupBs) void k_tr_refresh(const int* __restrict__ pptr, const int* __restrict__ pcol,
+                                                        const double* __restrict__ pval, int rows,
+                                                        const int* __restrict__ rptr, const int* __restrict__ rcol,
+                                                        double* __restrict__ rval) {
+    FV_GRID_LOOP(i, rows) {
+        for (int p = pptr[i]; p < pptr[i + 1]; ++p) {
+            const int c = pcol[p];
+            int lo = rptr[c], hi = rptr[c + 1];
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (rcol[mid] < (int)i) lo = mid + 1;
+                else hi = mid;
+            }
+            rval[lo] = pval[p];
+        }
+    }
+}
 
 // The aggregates of one level (agg: n entries, owned by the level); returns
 // the aggregate count in *na.
@@ -1239,7 +1331,7 @@ int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels,
             FV_LAUNCHED();
             const CsrView S{cur.n, cur.n, cur.nnz, cur.ptr, cur.col, sval.p};
             const CsrView Pt{cur.n, na, cur.n, pt_ptr.p, v.agg, ones.p};
-            rc = spgemm(S, Pt, P, s);
+            rc = spgemm(S, Pt, P, s, &v.plan_p);
             v.p_ptr = P.ptr;
             v.p_col = P.col;
             v.p_val = P.val;  // owned by the level from here on
@@ -1254,8 +1346,27 @@ int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels,
         v.r_ptr = R.ptr;
         v.r_col = R.col;
         v.r_val = R.val;
-        if ((rc = spgemm(cur, view(P), AP, s))) return rc;
-        if ((rc = spgemm(view(R), view(AP), Ac, s))) return rc;
+        if ((rc = spgemm(cur, view(P), AP, s, &v.plan_ap))) return rc;
+        if ((rc = spgemm(view(R), view(AP), Ac, s, &v.plan_c))) return rc;
+        // kept for the numeric refresh: A P, and the three products' row
+        // offsets widened to 64 bits
+        v.ap_ptr = AP.ptr;
+        v.ap_col = AP.col;
+        v.ap_val = AP.val;
+        v.ap_nnz = AP.nnz;
+        AP.ptr = nullptr;
+        AP.col = nullptr;
+        AP.val = nullptr;
+        if ((rc = dev_alloc(&v.p_off, (size_t)cur.n + 1, "AMG product offsets")) ||
+            (rc = dev_alloc(&v.ap_off, (size_t)cur.n + 1, "AMG product offsets")) ||
+            (rc = dev_alloc(&v.c_off, (size_t)na + 1, "AMG product offsets")))
+            return rc;
+        hipLaunchKernelGGL(k_widen, dim3(grid1d((long long)cur.n + 1)), dim3(kSetupBs), 0, s, v.p_ptr, cur.n + 1,
+                           v.p_off);
+        hipLaunchKernelGGL(k_widen, dim3(grid1d((long long)cur.n + 1)), dim3(kSetupBs), 0, s, v.ap_ptr, cur.n + 1,
+                           v.ap_off);
+        hipLaunchKernelGGL(k_widen, dim3(grid1d((long long)na + 1)), dim3(kSetupBs), 0, s, Ac.ptr, na + 1, v.c_off);
+        FV_LAUNCHED();
         v.nc = na;
         v.p_nnz = P.nnz;
         v.gp = lanes_for((size_t)P.nnz, P.n);
@@ -1268,10 +1379,7 @@ int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels,
         Ac.col = nullptr;
         Ac.val = nullptr;
         cur = CsrView{na, na, Ac.nnz, next.a_ptr, next.a_col, next.a_val};
-        if (l == 0) {
-            A0.release();
-            d0.reset();  // level 0's CSR diagonal is no longer needed
-        }
+        if (l == 0) d0.reset();  // level 0's CSR diagonal is no longer needed
         th *= FVPCG_AMG_THETA_DECAY;
         ++l;
     }
@@ -1281,32 +1389,16 @@ int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels,
         return set_error(FVPCG_UNSUPPORTED, "AMG: last level has %d unknowns (at most %d are solved exactly)", cur.n,
                          kAmgMaxCoarse);
     // the last level's inverse
-    const int nl = cur.n;
-    if ((rc = dev_alloc(&h->cinv, (size_t)nl * nl, "AMG coarse inverse"))) return rc;
-    {
-        DevBuf<double> f, g;
-        if ((rc = f.alloc((size_t)nl, "AMG elimination column")) || (rc = g.alloc((size_t)nl, "AMG elimination row")))
-            return rc;
-        FV_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
-        hipLaunchKernelGGL(k_dense_zero, dim3(grid1d((long long)nl * nl)), dim3(kSetupBs), 0, s, nl, h->cinv);
-        hipLaunchKernelGGL(k_dense_fill, dim3(grid1d(nl)), dim3(kSetupBs), 0, s, cur.ptr, cur.col, cur.val, nl,
-                           h->cinv);
-        if (nl < kGjGridMin) {
-            hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(kGjBs), 0, s, h->cinv, nl, f.p, bad.p);
-        } else {
-            for (int k = 0; k < nl; ++k) {
-                hipLaunchKernelGGL(k_gj_pivot, dim3(grid1d(nl)), dim3(kSetupBs), 0, s, h->cinv, nl, k, f.p, g.p,
-                                   bad.p);
-                hipLaunchKernelGGL(k_gj_update, dim3(grid1d((long long)nl * nl)), dim3(kSetupBs), 0, s, h->cinv,
-                                   nl, k, f.p, g.p, bad.p);
-            }
-        }
-        FV_LAUNCHED();
-        int hbad = 0;
-        if ((rc = read_scalar(&hbad, bad.p, s))) return rc;
-        if (hbad) return set_error(FVPCG_BREAKDOWN, "AMG: the last level is not positive definite");
-    }
-    // level 0's CSR and diagonal go out of scope here (single-level case)
+    if (!h->cinv && (rc = dev_alloc(&h->cinv, (size_t)cur.n * cur.n, "AMG coarse inverse"))) return rc;
+    if ((rc = invert_last(cur, h->cinv, bad.p, s))) return rc;
+    // level 0's CSR is kept for the numeric refresh
+    h->a0_ptr = A0.ptr;
+    h->a0_col = A0.col;
+    h->a0_val = A0.val;
+    h->a0_nnz = A0.nnz;
+    A0.ptr = nullptr;
+    A0.col = nullptr;
+    A0.val = nullptr;
     FV_HIP(hipStreamSynchronize(s));
     const size_t nn0 = (size_t)std::max(n0, 1);
     if ((rc = dev_alloc(&h->r, nn0, "AMG-PCG vectors")) || (rc = dev_alloc(&h->z, nn0, "AMG-PCG vectors")) ||
@@ -1324,4 +1416,79 @@ int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels,
     return FVPCG_OK;
 }
 
+int amg_refresh(fvpcg_amg* h, hipStream_t s) {
+    int rc;
+    const fvpcg_matrix* A = h->mat;
+    const fvpcg_mesh* msh = A->mesh;
+    const int n0 = msh->n, W = msh->W;
+    h->generation = kStaleGeneration;  // until the refresh completes
+    // level 0's values into the kept CSR (the ELL pattern gives the same columns)
+    hipLaunchKernelGGL(k_l0_fill, dim3(grid1d(n0)), dim3(kSetupBs), 0, s, msh->col, A->val, A->d, n0, W, h->a0_ptr,
+                       h->a0_col, h->a0_val);
+    FV_LAUNCHED();
+    CsrView cur{n0, n0, h->a0_nnz, h->a0_ptr, h->a0_col, h->a0_val};
+    DevBuf<double> d0;
+    DevBuf<unsigned long long> rho_bits;
+    DevBuf<int> bad;
+    if ((rc = d0.alloc((size_t)n0, "AMG level diagonal")) || (rc = rho_bits.alloc(1, "AMG spectral bound")) ||
+        (rc = bad.alloc(1, "AMG flag")))
+        return rc;
+    const int last = h->nlev - 1;
+    for (int l = 0; l <= last; ++l) {
+        AmgLevel& v = h->lev[l];
+        double* d = l == 0 ? d0.p : v.d;
+        FV_HIP(hipMemsetAsync(rho_bits.p, 0, sizeof(unsigned long long), s));
+        FV_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_lvl_diag, dim3(grid1d(cur.n)), dim3(kSetupBs), 0, s, cur.ptr, cur.col, cur.val, cur.n, d,
+                           rho_bits.p, bad.p);
+        FV_LAUNCHED();
+        unsigned long long rb = 0;
+        int hbad = 0;
+        if ((rc = read_scalar(&rb, rho_bits.p, s)) || (rc = read_scalar(&hbad, bad.p, s))) return rc;
+        double rho;
+        std::memcpy(&rho, &rb, sizeof(rho));
+        if (hbad || !(rho > 0.0) || !std::isfinite(rho))
+            return set_error(FVPCG_BREAKDOWN, "AMG: level %d has a diagonal entry that is not finite and positive", l);
+        v.omega = 4.0 / (3.0 * rho);
+        if (l > 0) {
+            hipLaunchKernelGGL(k_lvl_colscale, dim3(grid1d(cur.nnz)), dim3(kSetupBs), 0, s, cur.col, cur.val, d,
+                               cur.nnz, v.a_val_cs);
+            FV_LAUNCHED();
+        }
+        if (l == last) break;
+        {  // P = S P_t with the kept aggregates
+            DevBuf<double> sval, ones;
+            DevBuf<int> pt_ptr;
+            if ((rc = sval.alloc((size_t)std::max(cur.nnz, 1LL), "AMG smoother rows")) ||
+                (rc = ones.alloc((size_t)cur.n, "AMG tentative prolongator")) ||
+                (rc = pt_ptr.alloc((size_t)cur.n + 1, "AMG tentative prolongator")))
+                return rc;
+            hipLaunchKernelGGL(k_smoother_rows, dim3(grid1d(cur.n)), dim3(kSetupBs), 0, s, cur.ptr, cur.col, cur.val,
+                               d, cur.n, v.omega, sval.p);
+            hipLaunchKernelGGL(k_tentative, dim3(grid1d((long long)cur.n + 1)), dim3(kSetupBs), 0, s, cur.n, pt_ptr.p,
+                               ones.p);
+            FV_LAUNCHED();
+            const CsrView S{cur.n, cur.n, cur.nnz, cur.ptr, cur.col, sval.p};
+            const CsrView Pt{cur.n, v.nc, cur.n, pt_ptr.p, v.agg, ones.p};
+            if ((rc = spgemm_numeric(S, Pt, v.p_col, v.p_val, v.p_off, v.plan_p, s))) return rc;
+        }
+        hipLaunchKernelGGL(k_tr_refresh, dim3(grid1d(cur.n)), dim3(kSetupBs), 0, s, v.p_ptr, v.p_col, v.p_val, cur.n,
+                           v.r_ptr, v.r_col, v.r_val);
+        FV_LAUNCHED();
+        const CsrView P{cur.n, v.nc, v.p_nnz, v.p_ptr, v.p_col, v.p_val};
+        const CsrView R{v.nc, cur.n, v.p_nnz, v.r_ptr, v.r_col, v.r_val};
+        const CsrView AP{cur.n, v.nc, v.ap_nnz, v.ap_ptr, v.ap_col, v.ap_val};
+        AmgLevel& next = h->lev[l + 1];
+        if ((rc = spgemm_numeric(cur, P, v.ap_col, v.ap_val, v.ap_off, v.plan_ap, s)) ||
+            (rc = spgemm_numeric(R, AP, next.a_col, next.a_val, v.c_off, v.plan_c, s)))
+            return rc;
+        cur = CsrView{v.nc, v.nc, next.nnz, next.a_ptr, next.a_col, next.a_val};
+    }
+    if ((rc = invert_last(cur, h->cinv, bad.p, s))) return rc;
+    FV_HIP(hipStreamSynchronize(s));
+    h->generation = A->generation;
+    return FVPCG_OK;
+}
+
 }  // namespace fvpcg
+

@@ -64,6 +64,7 @@ int piso_run(fvpcg_piso* ps, double dt, int nsteps, int n_corr, double* U, doubl
 int piso_mesh_n(const fvpcg_piso* ps);
 int piso_mesh_f(const fvpcg_piso* ps);
 void amg_free(fvpcg_amg* h);
+int amg_update(fvpcg_amg* h, hipStream_t s);
 int amg_levels(const fvpcg_amg* h);
 int amg_level_n(const fvpcg_amg* h, int l);
 long long amg_level_nnz(const fvpcg_amg* h, int l);
@@ -586,6 +587,13 @@ int fvpcg_amg_create(const fvpcg_matrix* mat, double theta, int32_t max_levels, 
         if (!mat->vals_sym)
             return set_error(FVPCG_UNSUPPORTED, "AMG needs a symmetric matrix (lower == upper on every face)");
         return amg_create(mat, theta, max_levels, coarse_size, seed, (hipStream_t)stream, out);
+    });
+}
+
+int fvpcg_amg_refresh(fvpcg_amg* amg, void* stream) {
+    return guard([&]() -> int {
+        if (!amg) return set_error(FVPCG_INVALID_ARG, "amg is NULL");
+        return amg_update(amg, (hipStream_t)stream);
     });
 }
 

@@ -43,6 +43,7 @@ struct fvpcg_piso {
     double *phiH = nullptr, *cf = nullptr, *pupper = nullptr;  // [F]
     fvpcg_matrix* mom = nullptr;   // momentum matrix (lower != upper)
     fvpcg_matrix* pres = nullptr;  // pressure matrix (symmetric)
+    fvpcg_amg* amg = nullptr;      // its AMG hierarchy (AMG pressure solver), kept across steps and calls
 };
 
 namespace fvpcg {
@@ -58,6 +59,7 @@ int solve_bicgstab_multi(const fvpcg_matrix* A, int nrhs, const double* b, doubl
 int amg_create(const fvpcg_matrix* A, double theta, int max_levels, int coarse_size, uint64_t seed, hipStream_t s,
                fvpcg_amg** out);
 void amg_free(fvpcg_amg* h);
+int amg_update(fvpcg_amg* h, hipStream_t s);
 int solve_amg(const fvpcg_amg* h, const double* b, double* x, double tol, int maxit, int method, hipStream_t s,
               fvpcg_stats* stats);
 
@@ -233,6 +235,7 @@ int piso_mesh_f(const fvpcg_piso* ps) { return ps->mesh->F; }
 
 void piso_free(fvpcg_piso* ps) {
     if (!ps) return;
+    amg_free(ps->amg);  // before the matrix it refers to
     if (ps->mom) matrix_destroy(ps->mom);
     if (ps->pres) matrix_destroy(ps->pres);
     int8_t* i8[] = {ps->fdir, ps->fsgn};
@@ -338,7 +341,6 @@ int piso_run(fvpcg_piso* ps, double dt, int nsteps, int n_corr, double* U, doubl
         for (int k = 0; k < 3; ++k) iu += comp[k].iters;
         su = comp[0];
         if (rc != FVPCG_OK) break;
-        fvpcg_amg* amg = nullptr;
         for (int corr = 0; corr < n_corr && rc == FVPCG_OK; ++corr) {
             hipLaunchKernelGGL(k_hbya, dim3(gn), dim3(kPisoBs), 0, s, m->col, ps->mom->val, ps->mdiag, ps->bH, U, n,
                                W, V, ps->HbyA, ps->rAU);
@@ -350,12 +352,18 @@ int piso_run(fvpcg_piso* ps, double dt, int nsteps, int n_corr, double* U, doubl
             FV_LAUNCHED();
             if (corr == 0) {  // rAU, and so the pressure matrix, is fixed within a step
                 if ((rc = matrix_update(ps->pres, ps->pdiag, ps->pupper, nullptr, s))) break;
-                if (ps->psolver == FVPCG_PSOLVER_AMG &&
-                    (rc = amg_create(ps->pres, kPisoAmgTheta, 12, 64, 1, s, &amg)))
-                    break;
+                // AMG: built on the first step, then refreshed numerically (the
+                // pressure matrix keeps its pattern; its aggregates are kept)
+                if (ps->psolver == FVPCG_PSOLVER_AMG) {
+                    if (!ps->amg)
+                        rc = amg_create(ps->pres, kPisoAmgTheta, 12, 64, 1, s, &ps->amg);
+                    else
+                        rc = amg_update(ps->amg, s);
+                    if (rc) break;
+                }
             }
-            if (amg)
-                rc = solve_amg(amg, ps->prhs, p, tol_p, maxit, FVPCG_CG, s, &sp);
+            if (ps->psolver == FVPCG_PSOLVER_AMG)
+                rc = solve_amg(ps->amg, ps->prhs, p, tol_p, maxit, FVPCG_CG, s, &sp);
             else
                 rc = solve(ps->pres, ps->prhs, p, tol_p, maxit, FVPCG_CG, FVPCG_PRECOND_JACOBI, s, &sp);
             ip += sp.iters;
@@ -366,7 +374,6 @@ int piso_run(fvpcg_piso* ps, double dt, int nsteps, int n_corr, double* U, doubl
                                ps->bgrad, p, ps->HbyA, ps->rAU, n, W, h, U);
             FV_LAUNCHED();
         }
-        if (amg) amg_free(amg);
     }
     (void)hipEventRecord(e1, s);
     (void)hipEventSynchronize(e1);

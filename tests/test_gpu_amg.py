@@ -273,6 +273,101 @@ def test_amg_stale_after_update(fv, orc):
     torch.cuda.synchronize()
 
 
+def _assert_same_hierarchy(M1, M2, exact=True):
+    assert M1.levels == M2.levels
+    for l in range(M1.levels):
+        assert M1.level_info(l) == M2.level_info(l), l
+        keys = (["P", "R"] if l + 1 < M1.levels else []) + (["A"] if l >= 1 else [])
+        if l + 1 < M1.levels:
+            assert np.array_equal(M1.aggregates(l), M2.aggregates(l)), l
+        for key in keys:
+            a, b = M1.export(l, key), M2.export(l, key)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (l, key)
+            if exact:
+                assert np.array_equal(a[2], b[2]), (l, key)
+
+
+@pytest.mark.parametrize("name", ["varcoef_14x12x10_rcm", "cavity_24x24x8"])
+def test_amg_refresh_matches_oracle(fv, orc, name):
+    """fvpcg_amg_refresh after fvpcg_matrix_update (new coefficients on the
+    same mesh): the kept aggregates, P and the coarse operators within 1e-12
+    of the oracle's refresh, R = P^T bit for bit, one cycle within 1e-10,
+    AMG-PCG within one iteration of the oracle's; before the refresh the
+    handle's solves are refused."""
+    say("amg refresh", name)
+    case = CASES[name]()
+    rng = np.random.default_rng(21)
+    f = np.exp(rng.normal(0.0, 0.5, case.F))  # new face coefficients, same signs and mesh
+    up2 = case.upper * f
+    diag2 = case.diag.copy()
+    np.add.at(diag2, case.owner, -(up2 - case.upper))
+    np.add.at(diag2, case.neighbour, -(up2 - case.upper))
+    c2 = fc.Case("refresh", case.shape, case.n, case.owner, case.neighbour, diag2, up2, up2.copy(), case.b)
+    dc = DevCase(case)
+    M = fv.AMG(dc.A, coarse_size=16)
+    H = orc.AMG(case, coarse_size=16)
+    aggs = [M.aggregates(l) for l in range(M.levels - 1)]
+    dc.A.update(to_dev(diag2), to_dev(up2))
+    with pytest.raises(fv.FVPCGError) as e:
+        fv.solve_amg(M, dc.b, tol=1e-10)
+    assert e.value.code == fv.INVALID_ARG
+    M.refresh()
+    H.refresh(c2)
+    assert M.levels == H.levels
+    for l in range(H.levels):
+        if l + 1 < H.levels:
+            assert np.array_equal(M.aggregates(l), aggs[l]) and np.array_equal(H.aggregates(l), aggs[l]), l
+            ptr, col, val, shape = M.export(l, "P")
+            optr, ocol, oval, oshape = H.export(l, "P")
+            assert shape == oshape and np.array_equal(ptr, optr) and np.array_equal(col, ocol), l
+            assert np.max(np.abs(val - oval)) <= 1e-12 * np.max(np.abs(oval)), l
+            rptr, rcol, rval, rshape = M.export(l, "R")
+            R = sp.csr_matrix((rval, rcol, rptr), shape=rshape)
+            P = sp.csr_matrix((val, col, ptr), shape=shape)
+            assert (R != P.T.tocsr()).nnz == 0, l
+        if l >= 1:
+            ptr, col, val, shape = M.export(l, "A")
+            optr, ocol, oval, oshape = H.export(l, "A")
+            assert shape == oshape and np.array_equal(ptr, optr) and np.array_equal(col, ocol), l
+            assert np.max(np.abs(val - oval)) / np.max(np.abs(oval)) <= 1e-12, l
+    v = np.random.default_rng(7).standard_normal(case.n)
+    z = fv.amg_apply(M, to_dev(v)).cpu().numpy()
+    assert rel(z, H.vcycle(v)) <= 1e-10
+    x, st = fv.solve_amg(M, dc.b, tol=1e-10, maxit=500)
+    _, so = H.pcg(c2.b, tol=1e-10, maxit=500)
+    assert st["status"] == 0 and abs(st["iters"] - so["iters"]) <= 1
+    M.close()
+    dc.close()
+
+
+def test_amg_refresh_scaled_equals_fresh(fv, orc):
+    """Coefficients scaled by 2 keep every aggregate, so the refreshed
+    hierarchy equals a fresh setup of the scaled matrix bit for bit; a
+    refresh with unchanged coefficients reproduces the setup bit for bit."""
+    say("amg refresh scaled")
+    case = CASES["varcoef32_rcm"]()
+    dc = DevCase(case)
+    M = fv.AMG(dc.A, coarse_size=16)
+    F0 = fv.AMG(dc.A, coarse_size=16)
+    M.refresh()
+    _assert_same_hierarchy(M, F0)
+    F0.close()
+    dc.A.update(to_dev(2.0 * case.diag), to_dev(2.0 * case.upper))
+    M.refresh()
+    F = fv.AMG(dc.A, coarse_size=16)
+    _assert_same_hierarchy(M, F)
+    x1, s1 = fv.solve_amg(M, dc.b, tol=1e-10)
+    x2, s2 = fv.solve_amg(F, dc.b, tol=1e-10)
+    assert s1["iters"] == s2["iters"] and torch_equal(x1, x2)
+    M.close()
+    F.close()
+    dc.close()
+
+
+def torch_equal(a, b):
+    return bool((a == b).all().item())
+
+
 def test_amg_varcoef192(fv, orc):
     """The 7.08M-cell workload: the device setup (timed; the hierarchy's
     level sizes and aggregates of level 0 equal to the oracle's), AMG-PCG to
