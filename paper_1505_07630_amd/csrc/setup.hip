@@ -122,13 +122,15 @@ __global__ void k_gather_coeffs(const int* __restrict__ ref, const int* __restri
     }
 }
 
-// flag bit 2: lower differs from upper on some face (or either is NaN)
+// flag bit 2: lower differs from upper on some face (or either is NaN); one
+// atomic per wavefront that saw a difference (a non-symmetric matrix differs
+// on almost every face)
 __global__ void k_check_sym(const double* __restrict__ upper, const double* __restrict__ lower, int F,
                             unsigned* flags) {
-    unsigned asym = 0;
+    bool asym = false;
     for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < F; f += gridDim.x * blockDim.x)
-        if (!(upper[f] == lower[f])) asym = 2u;
-    if (asym) atomicOr(flags, asym);
+        if (!(upper[f] == lower[f])) asym = true;
+    if (__ballot(asym) != 0 && (threadIdx.x & 63) == 0) atomicOr(flags, 2u);
 }
 
 __global__ void k_copy_diag(const double* __restrict__ diag, int n, double* d, float* d32, unsigned* flags) {
