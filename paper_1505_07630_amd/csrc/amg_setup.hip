@@ -35,10 +35,6 @@
 
 #include "amg.hpp"
 
-#ifndef FVPCG_AMG_THETA_DECAY
-#define FVPCG_AMG_THETA_DECAY 0.5
-#endif
-
 namespace fvpcg {
 
 namespace {
@@ -1380,7 +1376,7 @@ int amg_build(fvpcg_amg* h, const fvpcg_matrix* A, double theta, int max_levels,
         Ac.val = nullptr;
         cur = CsrView{na, na, Ac.nnz, next.a_ptr, next.a_col, next.a_val};
         if (l == 0) d0.reset();  // level 0's CSR diagonal is no longer needed
-        th *= FVPCG_AMG_THETA_DECAY;
+        th *= 0.5;  // theta_l = theta / 2^l
         ++l;
     }
     h->nlev = l + 1;

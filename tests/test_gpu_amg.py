@@ -12,6 +12,7 @@ import scipy.sparse as sp
 
 import fvcases as fc
 from tests.gpu_util import DevCase, rel, say, to_dev
+from tests.helpers import dense
 
 pytestmark = pytest.mark.gpu
 
@@ -361,6 +362,53 @@ def test_amg_refresh_scaled_equals_fresh(fv, orc):
     assert s1["iters"] == s2["iters"] and torch_equal(x1, x2)
     M.close()
     F.close()
+    dc.close()
+
+
+def test_amg_refresh_edge_cases(fv, orc):
+    """Refresh after a non-symmetric update is refused (UNSUPPORTED) and the
+    handle stays refused; a non-positive diagonal gives BREAKDOWN and the
+    handle's solves are refused until a refresh with good coefficients
+    succeeds; a single-level hierarchy refreshes to the new exact solve."""
+    say("amg refresh edge cases")
+    case = CASES["laplace16"]()
+    dc = DevCase(case)
+    M = fv.AMG(dc.A, coarse_size=16)
+    dc.A.update(to_dev(case.diag), to_dev(case.upper), to_dev(0.5 * case.upper))
+    with pytest.raises(fv.FVPCGError) as e:
+        M.refresh()
+    assert e.value.code == fv.UNSUPPORTED
+    with pytest.raises(fv.FVPCGError) as e:
+        fv.solve_amg(M, dc.b, tol=1e-10)
+    assert e.value.code == fv.INVALID_ARG
+    bad = case.diag.copy()
+    bad[5] = -1.0
+    dc.A.update(to_dev(bad), to_dev(case.upper))
+    with pytest.raises(fv.FVPCGError) as e:
+        M.refresh()
+    assert e.value.code == fv.BREAKDOWN
+    with pytest.raises(fv.FVPCGError) as e:
+        fv.solve_amg(M, dc.b, tol=1e-10)
+    assert e.value.code == fv.INVALID_ARG
+    dc.A.update(to_dev(3.0 * case.diag), to_dev(3.0 * case.upper))
+    M.refresh()
+    F = fv.AMG(dc.A, coarse_size=16)
+    _assert_same_hierarchy(M, F)
+    F.close()
+    M.close()
+    # one level: the refresh inverts the new operator
+    small = fc.varcoef((5, 4, 3), seed=2, permute=False)
+    other = fc.varcoef((5, 4, 3), seed=7, permute=False)
+    ds = DevCase(small)
+    M1 = fv.AMG(ds.A, coarse_size=1000)
+    assert M1.levels == 1
+    ds.A.update(to_dev(other.diag), to_dev(other.upper))
+    M1.refresh()
+    x, st = fv.solve_amg(M1, to_dev(other.b), tol=1e-12, maxit=5)
+    xs = np.linalg.solve(dense(other), other.b)
+    assert st["status"] == 0 and st["iters"] <= 1 and rel(x.cpu().numpy(), xs) <= 1e-11
+    M1.close()
+    ds.close()
     dc.close()
 
 
