@@ -372,7 +372,7 @@ def test_amg_refresh_edge_cases(fv, orc):
     succeeds; a single-level hierarchy refreshes to the new exact solve."""
     say("amg refresh edge cases")
     case = CASES["laplace16"]()
-    dc = DevCase(case)
+    dc = DevCase(case, symmetric=False)  # explicit lower (equal to upper), so an update may change it
     M = fv.AMG(dc.A, coarse_size=16)
     dc.A.update(to_dev(case.diag), to_dev(case.upper), to_dev(0.5 * case.upper))
     with pytest.raises(fv.FVPCGError) as e:
@@ -383,14 +383,14 @@ def test_amg_refresh_edge_cases(fv, orc):
     assert e.value.code == fv.INVALID_ARG
     bad = case.diag.copy()
     bad[5] = -1.0
-    dc.A.update(to_dev(bad), to_dev(case.upper))
+    dc.A.update(to_dev(bad), to_dev(case.upper), to_dev(case.upper))
     with pytest.raises(fv.FVPCGError) as e:
         M.refresh()
     assert e.value.code == fv.BREAKDOWN
     with pytest.raises(fv.FVPCGError) as e:
         fv.solve_amg(M, dc.b, tol=1e-10)
     assert e.value.code == fv.INVALID_ARG
-    dc.A.update(to_dev(3.0 * case.diag), to_dev(3.0 * case.upper))
+    dc.A.update(to_dev(2.0 * case.diag), to_dev(2.0 * case.upper), to_dev(2.0 * case.upper))  # exact scaling
     M.refresh()
     F = fv.AMG(dc.A, coarse_size=16)
     _assert_same_hierarchy(M, F)
