@@ -363,8 +363,8 @@ FVPCG_API int fvpcg_amg_create(const fvpcg_matrix* mat, double theta, int32_t ma
  * the coarse operators, the last level's inverse), with the product kernels
  * the setup chose and no independent-set rounds.  The result equals a fresh
  * setup whenever the aggregates would not change (for instance all
- * coefficients scaled by one factor); otherwise it is the same method on the
- * kept aggregates.  Sync on `stream` at exit.  The matrix must still be
+ * coefficients scaled by a power of two, which scales every level exactly);
+ * otherwise it is the same method on the kept aggregates.  Sync on `stream` at exit.  The matrix must still be
  * symmetric (FVPCG_UNSUPPORTED); FVPCG_BREAKDOWN if a diagonal is not
  * positive or the last level is not positive definite, after which the
  * handle's solves return FVPCG_INVALID_ARG until a refresh succeeds. */
