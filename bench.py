@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--method", default="pipecg", choices=["pipecg", "cg", "pipecg_literal"])
     ap.add_argument("--roofline-iters", type=int, default=500)
-    ap.add_argument("--cpu-iters", type=int, default=300, help="oracle iterations on all host threads")
+    ap.add_argument("--cpu-iters", type=int, default=1000, help="oracle iterations on all host threads")
     ap.add_argument("--cpu-iters-single", type=int, default=60, help="oracle iterations on one thread")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (baseline and mixed-precision errors)")
     ap.add_argument("--no-mixed", action="store_true")
