@@ -105,11 +105,13 @@ def cpu_baseline(case, iters, iters_single):
     _, s1 = oracle.pipecg(A, case.b, tol=0.0, maxit=iters_single, precond="jacobi", folded=True)
     d1 = time.perf_counter() - t1
     thr = oracle.threads(omp=True)
+    bpi = alg_bytes_per_iter("pipecg", case.n, case.F, 1)
     return {"value": st["iters"] / dt, "unit": "CG iters/s", "cores": thr, "kind": "oracle",
+            "gbs_algorithmic": round(st["iters"] / dt * bpi / 1e9, 2),
             "sample": f"{st['iters']} fixed iterations (plus setup and final residual) of the folded pipelined "
                       f"Jacobi-CG on the full 192^3 workload, OpenMP build on {thr} threads, {dt:.1f} s",
             "seconds": dt, "single_thread": {"value": s1["iters"] / d1, "cores": 1, "iters": s1["iters"],
-                                             "seconds": d1},
+                                             "seconds": d1, "gbs_algorithmic": round(s1["iters"] / d1 * bpi / 1e9, 2)},
             "host": host_cpu()}
 
 
