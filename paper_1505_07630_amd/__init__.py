@@ -611,7 +611,7 @@ class AMG:
             pass
 
 
-def fvpcg_amg_create(A: Matrix, theta=0.0, max_levels=12, coarse_size=64, seed=1, stream=None) -> AMG:
+def fvpcg_amg_create(A: Matrix, theta=0.02, max_levels=12, coarse_size=64, seed=1, stream=None) -> AMG:
     return AMG(A, theta, max_levels, coarse_size, seed, stream)
 
 
