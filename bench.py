@@ -173,8 +173,12 @@ def main():
 
     calib = fv.stream_calibrate(1 << 30)
     # the attainable line for the fused kernel's own mix (it reads about 2.5
-    # bytes per byte written, from 12 to 20 streams), and a read-only kernel
-    mix = {"read_2_write_0": fv.stream_mix(2, 0, 256 << 20), "read_12_write_5": fv.stream_mix(12, 5, 256 << 20)}
+    # bytes per byte written, from 12 to 20 streams) on arrays of the
+    # solver's size (n doubles: the chip's 256 MB last-level cache then
+    # holds as much of them as it holds of the solver's), the same mix on
+    # 256 MiB arrays, and a read-only kernel
+    mix = {"read_2_write_0": fv.stream_mix(2, 0, 256 << 20), "read_12_write_5": fv.stream_mix(12, 5, 8 * case.n),
+           "read_12_write_5_256MiB": fv.stream_mix(12, 5, 256 << 20)}
     log(f"STREAM copy {calib['copy_gbs']:.0f} GB/s, triad {calib['triad_gbs']:.0f} GB/s, "
         f"read-only {mix['read_2_write_0']:.0f} GB/s, 12 in 5 out {mix['read_12_write_5']:.0f} GB/s")
 
@@ -226,8 +230,14 @@ def main():
         "alg_bytes_per_launch": bpi, "avg_launch_us": round(kern_s * 1e6, 2),
         "avg_launch_us_fixed_iters": round(kern_fixed_s * 1e6, 2),
     }
+    moved = None
     if kernel_bytes is not None:
+        # int16 column offsets when every |column - row| fits (the library's
+        # rule): six slots of 2 B instead of 4 B per row
+        col16 = int(np.max(np.abs(case.neighbour.astype(np.int64) - case.owner))) <= 32767 if F else False
+        moved = kernel_bytes - 12 * n if col16 else kernel_bytes
         roof["kernel_bytes_per_launch"] = kernel_bytes
+        roof["moved_bytes_per_launch"] = moved
         roof["kernel_bytes_gbs"] = round(kernel_bytes / kern_s / 1e9, 1)
         roof["kernel_bytes_frac"] = round(kernel_bytes / kern_s / 1e9 / HBM_PEAK_GBS, 4)
     out = {
@@ -254,9 +264,10 @@ def main():
         "stream_calibration_gbs": {"copy": round(calib["copy_gbs"], 1), "triad": round(calib["triad_gbs"], 1),
                                    **{k: round(v, 1) for k, v in mix.items()}},
         "frac_of_stream_copy": round(achieved / calib["copy_gbs"], 4) if calib["copy_gbs"] > 0 else None,
-        # the kernel's HBM traffic (counters when current, else the bytes it
-        # must move) per launch time, against the line for its own mix
-        "real_gbs_vs_stream_mix": round((traffic or kernel_bytes or bpi) / kern_s / 1e9 / mix["read_12_write_5"], 4),
+        # the bytes the kernel must move (with its int16 column offsets) per
+        # launch time, against the line for its own mix; the counted traffic
+        # also holds neighbour lines fetched into more than one XCD's L2
+        "real_gbs_vs_stream_mix": round((moved or bpi) / kern_s / 1e9 / mix["read_12_write_5"], 4),
     }
     pending = None
     if not args.no_mixed:

@@ -397,12 +397,13 @@ FVPCG_API int fvpcg_solve_amg(const fvpcg_amg* amg, const double* b, double* x, 
  * copy moves 2, triad 3 arrays per pass. */
 FVPCG_API int fvpcg_stream_calibrate(void* stream, uint64_t bytes_per_array, double* copy_gbs, double* triad_gbs);
 /* Attainable rate of a kernel that streams n_read device arrays in and
- * n_write out (1..16 and 0..8, each of `bytes_per_array` bytes; 0 = 256 MiB),
- * every workgroup over one contiguous chunk of each, as the solver kernels
- * read their vectors and matrix slots: the roofline line for a kernel with
- * that mix of reads and writes (Section 1 draws the paper's from STREAM).
- * Best over five grid sizes, in GB/s of (n_read + n_write) arrays per
- * pass.  The arrays are allocated and freed inside the call.  INVALID_ARG
+ * n_write out (1..16 and 0..8, each of `bytes_per_array` bytes; 0 = 256 MiB):
+ * the roofline line for a kernel with that mix of reads and writes (Section
+ * 1 draws the paper's from STREAM).  Best over two orders (every workgroup
+ * over one contiguous chunk of each array; all workgroups sweeping the
+ * arrays together in interleaved tiles, as the solver kernels read their
+ * vectors and matrix slots) and five grid sizes, in GB/s of (n_read +
+ * n_write) arrays per pass.  The arrays are allocated and freed inside the call.  INVALID_ARG
  * for counts out of range or arrays under 16 KiB. */
 FVPCG_API int fvpcg_stream_mix(void* stream, uint64_t bytes_per_array, int32_t n_read, int32_t n_write, double* gbs);
 

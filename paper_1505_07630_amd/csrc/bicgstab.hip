@@ -91,8 +91,8 @@ namespace {
 #endif
 // With several components, s = r - alpha v is stored in r's place by its own
 // streaming pass (k_bi_s) before t = A M^-1 s: the product then gathers one
-// vector per component instead of two, which keeps its gather window within
-// an XCD's L2 (three components: 1.49 GB fetched per launch instead of 0.77).
+// vector per component instead of two (three components: 766 us against 786
+// us per iteration at 7.08M cells, the pass included).
 #ifndef FVPCG_BICG_S_PASS
 #define FVPCG_BICG_S_PASS 1
 #endif

@@ -122,11 +122,16 @@ struct MixArgs {
     int nr, nw;
 };
 
-__global__ __launch_bounds__(kBlock) void k_mix_chunk(MixArgs m, size_t n2, size_t len) {
-    const size_t b0 = (size_t)blockIdx.x * len;
-    const size_t e = b0 + len < n2 ? b0 + len : n2;
+// CHUNK: workgroup b streams elements [b len, (b + 1) len); otherwise all
+// workgroups sweep the arrays together, workgroup b taking tiles b, b + G, ...
+// of kBlock elements (the solver kernels' order).
+template <bool CHUNK>
+__global__ __launch_bounds__(kBlock) void k_mix(MixArgs m, size_t n2, size_t len) {
+    const size_t b0 = CHUNK ? (size_t)blockIdx.x * len : (size_t)blockIdx.x * kBlock;
+    const size_t e = CHUNK ? (b0 + len < n2 ? b0 + len : n2) : n2;
+    const size_t step = CHUNK ? (size_t)kBlock : (size_t)gridDim.x * kBlock;
     double keep = 0.0;
-    for (size_t i = b0 + threadIdx.x; i < e; i += kBlock) {
+    for (size_t i = b0 + threadIdx.x; i < e; i += step) {
         double2 v[kMixMaxIn];
 #pragma unroll
         for (int k = 0; k < kMixMaxIn; ++k)
@@ -269,23 +274,29 @@ int stream_mix(hipStream_t s, uint64_t bytes, int nr, int nw, double* gbs) {
         const char* vb = getenv("FVPCG_CALIBRATE_VERBOSE");
         const bool verbose = vb && vb[0] == '1';
         double best = 0.0;
-        for (int gm : {1, 2, 4, 8, 16}) {
-            const int gg = cus * gm;
-            const size_t len = (n2 + gg - 1) / gg;
-            double mine = 0.0;
-            for (int rep = 0; rep < 4; ++rep) {
-                FV_HIP(hipEventRecord(e0, s));
-                hipLaunchKernelGGL(k_mix_chunk, dim3(gg), dim3(kBlock), 0, s, m, n2, len);
-                FV_LAUNCHED();
-                FV_HIP(hipEventRecord(e1, s));
-                FV_HIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                FV_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (rep > 0 && ms > 0) mine = std::fmax(mine, moved / (ms * 1e6));
+        for (int chunk = 1; chunk >= 0; --chunk)
+            for (int gm : {1, 2, 4, 8, 16}) {
+                const int gg = cus * gm;
+                const size_t len = (n2 + gg - 1) / gg;
+                double mine = 0.0;
+                for (int rep = 0; rep < 4; ++rep) {
+                    FV_HIP(hipEventRecord(e0, s));
+                    if (chunk)
+                        hipLaunchKernelGGL(k_mix<true>, dim3(gg), dim3(kBlock), 0, s, m, n2, len);
+                    else
+                        hipLaunchKernelGGL(k_mix<false>, dim3(gg), dim3(kBlock), 0, s, m, n2, len);
+                    FV_LAUNCHED();
+                    FV_HIP(hipEventRecord(e1, s));
+                    FV_HIP(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    FV_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (rep > 0 && ms > 0) mine = std::fmax(mine, moved / (ms * 1e6));
+                }
+                if (verbose)
+                    fprintf(stderr, "[calibrate] mix %2d in %d out %s grid %5d: %7.1f GB/s\n", nr, nw,
+                            chunk ? "chunks" : "sweep ", gg, mine);
+                best = std::fmax(best, mine);
             }
-            if (verbose) fprintf(stderr, "[calibrate] mix %2d in %d out grid %5d: %7.1f GB/s\n", nr, nw, gg, mine);
-            best = std::fmax(best, mine);
-        }
         *gbs = best;
         return FVPCG_OK;
     };

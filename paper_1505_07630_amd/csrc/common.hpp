@@ -146,15 +146,6 @@ void dev_free(T*& p) {
 // ---------------------------------------------------------------------------
 // Device helpers.
 
-// Workgroups are dispatched round-robin over the 8 XCDs of the chip; give
-// each XCD a contiguous band of rows so its L2 holds that band's neighbour
-// columns.  A bijection of [0, G) for any G.
-__device__ __forceinline__ int xcd_block(int b, int G) {
-    const int q = G >> 3, rem = G & 7;
-    const int x = b & 7, i = b >> 3;
-    return x * q + (x < rem ? x : rem) + i;
-}
-
 // v from the lane K places lower in the same row of 16 lanes, 0 for the
 // first K lanes of each row (DPP row_shr:K with bound_ctrl zero fill; the
 // two 32-bit halves move separately).
@@ -269,28 +260,14 @@ __device__ __forceinline__ void st_once(T* p, T v) {
 #endif
 }
 
-// Tiles of BS rows handled by workgroup b (see FV_ROWS).
+// Tiles of BS rows handled by workgroup b of G (see FV_ROWS): b, b + G,
+// b + 2G, ...
 struct TileRange {
     int first, end, step;
 };
 template <int BS>
-__device__ __forceinline__ TileRange xcd_tiles(int b, int G, int n) {
-    const int T = (n + BS - 1) / BS;
-    const int x = b & 7, j = b >> 3;
-    const int gx = (G >> 3) + (x < (G & 7) ? 1 : 0);
-    const int t0 = x * (T >> 3) + (x < (T & 7) ? x : (T & 7));
-    const int t1 = t0 + (T >> 3) + (x < (T & 7) ? 1 : 0);
-    return {t0 + j, t1, gx};
-}
-
-// Rows of workgroup `blk`.
-struct RowRange {
-    int begin, end;
-};
-__device__ __forceinline__ RowRange rows_of(int blk, int rows, int n) {
-    int b = blk * rows;
-    int e = b + rows;
-    return {b, e < n ? e : n};
+__device__ __forceinline__ TileRange block_tiles(int b, int G, int n) {
+    return {b, (n + BS - 1) / BS, G};
 }
 
 }  // namespace fvpcg

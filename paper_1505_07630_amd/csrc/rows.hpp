@@ -29,14 +29,18 @@ __device__ __forceinline__ T row_gather(const CI* __restrict__ col, const T* __r
     return acc;
 }
 
-// Tiles of BS rows (BS = the kernel's workgroup size).  XCD x (workgroups b
-// with b % 8 == x) owns a contiguous range of tiles; its Gx workgroups take
-// tiles t0 + j, t0 + j + Gx, ... so the workgroups resident on one XCD always
-// work on a compact window of rows and the neighbour columns they gather stay
-// in that XCD's L2.
+// Tiles of BS rows (BS = the kernel's workgroup size), interleaved over the
+// G workgroups: workgroup b takes tiles b, b + G, ..., so all G workgroups
+// sweep the rows together, one window of G tiles at a time.  The hardware
+// deals consecutive workgroups to the 8 XCDs in turn, so each XCD's L2 sees
+// every eighth tile of the window; the neighbour values a row gathers from
+// tiles another XCD owns come from the chip's last-level cache.  Measured on
+// MI355X at 7.08M cells, this order is 3-7% faster for every row-parallel
+// solver kernel than giving each XCD one contiguous band of tiles (which
+// keeps the gathers in the XCD's own L2).
 #define FV_ROWS(blk)                                                          \
     const int blk = (int)blockIdx.x;                                         \
-    const TileRange tr_ = xcd_tiles<BS>(blk, g.grid, n);                     \
+    const TileRange tr_ = block_tiles<BS>(blk, g.grid, n);                   \
     for (int t_ = tr_.first; t_ < tr_.end; t_ += tr_.step)                   \
         for (int c = t_ * BS + (int)threadIdx.x; c < n && c < (t_ + 1) * BS; c += n)
 
@@ -69,7 +73,7 @@ __device__ __forceinline__ void load_slots_raw(const CI* __restrict__ col, const
 template <int BS, typename T, int WT, typename CI, typename Body>
 __device__ __forceinline__ void rows_prefetched(const CI* __restrict__ col, const T* __restrict__ val, int n, Geom g,
                                                 Body&& body) {
-    const TileRange tr = xcd_tiles<BS>((int)blockIdx.x, g.grid, n);
+    const TileRange tr = block_tiles<BS>((int)blockIdx.x, g.grid, n);
     const int last = n - 1;
     int t = tr.first;
     CI ja[WT], jb[WT];

@@ -5,10 +5,10 @@
 // (Section 4.1: one reduction per iteration, overlapped with the product),
 // the FP32/FP64 refinement and the adjoint gradients.
 //
-// Every row-parallel kernel assigns workgroup `blk` (XCD-remapped) the rows
-// [blk*R, blk*R + R), with R a multiple of 64; lanes stride through them.
+// Every row-parallel kernel walks tiles of its workgroup size, interleaved
+// over the workgroups (FV_ROWS), one row per lane.
 // Inner products are accumulated per thread in row order, then per wave
-// (butterfly), per workgroup (fixed order) and finally by the last workgroup
+// (DPP scan), per workgroup (fixed order) and finally by the last workgroup
 // over all workgroup partials in index order: results are bitwise
 // reproducible for a given mesh.  The scalars of the recurrences (alpha,
 // beta, the stopping test, breakdown) are computed once, by that last
