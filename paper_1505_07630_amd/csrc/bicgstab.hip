@@ -97,11 +97,11 @@ namespace {
 #define FVPCG_BICG_S_PASS 1
 #endif
 #ifndef FVPCG_GRID_BICG_S
-#define FVPCG_GRID_BICG_S 1024
+#define FVPCG_GRID_BICG_S 8192
 #endif
 constexpr int kBsBi = FVPCG_BS_BICG;
 constexpr int kBiMaxGrid = FVPCG_GRID_BICG;  // workgroups per launch at most
-constexpr int kBiGridS = FVPCG_GRID_BICG_S;  // the s pass (no reduction: four workgroups per CU)
+constexpr int kBiGridS = FVPCG_GRID_BICG_S;  // the s pass (no reduction; measured best of 256-8192)
 constexpr bool kBiSPass = FVPCG_BICG_S_PASS != 0;
 
 Geom bi_geom(int n, int cap = kBiMaxGrid) {
