@@ -12,8 +12,15 @@ namespace fvpcg {
 __device__ __forceinline__ int slot_col(const int* p, size_t o, int) { return ld_once(p + o); }
 __device__ __forceinline__ int slot_col(const int16_t* p, size_t o, int c) { return c + (int)ld_once(p + o); }
 
-// acc + sum_k val[k][c] * v[col[k][c]] over the WT slots of row c.
-template <typename T, int WT, typename CI>
+// The same with a plain (caching) load: for a kernel launched again and
+// again whose slot columns, with its other small read-only arrays, fit in
+// the chip's 256 MB last-level cache beside its gathered vector.
+__device__ __forceinline__ int slot_col_keep(const int* p, size_t o, int) { return p[o]; }
+__device__ __forceinline__ int slot_col_keep(const int16_t* p, size_t o, int c) { return c + (int)p[o]; }
+
+// acc + sum_k val[k][c] * v[col[k][c]] over the WT slots of row c (KEEP:
+// columns loaded with slot_col_keep).
+template <typename T, int WT, typename CI, bool KEEP = false>
 __device__ __forceinline__ T row_gather(const CI* __restrict__ col, const T* __restrict__ val, int n, int c,
                                         const T* __restrict__ v, T acc) {
     int j[WT];
@@ -21,7 +28,7 @@ __device__ __forceinline__ T row_gather(const CI* __restrict__ col, const T* __r
 #pragma unroll
     for (int k = 0; k < WT; ++k) {
         size_t o = (size_t)k * n + c;
-        j[k] = slot_col(col, o, c);
+        j[k] = KEEP ? slot_col_keep(col, o, c) : slot_col(col, o, c);
         a[k] = ld_once(val + o);
     }
 #pragma unroll

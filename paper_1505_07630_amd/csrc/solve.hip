@@ -278,6 +278,11 @@ __global__ __launch_bounds__(BS) void k_pipe_init_w(const CI* __restrict__ col, 
 // is read anyway; the two products are added in order, giving the same x as
 // two separate updates); k_x_fixup adds a pending alpha_i p_i after an even
 // last iteration.  Saves two vector passes every other iteration.
+// d and the slot columns are read-only and re-read every launch; together
+// with w (read and written every launch) they fit in the chip's 256 MB
+// last-level cache at 7M cells, so they are loaded with caching loads and
+// the other streams non-temporally (measured: 2-3% faster than all
+// non-temporal; caching r or z or s as well is slower).
 template <typename T, bool LIT>
 struct PairX {
     static constexpr bool value = !LIT && sizeof(T) == 8;
@@ -293,8 +298,8 @@ __global__ __launch_bounds__(BS) void k_pipe_iter(PipeVec<T> a, int n, Geom g, D
     double acc[3] = {0.0, 0.0, 0.0};
     FV_ROWS(blk) {
         const T wc = a.w_in[c];
-        const T dc = ld_once(a.d + c);
-        const T nv = row_gather<T, WT, CI>((const CI*)a.col, a.val, n, c, a.w_in, JAC ? wc : dc * wc);
+        const T dc = a.d[c];
+        const T nv = row_gather<T, WT, CI, true>((const CI*)a.col, a.val, n, c, a.w_in, JAC ? wc : dc * wc);
         const T zc = nv + beta * ld_once(a.z + c);
         const T sc = wc + beta * ld_once(a.s + c);
         T rc = ld_once(a.r + c);
