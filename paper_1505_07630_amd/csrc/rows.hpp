@@ -1,5 +1,5 @@
 // Row-parallel building blocks shared by the solver kernels: the ELL slot
-// gather, the XCD-aware tile loop, the layout dispatch and the per-solver
+// gather, the interleaved tile loop, the layout dispatch and the per-solver
 // workgroup geometry.
 #pragma once
 
