@@ -123,14 +123,17 @@ __global__ void k_gather_coeffs(const int* __restrict__ ref, const int* __restri
 }
 
 // flag bit 2: lower differs from upper on some face (or either is NaN); one
-// atomic per wavefront that saw a difference (a non-symmetric matrix differs
-// on almost every face)
+// atomic per workgroup that saw a difference (a non-symmetric matrix differs
+// on almost every face, so the launch uses at most kCheckGrid workgroups:
+// with one atomic per wavefront over every face the same-address atomics
+// took 3 ms at 21M faces)
+constexpr int kCheckGrid = 1024;
 __global__ void k_check_sym(const double* __restrict__ upper, const double* __restrict__ lower, int F,
                             unsigned* flags) {
     bool asym = false;
     for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < F; f += gridDim.x * blockDim.x)
         if (!(upper[f] == lower[f])) asym = true;
-    if (__ballot(asym) != 0 && (threadIdx.x & 63) == 0) atomicOr(flags, 2u);
+    if (__syncthreads_or(asym) && threadIdx.x == 0) atomicOr(flags, 2u);
 }
 
 __global__ void k_copy_diag(const double* __restrict__ diag, int n, double* d, float* d32, unsigned* flags) {
@@ -182,7 +185,8 @@ int matrix_refresh(fvpcg_matrix* A, const double* diag, const double* upper, con
         if (hipMemsetAsync(dflag, 0, sizeof(unsigned), s) != hipSuccess) { rc = hip_fail(hipGetLastError(), "memset", __FILE__, __LINE__); break; }
         hipLaunchKernelGGL(k_copy_diag, dim3(grid_for(m->n)), dim3(kBlock), 0, s, diag, m->n, A->d, A->d32, dflag);
         if (lower && m->F > 0)
-            hipLaunchKernelGGL(k_check_sym, dim3(grid_for(m->F)), dim3(kBlock), 0, s, upper, lower, m->F, dflag);
+            hipLaunchKernelGGL(k_check_sym, dim3(std::min(grid_for(m->F), kCheckGrid)), dim3(kBlock), 0, s, upper,
+                               lower, m->F, dflag);
         hipLaunchKernelGGL(k_gather_coeffs, dim3(grid_for((size_t)m->W * m->n)), dim3(kBlock), 0, s, m->ref, m->col,
                            m->n, m->W, diag, upper, lo, A->val, A->val_cs, A->val32, A->val32_cs);
         hipError_t e = hipGetLastError();
