@@ -281,6 +281,32 @@ def test_autograd_function(fv, orc):
     dc.close()
 
 
+def test_single_asymmetric_face_detected(fv):
+    """One face with lower != upper among 774k (more faces than the
+    symmetry check's threads, so each thread checks several): CG refuses
+    the matrix; restoring that face makes it acceptable again.  Faces at
+    the start, the middle and the end of the list."""
+    say("single asymmetric face")
+    import torch
+
+    case = fc.varcoef((64, 64, 64), seed=3)
+    assert case.F > 1024 * 256
+    dc = DevCase(case, symmetric=False)
+    try:
+        for f in (0, case.F // 2 + 7, case.F - 1):
+            lower = dc.upper.clone()
+            lower[f] *= 1.0 + 2.0 ** -40
+            dc.A.update(dc.diag, dc.upper, lower)
+            with pytest.raises(fv.FVPCGError) as e:
+                fv.solve(dc.A, dc.b, tol=1e-8, method="pipecg")
+            assert e.value.code == fv.UNSUPPORTED, f
+            dc.A.update(dc.diag, dc.upper, dc.upper.clone())
+            _, st = fv.solve(dc.A, dc.b, tol=1e-8, method="pipecg")
+            assert st["status"] == 0, f
+    finally:
+        dc.close()
+
+
 def test_nonsymmetric_values_refused_by_cg_paths(fv):
     """CG, its pipelined forms, both mixed solvers, the adjoint and the
     batched solver assume A = A^T: with lower = upper / 2 on every face each
