@@ -53,6 +53,29 @@ int grid1d(long long work) {
 #define FV_GRID_LOOP(i, n) \
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
 
+// One global atomic per workgroup for a value every thread contributes to
+// (a count or a maximum over all rows): the workgroup combines its threads'
+// values in LDS first.  Same-address atomics from every thread took
+// milliseconds per launch at 7M rows.  Every thread of the workgroup must
+// call it.
+__device__ __forceinline__ void block_atomic_add(int* out, int v) {
+    __shared__ int s_sum;
+    if (threadIdx.x == 0) s_sum = 0;
+    __syncthreads();
+    if (v) atomicAdd(&s_sum, v);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_sum) atomicAdd(out, s_sum);
+}
+template <typename T>
+__device__ __forceinline__ void block_atomic_max(T* out, T v) {  // v >= 0
+    __shared__ T s_max;
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    if (v) atomicMax(&s_max, v);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_max) atomicMax(out, s_max);
+}
+
 // Device buffer owned by one setup step.
 template <typename T>
 struct DevBuf {
@@ -201,7 +224,7 @@ __global__ __launch_bounds__(kSetupBs) void k_lvl_diag(const int* __restrict__ p
             mx = bits > mx ? bits : mx;
         }
     }
-    if (mx) atomicMax(rho_bits, mx);
+    block_atomic_max<unsigned long long>(rho_bits, mx);
     if (b) atomicOr(bad, 1);
 }
 
@@ -259,6 +282,42 @@ __global__ __launch_bounds__(kSetupBs) void k_mis_max(const int* __restrict__ pt
     }
 }
 
+// The same maxima with G lanes per row, for the coarse levels whose rows
+// hold tens of entries: the lanes stride through the row and the group's
+// maximum is formed by butterfly shuffles within the group.  A maximum is
+// exact in any order, so the result is that of k_mis_max.
+template <int G>
+__global__ __launch_bounds__(kSetupBs) void k_mis_max_g(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                       const uint8_t* __restrict__ strong, int n,
+                                                       const uint64_t* __restrict__ in, uint64_t* __restrict__ out) {
+    const int lane = threadIdx.x & 63, sub = lane / G, gl = lane % G;
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long nwave = ((long long)gridDim.x * blockDim.x) >> 6;
+    for (long long base = wave * (64 / G); base < n; base += nwave * (64 / G)) {  // wave-uniform
+        const long long i = base + sub;
+        unsigned long long m = 0;
+        if (i < n) {
+            if (gl == 0) m = in[i];
+            for (int p = ptr[i] + gl; p < ptr[i + 1]; p += G)
+                if (strong[p]) {
+                    const unsigned long long v = in[col[p]];
+                    m = v > m ? v : m;
+                }
+        }
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) {
+            const unsigned long long v = __shfl_xor(m, o, 64);
+            m = v > m ? v : m;
+        }
+        if (i < n && gl == 0) out[i] = m;
+    }
+}
+
+int mis_group_grid(int n, int G) {
+    const long long rows_per_block = (long long)(kSetupBs / 64) * (64 / G);
+    return (int)std::max(1LL, std::min(((long long)n + rows_per_block - 1) / rows_per_block, 65536LL));
+}
+
 // Level 0 in the matrix's slot layout (slot k of row c at k n + c, padding
 // repeating the row with a zero value): the same strength relation, stored
 // per slot, and the same maxima, read with coalesced slot loads.
@@ -306,7 +365,7 @@ __global__ __launch_bounds__(kSetupBs) void k_mis_decide(int n, uint64_t* __rest
         else
             ++left;
     }
-    if (left) atomicAdd(undecided, left);
+    block_atomic_add(undecided, left);
 }
 
 __global__ __launch_bounds__(kSetupBs) void k_root_flags(int n, const uint64_t* __restrict__ key, int* __restrict__ f) {
@@ -396,7 +455,7 @@ __global__ __launch_bounds__(kSetupBs) void k_gemm_bound(const int* __restrict__
         ub[i] = t;
         m = max(m, xptr[i + 1] - xptr[i]);
     }
-    if (m) atomicMax(maxlen, m);
+    block_atomic_max<int>(maxlen, m);
 }
 
 // binary min-heap of 64-bit keys
@@ -733,7 +792,7 @@ __global__ __launch_bounds__(64) void k_gemm_tiled(const int* __restrict__ xptr,
 __global__ __launch_bounds__(kSetupBs) void k_max_rowlen(const int* __restrict__ ptr, int rows, int* out) {
     int m = 0;
     FV_GRID_LOOP(i, rows) m = max(m, ptr[i + 1] - ptr[i]);
-    if (m) atomicMax(out, m);
+    block_atomic_max<int>(out, m);
 }
 
 // 64-bit copy of a row-pointer array
@@ -1183,6 +1242,7 @@ int aggregate_level(const CsrView& A, const double* d, double theta, uint64_t se
                            theta, strong_ell.p);
         FV_LAUNCHED();
     }
+    const double avg_row = (double)A.nnz / (double)std::max(n, 1);
     int left = 1, rounds = 0;
     while (left > 0) {
         if (++rounds > kMaxMisRounds)
@@ -1193,6 +1253,11 @@ int aggregate_level(const CsrView& A, const double* d, double theta, uint64_t se
                                key.p, m1.p);
             hipLaunchKernelGGL(k_mis_max_ell, dim3(g), dim3(kSetupBs), 0, s, ell->col, strong_ell.p, n, ell->W,
                                m1.p, m2.p);
+        } else if (avg_row > 6.0) {
+            hipLaunchKernelGGL(k_mis_max_g<16>, dim3(mis_group_grid(n, 16)), dim3(kSetupBs), 0, s, A.ptr, A.col,
+                               strong.p, n, key.p, m1.p);
+            hipLaunchKernelGGL(k_mis_max_g<16>, dim3(mis_group_grid(n, 16)), dim3(kSetupBs), 0, s, A.ptr, A.col,
+                               strong.p, n, m1.p, m2.p);
         } else {
             hipLaunchKernelGGL(k_mis_max, dim3(g), dim3(kSetupBs), 0, s, A.ptr, A.col, strong.p, n, key.p, m1.p);
             hipLaunchKernelGGL(k_mis_max, dim3(g), dim3(kSetupBs), 0, s, A.ptr, A.col, strong.p, n, m1.p, m2.p);
