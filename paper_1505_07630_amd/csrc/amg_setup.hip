@@ -800,14 +800,20 @@ __global__ __launch_bounds__(kSetupBs) void k_widen(const int* __restrict__ ptr,
     FV_GRID_LOOP(i, n) out[i] = ptr[i];
 }
 
+// The rows, written at their upper-bound offsets, copied to C's row
+// pointers; G lanes per row so that each row's copy is coalesced.
+template <int G>
 __global__ __launch_bounds__(kSetupBs) void k_gemm_compact(int rows, const long long* __restrict__ off,
                                                           const int* __restrict__ cnt, const int* __restrict__ cptr,
                                                           const int* __restrict__ tcol, const double* __restrict__ tval,
                                                           int* __restrict__ ccol, double* __restrict__ cval) {
-    FV_GRID_LOOP(i, rows) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int gl = (int)(t % G);
+    const long long stride = (long long)gridDim.x * blockDim.x / G;
+    for (long long i = t / G; i < rows; i += stride) {
         const long long o = off[i];
-        const int q = cptr[i];
-        for (int k = 0; k < cnt[i]; ++k) {
+        const int q = cptr[i], c = cnt[i];
+        for (int k = gl; k < c; k += G) {
             ccol[q + k] = tcol[o + k];
             cval[q + k] = tval[o + k];
         }
@@ -1102,8 +1108,16 @@ int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s, ProdPla
     if ((rc = dev_alloc(&C.col, (size_t)std::max(nnz, 1), "product columns")) ||
         (rc = dev_alloc(&C.val, (size_t)std::max(nnz, 1), "product values")))
         return rc;
-    hipLaunchKernelGGL(k_gemm_compact, dim3(grid1d(rows)), dim3(kSetupBs), 0, s, rows, off.p, cnt.p, C.ptr, tcol.p,
-                       tval.p, C.col, C.val);
+    const double avg = (double)nnz / (double)std::max(rows, 1);
+    if (avg <= 5.0)
+        hipLaunchKernelGGL(k_gemm_compact<4>, dim3(grid1d(4LL * rows)), dim3(kSetupBs), 0, s, rows, off.p, cnt.p,
+                           C.ptr, tcol.p, tval.p, C.col, C.val);
+    else if (avg <= 12.0)
+        hipLaunchKernelGGL(k_gemm_compact<8>, dim3(grid1d(8LL * rows)), dim3(kSetupBs), 0, s, rows, off.p, cnt.p,
+                           C.ptr, tcol.p, tval.p, C.col, C.val);
+    else
+        hipLaunchKernelGGL(k_gemm_compact<16>, dim3(grid1d(16LL * rows)), dim3(kSetupBs), 0, s, rows, off.p, cnt.p,
+                           C.ptr, tcol.p, tval.p, C.col, C.val);
     FV_LAUNCHED();
     FV_HIP(hipStreamSynchronize(s));  // the scratch buffers are freed on return
     return FVPCG_OK;
