@@ -554,6 +554,70 @@ __device__ __forceinline__ void merge_row(long long i, const int* __restrict__ x
 }
 #pragma clang fp contract(on)
 
+// Row i of C = X Y for rows of X with at most SM entries (level 0's
+// products): the heads of the lists Y(k_t, :) stay in registers; each step
+// takes the smallest head column and adds, in X's column order t, the
+// products of the lists whose head it is (each product rounded, then added,
+// the first one taken as it is), then advances those lists.  Every column
+// thus receives its products in the heap merge's order, so the sums are
+// bitwise the merge's; the loads of the advanced heads are independent of
+// each other, where the heap merge waits on one load per product.
+constexpr int kShortLists = 8;
+#pragma clang fp contract(off)
+template <int SM>
+__global__ __launch_bounds__(kSetupBs) void k_gemm_short(const int* __restrict__ xptr, const int* __restrict__ xcol,
+                                                        const double* __restrict__ xval, const int* __restrict__ yptr,
+                                                        const int* __restrict__ ycol, const double* __restrict__ yval,
+                                                        int rows, const long long* __restrict__ off,
+                                                        int* __restrict__ tcol, double* __restrict__ tval,
+                                                        int* __restrict__ cnt) {
+    constexpr int kNone = 0x7fffffff;
+    FV_GRID_LOOP(i, rows) {
+        const int base = xptr[i], L = xptr[i + 1] - base;
+        int head[SM], pos[SM], end[SM];
+        double xv[SM];
+#pragma unroll
+        for (int t = 0; t < SM; ++t) {
+            head[t] = kNone;
+            pos[t] = 0;
+            end[t] = 0;
+            xv[t] = 0.0;
+            if (t < L) {
+                const int k = xcol[base + t];
+                xv[t] = xval[base + t];
+                pos[t] = yptr[k];
+                end[t] = yptr[k + 1];
+                if (pos[t] < end[t]) head[t] = ycol[pos[t]];
+            }
+        }
+        const long long o = off[i];
+        int out = 0;
+        for (;;) {
+            int c = kNone;
+#pragma unroll
+            for (int t = 0; t < SM; ++t) c = head[t] < c ? head[t] : c;
+            if (c == kNone) break;
+            double acc = 0.0;
+            bool first = true;
+#pragma unroll
+            for (int t = 0; t < SM; ++t) {
+                if (head[t] == c) {
+                    const double v = xv[t] * yval[pos[t]];
+                    acc = first ? v : acc + v;
+                    first = false;
+                    ++pos[t];
+                    head[t] = pos[t] < end[t] ? ycol[pos[t]] : kNone;
+                }
+            }
+            tcol[o + out] = c;
+            tval[o + out] = acc;
+            ++out;
+        }
+        cnt[i] = out;
+    }
+}
+#pragma clang fp contract(on)
+
 // One row per thread, heap and positions in device memory indexed like X
 // (rows whose list count exceeds the LDS budget).
 __global__ __launch_bounds__(kSetupBs) void k_gemm_merge(const int* __restrict__ xptr, const int* __restrict__ xcol,
@@ -1038,6 +1102,10 @@ int spgemm_launch(const CsrView& X, const CsrView& Y, const ProdPlan& plan, cons
             hipLaunchKernelGGL(k_gemm_tiled, dim3((unsigned)std::min(rows, 65536)), dim3(64), 0, s, X.ptr, X.col,
                                X.val, Y.ptr, Y.col, Y.val, rows, off, tcol, tval, cnt);
             break;
+        case kProdShort:  // rows of X of at most kShortLists entries
+            hipLaunchKernelGGL(k_gemm_short<kShortLists>, dim3(grid1d(rows)), dim3(kSetupBs), 0, s, X.ptr, X.col,
+                               X.val, Y.ptr, Y.col, Y.val, rows, off, tcol, tval, cnt);
+            break;
         case kProdMergeLds: {
             const long long blocks = ((long long)rows + plan.per_wg - 1) / plan.per_wg;
             hipLaunchKernelGGL(k_gemm_merge_lds, dim3((unsigned)std::max(blocks, 1LL)), dim3(kLdsBs),
@@ -1084,15 +1152,22 @@ int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s, ProdPla
     if ((rc = read_scalar(&mlen, mx.p, s))) return rc;
     lds_fit(mlen, &lcap, &per_wg);
     // Kernel choice: dense rows for narrow products, LDS column tiles for
-    // long rows, else the heap merge.  FVPCG_AMG_PRODUCT = merge | tiled |
-    // dense forces one where it applies (all give the same sums); tests use it.
+    // long rows, list heads in registers for rows of X of at most
+    // kShortLists entries, else the heap merge.  FVPCG_AMG_PRODUCT = merge |
+    // tiled | dense | short forces one where it applies (all give the same
+    // sums); tests use it.
     const char* force = getenv("FVPCG_AMG_PRODUCT");
     const std::string fk = force ? force : "";
     const bool dense_ok = (long long)rows * Y.m <= kDenseEntries, tiled_ok = mlen <= kTileMaxLists;
     const bool use_dense = dense_ok && (fk.empty() || fk == "dense");
     const bool use_tiled = !use_dense && tiled_ok &&
                            (fk == "tiled" || (fk.empty() && (total >= kTileMinWork * (long long)rows || per_wg < 1)));
-    plan->mode = use_dense ? kProdDense : use_tiled ? kProdTiled : per_wg >= 1 ? kProdMergeLds : kProdMerge;
+    const bool use_short = !use_dense && !use_tiled && mlen <= kShortLists && (fk.empty() || fk == "short");
+    plan->mode = use_dense ? kProdDense
+                 : use_tiled ? kProdTiled
+                 : use_short ? kProdShort
+                 : per_wg >= 1 ? kProdMergeLds
+                               : kProdMerge;
     plan->lcap = lcap;
     plan->per_wg = per_wg;
     if ((rc = spgemm_launch(X, Y, *plan, off.p, tcol.p, tval.p, cnt.p, s))) return rc;
