@@ -43,7 +43,7 @@ constexpr uint64_t kStaleGeneration = ~0ull;  // a hierarchy no matrix generatio
 
 // The sparse-product kernel chosen for one Galerkin product at setup, kept
 // so that a numeric refresh runs the same kernel without sizing it again.
-enum ProdMode { kProdDense = 0, kProdTiled = 1, kProdMergeLds = 2, kProdMerge = 3, kProdShort = 4 };
+enum ProdMode { kProdDense = 0, kProdTiled = 1, kProdMergeLds = 2, kProdMerge = 3, kProdShort = 4, kProdMergeLds32 = 5 };
 struct ProdPlan {
     int mode = kProdMerge;
     int lcap = 0, per_wg = 0;  // heap entries per row and rows per workgroup of the LDS merge

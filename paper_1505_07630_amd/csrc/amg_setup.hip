@@ -458,12 +458,15 @@ __global__ __launch_bounds__(kSetupBs) void k_gemm_bound(const int* __restrict__
     block_atomic_max<int>(maxlen, m);
 }
 
-// binary min-heap of 64-bit keys
-__device__ __forceinline__ void heap_up(unsigned long long* H, int i) {
-    const unsigned long long v = H[i];
+// binary min-heap of keys (column, list index): 64-bit keys (column << 32 |
+// index), or 32-bit ones (column << 6 | index) when there are at most 64
+// lists and under 2^26 columns; both order the heads alike.
+template <typename K>
+__device__ __forceinline__ void heap_up(K* H, int i) {
+    const K v = H[i];
     while (i > 0) {
         const int q = (i - 1) >> 1;
-        const unsigned long long pv = H[q];
+        const K pv = H[q];
         if (pv <= v) break;
         H[i] = pv;
         i = q;
@@ -471,14 +474,15 @@ __device__ __forceinline__ void heap_up(unsigned long long* H, int i) {
     H[i] = v;
 }
 
-__device__ __forceinline__ void heap_down(unsigned long long* H, int h, int i) {
-    const unsigned long long v = H[i];
+template <typename K>
+__device__ __forceinline__ void heap_down(K* H, int h, int i) {
+    const K v = H[i];
     for (;;) {
         int c = 2 * i + 1;
         if (c >= h) break;
-        unsigned long long cv = H[c];
+        K cv = H[c];
         if (c + 1 < h) {
-            const unsigned long long rv = H[c + 1];
+            const K rv = H[c + 1];
             if (rv < cv) {
                 ++c;
                 cv = rv;
@@ -491,6 +495,19 @@ __device__ __forceinline__ void heap_down(unsigned long long* H, int h, int i) {
     H[i] = v;
 }
 
+template <typename K>
+struct HeapKey;
+template <>
+struct HeapKey<unsigned long long> {
+    static constexpr int kShift = 32;
+};
+template <>
+struct HeapKey<unsigned int> {
+    static constexpr int kShift = 6;  // up to 64 lists
+};
+constexpr int kKey32Lists = 64;
+constexpr int kKey32Cols = 1 << 26;
+
 #pragma clang fp contract(off)
 // Row i of C = X Y by a k-way merge of the rows Y(k, :) for k in X(i, :):
 // the heap H holds (column << 32 | list index) of each list's head, P each
@@ -498,11 +515,14 @@ __device__ __forceinline__ void heap_down(unsigned long long* H, int h, int i) {
 // and, for equal columns, the lists in X's column order, in which their
 // products are summed (each product rounded, then added).  Output: the
 // row's distinct columns and sums at off[i] in (tcol, tval), and its count.
+template <typename K>
 __device__ __forceinline__ void merge_row(long long i, const int* __restrict__ xptr, const int* __restrict__ xcol,
                                           const double* __restrict__ xval, const int* __restrict__ yptr,
                                           const int* __restrict__ ycol, const double* __restrict__ yval,
-                                          const long long* __restrict__ off, unsigned long long* H, int* P,
+                                          const long long* __restrict__ off, K* H, int* P,
                                           int* __restrict__ tcol, double* __restrict__ tval, int* __restrict__ cnt) {
+    constexpr int kS = HeapKey<K>::kShift;
+    constexpr K kMask = ((K)1 << kS) - 1;
     const int base = xptr[i], L = xptr[i + 1] - base;
     int h = 0;
     for (int t = 0; t < L; ++t) {
@@ -510,7 +530,7 @@ __device__ __forceinline__ void merge_row(long long i, const int* __restrict__ x
         const int b = yptr[k];
         if (b < yptr[k + 1]) {
             P[t] = b;
-            H[h] = ((unsigned long long)(unsigned)ycol[b] << 32) | (unsigned)t;
+            H[h] = ((K)(unsigned)ycol[b] << kS) | (K)(unsigned)t;
             heap_up(H, h);
             ++h;
         }
@@ -519,8 +539,8 @@ __device__ __forceinline__ void merge_row(long long i, const int* __restrict__ x
     int out = 0, last = -1;
     double acc = 0.0;
     while (h > 0) {
-        const unsigned long long top = H[0];
-        const int c = (int)(top >> 32), t = (int)(top & 0xffffffffu);
+        const K top = H[0];
+        const int c = (int)(top >> kS), t = (int)(top & kMask);
         const int k = xcol[base + t];
         int p = P[t];
         const double v = xval[base + t] * yval[p];
@@ -538,7 +558,7 @@ __device__ __forceinline__ void merge_row(long long i, const int* __restrict__ x
         ++p;
         if (p < yptr[k + 1]) {
             P[t] = p;
-            H[0] = ((unsigned long long)(unsigned)ycol[p] << 32) | (unsigned)t;
+            H[0] = ((K)(unsigned)ycol[p] << kS) | (K)(unsigned)t;
             heap_down(H, h, 0);
         } else if (--h > 0) {
             H[0] = H[h];
@@ -629,7 +649,8 @@ __global__ __launch_bounds__(kSetupBs) void k_gemm_merge(const int* __restrict__
                                                         int* __restrict__ cnt) {
     FV_GRID_LOOP(i, rows) {
         const int base = xptr[i];
-        merge_row(i, xptr, xcol, xval, yptr, ycol, yval, off, heap + base, pos + base, tcol, tval, cnt);
+        merge_row<unsigned long long>(i, xptr, xcol, xval, yptr, ycol, yval, off, heap + base, pos + base, tcol,
+                                      tval, cnt);
     }
 }
 
@@ -640,6 +661,7 @@ __global__ __launch_bounds__(kSetupBs) void k_gemm_merge(const int* __restrict__
 constexpr int kLdsBs = 64;
 constexpr int kLdsBytes = 65536;
 constexpr long long kDenseEntries = 1LL << 27;  // rows x columns of a product accumulated densely (1.2 GB)
+template <typename K>
 __global__ __launch_bounds__(kLdsBs) void k_gemm_merge_lds(const int* __restrict__ xptr, const int* __restrict__ xcol,
                                                           const double* __restrict__ xval,
                                                           const int* __restrict__ yptr, const int* __restrict__ ycol,
@@ -647,13 +669,14 @@ __global__ __launch_bounds__(kLdsBs) void k_gemm_merge_lds(const int* __restrict
                                                           int lcap, const long long* __restrict__ off,
                                                           int* __restrict__ tcol, double* __restrict__ tval,
                                                           int* __restrict__ cnt) {
-    extern __shared__ unsigned long long lds_heap[];
+    extern __shared__ unsigned long long lds_heap_raw[];
+    K* lds_heap = reinterpret_cast<K*>(lds_heap_raw);
     const int t = (int)threadIdx.x;
     const long long i = (long long)blockIdx.x * per_wg + t;
     if (t >= per_wg || i >= rows) return;
-    unsigned long long* H = lds_heap + (size_t)t * lcap;
+    K* H = lds_heap + (size_t)t * lcap;
     int* P = reinterpret_cast<int*>(lds_heap + (size_t)per_wg * lcap) + (size_t)t * lcap;
-    merge_row(i, xptr, xcol, xval, yptr, ycol, yval, off, H, P, tcol, tval, cnt);
+    merge_row<K>(i, xptr, xcol, xval, yptr, ycol, yval, off, H, P, tcol, tval, cnt);
 }
 
 // Row i of C = X Y with one wavefront per row and a dense accumulator of
@@ -1108,8 +1131,15 @@ int spgemm_launch(const CsrView& X, const CsrView& Y, const ProdPlan& plan, cons
             break;
         case kProdMergeLds: {
             const long long blocks = ((long long)rows + plan.per_wg - 1) / plan.per_wg;
-            hipLaunchKernelGGL(k_gemm_merge_lds, dim3((unsigned)std::max(blocks, 1LL)), dim3(kLdsBs),
-                               (size_t)plan.per_wg * plan.lcap * 12, s, X.ptr, X.col, X.val, Y.ptr, Y.col, Y.val,
+            hipLaunchKernelGGL(k_gemm_merge_lds<unsigned long long>, dim3((unsigned)std::max(blocks, 1LL)),
+                               dim3(kLdsBs), (size_t)plan.per_wg * plan.lcap * 12, s, X.ptr, X.col, X.val, Y.ptr,
+                               Y.col, Y.val, rows, plan.per_wg, plan.lcap, off, tcol, tval, cnt);
+            break;
+        }
+        case kProdMergeLds32: {  // 32-bit heap keys: 8 bytes of LDS per list, more rows per CU
+            const long long blocks = ((long long)rows + plan.per_wg - 1) / plan.per_wg;
+            hipLaunchKernelGGL(k_gemm_merge_lds<unsigned int>, dim3((unsigned)std::max(blocks, 1LL)), dim3(kLdsBs),
+                               (size_t)plan.per_wg * plan.lcap * 8, s, X.ptr, X.col, X.val, Y.ptr, Y.col, Y.val,
                                rows, plan.per_wg, plan.lcap, off, tcol, tval, cnt);
             break;
         }
@@ -1153,9 +1183,9 @@ int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s, ProdPla
     lds_fit(mlen, &lcap, &per_wg);
     // Kernel choice: dense rows for narrow products, LDS column tiles for
     // long rows, list heads in registers for rows of X of at most
-    // kShortLists entries, else the heap merge.  FVPCG_AMG_PRODUCT = merge |
-    // tiled | dense | short forces one where it applies (all give the same
-    // sums); tests use it.
+    // kShortLists entries, else the heap merge (32-bit keys where they
+    // fit).  FVPCG_AMG_PRODUCT = merge | merge32 | tiled | dense | short
+    // forces one where it applies (all give the same sums); tests use it.
     const char* force = getenv("FVPCG_AMG_PRODUCT");
     const std::string fk = force ? force : "";
     const bool dense_ok = (long long)rows * Y.m <= kDenseEntries, tiled_ok = mlen <= kTileMaxLists;
@@ -1163,13 +1193,19 @@ int spgemm(const CsrView& X, const CsrView& Y, CsrOut& C, hipStream_t s, ProdPla
     const bool use_tiled = !use_dense && tiled_ok &&
                            (fk == "tiled" || (fk.empty() && (total >= kTileMinWork * (long long)rows || per_wg < 1)));
     const bool use_short = !use_dense && !use_tiled && mlen <= kShortLists && (fk.empty() || fk == "short");
+    // the LDS merge with 32-bit keys where the lists and columns fit them:
+    // 8 instead of 12 bytes of LDS per list, so more rows share a CU
+    const int per_wg32 = std::min(kLdsBs, kLdsBytes / (8 * lcap));
+    const bool use_k32 = !use_dense && !use_tiled && !use_short && per_wg >= 1 && mlen <= kKey32Lists &&
+                         Y.m < kKey32Cols && (fk.empty() || fk == "merge32");
     plan->mode = use_dense ? kProdDense
                  : use_tiled ? kProdTiled
                  : use_short ? kProdShort
+                 : use_k32 ? kProdMergeLds32
                  : per_wg >= 1 ? kProdMergeLds
                                : kProdMerge;
     plan->lcap = lcap;
-    plan->per_wg = per_wg;
+    plan->per_wg = use_k32 ? per_wg32 : per_wg;
     if ((rc = spgemm_launch(X, Y, *plan, off.p, tcol.p, tval.p, cnt.p, s))) return rc;
     C.n = rows;
     C.m = Y.m;

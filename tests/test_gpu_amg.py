@@ -62,16 +62,16 @@ def _hierarchy(M, levels):
 @pytest.mark.parametrize("theta", [0.0, 0.02])
 @pytest.mark.parametrize("name", ["varcoef32_rcm", "cavity_24x24x8"])
 def test_amg_product_kernels_agree(fv, orc, name, theta, monkeypatch):
-    """The sparse-product kernels of the setup (heap merge, LDS column tiles,
-    dense rows, list heads in registers for short rows; FVPCG_AMG_PRODUCT
-    forces one where it applies) sum every entry in the same order: the
-    hierarchies are equal entry for entry, and equal the oracle's within
-    1e-12 (theta > 0 included)."""
+    """The sparse-product kernels of the setup (heap merge with 64- or 32-bit
+    keys, LDS column tiles, dense rows, list heads in registers for short
+    rows; FVPCG_AMG_PRODUCT forces one where it applies) sum every entry in
+    the same order: the hierarchies are equal entry for entry, and equal the
+    oracle's within 1e-12 (theta > 0 included)."""
     say("amg product kernels", name, theta)
     case = CASES[name]()
     dc = DevCase(case)
     hs = {}
-    for mode in ("merge", "tiled", "dense", "short"):
+    for mode in ("merge", "merge32", "tiled", "dense", "short"):
         monkeypatch.setenv("FVPCG_AMG_PRODUCT", mode)
         M = fv.AMG(dc.A, theta=theta, coarse_size=16)
         hs[mode] = (M.levels, _hierarchy(M, M.levels))
@@ -80,7 +80,7 @@ def test_amg_product_kernels_agree(fv, orc, name, theta, monkeypatch):
     H = orc.AMG(case, theta=theta, coarse_size=16)
     levels, ref = hs["merge"]
     assert levels == H.levels
-    for mode in ("tiled", "dense", "short"):
+    for mode in ("merge32", "tiled", "dense", "short"):
         assert hs[mode][0] == levels
         for l, (a, b) in enumerate(zip(ref, hs[mode][1])):
             assert a["info"] == b["info"], (mode, l)
